@@ -1,0 +1,636 @@
+/*
+ * Plain FP64 CPU oracle (test infrastructure only; see oracle.h).
+ *
+ * Everything here is written for a reader checking it against the paper by
+ * eye: dense hyper-dual numbers carry (value, gradient, full Hessian) over
+ * the element's stencil DOFs (Sec. 5.1, Sec. 6.2), every energy is the
+ * formula as stated, assembly is the serial sum of Eq. 2, and the Hessian
+ * filter is a textbook cyclic Jacobi eigen-decomposition followed by the
+ * eigenvalue clamp of Sec. 7.1. No blocking, no fusion, no reordering.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define KMAX 12
+
+/* ------------------------------------------------------------------------- */
+/* Hyper-dual scalar over k local variables (Sec. 5.1 "ActiveT", Sec. 6.2). */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int k;
+    double v;
+    double g[KMAX];
+    double h[KMAX][KMAX];
+} hd;
+
+static hd hd_const(int k, double c) {
+    hd r;
+    memset(&r, 0, sizeof r);
+    r.k = k;
+    r.v = c;
+    return r;
+}
+
+/* the i-th active variable with value v (seed: gradient e_i, zero Hessian) */
+static hd hd_var(int k, int i, double v) {
+    hd r = hd_const(k, v);
+    if (i < k) r.g[i] = 1.0;
+    return r;
+}
+
+static hd hd_add(hd a, hd b) {
+    hd r = hd_const(a.k, a.v + b.v);
+    for (int i = 0; i < a.k; ++i) {
+        r.g[i] = a.g[i] + b.g[i];
+        for (int j = 0; j < a.k; ++j) r.h[i][j] = a.h[i][j] + b.h[i][j];
+    }
+    return r;
+}
+
+static hd hd_sub(hd a, hd b) {
+    hd r = hd_const(a.k, a.v - b.v);
+    for (int i = 0; i < a.k; ++i) {
+        r.g[i] = a.g[i] - b.g[i];
+        for (int j = 0; j < a.k; ++j) r.h[i][j] = a.h[i][j] - b.h[i][j];
+    }
+    return r;
+}
+
+static hd hd_scale(hd a, double c) {
+    hd r = hd_const(a.k, c * a.v);
+    for (int i = 0; i < a.k; ++i) {
+        r.g[i] = c * a.g[i];
+        for (int j = 0; j < a.k; ++j) r.h[i][j] = c * a.h[i][j];
+    }
+    return r;
+}
+
+static hd hd_addc(hd a, double c) {
+    a.v += c;
+    return a;
+}
+
+/* product rule: (ab)'' = a b'' + b a'' + a' b'^T + b' a'^T */
+static hd hd_mul(hd a, hd b) {
+    hd r = hd_const(a.k, a.v * b.v);
+    for (int i = 0; i < a.k; ++i) {
+        r.g[i] = a.v * b.g[i] + b.v * a.g[i];
+        for (int j = 0; j < a.k; ++j)
+            r.h[i][j] = a.v * b.h[i][j] + b.v * a.h[i][j] + a.g[i] * b.g[j] + b.g[i] * a.g[j];
+    }
+    return r;
+}
+
+/* scalar chain rule for a unary f with f(a), f'(a), f''(a) */
+static hd hd_unary(hd a, double f0, double f1, double f2) {
+    hd r = hd_const(a.k, f0);
+    for (int i = 0; i < a.k; ++i) {
+        r.g[i] = f1 * a.g[i];
+        for (int j = 0; j < a.k; ++j) r.h[i][j] = f1 * a.h[i][j] + f2 * a.g[i] * a.g[j];
+    }
+    return r;
+}
+
+/* chain rule for a binary f(a, b) with its first and second partials */
+static hd hd_binary(hd a, hd b, double f0, double fa, double fb, double faa, double fbb, double fab) {
+    hd r = hd_const(a.k, f0);
+    for (int i = 0; i < a.k; ++i) {
+        r.g[i] = fa * a.g[i] + fb * b.g[i];
+        for (int j = 0; j < a.k; ++j)
+            r.h[i][j] = fa * a.h[i][j] + fb * b.h[i][j] + faa * a.g[i] * a.g[j] + fbb * b.g[i] * b.g[j]
+                        + fab * (a.g[i] * b.g[j] + b.g[i] * a.g[j]);
+    }
+    return r;
+}
+
+static hd hd_sq(hd a) { return hd_mul(a, a); }
+
+static hd hd_recip(hd a) {
+    double v = a.v;
+    return hd_unary(a, 1.0 / v, -1.0 / (v * v), 2.0 / (v * v * v));
+}
+
+static hd hd_div(hd a, hd b) { return hd_mul(a, hd_recip(b)); }
+
+static hd hd_sqrt(hd a) {
+    double s = sqrt(a.v);
+    return hd_unary(a, s, 0.5 / s, -0.25 / (s * a.v));
+}
+
+/* atan2(y, x): d/dy = x/r2, d/dx = -y/r2, d2/dy2 = -2xy/r4, d2/dx2 = 2xy/r4,
+ * d2/dxdy = (y^2 - x^2)/r4 */
+static hd hd_atan2(hd y, hd x) {
+    double r2 = x.v * x.v + y.v * y.v;
+    double r4 = r2 * r2;
+    return hd_binary(y, x, atan2(y.v, x.v), x.v / r2, -y.v / r2, -2.0 * x.v * y.v / r4,
+                     2.0 * x.v * y.v / r4, (y.v * y.v - x.v * x.v) / r4);
+}
+
+/* 3-vectors of hyper-duals */
+typedef struct { hd c[3]; } hd3;
+
+static hd3 hd3_sub(hd3 a, hd3 b) {
+    hd3 r;
+    for (int i = 0; i < 3; ++i) r.c[i] = hd_sub(a.c[i], b.c[i]);
+    return r;
+}
+
+static hd hd3_dot(hd3 a, hd3 b) {
+    hd r = hd_mul(a.c[0], b.c[0]);
+    r = hd_add(r, hd_mul(a.c[1], b.c[1]));
+    return hd_add(r, hd_mul(a.c[2], b.c[2]));
+}
+
+static hd3 hd3_cross(hd3 a, hd3 b) {
+    hd3 r;
+    r.c[0] = hd_sub(hd_mul(a.c[1], b.c[2]), hd_mul(a.c[2], b.c[1]));
+    r.c[1] = hd_sub(hd_mul(a.c[2], b.c[0]), hd_mul(a.c[0], b.c[2]));
+    r.c[2] = hd_sub(hd_mul(a.c[0], b.c[1]), hd_mul(a.c[1], b.c[0]));
+    return r;
+}
+
+/* lift vertex s of the stencil (VarDim 3) as active variables 3s..3s+2 */
+static hd3 lift3(int k, const double *xloc, int s) {
+    hd3 r;
+    for (int d = 0; d < 3; ++d) r.c[d] = hd_var(k, 3 * s + d, xloc[3 * s + d]);
+    return r;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Element energies.                                                          */
+/* ------------------------------------------------------------------------- */
+
+/* Listing 1: squared edge length |x0 - x1|^2 (Op::EV, k = 6) */
+static hd e_edge_sqlen(int k, const double *xloc) {
+    hd3 d = hd3_sub(lift3(k, xloc, 0), lift3(k, xloc, 1));
+    return hd3_dot(d, d);
+}
+
+/* Sec. 7.6: area 0.5 |(x1 - x0) x (x2 - x0)| (Op::FV, k = 9) */
+static hd e_tri_area(int k, const double *xloc) {
+    hd3 x0 = lift3(k, xloc, 0), x1 = lift3(k, xloc, 1), x2 = lift3(k, xloc, 2);
+    hd3 n = hd3_cross(hd3_sub(x1, x0), hd3_sub(x2, x0));
+    return hd_scale(hd_sqrt(hd3_dot(n, n)), 0.5);
+}
+
+/* Scalar Dirichlet energy 0.5 A |grad u|^2 of the piecewise-linear field u on a
+ * triangle whose (passive) rest positions give Dm; grad u = Dm^{-T} (u1-u0, u2-u0). */
+static hd e_dirichlet(int k, const double *xloc, const double *rest) {
+    const double *mi = rest; /* Dm^{-1} row-major */
+    double area = rest[4];
+    hd u0 = hd_var(k, 0, xloc[0]), u1 = hd_var(k, 1, xloc[1]), u2 = hd_var(k, 2, xloc[2]);
+    hd d1 = hd_sub(u1, u0), d2 = hd_sub(u2, u0);
+    hd g0 = hd_add(hd_scale(d1, mi[0]), hd_scale(d2, mi[2]));
+    hd g1 = hd_add(hd_scale(d1, mi[1]), hd_scale(d2, mi[3]));
+    return hd_scale(hd_add(hd_sq(g0), hd_sq(g1)), 0.5 * area);
+}
+
+/* StVK membrane: F = Ds Dm^{-1} (3x2), E = (F^T F - I)/2,
+ * f = A (mu tr(E^2) + lambda/2 tr(E)^2). */
+static hd e_stvk(int k, const double *xloc, const double *rest, const double *prm) {
+    const double *mi = rest;
+    double area = rest[4], mu = prm[0], lam = prm[1];
+    hd3 xa = lift3(k, xloc, 0), xb = lift3(k, xloc, 1), xc = lift3(k, xloc, 2);
+    hd3 d1 = hd3_sub(xb, xa), d2 = hd3_sub(xc, xa);
+    hd F[3][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 2; ++j)
+            F[i][j] = hd_add(hd_scale(d1.c[i], mi[0 * 2 + j]), hd_scale(d2.c[i], mi[1 * 2 + j]));
+    hd E[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            hd c = hd_mul(F[0][a], F[0][b]);
+            c = hd_add(c, hd_mul(F[1][a], F[1][b]));
+            c = hd_add(c, hd_mul(F[2][a], F[2][b]));
+            E[a][b] = hd_scale(hd_addc(c, a == b ? -1.0 : 0.0), 0.5);
+        }
+    hd trE = hd_add(E[0][0], E[1][1]);
+    hd trE2 = hd_add(hd_add(hd_sq(E[0][0]), hd_sq(E[1][1])), hd_add(hd_mul(E[0][1], E[1][0]), hd_mul(E[1][0], E[0][1])));
+    hd psi = hd_add(hd_scale(trE2, mu), hd_scale(hd_sq(trE), 0.5 * lam));
+    return hd_scale(psi, area);
+}
+
+/* dihedral angle of the diamond (x0, x1, x2, x3) about the edge e = x1 - x0:
+ * n1 = e x (x2 - x0), n2 = (x3 - x0) x e, theta = atan2(((n1 x n2).e)/|e|, n1.n2) */
+static hd dihedral(hd3 x0, hd3 x1, hd3 x2, hd3 x3) {
+    hd3 e = hd3_sub(x1, x0);
+    hd3 n1 = hd3_cross(e, hd3_sub(x2, x0));
+    hd3 n2 = hd3_cross(hd3_sub(x3, x0), e);
+    hd y = hd_div(hd3_dot(hd3_cross(n1, n2), e), hd_sqrt(hd3_dot(e, e)));
+    hd xx = hd3_dot(n1, n2);
+    return hd_atan2(y, xx);
+}
+
+/* Sec. 7.7: E_bend = k_b (A/3) (theta - theta')^2 h^2 */
+static hd e_bending(int k, const double *xloc, const double *rest, const double *prm) {
+    double abar = rest[0], theta0 = rest[1], kb = prm[0], ht = prm[1];
+    hd th = dihedral(lift3(k, xloc, 0), lift3(k, xloc, 1), lift3(k, xloc, 2), lift3(k, xloc, 3));
+    hd d = hd_addc(th, -theta0);
+    return hd_scale(hd_sq(d), kb * abar / 3.0 * ht * ht);
+}
+
+/* Sec. 7.2: f = area (|J|_F^2 + |J^{-1}|_F^2), J = [b-a, c-a] [b_r-a_r, c_r-a_r]^{-1} */
+static hd e_symdir(int k, const double *xloc, const double *rest) {
+    const double *mi = rest;
+    double area = rest[4];
+    hd a[2], b[2], c[2];
+    for (int d = 0; d < 2; ++d) {
+        a[d] = hd_var(k, 0 + d, xloc[0 + d]);
+        b[d] = hd_var(k, 2 + d, xloc[2 + d]);
+        c[d] = hd_var(k, 4 + d, xloc[4 + d]);
+    }
+    hd J[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            J[i][j] = hd_add(hd_scale(hd_sub(b[i], a[i]), mi[0 * 2 + j]), hd_scale(hd_sub(c[i], a[i]), mi[1 * 2 + j]));
+    hd det = hd_sub(hd_mul(J[0][0], J[1][1]), hd_mul(J[0][1], J[1][0]));
+    hd idet = hd_recip(det);
+    hd Ji[2][2];
+    Ji[0][0] = hd_mul(J[1][1], idet);
+    Ji[0][1] = hd_scale(hd_mul(J[0][1], idet), -1.0);
+    Ji[1][0] = hd_scale(hd_mul(J[1][0], idet), -1.0);
+    Ji[1][1] = hd_mul(J[0][0], idet);
+    hd nJ = hd_const(k, 0.0), nJi = hd_const(k, 0.0);
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            nJ = hd_add(nJ, hd_sq(J[i][j]));
+            nJi = hd_add(nJi, hd_sq(Ji[i][j]));
+        }
+    return hd_scale(hd_add(nJ, nJi), area);
+}
+
+static int kind_stencil(int kind) {
+    switch (kind) {
+    case OR_EDGE_SQLEN: return 2;
+    case OR_TRI_AREA: case OR_DIRICHLET: case OR_STVK: case OR_SYMDIR: case OR_MLP: return 3;
+    case OR_BENDING: return 4;
+    default: return -1;
+    }
+}
+
+static int kind_vardim(int kind) {
+    switch (kind) {
+    case OR_DIRICHLET: return 1;
+    case OR_SYMDIR: return 2;
+    case OR_EDGE_SQLEN: case OR_TRI_AREA: case OR_STVK: case OR_BENDING: case OR_MLP: return 3;
+    default: return -1;
+    }
+}
+
+/* evaluate one element with k active variables (k = 0: passive, value only) */
+static int eval_elem(int kind, int k, const double *prm, const double *rest, const double *xloc, hd *out) {
+    switch (kind) {
+    case OR_EDGE_SQLEN: *out = e_edge_sqlen(k, xloc); return 0;
+    case OR_TRI_AREA: *out = e_tri_area(k, xloc); return 0;
+    case OR_DIRICHLET: *out = e_dirichlet(k, xloc, rest); return 0;
+    case OR_STVK: *out = e_stvk(k, xloc, rest, prm); return 0;
+    case OR_BENDING: *out = e_bending(k, xloc, rest, prm); return 0;
+    case OR_SYMDIR: *out = e_symdir(k, xloc, rest); return 0;
+    default: return -1;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hessian filtering (Sec. 7.1): clamp eigenvalues of each term's local       */
+/* Hessian from below. Cyclic Jacobi rotations (textbook symmetric Schur       */
+/* decomposition), then out = Q diag(max(lambda, eps)) Q^T.                    */
+/* ------------------------------------------------------------------------- */
+int oracle_spd_project(int n, const double *Ain, double eps, double *out) {
+    if (n <= 0 || n > KMAX) return -1;
+    double A[KMAX][KMAX], Q[KMAX][KMAX];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            A[i][j] = 0.5 * (Ain[i * n + j] + Ain[j * n + i]);
+            Q[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = 0.0, fro = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                fro += A[i][j] * A[i][j];
+                if (i != j) off += A[i][j] * A[i][j];
+            }
+        if (off <= 1e-30 * fro || fro == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                if (A[p][q] == 0.0) continue;
+                double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+                /* A <- A J (columns p, q), then A <- J^T A (rows p, q), Q <- Q J */
+                for (int r = 0; r < n; ++r) {
+                    double ap = A[r][p], aq = A[r][q];
+                    A[r][p] = c * ap - s * aq;
+                    A[r][q] = s * ap + c * aq;
+                }
+                for (int r = 0; r < n; ++r) {
+                    double ap = A[p][r], aq = A[q][r];
+                    A[p][r] = c * ap - s * aq;
+                    A[q][r] = s * ap + c * aq;
+                }
+                for (int r = 0; r < n; ++r) {
+                    double qp = Q[r][p], qq = Q[r][q];
+                    Q[r][p] = c * qp - s * qq;
+                    Q[r][q] = s * qp + c * qq;
+                }
+            }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int m = 0; m < n; ++m) {
+                double lam = A[m][m] > eps ? A[m][m] : eps;
+                acc += Q[i][m] * lam * Q[j][m];
+            }
+            out[i * n + j] = acc;
+        }
+    return 0;
+}
+
+int oracle_element(int kind, const double *params, const double *rest, const double *xloc,
+                   int mode, double spd_eps, double *f, double *g, double *H) {
+    int ss = kind_stencil(kind), vd = kind_vardim(kind);
+    if (ss < 0 || vd < 0) return -1;
+    int k = ss * vd;
+    int kk = (mode & (OR_GRAD | OR_HESS)) ? k : 0;
+    hd r;
+    if (eval_elem(kind, kk, params, rest, xloc, &r) != 0) return -1;
+    if (f) *f = r.v;
+    if (g && (mode & OR_GRAD))
+        for (int i = 0; i < k; ++i) g[i] = r.g[i];
+    if (H && (mode & OR_HESS)) {
+        double tmp[KMAX * KMAX];
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) tmp[i * k + j] = r.h[i][j];
+        if (mode & OR_SPD) return oracle_spd_project(k, tmp, spd_eps, H);
+        memcpy(H, tmp, sizeof(double) * k * k);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Topology: edges and edge diamonds (Sec. 6 pipeline input).                 */
+/* ------------------------------------------------------------------------- */
+typedef struct { int32_t lo, hi, face, from, to, opp; } erec;
+
+static int erec_cmp(const void *pa, const void *pb) {
+    const erec *a = pa, *b = pb;
+    if (a->lo != b->lo) return a->lo < b->lo ? -1 : 1;
+    if (a->hi != b->hi) return a->hi < b->hi ? -1 : 1;
+    if (a->face != b->face) return a->face < b->face ? -1 : 1;
+    return 0;
+}
+
+int oracle_topology(int64_t nv, int64_t nt, const int32_t *tris, int64_t *n_edges, int32_t *edges,
+                    int32_t *edge_nf, int64_t *n_diamonds, int32_t *diamonds, int32_t *diamond_faces) {
+    erec *rec = malloc(sizeof(erec) * (size_t)(3 * nt + 1));
+    if (!rec) return -4;
+    for (int64_t f = 0; f < nt; ++f) {
+        const int32_t *t = tris + 3 * f;
+        for (int c = 0; c < 3; ++c) {
+            if (t[c] < 0 || t[c] >= nv) { free(rec); return -1; }
+        }
+        if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2]) { free(rec); return -1; }
+        for (int c = 0; c < 3; ++c) {
+            erec *r = &rec[3 * f + c];
+            r->from = t[c];
+            r->to = t[(c + 1) % 3];
+            r->opp = t[(c + 2) % 3];
+            r->lo = r->from < r->to ? r->from : r->to;
+            r->hi = r->from < r->to ? r->to : r->from;
+            r->face = (int32_t)f;
+        }
+    }
+    qsort(rec, (size_t)(3 * nt), sizeof(erec), erec_cmp);
+    int64_t ne = 0, nd = 0;
+    for (int64_t i = 0; i < 3 * nt;) {
+        int64_t j = i;
+        while (j < 3 * nt && rec[j].lo == rec[i].lo && rec[j].hi == rec[i].hi) ++j;
+        edges[2 * ne] = rec[i].lo;
+        edges[2 * ne + 1] = rec[i].hi;
+        edge_nf[ne] = (int32_t)(j - i);
+        if (j - i == 2) {
+            /* f1 = rec[i] (lower face index after sorting), f2 = rec[i+1] */
+            int32_t *d = diamonds + 4 * nd;
+            d[0] = rec[i].from;
+            d[1] = rec[i].to;
+            d[2] = rec[i].opp;
+            d[3] = rec[i + 1].opp;
+            diamond_faces[2 * nd] = rec[i].face;
+            diamond_faces[2 * nd + 1] = rec[i + 1].face;
+            ++nd;
+        }
+        ++ne;
+        i = j;
+    }
+    *n_edges = ne;
+    *n_diamonds = nd;
+    free(rec);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Rest data.                                                                 */
+/* ------------------------------------------------------------------------- */
+/* rest triangle in its own 2D frame: Dm = [[|e1|, e1.e2/|e1|], [0, |e1 x e2|/|e1|]] */
+static int rest_frame(const double *X0, const double *X1, const double *X2, double *mi, double *area) {
+    double e1[3], e2[3], c[3];
+    for (int d = 0; d < 3; ++d) {
+        e1[d] = X1[d] - X0[d];
+        e2[d] = X2[d] - X0[d];
+    }
+    c[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    c[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    c[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    double cn = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    if (!(l1 > 0.0) || !(cn > 0.0)) return -2;
+    double dm00 = l1, dm01 = (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]) / l1;
+    double dm10 = 0.0, dm11 = cn / l1;
+    double det = dm00 * dm11 - dm01 * dm10;
+    mi[0] = dm11 / det;
+    mi[1] = -dm01 / det;
+    mi[2] = -dm10 / det;
+    mi[3] = dm00 / det;
+    *area = 0.5 * cn;
+    return 0;
+}
+
+int oracle_rest_tri(int64_t nt, const int32_t *tris, const double *rest, double *dminv, double *area) {
+    for (int64_t f = 0; f < nt; ++f) {
+        const int32_t *t = tris + 3 * f;
+        if (rest_frame(rest + 3 * t[0], rest + 3 * t[1], rest + 3 * t[2], dminv + 4 * f, area + f) != 0) return -2;
+    }
+    return 0;
+}
+
+int oracle_rest_diamond(int64_t nd, const int32_t *diamonds, const int32_t *diamond_faces,
+                        const int32_t *tris, const double *rest, double *abar, double *theta0) {
+    for (int64_t e = 0; e < nd; ++e) {
+        double mi[4], a1, a2;
+        const int32_t *t1 = tris + 3 * diamond_faces[2 * e], *t2 = tris + 3 * diamond_faces[2 * e + 1];
+        if (rest_frame(rest + 3 * t1[0], rest + 3 * t1[1], rest + 3 * t1[2], mi, &a1) != 0) return -2;
+        if (rest_frame(rest + 3 * t2[0], rest + 3 * t2[1], rest + 3 * t2[2], mi, &a2) != 0) return -2;
+        abar[e] = 0.5 * (a1 + a2);
+        double xl[12];
+        for (int s = 0; s < 4; ++s)
+            for (int d = 0; d < 3; ++d) xl[3 * s + d] = rest[3 * diamonds[4 * e + s] + d];
+        hd th = dihedral(lift3(0, xl, 0), lift3(0, xl, 1), lift3(0, xl, 2), lift3(0, xl, 3));
+        theta0[e] = th.v;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Pattern (Sec. 6.1): sorted unique block pairs, prefix sum to row pointers. */
+/* ------------------------------------------------------------------------- */
+static int cmp_i64(const void *a, const void *b) {
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int oracle_pattern(int64_t nv, int n_terms, const int64_t *n_elem, const int *stencil_size,
+                   const int32_t *const *stencils, int32_t *rowptr, int32_t *colidx, int64_t *nnzb) {
+    int64_t total = nv;
+    for (int t = 0; t < n_terms; ++t) total += n_elem[t] * stencil_size[t] * stencil_size[t];
+    int64_t *keys = malloc(sizeof(int64_t) * (size_t)(total > 0 ? total : 1));
+    if (!keys) return -4;
+    int64_t m = 0;
+    for (int64_t i = 0; i < nv; ++i) keys[m++] = i * nv + i;
+    for (int t = 0; t < n_terms; ++t) {
+        int ss = stencil_size[t];
+        for (int64_t e = 0; e < n_elem[t]; ++e) {
+            const int32_t *s = stencils[t] + ss * e;
+            for (int a = 0; a < ss; ++a) {
+                if (s[a] < 0 || s[a] >= nv) { free(keys); return -1; }
+                for (int b = 0; b < ss; ++b) keys[m++] = (int64_t)s[a] * nv + s[b];
+            }
+        }
+    }
+    qsort(keys, (size_t)m, sizeof(int64_t), cmp_i64);
+    int64_t u = 0;
+    for (int64_t i = 0; i < m; ++i)
+        if (i == 0 || keys[i] != keys[i - 1]) keys[u++] = keys[i];
+    *nnzb = u;
+    if (u > 2147483647LL) { free(keys); return -3; }
+    if (colidx) {
+        for (int64_t i = 0; i <= nv; ++i) rowptr[i] = 0;
+        for (int64_t i = 0; i < u; ++i) rowptr[keys[i] / nv + 1] += 1;
+        for (int64_t i = 0; i < nv; ++i) rowptr[i + 1] += rowptr[i];
+        for (int64_t i = 0; i < u; ++i) colidx[i] = (int32_t)(keys[i] % nv);
+    }
+    free(keys);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Energy reduction (Sec. 5.5): Neumaier compensated summation.                */
+/* ------------------------------------------------------------------------- */
+double oracle_neumaier_sum(int64_t n, const double *v) {
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = s + v[i];
+        if (fabs(s) >= fabs(v[i])) c += (s - t) + v[i];
+        else c += (v[i] - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Evaluation and assembly (Eq. 1-2).                                         */
+/* ------------------------------------------------------------------------- */
+static int64_t find_block(const int32_t *rowptr, const int32_t *colidx, int32_t r, int32_t c) {
+    int32_t lo = rowptr[r], hi = rowptr[r + 1] - 1;
+    while (lo <= hi) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (colidx[mid] == c) return mid;
+        if (colidx[mid] < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int64_t *n_elem,
+                const int32_t *const *stencil, const double *const *rest, const double *const *params,
+                const double *x, int mode, double spd_eps, const char *row_mask, const int32_t *rowptr,
+                const int32_t *colidx, double *energy, double *esum_abs, double *grad, double *gscale,
+                double *hess, double *hscale) {
+    const int d = var_dim;
+    int64_t nnzb = rowptr ? rowptr[nv] : 0;
+    if (grad) {
+        memset(grad, 0, sizeof(double) * (size_t)(nv * d));
+        if (gscale) memset(gscale, 0, sizeof(double) * (size_t)(nv * d));
+    }
+    if (hess) {
+        memset(hess, 0, sizeof(double) * (size_t)(nnzb * d * d));
+        if (hscale) memset(hscale, 0, sizeof(double) * (size_t)(nnzb * d * d));
+    }
+    int64_t total = 0;
+    for (int t = 0; t < n_terms; ++t) total += n_elem[t];
+    double *fvals = malloc(sizeof(double) * (size_t)(total > 0 ? total : 1));
+    if (!fvals) return -4;
+    int64_t fi = 0;
+    double abs_sum = 0.0;
+    for (int t = 0; t < n_terms; ++t) {
+        int ss = kind_stencil(kind[t]);
+        if (ss < 0 || kind_vardim(kind[t]) != d) { free(fvals); return -1; }
+        int k = ss * d;
+        int rest_stride = (kind[t] == OR_BENDING) ? 2 : ((kind[t] == OR_DIRICHLET || kind[t] == OR_STVK || kind[t] == OR_SYMDIR) ? 5 : 0);
+        for (int64_t e = 0; e < n_elem[t]; ++e) {
+            const int32_t *s = stencil[t] + ss * e;
+            double xloc[KMAX];
+            int touches = (row_mask == NULL);
+            for (int a = 0; a < ss; ++a) {
+                for (int c = 0; c < d; ++c) xloc[a * d + c] = x[(int64_t)s[a] * d + c];
+                if (row_mask && row_mask[s[a]]) touches = 1;
+            }
+            const double *rs = rest_stride ? rest[t] + rest_stride * e : NULL;
+            int want_deriv = touches && (mode & (OR_GRAD | OR_HESS));
+            hd r;
+            if (eval_elem(kind[t], want_deriv ? k : 0, params[t], rs, xloc, &r) != 0) { free(fvals); return -1; }
+            fvals[fi++] = r.v;
+            abs_sum += fabs(r.v);
+            if (!want_deriv) continue;
+            if ((mode & OR_GRAD) && grad) {
+                double gmax = 0.0;
+                for (int i = 0; i < k; ++i) gmax = fabs(r.g[i]) > gmax ? fabs(r.g[i]) : gmax;
+                for (int a = 0; a < ss; ++a) {
+                    if (row_mask && !row_mask[s[a]]) continue;
+                    for (int c = 0; c < d; ++c) {
+                        grad[(int64_t)s[a] * d + c] += r.g[a * d + c];
+                        if (gscale) gscale[(int64_t)s[a] * d + c] += gmax;
+                    }
+                }
+            }
+            if ((mode & OR_HESS) && hess) {
+                double Hl[KMAX * KMAX], Hp[KMAX * KMAX];
+                for (int i = 0; i < k; ++i)
+                    for (int j = 0; j < k; ++j) Hl[i * k + j] = r.h[i][j];
+                if (mode & OR_SPD) oracle_spd_project(k, Hl, spd_eps, Hp);
+                else memcpy(Hp, Hl, sizeof(double) * k * k);
+                double hmax = 0.0;
+                for (int i = 0; i < k * k; ++i) hmax = fabs(Hp[i]) > hmax ? fabs(Hp[i]) : hmax;
+                for (int a = 0; a < ss; ++a) {
+                    if (row_mask && !row_mask[s[a]]) continue;
+                    for (int b = 0; b < ss; ++b) {
+                        int64_t blk = find_block(rowptr, colidx, s[a], s[b]);
+                        if (blk < 0) { free(fvals); return -5; }
+                        for (int i = 0; i < d; ++i)
+                            for (int j = 0; j < d; ++j) {
+                                hess[blk * d * d + i * d + j] += Hp[(a * d + i) * k + (b * d + j)];
+                                if (hscale) hscale[blk * d * d + i * d + j] += hmax;
+                            }
+                    }
+                }
+            }
+        }
+    }
+    if (energy) *energy = oracle_neumaier_sum(fi, fvals);
+    if (esum_abs) *esum_abs = abs_sum;
+    free(fvals);
+    return 0;
+}
