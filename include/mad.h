@@ -1,0 +1,189 @@
+/*
+ * mad.h -- C ABI of the locality-aware mesh AD library for MI355X (gfx950).
+ *
+ * The library evaluates objectives of the partially separable form of
+ * Sec. 4.1, Eq. 1, F(x) = sum_j f_j(S_j x), over the elements of a triangle
+ * mesh, differentiates every local term by second-order forward-mode AD over
+ * the element's stencil (Sec. 5.1, Sec. 6.2), and assembles the global
+ * gradient and the sparse block-CSR Hessian of Eq. 2 on the GPU, with the
+ * block pattern built once from connectivity (Sec. 6.1). Each term's local
+ * Hessian can be filtered by clamping its eigenvalues from below before
+ * assembly (Sec. 7.1).
+ *
+ * The paper's user lambdas cannot cross a C ABI; terms come from a fixed
+ * catalogue (mad_term_kind) with a per-term parameter block.
+ *
+ * Conventions
+ *  - Every call returns a mad_status; 0 is success. On failure
+ *    mad_last_error() (thread-local) describes the cause. Argument and mesh
+ *    validation is synchronous and happens before any device work.
+ *  - Pointers named *_host are host memory; *_dev are device memory of the
+ *    current HIP device; stream is a hipStream_t (NULL = default stream).
+ *  - The caller owns every *_dev buffer it passes (DOFs and outputs). The
+ *    library owns the mesh topology, patches, pattern and its scratch.
+ *  - DOFs are vertex-major and interleaved: x[v * var_dim + c].
+ *  - Hessian values are stored per block, row-major inside each
+ *    var_dim x var_dim block, blocks in CSR order: hess[b * d * d + i * d + j].
+ *    Block rows/columns use the caller's vertex numbering, columns sorted
+ *    ascending, every diagonal block present.
+ *  - A problem must not be used from two host threads at once.
+ */
+#ifndef MAD_H
+#define MAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mad_mesh mad_mesh;
+typedef struct mad_problem mad_problem;
+
+typedef enum mad_status {
+    MAD_OK = 0,
+    MAD_E_INVALID_ARG = -1,     /* null pointer, bad size, bad enum value */
+    MAD_E_BAD_MESH = -2,        /* vertex index out of range, repeated vertex in a face */
+    MAD_E_DEGENERATE_REST = -3, /* a rest triangle of a term has zero area */
+    MAD_E_OVERFLOW = -4,        /* block count or stencil incidence exceeds int32 */
+    MAD_E_OOM = -5,             /* device or host allocation failed */
+    MAD_E_HIP = -6,             /* a HIP runtime call or kernel launch failed */
+    MAD_E_STATE = -7,           /* call out of order (e.g. eval before finalize) */
+    MAD_E_UNSUPPORTED = -8      /* kind/var_dim/precision combination not provided */
+} mad_status;
+
+/* Term catalogue. Stencil, VarDim and the params block of each kind:
+ *  MAD_EDGE_SQLEN  edge (2 vertices), VarDim 3: |x0 - x1|^2 (Listing 1). params unused.
+ *  MAD_TRI_AREA    face (3 vertices), VarDim 3: triangle area (Sec. 7.6). params unused.
+ *  MAD_DIRICHLET   face, VarDim 1: 0.5 * A * |grad u|^2 of a piecewise-linear scalar u over the
+ *                  rest triangle (A = rest area). params unused. Needs rest positions.
+ *  MAD_STVK        face, VarDim 3: A * (mu tr(E^2) + lambda/2 tr(E)^2), E = (F^T F - I)/2,
+ *                  F = Ds Dm^{-1}. params = {mu, lambda}. Needs rest positions.
+ *  MAD_BENDING     interior-edge diamond (4 vertices), VarDim 3 (Sec. 7.7):
+ *                  k_b (A/3) (theta - theta_rest)^2 h^2, A = mean rest area of the two faces.
+ *                  params = {k_b, h}. Needs rest positions. Boundary edges (one face) and
+ *                  non-manifold edges (three or more faces) carry no bending term.
+ *  MAD_SYMDIR      face, VarDim 2 (Sec. 7.2): A (|J|_F^2 + |J^{-1}|_F^2). params unused.
+ *                  Needs rest positions.
+ */
+typedef enum mad_term_kind {
+    MAD_EDGE_SQLEN = 1,
+    MAD_TRI_AREA = 2,
+    MAD_DIRICHLET = 3,
+    MAD_STVK = 4,
+    MAD_BENDING = 5,
+    MAD_SYMDIR = 6
+} mad_term_kind;
+
+/* evaluation mode bits (Sec. 6.2: passive, gradient-only, full Hessian; Sec. 7.1 filtering) */
+typedef enum mad_mode {
+    MAD_ENERGY = 1,  /* write the FP64 energy (always computed) */
+    MAD_GRAD = 2,    /* assemble the gradient */
+    MAD_HESS = 4,    /* assemble the block-CSR Hessian */
+    MAD_SPD = 8      /* clamp each term's local Hessian eigenvalues to >= spd_eps before assembly */
+} mad_mode;
+
+typedef enum mad_precision {
+    MAD_F64 = 0,  /* derivative arithmetic and outputs in FP64 */
+    MAD_F32 = 1   /* derivative arithmetic and outputs in FP32; primal values, energy in FP64 */
+} mad_precision;
+
+typedef enum mad_scatter {
+    MAD_SCATTER_AUTO = 0,    /* library default */
+    MAD_SCATTER_ATOMIC = 1   /* device-wide atomic adds into pre-zeroed outputs (Sec. 5.5) */
+} mad_scatter;
+
+typedef struct mad_options {
+    int32_t scatter;         /* mad_scatter; 0 = default */
+    int32_t patch_faces;     /* target faces per patch (Sec. 7.1 patch study); 0 = 512 */
+    double spd_eps;          /* eigenvalue floor of MAD_SPD; default 0 (PSD) */
+    double degenerate_q;     /* MAD_F32: elements whose triangle quality 4 sqrt(3) A / sum(l^2)
+                                falls below this are evaluated and projected in FP64; 0 = 1e-2 */
+    int32_t reserved[8];     /* must be zero */
+} mad_options;
+
+/* library version (major * 10000 + minor * 100 + patch) */
+int32_t mad_version(void);
+
+/* description of the last failure on this thread ("" if none) */
+const char *mad_last_error(void);
+
+/* Fill *opt with the defaults. */
+int32_t mad_options_default(mad_options *opt);
+
+/* Ingest a triangle mesh (Sec. 6: triangle surface mesh, possibly non-manifold, possibly with
+ * disconnected components). tris_host: [n_tris][3] vertex indices, copied. comp_vert_offsets:
+ * NULL, or [n_comp + 1] ascending vertex offsets partitioning the vertices into disjoint
+ * components (batched meshes); energies are then also reported per component. Builds the edge
+ * list and the interior-edge diamonds: (v0, v1) the edge as directed in the lower-indexed face,
+ * v2 that face's opposite vertex, v3 the other face's opposite vertex. */
+int32_t mad_mesh_create(int64_t n_verts, int64_t n_tris, const int32_t *tris_host, int32_t n_comp,
+                        const int64_t *comp_vert_offsets, mad_mesh **out);
+
+/* Sizes of an ingested mesh (any output pointer may be NULL). */
+int32_t mad_mesh_info(const mad_mesh *mesh, int64_t *n_verts, int64_t *n_tris, int64_t *n_edges,
+                      int64_t *n_diamonds);
+
+/* Copy the diamonds ([n_diamonds][4]) to host memory. */
+int32_t mad_mesh_copy_diamonds(const mad_mesh *mesh, int32_t *diamonds_host);
+
+int32_t mad_mesh_destroy(mad_mesh *mesh);
+
+/* Create a problem over a mesh: var_dim DOFs per vertex (1, 2 or 3), precision mad_precision.
+ * opt may be NULL (defaults). The mesh must outlive the problem. */
+int32_t mad_problem_create(const mad_mesh *mesh, int32_t var_dim, int32_t precision,
+                           const mad_options *opt, mad_problem **out);
+
+/* Add a local term (Sec. 4.2, add_term). params_host: n_params doubles (see mad_term_kind).
+ * rest_pos_host: [n_verts][3] rest positions for kinds that need them (copied; rest-frame data
+ * is computed here). Returns MAD_E_DEGENERATE_REST if a rest triangle has zero area. */
+int32_t mad_problem_add_term(mad_problem *prob, int32_t kind, const double *params_host, int32_t n_params,
+                             const double *rest_pos_host);
+
+/* Build patches, upload element data and build the block pattern on the GPU (Sec. 6.1), once.
+ * Synchronises the stream before returning. */
+int32_t mad_problem_finalize(mad_problem *prob, void *stream);
+
+/* Pattern sizes: block rows (= n_verts), nnzb blocks, block_dim (= var_dim). */
+int32_t mad_problem_pattern_info(const mad_problem *prob, int64_t *n_block_rows, int64_t *nnzb,
+                                 int32_t *block_dim);
+
+/* Number of doubles written to energy_dev by mad_problem_eval: 1, or 1 + n_comp for a mesh
+ * created with components (entry 0 is the total, entry 1 + c component c). */
+int32_t mad_problem_energy_count(const mad_problem *prob, int32_t *count);
+
+/* Copy the pattern: rowptr_dev [n_block_rows + 1], colidx_dev [nnzb] (device int32). */
+int32_t mad_problem_copy_pattern(const mad_problem *prob, int32_t *rowptr_dev, int32_t *colidx_dev,
+                                 void *stream);
+
+/* Evaluate every term at x_dev ([n_verts * var_dim] FP64) and assemble (Eq. 1-2).
+ * mode: OR of mad_mode bits. energy_dev: [energy_count] FP64 (may be NULL without MAD_ENERGY).
+ * grad_dev: [n_verts * var_dim], hess_dev: [nnzb * var_dim^2], both FP64 for MAD_F64 and FP32
+ * for MAD_F32 (may be NULL when not requested). Outputs are overwritten, not accumulated.
+ * Asynchronous on stream: no host synchronisation. The energy is a deterministic FP64 sum. */
+int32_t mad_problem_eval(mad_problem *prob, const double *x_dev, uint32_t mode, double *energy_dev,
+                         void *grad_dev, void *hess_dev, void *stream);
+
+/* Synchronise the stream and report whether any evaluation since the last call produced a
+ * non-finite element energy or derivative (*nonfinite = 1) and how many elements took the FP64
+ * fallback (*fp64_fallbacks); both counters are reset. */
+int32_t mad_problem_status(mad_problem *prob, int32_t *nonfinite, int64_t *fp64_fallbacks, void *stream);
+
+/* Per-stage timing (profiling aid). enable = 1 starts recording HIP events on the eval stream
+ * around each stage of every mad_problem_eval (zero fill, one kernel per term, energy reduction)
+ * and clears earlier records; enable = 0 stops recording. Recording adds no synchronisation. */
+int32_t mad_problem_set_profiling(mad_problem *prob, int32_t enable);
+
+/* Synchronise with the recorded events and report, summed over the evaluations recorded since
+ * profiling was enabled: ms_out[0] zero fill, ms_out[1 + t] the kernel of term t (in add order),
+ * ms_out[1 + n_terms] the energy reduction. *n_stages = n_terms + 2, *n_evals = evaluations.
+ * ms_out must hold at least 10 doubles. Records are kept (call set_profiling(1) to clear). */
+int32_t mad_problem_profile(mad_problem *prob, double *ms_out, int32_t *n_stages, int64_t *n_evals);
+
+int32_t mad_problem_destroy(mad_problem *prob);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAD_H */

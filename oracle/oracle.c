@@ -588,6 +588,7 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
                 for (int c = 0; c < d; ++c) xloc[a * d + c] = x[(int64_t)s[a] * d + c];
                 if (row_mask && row_mask[s[a]]) touches = 1;
             }
+            if (!touches && !(mode & OR_ENERGY)) continue; /* contributes to no requested output */
             const double *rs = rest_stride ? rest[t] + rest_stride * e : NULL;
             int want_deriv = touches && (mode & (OR_GRAD | OR_HESS));
             hd r;

@@ -75,7 +75,8 @@ int oracle_element(int kind, const double *params, const double *rest, const dou
  * ([n_elem][ss]), rest[t] (per-element rest data), params[t].
  * row_mask (nullable, char[nv]): if given, derivatives are assembled only into
  * masked block rows / gradient entries (elements touching no masked vertex
- * are evaluated passively, for the energy only).
+ * are evaluated passively for the energy, or skipped when mode has no
+ * OR_ENERGY bit).
  * Outputs (nullable when not requested): energy[1], esum_abs[1] (sum |f_j|),
  * grad[nv*var_dim], gscale[nv*var_dim], hess[nnzb*var_dim^2], hscale[same].
  * gscale / hscale accumulate, for each entry, the max-abs entry of every

@@ -1,0 +1,418 @@
+// C ABI entry points (include/mad.h). Validation is synchronous and precedes
+// any device work; evaluation is asynchronous on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+
+#include "mad_internal.hpp"
+
+namespace mad {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+}  // namespace mad
+
+using namespace mad;
+
+extern "C" {
+
+int32_t mad_version(void) { return 100; }
+
+const char* mad_last_error(void) { return g_last_error.c_str(); }
+
+int32_t mad_options_default(mad_options* opt) {
+    if (!opt) return fail(MAD_E_INVALID_ARG, "opt is NULL");
+    std::memset(opt, 0, sizeof(*opt));
+    opt->scatter = MAD_SCATTER_ATOMIC;
+    opt->patch_faces = 512;
+    opt->spd_eps = 0.0;
+    opt->degenerate_q = 1e-2;
+    return MAD_OK;
+}
+
+int32_t mad_mesh_create(int64_t n_verts, int64_t n_tris, const int32_t* tris_host, int32_t n_comp,
+                        const int64_t* comp_vert_offsets, mad_mesh** out) {
+    if (!out) return fail(MAD_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_verts <= 0 || n_tris < 0) return fail(MAD_E_INVALID_ARG, "n_verts must be > 0 and n_tris >= 0");
+    if (n_tris > 0 && !tris_host) return fail(MAD_E_INVALID_ARG, "tris_host is NULL");
+    if (n_verts >= INT32_MAX || n_tris >= INT32_MAX / 3) return fail(MAD_E_OVERFLOW, "mesh too large for int32 indices");
+    if (n_comp < 0 || (n_comp > 0 && !comp_vert_offsets)) return fail(MAD_E_INVALID_ARG, "bad component offsets");
+    if (n_comp > 0) {
+        if (comp_vert_offsets[0] != 0 || comp_vert_offsets[n_comp] != n_verts)
+            return fail(MAD_E_INVALID_ARG, "component offsets must start at 0 and end at n_verts");
+        for (int32_t c = 0; c < n_comp; ++c)
+            if (comp_vert_offsets[c + 1] <= comp_vert_offsets[c])
+                return fail(MAD_E_INVALID_ARG, "component offsets must be strictly increasing");
+    }
+    mad_mesh* m = new (std::nothrow) mad_mesh();
+    if (!m) return fail(MAD_E_OOM, "mesh");
+    m->nv = n_verts;
+    m->nt = n_tris;
+    m->tris.assign(tris_host, tris_host + 3 * n_tris);
+    for (int64_t f = 0; f < n_tris; ++f) {
+        const int32_t* t = &m->tris[3 * f];
+        for (int c = 0; c < 3; ++c)
+            if (t[c] < 0 || t[c] >= n_verts) {
+                delete m;
+                return fail(MAD_E_BAD_MESH, "face " + std::to_string(f) + " has a vertex index out of range");
+            }
+        if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2]) {
+            delete m;
+            return fail(MAD_E_BAD_MESH, "face " + std::to_string(f) + " repeats a vertex");
+        }
+    }
+    if (n_comp > 0) {
+        m->comp_off.assign(comp_vert_offsets, comp_vert_offsets + n_comp + 1);
+        m->batched = true;
+        // a face must not straddle components
+        for (int64_t f = 0; f < n_tris; ++f) {
+            const int32_t* t = &m->tris[3 * f];
+            auto comp = [&](int32_t v) {
+                return std::upper_bound(m->comp_off.begin(), m->comp_off.end(), (int64_t)v) - m->comp_off.begin();
+            };
+            if (comp(t[0]) != comp(t[1]) || comp(t[0]) != comp(t[2])) {
+                delete m;
+                return fail(MAD_E_BAD_MESH, "face " + std::to_string(f) + " spans two components");
+            }
+        }
+    } else {
+        m->comp_off = {0, n_verts};
+    }
+    int rc = build_topology(*m);
+    if (rc != MAD_OK) {
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return MAD_OK;
+}
+
+int32_t mad_mesh_info(const mad_mesh* m, int64_t* nv, int64_t* nt, int64_t* ne, int64_t* nd) {
+    if (!m) return fail(MAD_E_INVALID_ARG, "mesh is NULL");
+    if (nv) *nv = m->nv;
+    if (nt) *nt = m->nt;
+    if (ne) *ne = m->ne();
+    if (nd) *nd = m->nd();
+    return MAD_OK;
+}
+
+int32_t mad_mesh_copy_diamonds(const mad_mesh* m, int32_t* out) {
+    if (!m || (!out && m->nd() > 0)) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    std::copy(m->diamonds.begin(), m->diamonds.end(), out);
+    return MAD_OK;
+}
+
+int32_t mad_mesh_destroy(mad_mesh* m) {
+    delete m;
+    return MAD_OK;
+}
+
+int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precision, const mad_options* opt,
+                           mad_problem** out) {
+    if (!out) return fail(MAD_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!mesh) return fail(MAD_E_INVALID_ARG, "mesh is NULL");
+    if (var_dim < 1 || var_dim > 3) return fail(MAD_E_INVALID_ARG, "var_dim must be 1, 2 or 3");
+    if (precision != MAD_F64 && precision != MAD_F32) return fail(MAD_E_INVALID_ARG, "bad precision");
+    mad_options o;
+    mad_options_default(&o);
+    if (opt) {
+        for (int i = 0; i < 8; ++i)
+            if (opt->reserved[i] != 0) return fail(MAD_E_INVALID_ARG, "reserved option fields must be zero");
+        if (opt->scatter != MAD_SCATTER_AUTO && opt->scatter != MAD_SCATTER_ATOMIC)
+            return fail(MAD_E_INVALID_ARG, "bad scatter mode");
+        if (opt->patch_faces < 0 || opt->patch_faces > (1 << 20)) return fail(MAD_E_INVALID_ARG, "bad patch_faces");
+        if (!(opt->spd_eps >= 0.0) || !std::isfinite(opt->spd_eps)) return fail(MAD_E_INVALID_ARG, "spd_eps must be >= 0");
+        if (!(opt->degenerate_q >= 0.0) || opt->degenerate_q > 1.0) return fail(MAD_E_INVALID_ARG, "degenerate_q in [0, 1]");
+        if (opt->patch_faces > 0) o.patch_faces = opt->patch_faces;
+        o.spd_eps = opt->spd_eps;
+        if (opt->degenerate_q > 0.0) o.degenerate_q = opt->degenerate_q;
+    }
+    mad_problem* p = new (std::nothrow) mad_problem();
+    if (!p) return fail(MAD_E_OOM, "problem");
+    p->mesh = mesh;
+    p->d = var_dim;
+    p->prec = precision;
+    p->opt = o;
+    *out = p;
+    return MAD_OK;
+}
+
+int32_t mad_problem_add_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params,
+                             const double* rest_pos) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (p->finalized) return fail(MAD_E_STATE, "add_term after finalize");
+    const int ns = kind_stencil(kind);
+    if (ns < 0) return fail(MAD_E_INVALID_ARG, "unknown term kind");
+    if (kind_vardim(kind) != p->d) return fail(MAD_E_UNSUPPORTED, "term kind does not match the problem's var_dim");
+    if (n_params < 0 || n_params > 4 || (n_params > 0 && !params)) return fail(MAD_E_INVALID_ARG, "bad params");
+    if (p->terms.size() >= 8) return fail(MAD_E_UNSUPPORTED, "at most 8 terms");
+    const int nrest = kind_nrest(kind);
+    if (nrest > 0 && !rest_pos) return fail(MAD_E_INVALID_ARG, "this term kind needs rest positions");
+    const mad_mesh& m = *p->mesh;
+    Term t;
+    t.kind = kind;
+    t.ns = ns;
+    t.d = p->d;
+    t.nrest = nrest;
+    for (int i = 0; i < n_params; ++i) {
+        if (!std::isfinite(params[i])) return fail(MAD_E_INVALID_ARG, "non-finite parameter");
+        t.prm[i] = params[i];
+    }
+    int rc = MAD_OK;
+    switch (kind) {
+    case MAD_EDGE_SQLEN:
+        t.n = m.ne();
+        t.stencil = m.edges;
+        break;
+    case MAD_TRI_AREA:
+        t.n = m.nt;
+        t.stencil = m.tris;
+        break;
+    case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR:
+        t.n = m.nt;
+        t.stencil = m.tris;
+        rc = rest_tri(m, rest_pos, t.rest);
+        break;
+    case MAD_BENDING:
+        t.n = m.nd();
+        t.stencil = m.diamonds;
+        rc = rest_diamond(m, rest_pos, t.rest);
+        break;
+    }
+    if (rc != MAD_OK) return rc;
+    p->terms.push_back(std::move(t));
+    return MAD_OK;
+}
+
+static int upload(mad_problem* p, void** dst, const void* src, size_t bytes, hipStream_t s) {
+    MAD_HIP_TRY(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+    p->owned.push_back(*dst);
+    if (bytes) MAD_HIP_TRY(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s));
+    return MAD_OK;
+}
+
+int32_t mad_problem_finalize(mad_problem* p, void* stream) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (p->finalized) return fail(MAD_E_STATE, "already finalized");
+    if (p->terms.empty()) return fail(MAD_E_STATE, "no terms");
+    hipStream_t s = (hipStream_t)stream;
+    const mad_mesh& m = *p->mesh;
+    MAD_HIP_TRY(hipGetDevice(&p->device));
+    build_patches(m, p->opt.patch_faces, p->patches);
+    const int32_t np = p->patches.n;
+    int rc;
+    for (auto& t : p->terms) {
+        // patch of each element: faces by their patch, diamonds by f1, edges by their first face
+        std::vector<int32_t> ep((size_t)t.n);
+        std::vector<int32_t> key((size_t)t.n);   // position inside the patch ordering
+        for (int64_t e = 0; e < t.n; ++e) {
+            int32_t f;
+            if (t.kind == MAD_BENDING) f = m.diamond_faces[2 * e];
+            else if (t.kind == MAD_EDGE_SQLEN) f = m.edge_face0[e];
+            else f = (int32_t)e;
+            ep[e] = p->patches.face_patch[f];
+            key[e] = f;
+        }
+        t.perm.resize((size_t)t.n);
+        std::iota(t.perm.begin(), t.perm.end(), 0);
+        std::stable_sort(t.perm.begin(), t.perm.end(), [&](int32_t a, int32_t b) {
+            if (ep[a] != ep[b]) return ep[a] < ep[b];
+            return key[a] < key[b];
+        });
+        t.elem_ptr.assign((size_t)np + 1, 0);
+        for (int64_t e = 0; e < t.n; ++e) t.elem_ptr[ep[e] + 1]++;
+        for (int32_t q = 0; q < np; ++q) t.elem_ptr[q + 1] += t.elem_ptr[q];
+        std::vector<int32_t> st((size_t)t.n * t.ns);
+        std::vector<double> rs((size_t)t.n * t.nrest);
+        for (int64_t i = 0; i < t.n; ++i) {
+            const int32_t e = t.perm[i];
+            for (int a = 0; a < t.ns; ++a) st[i * t.ns + a] = t.stencil[(int64_t)e * t.ns + a];
+            for (int k = 0; k < t.nrest; ++k) rs[(int64_t)k * t.n + i] = t.rest[(int64_t)e * t.nrest + k];
+        }
+        if ((rc = upload(p, (void**)&t.d_stencil, st.data(), st.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&t.d_rest, rs.data(), rs.size() * 8, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&t.d_elem_ptr, t.elem_ptr.data(), t.elem_ptr.size() * 4, s)) != MAD_OK) return rc;
+    }
+    if ((rc = upload(p, (void**)&p->d_comp_patch_ptr, p->patches.comp_patch_ptr.data(),
+                     p->patches.comp_patch_ptr.size() * 4, s)) != MAD_OK)
+        return rc;
+    MAD_HIP_TRY(hipMalloc((void**)&p->d_partial, sizeof(double) * std::max<size_t>(1, (size_t)np * p->terms.size())));
+    p->owned.push_back(p->d_partial);
+    MAD_HIP_TRY(hipMalloc((void**)&p->d_flags, sizeof(int32_t) * 4));
+    p->owned.push_back(p->d_flags);
+    MAD_HIP_TRY(hipMalloc((void**)&p->d_fallbacks, sizeof(unsigned long long)));
+    p->owned.push_back(p->d_fallbacks);
+    MAD_HIP_TRY(launch_fill(p->d_flags, 4, 4, s));
+    MAD_HIP_TRY(launch_fill(p->d_fallbacks, 1, 8, s));
+    std::vector<PatternTerm> pts;
+    for (auto& t : p->terms) pts.push_back({t.d_stencil, t.n, t.ns});
+    if ((rc = build_pattern_device(m.nv, pts, &p->d_rowptr, &p->d_colidx, &p->nnzb, p->owned, s)) != MAD_OK) return rc;
+    for (auto& t : p->terms) {
+        MAD_HIP_TRY(hipMalloc((void**)&t.d_slots, sizeof(int32_t) * std::max<int64_t>(1, t.n * t.ns * t.ns)));
+        p->owned.push_back(t.d_slots);
+        MAD_HIP_TRY(launch_slots(t.d_stencil, t.n, t.ns, p->d_rowptr, p->d_colidx, t.d_slots, p->d_flags, s));
+    }
+    int32_t hflags[4];
+    MAD_HIP_TRY(hipMemcpyAsync(hflags, p->d_flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    if (hflags[1] != 0) return fail(MAD_E_HIP, "internal error: element block missing from the pattern");
+    // host copies of element data are no longer needed
+    for (auto& t : p->terms) {
+        std::vector<int32_t>().swap(t.stencil);
+        std::vector<double>().swap(t.rest);
+    }
+    p->finalized = true;
+    return MAD_OK;
+}
+
+int32_t mad_problem_pattern_info(const mad_problem* p, int64_t* rows, int64_t* nnzb, int32_t* bd) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
+    if (rows) *rows = p->mesh->nv;
+    if (nnzb) *nnzb = p->nnzb;
+    if (bd) *bd = p->d;
+    return MAD_OK;
+}
+
+int32_t mad_problem_energy_count(const mad_problem* p, int32_t* count) {
+    if (!p || !count) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    *count = p->mesh->batched ? 1 + (int32_t)(p->mesh->comp_off.size() - 1) : 1;
+    return MAD_OK;
+}
+
+int32_t mad_problem_copy_pattern(const mad_problem* p, int32_t* rowptr, int32_t* colidx, void* stream) {
+    if (!p || !rowptr || !colidx) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
+    hipStream_t s = (hipStream_t)stream;
+    MAD_HIP_TRY(hipMemcpyAsync(rowptr, p->d_rowptr, sizeof(int32_t) * (p->mesh->nv + 1), hipMemcpyDeviceToDevice, s));
+    MAD_HIP_TRY(hipMemcpyAsync(colidx, p->d_colidx, sizeof(int32_t) * p->nnzb, hipMemcpyDeviceToDevice, s));
+    return MAD_OK;
+}
+
+int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
+                         void* stream) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (!p->finalized) return fail(MAD_E_STATE, "eval before finalize");
+    if (!x) return fail(MAD_E_INVALID_ARG, "x is NULL");
+    if (mode & ~15u) return fail(MAD_E_INVALID_ARG, "unknown mode bits");
+    if ((mode & MAD_ENERGY) && !energy) return fail(MAD_E_INVALID_ARG, "energy output is NULL");
+    if ((mode & MAD_GRAD) && !grad) return fail(MAD_E_INVALID_ARG, "gradient output is NULL");
+    if ((mode & MAD_HESS) && !hess) return fail(MAD_E_INVALID_ARG, "Hessian output is NULL");
+    if ((mode & MAD_SPD) && !(mode & MAD_HESS)) return fail(MAD_E_INVALID_ARG, "MAD_SPD needs MAD_HESS");
+    hipStream_t s = (hipStream_t)stream;
+    const mad_mesh& m = *p->mesh;
+    const int d = p->d;
+    const int eb = p->prec == MAD_F32 ? 4 : 8;
+    std::vector<hipEvent_t>* ev = nullptr;
+    if (p->profiling) {
+        const size_t need = p->terms.size() + 3;
+        if ((size_t)p->prof_count >= p->prof_events.size()) {
+            std::vector<hipEvent_t> row(need, nullptr);
+            for (auto& e : row) MAD_HIP_TRY(hipEventCreate(&e));
+            p->prof_events.push_back(std::move(row));
+        }
+        ev = &p->prof_events[(size_t)p->prof_count++];
+        MAD_HIP_TRY(hipEventRecord((*ev)[0], s));
+    }
+    if (mode & MAD_GRAD) MAD_HIP_TRY(launch_fill(grad, m.nv * d, eb, s));
+    if (mode & MAD_HESS) MAD_HIP_TRY(launch_fill(hess, p->nnzb * d * d, eb, s));
+    if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[1], s));
+    const int kmode = (mode & MAD_HESS) ? ((mode & MAD_SPD) ? 3 : 2) : ((mode & MAD_GRAD) ? 1 : 0);
+    const int np = p->patches.n;
+    for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+        const Term& t = p->terms[ti];
+        EvalLaunch L{};
+        L.kind = t.kind;
+        L.prec = p->prec;
+        L.mode = kmode;
+        L.want_grad = (mode & MAD_GRAD) ? 1 : 0;
+        L.n_patch = np;
+        L.x = x;
+        L.stencil = t.d_stencil;
+        L.rest = t.d_rest;
+        L.n = t.n;
+        L.elem_ptr = t.d_elem_ptr;
+        L.slots = t.d_slots;
+        L.grad = grad;
+        L.hess = hess;
+        L.partial = p->d_partial + ti * (size_t)np;
+        L.flags = p->d_flags;
+        L.fallbacks = p->d_fallbacks;
+        std::memcpy(L.prm, t.prm, sizeof(L.prm));
+        L.eps = p->opt.spd_eps;
+        L.qmin = p->opt.degenerate_q;
+        MAD_HIP_TRY(launch_eval(L, s));
+        if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2 + ti], s));
+    }
+    if (mode & MAD_ENERGY) {
+        const int ncomp = (int)m.comp_off.size() - 1;
+        MAD_HIP_TRY(launch_energy_reduce(p->d_partial, (int)p->terms.size(), np, p->d_comp_patch_ptr,
+                                         std::max(ncomp, 1), m.batched, energy, s));
+    }
+    if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2 + p->terms.size()], s));
+    return MAD_OK;
+}
+
+int32_t mad_problem_set_profiling(mad_problem* p, int32_t enable) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    p->profiling = enable != 0;
+    if (p->profiling) p->prof_count = 0;
+    return MAD_OK;
+}
+
+int32_t mad_problem_profile(mad_problem* p, double* ms, int32_t* n_stages, int64_t* n_evals) {
+    if (!p || !ms) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    const int ns = (int)p->terms.size() + 2;
+    for (int i = 0; i < 10; ++i) ms[i] = 0.0;
+    for (int64_t k = 0; k < p->prof_count; ++k) {
+        auto& row = p->prof_events[(size_t)k];
+        MAD_HIP_TRY(hipEventSynchronize(row[ns]));
+        for (int st = 0; st < ns; ++st) {
+            float t = 0.f;
+            MAD_HIP_TRY(hipEventElapsedTime(&t, row[st], row[st + 1]));
+            ms[st] += t;
+        }
+    }
+    if (n_stages) *n_stages = ns;
+    if (n_evals) *n_evals = p->prof_count;
+    return MAD_OK;
+}
+
+int32_t mad_problem_status(mad_problem* p, int32_t* nonfinite, int64_t* fallbacks, void* stream) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t hf[4];
+    unsigned long long hb = 0;
+    MAD_HIP_TRY(hipMemcpyAsync(hf, p->d_flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    MAD_HIP_TRY(hipMemcpyAsync(&hb, p->d_fallbacks, sizeof(hb), hipMemcpyDeviceToHost, s));
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    MAD_HIP_TRY(launch_fill(p->d_flags, 4, 4, s));
+    MAD_HIP_TRY(launch_fill(p->d_fallbacks, 1, 8, s));
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    if (nonfinite) *nonfinite = hf[0] != 0;
+    if (fallbacks) *fallbacks = (int64_t)hb;
+    return MAD_OK;
+}
+
+int32_t mad_problem_destroy(mad_problem* p) {
+    if (!p) return MAD_OK;
+    for (auto& row : p->prof_events)
+        for (hipEvent_t e : row) (void)hipEventDestroy(e);
+    for (void* q : p->owned) (void)hipFree(q);
+    delete p;
+    return MAD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// Host-side setup, run once per mesh / problem (timings of the paper exclude
+// it, Sec. 7): edge topology and edge diamonds, rest-frame data of each
+// term, and the locality-ordered patches that element arrays are laid out by.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <numeric>
+
+#include "mad_internal.hpp"
+
+namespace mad {
+
+int kind_stencil(int kind) {
+    switch (kind) {
+    case MAD_EDGE_SQLEN: return 2;
+    case MAD_TRI_AREA: case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: return 3;
+    case MAD_BENDING: return 4;
+    default: return -1;
+    }
+}
+int kind_vardim(int kind) {
+    switch (kind) {
+    case MAD_DIRICHLET: return 1;
+    case MAD_SYMDIR: return 2;
+    case MAD_EDGE_SQLEN: case MAD_TRI_AREA: case MAD_STVK: case MAD_BENDING: return 3;
+    default: return -1;
+    }
+}
+int kind_nrest(int kind) {
+    switch (kind) {
+    case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: return 5;
+    case MAD_BENDING: return 2;
+    default: return 0;
+    }
+}
+
+// Edges sorted by (min, max) vertex; per edge the incident faces in ascending order.
+// An edge with exactly two incident faces yields a diamond (v0, v1, v2, v3): (v0, v1) as the
+// edge is directed in the lower-indexed face f1, v2 opposite in f1, v3 opposite in f2.
+int build_topology(mad_mesh& m) {
+    struct Rec {
+        int32_t lo, hi, face, from, to, opp;
+    };
+    const int64_t nr = 3 * m.nt;
+    std::vector<Rec> rec((size_t)nr);
+    for (int64_t f = 0; f < m.nt; ++f) {
+        const int32_t* t = &m.tris[3 * f];
+        for (int c = 0; c < 3; ++c) {
+            Rec& r = rec[3 * f + c];
+            r.from = t[c];
+            r.to = t[(c + 1) % 3];
+            r.opp = t[(c + 2) % 3];
+            r.lo = std::min(r.from, r.to);
+            r.hi = std::max(r.from, r.to);
+            r.face = (int32_t)f;
+        }
+    }
+    std::sort(rec.begin(), rec.end(), [](const Rec& a, const Rec& b) {
+        if (a.lo != b.lo) return a.lo < b.lo;
+        if (a.hi != b.hi) return a.hi < b.hi;
+        return a.face < b.face;
+    });
+    m.edges.clear();
+    m.edge_nf.clear();
+    m.edge_face0.clear();
+    m.diamonds.clear();
+    m.diamond_faces.clear();
+    std::vector<int32_t> deg((size_t)m.nt, 0);
+    std::vector<std::pair<int32_t, int32_t>> links;
+    for (int64_t i = 0; i < nr;) {
+        int64_t j = i;
+        while (j < nr && rec[j].lo == rec[i].lo && rec[j].hi == rec[i].hi) ++j;
+        m.edges.push_back(rec[i].lo);
+        m.edges.push_back(rec[i].hi);
+        m.edge_nf.push_back((int32_t)(j - i));
+        m.edge_face0.push_back(rec[i].face);
+        if (j - i == 2) {
+            m.diamonds.insert(m.diamonds.end(), {rec[i].from, rec[i].to, rec[i].opp, rec[i + 1].opp});
+            m.diamond_faces.insert(m.diamond_faces.end(), {rec[i].face, rec[i + 1].face});
+        }
+        for (int64_t a = i; a < j; ++a)
+            for (int64_t b = a + 1; b < j; ++b)
+                if (rec[a].face != rec[b].face) links.push_back({rec[a].face, rec[b].face});
+        i = j;
+    }
+    // face adjacency CSR
+    for (auto& l : links) {
+        ++deg[l.first];
+        ++deg[l.second];
+    }
+    m.fadj_ptr.assign((size_t)m.nt + 1, 0);
+    for (int64_t f = 0; f < m.nt; ++f) m.fadj_ptr[f + 1] = m.fadj_ptr[f] + deg[f];
+    m.fadj.assign((size_t)m.fadj_ptr[m.nt], 0);
+    std::vector<int32_t> cur(m.fadj_ptr.begin(), m.fadj_ptr.end() - 1);
+    for (auto& l : links) {
+        m.fadj[cur[l.first]++] = l.second;
+        m.fadj[cur[l.second]++] = l.first;
+    }
+    for (int64_t f = 0; f < m.nt; ++f) std::sort(m.fadj.begin() + m.fadj_ptr[f], m.fadj.begin() + m.fadj_ptr[f + 1]);
+    return MAD_OK;
+}
+
+// Rest triangle in its own 2D frame: Dm = [[|e1|, e1.e2/|e1|], [0, |e1 x e2|/|e1|]].
+static bool rest_frame(const double* X0, const double* X1, const double* X2, double* mi, double* area) {
+    const double e1[3] = {X1[0] - X0[0], X1[1] - X0[1], X1[2] - X0[2]};
+    const double e2[3] = {X2[0] - X0[0], X2[1] - X0[1], X2[2] - X0[2]};
+    const double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    const double cn = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    if (!(l1 > 0.0) || !(cn > 0.0) || !std::isfinite(cn)) return false;
+    const double a = l1, b = (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]) / l1, d = cn / l1;
+    // inverse of the upper-triangular [[a, b], [0, d]]
+    mi[0] = 1.0 / a;
+    mi[1] = -b / (a * d);
+    mi[2] = 0.0;
+    mi[3] = 1.0 / d;
+    *area = 0.5 * cn;
+    return true;
+}
+
+int rest_tri(const mad_mesh& m, const double* X, std::vector<double>& out) {
+    out.assign((size_t)m.nt * 5, 0.0);
+    for (int64_t f = 0; f < m.nt; ++f) {
+        const int32_t* t = &m.tris[3 * f];
+        if (!rest_frame(X + 3 * (int64_t)t[0], X + 3 * (int64_t)t[1], X + 3 * (int64_t)t[2], &out[5 * f], &out[5 * f + 4]))
+            return fail(MAD_E_DEGENERATE_REST, "rest triangle " + std::to_string(f) + " has zero area");
+    }
+    return MAD_OK;
+}
+
+// rest dihedral of a diamond: atan2(-|e| (n1 . b), n1 . n2) with e = X1 - X0, n1 = e x (X2 - X0),
+// n2 = (X3 - X0) x e, b = X3 - X0 (the same angle as atan2(((n1 x n2) . e)/|e|, n1 . n2))
+static double dihedral(const double* X0, const double* X1, const double* X2, const double* X3) {
+    double e[3], a[3], b[3];
+    for (int k = 0; k < 3; ++k) {
+        e[k] = X1[k] - X0[k];
+        a[k] = X2[k] - X0[k];
+        b[k] = X3[k] - X0[k];
+    }
+    const double n1[3] = {e[1] * a[2] - e[2] * a[1], e[2] * a[0] - e[0] * a[2], e[0] * a[1] - e[1] * a[0]};
+    const double n2[3] = {b[1] * e[2] - b[2] * e[1], b[2] * e[0] - b[0] * e[2], b[0] * e[1] - b[1] * e[0]};
+    const double c = n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2];
+    const double s = -std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]) * (n1[0] * b[0] + n1[1] * b[1] + n1[2] * b[2]);
+    return std::atan2(s, c);
+}
+
+int rest_diamond(const mad_mesh& m, const double* X, std::vector<double>& out) {
+    const int64_t nd = m.nd();
+    out.assign((size_t)nd * 2, 0.0);
+    for (int64_t e = 0; e < nd; ++e) {
+        double mi[4], a1, a2;
+        const int32_t* t1 = &m.tris[3 * (int64_t)m.diamond_faces[2 * e]];
+        const int32_t* t2 = &m.tris[3 * (int64_t)m.diamond_faces[2 * e + 1]];
+        if (!rest_frame(X + 3 * (int64_t)t1[0], X + 3 * (int64_t)t1[1], X + 3 * (int64_t)t1[2], mi, &a1) ||
+            !rest_frame(X + 3 * (int64_t)t2[0], X + 3 * (int64_t)t2[1], X + 3 * (int64_t)t2[2], mi, &a2))
+            return fail(MAD_E_DEGENERATE_REST, "rest face of diamond " + std::to_string(e) + " has zero area");
+        out[2 * e] = 0.5 * (a1 + a2);
+        const int32_t* d = &m.diamonds[4 * e];
+        out[2 * e + 1] = dihedral(X + 3 * (int64_t)d[0], X + 3 * (int64_t)d[1], X + 3 * (int64_t)d[2], X + 3 * (int64_t)d[3]);
+    }
+    return MAD_OK;
+}
+
+// Patches: faces grouped into connected pieces of about target_faces by breadth-first growth
+// over face adjacency. A new patch is seeded from the previous patch's unvisited frontier (so
+// consecutive patches are neighbours), otherwise from the lowest unassigned face. Growth never
+// crosses a component boundary, so every patch lies in one component; patches are numbered
+// component by component.
+void build_patches(const mad_mesh& m, int target, Patches& P) {
+    const int64_t nt = m.nt;
+    P.face_patch.assign((size_t)nt, -1);
+    const int64_t ncomp = (int64_t)m.comp_off.size() - 1;
+    // component of each face = component of its first vertex
+    std::vector<int32_t> fcomp((size_t)nt, 0);
+    if (ncomp > 1) {
+        for (int64_t f = 0; f < nt; ++f) {
+            const int64_t v = m.tris[3 * f];
+            fcomp[f] = (int32_t)(std::upper_bound(m.comp_off.begin(), m.comp_off.end(), v) - m.comp_off.begin() - 1);
+        }
+    }
+    // faces ordered by component, then index: seeds are taken in this order
+    std::vector<int32_t> order((size_t)nt);
+    std::iota(order.begin(), order.end(), 0);
+    if (ncomp > 1)
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return fcomp[a] < fcomp[b]; });
+    int32_t np = 0;
+    size_t scan = 0;
+    std::deque<int32_t> q;
+    std::vector<int32_t> frontier;
+    std::vector<int32_t> patch_comp;
+    while (true) {
+        int32_t seed = -1;
+        for (int32_t f : frontier)
+            if (P.face_patch[f] < 0) {
+                seed = f;
+                break;
+            }
+        if (seed < 0) {
+            while (scan < order.size() && P.face_patch[order[scan]] >= 0) ++scan;
+            if (scan == order.size()) break;
+            seed = order[scan];
+        }
+        const int32_t pid = np++;
+        patch_comp.push_back(fcomp[seed]);
+        int32_t count = 0;
+        q.clear();
+        q.push_back(seed);
+        P.face_patch[seed] = pid;
+        std::vector<int32_t> next_frontier;
+        while (!q.empty()) {
+            const int32_t f = q.front();
+            q.pop_front();
+            ++count;
+            for (int32_t k = m.fadj_ptr[f]; k < m.fadj_ptr[f + 1]; ++k) {
+                const int32_t g = m.fadj[k];
+                if (P.face_patch[g] >= 0) continue;
+                if (count + (int32_t)q.size() < target) {
+                    P.face_patch[g] = pid;
+                    q.push_back(g);
+                } else {
+                    next_frontier.push_back(g);
+                }
+            }
+        }
+        frontier.swap(next_frontier);
+    }
+    P.n = np;
+    P.comp_patch_ptr.assign((size_t)std::max<int64_t>(ncomp, 1) + 1, 0);
+    for (int32_t p = 0; p < np; ++p) P.comp_patch_ptr[patch_comp[p] + 1]++;
+    for (size_t c = 1; c < P.comp_patch_ptr.size(); ++c) P.comp_patch_ptr[c] += P.comp_patch_ptr[c - 1];
+    // patches were created component by component only if seeds never jumped back; renumber so
+    // that patches of component c form one contiguous range
+    std::vector<int32_t> newid((size_t)np);
+    std::vector<int32_t> fill(P.comp_patch_ptr.begin(), P.comp_patch_ptr.end() - 1);
+    for (int32_t p = 0; p < np; ++p) newid[p] = fill[patch_comp[p]]++;
+    for (int64_t f = 0; f < nt; ++f) P.face_patch[f] = newid[P.face_patch[f]];
+}
+
+}  // namespace mad

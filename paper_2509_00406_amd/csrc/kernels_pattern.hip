@@ -1,0 +1,325 @@
+// Block sparsity pattern from topology, on the GPU (Sec. 6.1): enumerate the
+// element-element couplings in parallel, prefix-sum the per-row counts into
+// row offsets, then fill the columns.
+//
+// Every block row is owned by one lane, which gathers the stencils of the
+// elements incident to its vertex (from a vertex -> element incidence built
+// by a count / scan / fill pass) into a sorted, de-duplicated list. The
+// result is unique (sorted unique columns per row, diagonal always present),
+// so the pattern is bit-exact regardless of the order in which atomics
+// filled the incidence lists. Scans are exclusive three-phase scans
+// (block sums, scan of block sums, block-local rescan) with int64 totals so
+// int32 overflow is detected before the int32 row pointer is written.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "mad_internal.hpp"
+
+namespace mad {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+constexpr int kMaxRow = 256;   // max distinct block columns per row gathered by one lane
+
+// ---- exclusive scan: out[i] = sum_{j<i} in[j], out[n] = total (int64) ---------------------------
+template <typename TI>
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const TI* in, int64_t n, int64_t* bsum) {
+    __shared__ int64_t red[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    int64_t acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+        if (i < n) acc += (int64_t)in[i];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kScanThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+// in-place exclusive scan of a thread-block-sized array in LDS; returns the block total
+__device__ int64_t block_exclusive_scan(int64_t* s) {
+    const int t = threadIdx.x;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        const int64_t v = (t >= off) ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    const int64_t total = s[kScanThreads - 1];
+    const int64_t incl = s[t];
+    __syncthreads();
+    s[t] = incl;   // inclusive
+    __syncthreads();
+    const int64_t excl = (t == 0) ? 0 : s[t - 1];
+    __syncthreads();
+    s[t] = excl;
+    __syncthreads();
+    return total;
+}
+
+// single workgroup: exclusive scan of the block sums, carrying across chunks of kScanThreads
+__global__ __launch_bounds__(kScanThreads) void k_scan_bsum(int64_t* bsum, int64_t nb, int64_t* total_out) {
+    __shared__ int64_t s[kScanThreads];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kScanThreads) {
+        const int64_t i = base + threadIdx.x;
+        s[threadIdx.x] = (i < nb) ? bsum[i] : 0;
+        const int64_t tot = block_exclusive_scan(s);
+        if (i < nb) bsum[i] = s[threadIdx.x] + carry;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(const TI* in, int64_t n, const int64_t* boff, TO* out,
+                                                             const int64_t* total) {
+    __shared__ int64_t s[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        v[k] = (i < n) ? (int64_t)in[i] : 0;
+        acc += v[k];
+    }
+    s[threadIdx.x] = acc;
+    block_exclusive_scan(s);
+    int64_t run = s[threadIdx.x] + boff[blockIdx.x];
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t i = base + k;
+        if (i < n) out[i] = (TO)run;
+        run += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (TO)(*total);
+}
+
+// ---- incidence -----------------------------------------------------------------------------------
+struct TermTable {
+    const int32_t* stencil[8];
+    int64_t off[9];     // global element offsets
+    int32_t ns[8];
+    int32_t n_terms;
+};
+
+__global__ void k_count(const int32_t* stencil, int64_t n, int ns, int32_t* deg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n * ns) atomicAdd(deg + stencil[i], 1);
+}
+
+__global__ void k_incidence(const int32_t* stencil, int64_t n, int ns, int64_t elem_off, const int32_t* vptr,
+                            int32_t* cursor, int32_t* inc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n * ns) {
+        const int32_t v = stencil[i];
+        const int32_t pos = atomicAdd(cursor + v, 1);
+        inc[vptr[v] + pos] = (int32_t)(elem_off + i / ns);
+    }
+}
+
+// per vertex: sorted unique neighbour list; pass 0 writes counts, pass 1 writes columns
+__global__ void k_rows(TermTable tt, int64_t nv, const int32_t* vptr, const int32_t* inc, int32_t* cnt,
+                       const int32_t* rowptr, int32_t* colidx, int32_t* flags, int pass) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    int32_t list[kMaxRow];
+    int len = 1;
+    list[0] = (int32_t)v;
+    for (int32_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+        const int64_t g = inc[k];
+        int t = 0;
+        while (t + 1 < tt.n_terms && g >= tt.off[t + 1]) ++t;
+        const int ns = tt.ns[t];
+        const int32_t* st = tt.stencil[t] + (g - tt.off[t]) * ns;
+        for (int a = 0; a < ns; ++a) {
+            const int32_t c = st[a];
+            // insertion into the sorted list, skipping duplicates
+            int pos = len;
+            while (pos > 0 && list[pos - 1] > c) --pos;
+            if (pos > 0 && list[pos - 1] == c) continue;
+            if (len >= kMaxRow) {
+                atomicOr(flags + 1, 2);
+                continue;
+            }
+            for (int q = len; q > pos; --q) list[q] = list[q - 1];
+            list[pos] = c;
+            ++len;
+        }
+    }
+    if (pass == 0) {
+        cnt[v] = len;
+    } else {
+        const int32_t b = rowptr[v];
+        for (int q = 0; q < len; ++q) colidx[b + q] = list[q];
+    }
+}
+
+__global__ void k_i64_to_i32(const int64_t* in, int32_t* out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (int32_t)in[i];
+}
+
+template <typename TI, typename TO>
+static hipError_t scan_exclusive(const TI* in, int64_t n, TO* out, int64_t* d_tmp /* >= nb + 1 */, hipStream_t s) {
+    const int64_t nb = std::max<int64_t>(1, (n + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL((k_scan_sums<TI>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, d_tmp);
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanThreads), 0, s, d_tmp, nb, d_tmp + nb);
+    hipLaunchKernelGGL((k_scan_final<TI, TO>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, d_tmp, out,
+                       d_tmp + nb);
+    return hipGetLastError();
+}
+
+static unsigned blocks_for(int64_t n, int threads) { return (unsigned)std::max<int64_t>(1, (n + threads - 1) / threads); }
+
+int build_pattern_device(int64_t nv, const std::vector<PatternTerm>& terms, int32_t** rowptr_out,
+                         int32_t** colidx_out, int64_t* nnzb_out, std::vector<void*>& owned, hipStream_t s) {
+    if (terms.size() > 8) return fail(MAD_E_UNSUPPORTED, "at most 8 terms");
+    int64_t slots_total = 0, elems_total = 0;
+    TermTable tt{};
+    tt.n_terms = (int32_t)terms.size();
+    for (size_t t = 0; t < terms.size(); ++t) {
+        tt.stencil[t] = terms[t].stencil;
+        tt.ns[t] = terms[t].ns;
+        tt.off[t] = elems_total;
+        elems_total += terms[t].n;
+        slots_total += terms[t].n * terms[t].ns;
+    }
+    tt.off[terms.size()] = elems_total;
+    if (slots_total > INT32_MAX || elems_total > INT32_MAX || nv >= INT32_MAX)
+        return fail(MAD_E_OVERFLOW, "stencil incidence exceeds int32");
+
+    std::vector<void*> tmp;
+    auto alloc = [&](void** p, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+        if (e == hipSuccess) tmp.push_back(*p);
+        return e;
+    };
+    auto cleanup = [&]() {
+        for (void* p : tmp) (void)hipFree(p);
+        tmp.clear();
+    };
+    int32_t *deg = nullptr, *vptr = nullptr, *cursor = nullptr, *inc = nullptr, *cnt = nullptr, *flags = nullptr;
+    int64_t *scan_tmp = nullptr, *rowptr64 = nullptr;
+    const int64_t nb = (std::max<int64_t>(nv, 1) + kScanChunk) / kScanChunk + 2;
+    hipError_t e = hipSuccess;
+    if ((e = alloc((void**)&deg, sizeof(int32_t) * nv)) != hipSuccess ||
+        (e = alloc((void**)&vptr, sizeof(int32_t) * (nv + 1))) != hipSuccess ||
+        (e = alloc((void**)&cursor, sizeof(int32_t) * nv)) != hipSuccess ||
+        (e = alloc((void**)&inc, sizeof(int32_t) * slots_total)) != hipSuccess ||
+        (e = alloc((void**)&cnt, sizeof(int32_t) * nv)) != hipSuccess ||
+        (e = alloc((void**)&flags, sizeof(int32_t) * 4)) != hipSuccess ||
+        (e = alloc((void**)&scan_tmp, sizeof(int64_t) * (nb + 1))) != hipSuccess ||
+        (e = alloc((void**)&rowptr64, sizeof(int64_t) * (nv + 1))) != hipSuccess) {
+        cleanup();
+        return fail(MAD_E_OOM, std::string("pattern scratch: ") + hipGetErrorString(e));
+    }
+#define PT_TRY(x)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess) {                                                     \
+            cleanup();                                                              \
+            return fail(MAD_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+        }                                                                           \
+    } while (0)
+    PT_TRY(launch_fill(deg, nv, 4, s));
+    PT_TRY(launch_fill(cursor, nv, 4, s));
+    PT_TRY(launch_fill(flags, 4, 4, s));
+    for (const auto& t : terms) {
+        if (t.n == 0) continue;
+        hipLaunchKernelGGL(k_count, dim3(blocks_for(t.n * t.ns, 256)), dim3(256), 0, s, t.stencil, t.n, t.ns, deg);
+    }
+    PT_TRY(hipGetLastError());
+    PT_TRY((scan_exclusive<int32_t, int32_t>(deg, nv, vptr, scan_tmp, s)));
+    for (size_t t = 0; t < terms.size(); ++t) {
+        if (terms[t].n == 0) continue;
+        hipLaunchKernelGGL(k_incidence, dim3(blocks_for(terms[t].n * terms[t].ns, 256)), dim3(256), 0, s,
+                           terms[t].stencil, terms[t].n, terms[t].ns, tt.off[t], vptr, cursor, inc);
+    }
+    PT_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_rows, dim3(blocks_for(nv, 128)), dim3(128), 0, s, tt, nv, vptr, inc, cnt,
+                       (const int32_t*)nullptr, (int32_t*)nullptr, flags, 0);
+    PT_TRY(hipGetLastError());
+    PT_TRY((scan_exclusive<int32_t, int64_t>(cnt, nv, rowptr64, scan_tmp, s)));
+    int64_t total = 0;
+    int32_t hflags[4] = {0, 0, 0, 0};
+    PT_TRY(hipMemcpyAsync(&total, rowptr64 + nv, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PT_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    PT_TRY(hipStreamSynchronize(s));
+    if (hflags[1] != 0) {
+        cleanup();
+        return fail(MAD_E_UNSUPPORTED, "a vertex couples to more than 255 other vertices");
+    }
+    if (total > INT32_MAX) {
+        cleanup();
+        return fail(MAD_E_OVERFLOW, "block count exceeds int32");
+    }
+    int32_t *rowptr = nullptr, *colidx = nullptr;
+    e = hipMalloc((void**)&rowptr, sizeof(int32_t) * (nv + 1));
+    if (e == hipSuccess) {
+        owned.push_back(rowptr);
+        e = hipMalloc((void**)&colidx, sizeof(int32_t) * std::max<int64_t>(total, 1));
+        if (e == hipSuccess) owned.push_back(colidx);
+    }
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(MAD_E_OOM, "pattern arrays");
+    }
+    hipLaunchKernelGGL(k_i64_to_i32, dim3(blocks_for(nv + 1, 256)), dim3(256), 0, s, rowptr64, rowptr, nv + 1);
+    hipLaunchKernelGGL(k_rows, dim3(blocks_for(nv, 128)), dim3(128), 0, s, tt, nv, vptr, inc, cnt,
+                       (const int32_t*)rowptr, colidx, flags, 1);
+    PT_TRY(hipGetLastError());
+    PT_TRY(hipStreamSynchronize(s));
+#undef PT_TRY
+    cleanup();
+    *rowptr_out = rowptr;
+    *colidx_out = colidx;
+    *nnzb_out = total;
+    return MAD_OK;
+}
+
+// slot of block (s, t) for every element: binary search of column v_t in row v_s
+__global__ void k_slots(const int32_t* stencil, int64_t n, int ns, const int32_t* rowptr, const int32_t* colidx,
+                        int32_t* slots, int32_t* flags) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    for (int a = 0; a < ns; ++a) {
+        const int32_t r = stencil[e * ns + a];
+        for (int b = 0; b < ns; ++b) {
+            const int32_t c = stencil[e * ns + b];
+            int32_t lo = rowptr[r], hi = rowptr[r + 1] - 1, found = -1;
+            while (lo <= hi) {
+                const int32_t mid = lo + (hi - lo) / 2;
+                const int32_t m = colidx[mid];
+                if (m == c) {
+                    found = mid;
+                    break;
+                }
+                if (m < c) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            if (found < 0) {
+                atomicOr(flags + 1, 4);
+                found = rowptr[r];
+            }
+            slots[(int64_t)(a * ns + b) * n + e] = found;
+        }
+    }
+}
+
+hipError_t launch_slots(const int32_t* stencil, int64_t n, int ns, const int32_t* rowptr, const int32_t* colidx,
+                        int32_t* slots, int32_t* flags, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, stencil, n, ns, rowptr, colidx, slots,
+                       flags);
+    return hipGetLastError();
+}
+
+}  // namespace mad

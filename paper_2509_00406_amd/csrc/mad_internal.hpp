@@ -1,0 +1,138 @@
+// Host-side structures of the library and the launchers the C ABI calls.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mad.h"
+
+struct mad_mesh {
+    int64_t nv = 0, nt = 0;
+    std::vector<int32_t> tris;           // [nt][3]
+    std::vector<int64_t> comp_off;       // [ncomp + 1]; {0, nv} when not batched
+    bool batched = false;
+    // topology (built at create): edges sorted by (min, max)
+    std::vector<int32_t> edges;          // [ne][2]
+    std::vector<int32_t> edge_nf;        // [ne] incident face count
+    std::vector<int32_t> edge_face0;     // [ne] lowest incident face
+    std::vector<int32_t> diamonds;       // [nd][4]
+    std::vector<int32_t> diamond_faces;  // [nd][2]
+    // face adjacency across manifold and non-manifold edges (CSR), for patching
+    std::vector<int32_t> fadj_ptr, fadj;
+    int64_t ne() const { return (int64_t)edge_nf.size(); }
+    int64_t nd() const { return (int64_t)diamond_faces.size() / 2; }
+};
+
+namespace mad {
+
+struct Term {
+    int kind = 0;
+    int ns = 0, d = 0, nrest = 0;
+    double prm[4] = {0, 0, 0, 0};
+    int64_t n = 0;
+    std::vector<int32_t> stencil;        // original order [n][ns]
+    std::vector<double> rest;            // original order [n][nrest]
+    std::vector<int32_t> elem_patch;     // patch of each element (original order)
+    // patch-ordered device data
+    std::vector<int32_t> perm;           // device slot -> original element
+    std::vector<int32_t> elem_ptr;       // [n_patch + 1]
+    int32_t* d_stencil = nullptr;        // [n][ns]
+    double* d_rest = nullptr;            // SoA [nrest][n]
+    int32_t* d_elem_ptr = nullptr;       // [n_patch + 1]
+    int32_t* d_slots = nullptr;          // SoA [ns*ns][n]
+};
+
+// one contiguous range of patches per component
+struct Patches {
+    int32_t n = 0;
+    std::vector<int32_t> face_patch;     // [nt]
+    std::vector<int32_t> comp_patch_ptr; // [ncomp + 1]
+};
+
+}  // namespace mad
+
+struct mad_problem {
+    const mad_mesh* mesh = nullptr;
+    int d = 0, prec = 0;
+    mad_options opt{};
+    std::vector<mad::Term> terms;
+    bool finalized = false;
+    int device = 0;
+    mad::Patches patches;
+    int64_t nnzb = 0;
+    int32_t* d_rowptr = nullptr;
+    int32_t* d_colidx = nullptr;
+    int32_t* d_comp_patch_ptr = nullptr;
+    double* d_partial = nullptr;          // [n_terms][n_patch]
+    int32_t* d_flags = nullptr;           // [0] nonfinite, [1] internal error
+    unsigned long long* d_fallbacks = nullptr;
+    std::vector<void*> owned;             // every device allocation, freed at destroy
+    // profiling: one row of n_terms + 3 events per recorded evaluation
+    bool profiling = false;
+    int64_t prof_count = 0;
+    std::vector<std::vector<hipEvent_t>> prof_events;
+};
+
+namespace mad {
+
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define MAD_HIP_TRY(expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return ::mad::fail(MAD_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int kind_stencil(int kind);
+int kind_vardim(int kind);
+int kind_nrest(int kind);
+
+// host setup (host_mesh.cpp)
+int build_topology(mad_mesh& m);
+int rest_tri(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);        // [nt][5]
+int rest_diamond(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);    // [nd][2]
+void build_patches(const mad_mesh& m, int target_faces, Patches& p);
+
+// device launchers (kernels_*.hip); all asynchronous on `stream`
+struct EvalLaunch {
+    int kind;
+    int prec;       // MAD_F64 / MAD_F32
+    int mode;       // 0 passive, 1 grad, 2 hess, 3 clamped hess
+    int want_grad;
+    int n_patch;
+    const double* x;
+    const int32_t* stencil;
+    const double* rest;
+    int64_t n;      // elements (rest/slot SoA stride)
+    const int32_t* elem_ptr;
+    const int32_t* slots;
+    void* grad;
+    void* hess;
+    double* partial;
+    int32_t* flags;
+    unsigned long long* fallbacks;
+    double prm[4];
+    double eps;
+    double qmin;
+};
+hipError_t launch_eval(const EvalLaunch& L, hipStream_t s);
+hipError_t launch_fill(void* ptr, int64_t n_elems, int elem_bytes, hipStream_t s);
+hipError_t launch_energy_reduce(const double* partial, int n_terms, int n_patch, const int32_t* comp_patch_ptr,
+                                int n_comp, bool batched, double* energy, hipStream_t s);
+
+// pattern builder (kernels_pattern.hip)
+struct PatternTerm {
+    const int32_t* stencil;  // device [n][ns]
+    int64_t n;
+    int ns;
+};
+// Builds rowptr/colidx on the device (allocated here, appended to `owned`); nnzb returned.
+int build_pattern_device(int64_t nv, const std::vector<PatternTerm>& terms, int32_t** rowptr, int32_t** colidx,
+                         int64_t* nnzb, std::vector<void*>& owned, hipStream_t s);
+hipError_t launch_slots(const int32_t* stencil, int64_t n, int ns, const int32_t* rowptr, const int32_t* colidx,
+                        int32_t* slots, int32_t* flags, hipStream_t s);
+
+}  // namespace mad

@@ -1,0 +1,279 @@
+"""Python binding of libmad.so: argument marshalling only.
+
+Every function named ``mad_*`` mirrors the C entry point of the same name in
+include/mad.h. Device buffers are torch CUDA (HIP) tensors; streams are torch
+streams. Every step of the evaluation runs in the library's HIP kernels. If the
+library is missing this module raises; it never falls back to another path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmad.so")
+
+EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR = 1, 2, 3, 4, 5, 6
+ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
+F64, F32 = 0, 1
+SCATTER_AUTO, SCATTER_ATOMIC = 0, 1
+
+STATUS = {0: "MAD_OK", -1: "MAD_E_INVALID_ARG", -2: "MAD_E_BAD_MESH", -3: "MAD_E_DEGENERATE_REST",
+          -4: "MAD_E_OVERFLOW", -5: "MAD_E_OOM", -6: "MAD_E_HIP", -7: "MAD_E_STATE", -8: "MAD_E_UNSUPPORTED"}
+VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2}
+NEEDS_REST = {DIRICHLET, STVK, BENDING, SYMDIR}
+
+
+class MadError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what}: {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class mad_options(C.Structure):
+    _fields_ = [("scatter", C.c_int32), ("patch_faces", C.c_int32), ("spd_eps", C.c_double),
+                ("degenerate_q", C.c_double), ("reserved", C.c_int32 * 8)]
+
+
+_lib = None
+
+_SIGS = {
+    "mad_version": ([], C.c_int32),
+    "mad_last_error": ([], C.c_char_p),
+    "mad_options_default": ([C.POINTER(mad_options)], C.c_int32),
+    "mad_mesh_create": ([C.c_int64, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)], C.c_int32),
+    "mad_mesh_info": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                       C.POINTER(C.c_int64)], C.c_int32),
+    "mad_mesh_copy_diamonds": ([C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_mesh_destroy": ([C.c_void_p], C.c_int32),
+    "mad_problem_create": ([C.c_void_p, C.c_int32, C.c_int32, C.POINTER(mad_options), C.POINTER(C.c_void_p)],
+                           C.c_int32),
+    "mad_problem_add_term": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p], C.c_int32),
+    "mad_problem_finalize": ([C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_problem_pattern_info": ([C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)],
+                                 C.c_int32),
+    "mad_problem_energy_count": ([C.c_void_p, C.POINTER(C.c_int32)], C.c_int32),
+    "mad_problem_copy_pattern": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_problem_eval": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+                         C.c_int32),
+    "mad_problem_status": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_void_p], C.c_int32),
+    "mad_problem_set_profiling": ([C.c_void_p, C.c_int32], C.c_int32),
+    "mad_problem_profile": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
+                            C.c_int32),
+    "mad_problem_destroy": ([C.c_void_p], C.c_int32),
+}
+
+
+def lib() -> C.CDLL:
+    """Load libmad.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_2509_00406_amd.build)")
+        h = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = h
+    return _lib
+
+
+def exported_symbols() -> list[str]:
+    return sorted(_SIGS)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise MadError(rc, what, lib().mad_last_error().decode(errors="replace"))
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    """torch stream -> hipStream_t; None = torch's current stream; an int is taken as a raw handle."""
+    if isinstance(stream, int):
+        return stream
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# ---- thin wrappers, one per C entry point --------------------------------------------------------
+def mad_version() -> int:
+    return lib().mad_version()
+
+
+def mad_options_default() -> mad_options:
+    o = mad_options()
+    _check(lib().mad_options_default(C.byref(o)), "mad_options_default")
+    return o
+
+
+def mad_mesh_create(n_verts: int, tris: np.ndarray, comp_offsets: np.ndarray | None = None) -> C.c_void_p:
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    h = C.c_void_p()
+    co = None if comp_offsets is None else np.ascontiguousarray(comp_offsets, dtype=np.int64)
+    n_comp = 0 if co is None else co.size - 1
+    _check(lib().mad_mesh_create(n_verts, tris.shape[0], _ptr(tris), n_comp, _ptr(co), C.byref(h)),
+           "mad_mesh_create")
+    return h
+
+
+def mad_mesh_info(mesh) -> tuple[int, int, int, int]:
+    v = [C.c_int64() for _ in range(4)]
+    _check(lib().mad_mesh_info(mesh, *[C.byref(a) for a in v]), "mad_mesh_info")
+    return tuple(a.value for a in v)
+
+
+def mad_mesh_copy_diamonds(mesh) -> np.ndarray:
+    nd = mad_mesh_info(mesh)[3]
+    out = np.zeros((nd, 4), np.int32)
+    _check(lib().mad_mesh_copy_diamonds(mesh, _ptr(out)), "mad_mesh_copy_diamonds")
+    return out
+
+
+def mad_mesh_destroy(mesh):
+    _check(lib().mad_mesh_destroy(mesh), "mad_mesh_destroy")
+
+
+def mad_problem_create(mesh, var_dim: int, precision: int, opt: mad_options | None = None) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().mad_problem_create(mesh, var_dim, precision, C.byref(opt) if opt is not None else None,
+                                    C.byref(h)), "mad_problem_create")
+    return h
+
+
+def mad_problem_add_term(prob, kind: int, params=(), rest_pos: np.ndarray | None = None):
+    prm = np.ascontiguousarray(params, dtype=np.float64)
+    rp = None if rest_pos is None else np.ascontiguousarray(rest_pos, dtype=np.float64)
+    _check(lib().mad_problem_add_term(prob, kind, _ptr(prm) if prm.size else None, prm.size, _ptr(rp)),
+           "mad_problem_add_term")
+
+
+def mad_problem_finalize(prob, stream=None):
+    _check(lib().mad_problem_finalize(prob, _stream(stream)), "mad_problem_finalize")
+
+
+def mad_problem_pattern_info(prob) -> tuple[int, int, int]:
+    r, n, b = C.c_int64(), C.c_int64(), C.c_int32()
+    _check(lib().mad_problem_pattern_info(prob, C.byref(r), C.byref(n), C.byref(b)), "mad_problem_pattern_info")
+    return r.value, n.value, b.value
+
+
+def mad_problem_energy_count(prob) -> int:
+    c = C.c_int32()
+    _check(lib().mad_problem_energy_count(prob, C.byref(c)), "mad_problem_energy_count")
+    return c.value
+
+
+def mad_problem_copy_pattern(prob, rowptr, colidx, stream=None):
+    _check(lib().mad_problem_copy_pattern(prob, _ptr(rowptr), _ptr(colidx), _stream(stream)),
+           "mad_problem_copy_pattern")
+
+
+def mad_problem_eval(prob, x, mode: int, energy=None, grad=None, hess=None, stream=None):
+    _check(lib().mad_problem_eval(prob, _ptr(x), mode, _ptr(energy), _ptr(grad), _ptr(hess), _stream(stream)),
+           "mad_problem_eval")
+
+
+def mad_problem_status(prob, stream=None) -> tuple[bool, int]:
+    nf, fb = C.c_int32(), C.c_int64()
+    _check(lib().mad_problem_status(prob, C.byref(nf), C.byref(fb), _stream(stream)), "mad_problem_status")
+    return bool(nf.value), fb.value
+
+
+def mad_problem_set_profiling(prob, enable: bool):
+    _check(lib().mad_problem_set_profiling(prob, 1 if enable else 0), "mad_problem_set_profiling")
+
+
+def mad_problem_profile(prob) -> tuple[list[float], int]:
+    ms = (C.c_double * 10)()
+    n, k = C.c_int32(), C.c_int64()
+    _check(lib().mad_problem_profile(prob, ms, C.byref(n), C.byref(k)), "mad_problem_profile")
+    return [ms[i] for i in range(n.value)], k.value
+
+
+def mad_problem_destroy(prob):
+    _check(lib().mad_problem_destroy(prob), "mad_problem_destroy")
+
+
+# ---- convenience objects (still marshalling only) -----------------------------------------------
+class Mesh:
+    def __init__(self, tris: np.ndarray, n_verts: int, comp_offsets: np.ndarray | None = None):
+        self.handle = mad_mesh_create(n_verts, tris, comp_offsets)
+        self.n_verts, self.n_tris, self.n_edges, self.n_diamonds = mad_mesh_info(self.handle)
+
+    def diamonds(self) -> np.ndarray:
+        return mad_mesh_copy_diamonds(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.mad_mesh_destroy(h)
+            self.handle = None
+
+
+class Problem:
+    """mesh + var_dim + precision -> terms -> finalize -> eval (Sec. 4.2 programming model)."""
+
+    def __init__(self, mesh: Mesh, var_dim: int, precision: int = F64, patch_faces: int = 0,
+                 spd_eps: float = 0.0, degenerate_q: float = 0.0):
+        o = mad_options_default()
+        o.patch_faces = patch_faces
+        o.spd_eps = spd_eps
+        o.degenerate_q = degenerate_q
+        self.mesh = mesh
+        self.var_dim = var_dim
+        self.precision = precision
+        self.handle = mad_problem_create(mesh.handle, var_dim, precision, o)
+
+    def add_term(self, kind: int, params=(), rest_pos: np.ndarray | None = None):
+        mad_problem_add_term(self.handle, kind, params, rest_pos)
+
+    def finalize(self, stream=None):
+        mad_problem_finalize(self.handle, stream)
+        self.n_rows, self.nnzb, self.block_dim = mad_problem_pattern_info(self.handle)
+        self.energy_count = mad_problem_energy_count(self.handle)
+
+    def pattern(self, device="cuda"):
+        import torch
+        rowptr = torch.empty(self.n_rows + 1, dtype=torch.int32, device=device)
+        colidx = torch.empty(max(self.nnzb, 1), dtype=torch.int32, device=device)
+        mad_problem_copy_pattern(self.handle, rowptr, colidx)
+        return rowptr, colidx[:self.nnzb]
+
+    def outputs(self, device="cuda"):
+        """Allocate (energy, grad, hess) device buffers of the right dtype and size."""
+        import torch
+        dt = torch.float32 if self.precision == F32 else torch.float64
+        d = self.var_dim
+        energy = torch.empty(self.energy_count, dtype=torch.float64, device=device)
+        grad = torch.empty(self.n_rows * d, dtype=dt, device=device)
+        hess = torch.empty((self.nnzb, d, d), dtype=dt, device=device)
+        return energy, grad, hess
+
+    def eval(self, x, mode: int = ENERGY | GRAD | HESS, out=None, stream=None):
+        energy, grad, hess = out if out is not None else self.outputs(x.device)
+        mad_problem_eval(self.handle, x, mode, energy if mode & ENERGY else None,
+                         grad if mode & GRAD else None, hess if mode & HESS else None, stream)
+        return energy, grad, hess
+
+    def status(self, stream=None):
+        return mad_problem_status(self.handle, stream)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.mad_problem_destroy(h)
+            self.handle = None

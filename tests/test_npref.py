@@ -1,0 +1,19 @@
+"""The vectorised numpy energies agree with the oracle on small meshes."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_00406_amd import meshgen
+from tests import npref
+
+
+@pytest.mark.parametrize("noise", ["relative", "absolute"])
+def test_npref_shell_energy_matches_oracle(noise):
+    inp = meshgen.shell_cylinder(n=20, seed=4, noise=noise)
+    P = O.Problem(inp.tris, inp.rest, inp.n_verts, 3)
+    P.add_term(O.STVK, (0.9, 1.3))
+    P.add_term(O.BENDING, (1.1, 1.0))
+    r = P.eval(inp.x, O.ENERGY)
+    e, s = npref.shell_energy(inp.tris, inp.rest, inp.x, P.topo.diamonds, P.topo.diamond_faces, (0.9, 1.3), (1.1, 1.0))
+    assert e == pytest.approx(r.energy, rel=1e-12)
+    assert s == pytest.approx(r.esum_abs, rel=1e-12)
