@@ -89,8 +89,13 @@ typedef enum mad_precision {
 } mad_precision;
 
 typedef enum mad_scatter {
-    MAD_SCATTER_AUTO = 0,    /* library default */
-    MAD_SCATTER_ATOMIC = 1   /* device-wide atomic adds into pre-zeroed outputs (Sec. 5.5) */
+    MAD_SCATTER_AUTO = 0,    /* library default (MAD_SCATTER_PATCH) */
+    MAD_SCATTER_ATOMIC = 1,  /* one kernel per term; every element adds its gradient and Hessian
+                                entries with device-wide atomics into pre-zeroed outputs (Sec. 5.5) */
+    MAD_SCATTER_PATCH = 2    /* one fused kernel over all terms, one workgroup per patch: x staged
+                                in LDS, element contributions summed in LDS, each touched entry then
+                                written once (plain store if no other patch touches it, else one
+                                device-wide atomic add) */
 } mad_scatter;
 
 typedef struct mad_options {

@@ -16,13 +16,13 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libmad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "api.cpp"]
+SOURCES = ["kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "host_patch.cpp", "api.cpp"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 (v_pk_*_f32) instructions.
 # -munsafe-fp-atomics: hardware FP32/FP64 atomic add instead of compare-and-swap loops.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-atomics",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-Wall", "-Wno-unused-function", "-I", os.path.join(os.path.dirname(HERE), "include")]
+          "-Wall", "-Wno-unused-function", "-pthread", "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
@@ -52,7 +52,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
     tmp = LIB + ".tmp"
-    subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs])
+    subprocess.check_call([HIPCC, "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f}s")

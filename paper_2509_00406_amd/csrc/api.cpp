@@ -32,7 +32,7 @@ const char* mad_last_error(void) { return g_last_error.c_str(); }
 int32_t mad_options_default(mad_options* opt) {
     if (!opt) return fail(MAD_E_INVALID_ARG, "opt is NULL");
     std::memset(opt, 0, sizeof(*opt));
-    opt->scatter = MAD_SCATTER_ATOMIC;
+    opt->scatter = MAD_SCATTER_PATCH;
     opt->patch_faces = 512;
     opt->spd_eps = 0.0;
     opt->degenerate_q = 1e-2;
@@ -129,8 +129,9 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
     if (opt) {
         for (int i = 0; i < 8; ++i)
             if (opt->reserved[i] != 0) return fail(MAD_E_INVALID_ARG, "reserved option fields must be zero");
-        if (opt->scatter != MAD_SCATTER_AUTO && opt->scatter != MAD_SCATTER_ATOMIC)
+        if (opt->scatter != MAD_SCATTER_AUTO && opt->scatter != MAD_SCATTER_ATOMIC && opt->scatter != MAD_SCATTER_PATCH)
             return fail(MAD_E_INVALID_ARG, "bad scatter mode");
+        o.scatter = opt->scatter == MAD_SCATTER_AUTO ? MAD_SCATTER_PATCH : opt->scatter;
         if (opt->patch_faces < 0 || opt->patch_faces > (1 << 20)) return fail(MAD_E_INVALID_ARG, "bad patch_faces");
         if (!(opt->spd_eps >= 0.0) || !std::isfinite(opt->spd_eps)) return fail(MAD_E_INVALID_ARG, "spd_eps must be >= 0");
         if (!(opt->degenerate_q >= 0.0) || opt->degenerate_q > 1.0) return fail(MAD_E_INVALID_ARG, "degenerate_q in [0, 1]");
@@ -144,6 +145,7 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
     p->d = var_dim;
     p->prec = precision;
     p->opt = o;
+    p->scatter = o.scatter;
     *out = p;
     return MAD_OK;
 }
@@ -202,20 +204,13 @@ static int upload(mad_problem* p, void** dst, const void* src, size_t bytes, hip
     return MAD_OK;
 }
 
-int32_t mad_problem_finalize(mad_problem* p, void* stream) {
-    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
-    if (p->finalized) return fail(MAD_E_STATE, "already finalized");
-    if (p->terms.empty()) return fail(MAD_E_STATE, "no terms");
-    hipStream_t s = (hipStream_t)stream;
+// Patch order of every term's elements: faces by their patch, diamonds by their lower face,
+// edges by their first face; inside a patch, by that face's index.
+static void order_terms(mad_problem* p) {
     const mad_mesh& m = *p->mesh;
-    MAD_HIP_TRY(hipGetDevice(&p->device));
-    build_patches(m, p->opt.patch_faces, p->patches);
     const int32_t np = p->patches.n;
-    int rc;
     for (auto& t : p->terms) {
-        // patch of each element: faces by their patch, diamonds by f1, edges by their first face
-        std::vector<int32_t> ep((size_t)t.n);
-        std::vector<int32_t> key((size_t)t.n);   // position inside the patch ordering
+        std::vector<int32_t> ep((size_t)t.n), key((size_t)t.n);
         for (int64_t e = 0; e < t.n; ++e) {
             int32_t f;
             if (t.kind == MAD_BENDING) f = m.diamond_faces[2 * e];
@@ -233,6 +228,65 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
         t.elem_ptr.assign((size_t)np + 1, 0);
         for (int64_t e = 0; e < t.n; ++e) t.elem_ptr[ep[e] + 1]++;
         for (int32_t q = 0; q < np; ++q) t.elem_ptr[q + 1] += t.elem_ptr[q];
+    }
+}
+
+// largest per-patch vertex and upper-block counts of the current patching
+static void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb) {
+    const int64_t nv = p->mesh->nv;
+    int32_t mv = 0, mb = 0;
+    std::vector<int32_t> verts;
+    std::vector<int64_t> keys;
+    for (int32_t q = 0; q < p->patches.n; ++q) {
+        verts.clear();
+        keys.clear();
+        for (const auto& t : p->terms)
+            for (int32_t i = t.elem_ptr[q]; i < t.elem_ptr[q + 1]; ++i) {
+                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                for (int a = 0; a < t.ns; ++a) {
+                    verts.push_back(st[a]);
+                    for (int b = a; b < t.ns; ++b)
+                        keys.push_back((int64_t)std::min(st[a], st[b]) * nv + std::max(st[a], st[b]));
+                }
+            }
+        std::sort(verts.begin(), verts.end());
+        std::sort(keys.begin(), keys.end());
+        mv = std::max(mv, (int32_t)(std::unique(verts.begin(), verts.end()) - verts.begin()));
+        mb = std::max(mb, (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin()));
+    }
+    *max_lv = mv;
+    *max_lb = mb;
+}
+
+static constexpr size_t kLdsBudget = 60 * 1024;  // dynamic LDS per workgroup; 2 workgroups per CU
+
+int32_t mad_problem_finalize(mad_problem* p, void* stream) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (p->finalized) return fail(MAD_E_STATE, "already finalized");
+    if (p->terms.empty()) return fail(MAD_E_STATE, "no terms");
+    hipStream_t s = (hipStream_t)stream;
+    const mad_mesh& m = *p->mesh;
+    MAD_HIP_TRY(hipGetDevice(&p->device));
+    int target = p->opt.patch_faces;
+    build_patches(m, target, p->patches);
+    order_terms(p);
+    if (p->scatter == MAD_SCATTER_PATCH) {
+        // shrink the patch target until the largest patch's LDS working set fits the budget
+        for (;;) {
+            int32_t mv, mb;
+            patch_extent(p, &mv, &mb);
+            p->lds_bytes = patch_lds_bytes(p->d, p->prec, 3, mv, mb);
+            if (p->lds_bytes <= kLdsBudget) break;
+            if (target <= 1) return fail(MAD_E_UNSUPPORTED, "a single element exceeds the LDS budget");
+            target = std::max(1, (int)(target * 0.75));
+            build_patches(m, target, p->patches);
+            order_terms(p);
+        }
+        p->opt.patch_faces = target;
+    }
+    const int32_t np = p->patches.n;
+    int rc;
+    for (auto& t : p->terms) {
         std::vector<int32_t> st((size_t)t.n * t.ns);
         std::vector<double> rs((size_t)t.n * t.nrest);
         for (int64_t i = 0; i < t.n; ++i) {
@@ -258,10 +312,35 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
     std::vector<PatternTerm> pts;
     for (auto& t : p->terms) pts.push_back({t.d_stencil, t.n, t.ns});
     if ((rc = build_pattern_device(m.nv, pts, &p->d_rowptr, &p->d_colidx, &p->nnzb, p->owned, s)) != MAD_OK) return rc;
-    for (auto& t : p->terms) {
-        MAD_HIP_TRY(hipMalloc((void**)&t.d_slots, sizeof(int32_t) * std::max<int64_t>(1, t.n * t.ns * t.ns)));
-        p->owned.push_back(t.d_slots);
-        MAD_HIP_TRY(launch_slots(t.d_stencil, t.n, t.ns, p->d_rowptr, p->d_colidx, t.d_slots, p->d_flags, s));
+    if (p->scatter == MAD_SCATTER_ATOMIC) {
+        for (auto& t : p->terms) {
+            MAD_HIP_TRY(hipMalloc((void**)&t.d_slots, sizeof(int32_t) * std::max<int64_t>(1, t.n * t.ns * t.ns)));
+            p->owned.push_back(t.d_slots);
+            MAD_HIP_TRY(launch_slots(t.d_stencil, t.n, t.ns, p->d_rowptr, p->d_colidx, t.d_slots, p->d_flags, s));
+        }
+    } else {
+        std::vector<int32_t> rowptr((size_t)m.nv + 1), colidx((size_t)std::max<int64_t>(p->nnzb, 1));
+        MAD_HIP_TRY(hipMemcpyAsync(rowptr.data(), p->d_rowptr, rowptr.size() * 4, hipMemcpyDeviceToHost, s));
+        MAD_HIP_TRY(hipMemcpyAsync(colidx.data(), p->d_colidx, (size_t)p->nnzb * 4, hipMemcpyDeviceToHost, s));
+        MAD_HIP_TRY(hipStreamSynchronize(s));
+        colidx.resize((size_t)p->nnzb);
+        PatchLocal L;
+        if ((rc = build_patch_local(*p, rowptr, colidx, L)) != MAD_OK) return rc;
+        p->max_lv = L.max_lv;
+        p->max_lb = L.max_lb;
+        p->lds_bytes = patch_lds_bytes(p->d, p->prec, 3, L.max_lv, L.max_lb);
+        if ((rc = upload(p, (void**)&p->d_lv_ptr, L.lv_ptr.data(), L.lv_ptr.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_lv_global, L.lv_global.data(), L.lv_global.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_lv_excl, L.lv_excl.data(), L.lv_excl.size(), s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_lb_ptr, L.lb_ptr.data(), L.lb_ptr.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_lb_gidx, L.lb_gidx.data(), L.lb_gidx.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_lb_gidxT, L.lb_gidxT.data(), L.lb_gidxT.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_lb_excl, L.lb_excl.data(), L.lb_excl.size(), s)) != MAD_OK) return rc;
+        for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+            auto& t = p->terms[ti];
+            if ((rc = upload(p, (void**)&t.d_lvert, L.lvert[ti].data(), L.lvert[ti].size() * 2, s)) != MAD_OK) return rc;
+            if ((rc = upload(p, (void**)&t.d_lslot, L.lslot[ti].data(), L.lslot[ti].size() * 2, s)) != MAD_OK) return rc;
+        }
     }
     int32_t hflags[4];
     MAD_HIP_TRY(hipMemcpyAsync(hflags, p->d_flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
@@ -271,6 +350,7 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
     for (auto& t : p->terms) {
         std::vector<int32_t>().swap(t.stencil);
         std::vector<double>().swap(t.rest);
+        std::vector<int32_t>().swap(t.perm);
     }
     p->finalized = true;
     return MAD_OK;
@@ -330,7 +410,48 @@ int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double*
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[1], s));
     const int kmode = (mode & MAD_HESS) ? ((mode & MAD_SPD) ? 3 : 2) : ((mode & MAD_GRAD) ? 1 : 0);
     const int np = p->patches.n;
-    for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+    int n_partial_terms = (int)p->terms.size();
+    if (p->scatter == MAD_SCATTER_PATCH) {
+        PatchLaunch L{};
+        L.prec = p->prec;
+        L.mode = kmode;
+        L.want_grad = (mode & MAD_GRAD) ? 1 : 0;
+        L.var_dim = d;
+        L.n_terms = (int)p->terms.size();
+        L.n_patch = np;
+        L.lds_bytes = patch_lds_bytes(d, p->prec, kmode, p->max_lv, p->max_lb);
+        L.x = x;
+        L.grad = grad;
+        L.hess = hess;
+        L.lv_ptr = p->d_lv_ptr;
+        L.lv_global = p->d_lv_global;
+        L.lv_excl = p->d_lv_excl;
+        L.lb_ptr = p->d_lb_ptr;
+        L.lb_gidx = p->d_lb_gidx;
+        L.lb_gidxT = p->d_lb_gidxT;
+        L.lb_excl = p->d_lb_excl;
+        L.partial = p->d_partial;
+        L.flags = p->d_flags;
+        L.fallbacks = p->d_fallbacks;
+        L.eps = p->opt.spd_eps;
+        L.qmin = p->opt.degenerate_q;
+        for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+            const Term& t = p->terms[ti];
+            PatchTermArgs& A = L.terms[ti];
+            A.kind = t.kind;
+            A.n = t.n;
+            A.rest = t.d_rest;
+            A.lvert = t.d_lvert;
+            A.lslot = t.d_lslot;
+            A.elem_ptr = t.d_elem_ptr;
+            std::memcpy(A.prm, t.prm, sizeof(A.prm));
+        }
+        MAD_HIP_TRY(launch_eval_patch(L, s));
+        if (ev)
+            for (size_t ti = 0; ti < p->terms.size(); ++ti) MAD_HIP_TRY(hipEventRecord((*ev)[2 + ti], s));
+        n_partial_terms = 1;
+    }
+    for (size_t ti = 0; p->scatter == MAD_SCATTER_ATOMIC && ti < p->terms.size(); ++ti) {
         const Term& t = p->terms[ti];
         EvalLaunch L{};
         L.kind = t.kind;
@@ -357,7 +478,7 @@ int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double*
     }
     if (mode & MAD_ENERGY) {
         const int ncomp = (int)m.comp_off.size() - 1;
-        MAD_HIP_TRY(launch_energy_reduce(p->d_partial, (int)p->terms.size(), np, p->d_comp_patch_ptr,
+        MAD_HIP_TRY(launch_energy_reduce(p->d_partial, n_partial_terms, np, p->d_comp_patch_ptr,
                                          std::max(ncomp, 1), m.batched, energy, s));
     }
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2 + p->terms.size()], s));

@@ -1,0 +1,150 @@
+// Patch-local index structures for the LDS-accumulating assembly.
+//
+// For every patch: the sorted list of vertices its elements touch (x is
+// staged into LDS from this list, gradient entries are flushed through it)
+// and the sorted list of upper-triangle blocks (r <= c) its elements add to
+// (the workgroup accumulates them in LDS and writes each once). An entry is
+// "exclusive" when no other patch touches it: it is written with a plain
+// store; shared entries are flushed with a global atomic add.
+//
+// Per element, the stencil becomes patch-local vertex indices (u16) and, for
+// each unordered stencil pair s <= t, a local block index (low 14 bits) with
+// two flag bits: bit 14 = the element's (s, t) block lands transposed in the
+// stored (min, max) block; bit 15 = s != t name the same vertex (a degenerate
+// stencil), so both (s, t) and (t, s) add into that diagonal block.
+#include <algorithm>
+#include <atomic>
+#include <thread>
+
+#include "mad_internal.hpp"
+
+namespace mad {
+
+static int32_t find_block(const std::vector<int32_t>& rowptr, const std::vector<int32_t>& colidx, int32_t r,
+                          int32_t c) {
+    auto b = colidx.begin() + rowptr[r], e = colidx.begin() + rowptr[r + 1];
+    auto it = std::lower_bound(b, e, c);
+    return (it != e && *it == c) ? (int32_t)(it - colidx.begin()) : -1;
+}
+
+int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& colidx,
+                      PatchLocal& L) {
+    const int32_t np = P.patches.n;
+    const int nt = (int)P.terms.size();
+    const int64_t nv = P.mesh->nv;
+    std::vector<std::vector<int32_t>> pv((size_t)np), pb_r((size_t)np), pb_c((size_t)np);
+    // per term, per element (patch order): local maps
+    L.lvert.assign(nt, {});
+    L.lslot.assign(nt, {});
+    for (int t = 0; t < nt; ++t) {
+        const Term& T = P.terms[t];
+        L.lvert[t].assign((size_t)T.n * T.ns, 0);
+        L.lslot[t].assign((size_t)T.n * (T.ns * (T.ns + 1) / 2), 0);
+    }
+    std::atomic<int> err{0};
+    auto work = [&](int32_t p0, int32_t p1) {
+        std::vector<int32_t> verts;
+        std::vector<int64_t> keys;
+        for (int32_t p = p0; p < p1; ++p) {
+            verts.clear();
+            keys.clear();
+            for (int t = 0; t < nt; ++t) {
+                const Term& T = P.terms[t];
+                for (int32_t i = T.elem_ptr[p]; i < T.elem_ptr[p + 1]; ++i) {
+                    const int32_t* st = &T.stencil[(int64_t)T.perm[i] * T.ns];
+                    for (int a = 0; a < T.ns; ++a) {
+                        verts.push_back(st[a]);
+                        for (int b = a; b < T.ns; ++b) {
+                            const int64_t r = std::min(st[a], st[b]), c = std::max(st[a], st[b]);
+                            keys.push_back(r * nv + c);
+                        }
+                    }
+                }
+            }
+            std::sort(verts.begin(), verts.end());
+            verts.erase(std::unique(verts.begin(), verts.end()), verts.end());
+            std::sort(keys.begin(), keys.end());
+            keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+            if (keys.size() > (1u << 14) || verts.size() > (1u << 16)) {
+                err.store(1);
+                continue;
+            }
+            pv[p] = verts;
+            pb_r[p].resize(keys.size());
+            pb_c[p].resize(keys.size());
+            for (size_t k = 0; k < keys.size(); ++k) {
+                pb_r[p][k] = (int32_t)(keys[k] / nv);
+                pb_c[p][k] = (int32_t)(keys[k] % nv);
+            }
+            for (int t = 0; t < nt; ++t) {
+                const Term& T = P.terms[t];
+                const int npair = T.ns * (T.ns + 1) / 2;
+                for (int32_t i = T.elem_ptr[p]; i < T.elem_ptr[p + 1]; ++i) {
+                    const int32_t* st = &T.stencil[(int64_t)T.perm[i] * T.ns];
+                    int k = 0;
+                    for (int a = 0; a < T.ns; ++a) {
+                        L.lvert[t][(size_t)a * T.n + i] =
+                            (uint16_t)(std::lower_bound(verts.begin(), verts.end(), st[a]) - verts.begin());
+                        for (int b = a; b < T.ns; ++b, ++k) {
+                            const int64_t r = std::min(st[a], st[b]), c = std::max(st[a], st[b]);
+                            const uint32_t idx =
+                                (uint32_t)(std::lower_bound(keys.begin(), keys.end(), r * nv + c) - keys.begin());
+                            uint32_t flag = 0;
+                            if (a != b && st[a] == st[b]) flag = 2u;
+                            else if (st[a] > st[b]) flag = 1u;
+                            L.lslot[t][(size_t)k * T.n + i] = (uint16_t)(idx | (flag << 14));
+                        }
+                    }
+                    (void)npair;
+                }
+            }
+        }
+    };
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int w = 0; w < nth; ++w) {
+        const int32_t p0 = (int32_t)((int64_t)np * w / nth), p1 = (int32_t)((int64_t)np * (w + 1) / nth);
+        th.emplace_back(work, p0, p1);
+    }
+    for (auto& x : th) x.join();
+    if (err.load()) return fail(MAD_E_UNSUPPORTED, "a patch touches more than 16384 blocks; use smaller patches");
+
+    // concatenate, resolve global block indices, count patch occurrences for exclusivity
+    L.lv_ptr.assign((size_t)np + 1, 0);
+    L.lb_ptr.assign((size_t)np + 1, 0);
+    for (int32_t p = 0; p < np; ++p) {
+        L.lv_ptr[p + 1] = L.lv_ptr[p] + (int32_t)pv[p].size();
+        L.lb_ptr[p + 1] = L.lb_ptr[p] + (int32_t)pb_r[p].size();
+    }
+    L.lv_global.resize((size_t)L.lv_ptr[np]);
+    L.lv_excl.resize((size_t)L.lv_ptr[np]);
+    L.lb_gidx.resize((size_t)L.lb_ptr[np]);
+    L.lb_gidxT.resize((size_t)L.lb_ptr[np]);
+    L.lb_excl.resize((size_t)L.lb_ptr[np]);
+    std::vector<int32_t> vcount((size_t)nv, 0), bcount(colidx.size(), 0);
+    for (int32_t p = 0; p < np; ++p) {
+        for (size_t k = 0; k < pv[p].size(); ++k) {
+            L.lv_global[L.lv_ptr[p] + k] = pv[p][k];
+            vcount[pv[p][k]]++;
+        }
+        for (size_t k = 0; k < pb_r[p].size(); ++k) {
+            const int32_t g = find_block(rowptr, colidx, pb_r[p][k], pb_c[p][k]);
+            const int32_t gt = find_block(rowptr, colidx, pb_c[p][k], pb_r[p][k]);
+            if (g < 0 || gt < 0) return fail(MAD_E_HIP, "internal error: patch block missing from the pattern");
+            L.lb_gidx[L.lb_ptr[p] + k] = g;
+            L.lb_gidxT[L.lb_ptr[p] + k] = gt;
+            bcount[g]++;
+        }
+    }
+    for (size_t k = 0; k < L.lv_global.size(); ++k) L.lv_excl[k] = vcount[L.lv_global[k]] == 1;
+    for (size_t k = 0; k < L.lb_gidx.size(); ++k) L.lb_excl[k] = bcount[L.lb_gidx[k]] == 1;
+    L.max_lv = 0;
+    L.max_lb = 0;
+    for (int32_t p = 0; p < np; ++p) {
+        L.max_lv = std::max(L.max_lv, L.lv_ptr[p + 1] - L.lv_ptr[p]);
+        L.max_lb = std::max(L.max_lb, L.lb_ptr[p + 1] - L.lb_ptr[p]);
+    }
+    return MAD_OK;
+}
+
+}  // namespace mad

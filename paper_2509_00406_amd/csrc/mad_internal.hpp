@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mad.h"
+#include "mad.h"
 
 struct mad_mesh {
     int64_t nv = 0, nt = 0;
@@ -41,7 +41,20 @@ struct Term {
     int32_t* d_stencil = nullptr;        // [n][ns]
     double* d_rest = nullptr;            // SoA [nrest][n]
     int32_t* d_elem_ptr = nullptr;       // [n_patch + 1]
-    int32_t* d_slots = nullptr;          // SoA [ns*ns][n]
+    int32_t* d_slots = nullptr;          // SoA [ns*ns][n] global block of (s, t) (atomic scatter)
+    uint16_t* d_lvert = nullptr;         // SoA [ns][n] patch-local vertex (patch scatter)
+    uint16_t* d_lslot = nullptr;         // SoA [ns(ns+1)/2][n] patch-local block + flags
+};
+
+// patch-local index structures of the LDS-accumulating assembly (host_patch.cpp)
+struct PatchLocal {
+    std::vector<int32_t> lv_ptr, lv_global;          // per patch: touched vertices (sorted)
+    std::vector<uint8_t> lv_excl;                    // vertex touched by this patch only
+    std::vector<int32_t> lb_ptr, lb_gidx, lb_gidxT;  // per patch: upper blocks (r <= c): (r,c), (c,r)
+    std::vector<uint8_t> lb_excl;                    // block touched by this patch only
+    std::vector<std::vector<uint16_t>> lvert;        // per term, SoA [ns][n] local vertex
+    std::vector<std::vector<uint16_t>> lslot;        // per term, SoA [ns(ns+1)/2][n] local block + flags
+    int32_t max_lv = 0, max_lb = 0;
 };
 
 // one contiguous range of patches per component
@@ -68,6 +81,16 @@ struct mad_problem {
     double* d_partial = nullptr;          // [n_terms][n_patch]
     int32_t* d_flags = nullptr;           // [0] nonfinite, [1] internal error
     unsigned long long* d_fallbacks = nullptr;
+    int scatter = MAD_SCATTER_PATCH;
+    int32_t* d_lv_ptr = nullptr;
+    int32_t* d_lv_global = nullptr;
+    uint8_t* d_lv_excl = nullptr;
+    int32_t* d_lb_ptr = nullptr;
+    int32_t* d_lb_gidx = nullptr;
+    int32_t* d_lb_gidxT = nullptr;
+    uint8_t* d_lb_excl = nullptr;
+    size_t lds_bytes = 0;
+    int32_t max_lv = 0, max_lb = 0;
     std::vector<void*> owned;             // every device allocation, freed at destroy
     // profiling: one row of n_terms + 3 events per recorded evaluation
     bool profiling = false;
@@ -95,6 +118,9 @@ int build_topology(mad_mesh& m);
 int rest_tri(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);        // [nt][5]
 int rest_diamond(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);    // [nd][2]
 void build_patches(const mad_mesh& m, int target_faces, Patches& p);
+int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& colidx,
+                      PatchLocal& L);
+size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t max_lb);
 
 // device launchers (kernels_*.hip); all asynchronous on `stream`
 struct EvalLaunch {
@@ -119,6 +145,37 @@ struct EvalLaunch {
     double qmin;
 };
 hipError_t launch_eval(const EvalLaunch& L, hipStream_t s);
+
+// fused patch kernel: every term of a patch in one workgroup, LDS accumulation, one flush
+struct PatchTermArgs {
+    int kind;
+    int64_t n;
+    const double* rest;
+    const uint16_t* lvert;
+    const uint16_t* lslot;
+    const int32_t* elem_ptr;
+    double prm[4];
+};
+struct PatchLaunch {
+    int prec, mode, want_grad, var_dim, n_terms, n_patch;
+    size_t lds_bytes;
+    const double* x;
+    void* grad;
+    void* hess;
+    const int32_t* lv_ptr;
+    const int32_t* lv_global;
+    const uint8_t* lv_excl;
+    const int32_t* lb_ptr;
+    const int32_t* lb_gidx;
+    const int32_t* lb_gidxT;
+    const uint8_t* lb_excl;
+    double* partial;
+    int32_t* flags;
+    unsigned long long* fallbacks;
+    double eps, qmin;
+    PatchTermArgs terms[8];
+};
+hipError_t launch_eval_patch(const PatchLaunch& L, hipStream_t s);
 hipError_t launch_fill(void* ptr, int64_t n_elems, int elem_bytes, hipStream_t s);
 hipError_t launch_energy_reduce(const double* partial, int n_terms, int n_patch, const int32_t* comp_patch_ptr,
                                 int n_comp, bool batched, double* energy, hipStream_t s);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmad.so")
 EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR = 1, 2, 3, 4, 5, 6
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 F64, F32 = 0, 1
-SCATTER_AUTO, SCATTER_ATOMIC = 0, 1
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_PATCH = 0, 1, 2
 
 STATUS = {0: "MAD_OK", -1: "MAD_E_INVALID_ARG", -2: "MAD_E_BAD_MESH", -3: "MAD_E_DEGENERATE_REST",
           -4: "MAD_E_OVERFLOW", -5: "MAD_E_OOM", -6: "MAD_E_HIP", -7: "MAD_E_STATE", -8: "MAD_E_UNSUPPORTED"}
@@ -228,8 +228,9 @@ class Problem:
     """mesh + var_dim + precision -> terms -> finalize -> eval (Sec. 4.2 programming model)."""
 
     def __init__(self, mesh: Mesh, var_dim: int, precision: int = F64, patch_faces: int = 0,
-                 spd_eps: float = 0.0, degenerate_q: float = 0.0):
+                 spd_eps: float = 0.0, degenerate_q: float = 0.0, scatter: int = SCATTER_AUTO):
         o = mad_options_default()
+        o.scatter = scatter
         o.patch_faces = patch_faces
         o.spd_eps = spd_eps
         o.degenerate_q = degenerate_q

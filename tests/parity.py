@@ -29,10 +29,11 @@ def build_oracle(tris, rest, nv, var_dim, terms):
     return P
 
 
-def build_gpu(tris, rest, nv, var_dim, terms, precision, comp_offsets=None, patch_faces=0, spd_eps=0.0):
+def build_gpu(tris, rest, nv, var_dim, terms, precision, comp_offsets=None, patch_faces=0, spd_eps=0.0,
+              scatter=0):
     from paper_2509_00406_amd import mad
     mesh = mad.Mesh(tris, nv, comp_offsets)
-    prob = mad.Problem(mesh, var_dim, precision, patch_faces=patch_faces, spd_eps=spd_eps)
+    prob = mad.Problem(mesh, var_dim, precision, patch_faces=patch_faces, spd_eps=spd_eps, scatter=scatter)
     for kind, prm in terms:
         prob.add_term(kind, prm, rest if kind in mad.NEEDS_REST else None)
     prob.finalize()

@@ -33,9 +33,10 @@ def torch_cuda():
 
 
 def run_case(torch, tris, rest, x, var_dim, terms, precision, mode, patch_faces=0, comp_offsets=None,
-             spd_eps=0.0, check_energy=True):
+             spd_eps=0.0, check_energy=True, scatter=0):
     nv = rest.shape[0]
-    mesh, prob = PR.build_gpu(tris, rest, nv, var_dim, terms, precision, comp_offsets, patch_faces, spd_eps)
+    mesh, prob = PR.build_gpu(tris, rest, nv, var_dim, terms, precision, comp_offsets, patch_faces, spd_eps,
+                              scatter)
     P = PR.build_oracle(tris, rest, nv, var_dim, terms)
     rowptr, colidx = prob.pattern()
     assert np.array_equal(rowptr.cpu().numpy(), P.rowptr), "pattern rowptr differs"
@@ -88,13 +89,15 @@ def test_dirichlet_64_fp64_vs_oracle_and_cot_laplacian(torch_cuda):
 
 
 # ---------------------------------------------------------------- elastic shell: StVK + bending
+@pytest.mark.parametrize("scatter", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("spd", [False, True])
-def test_shell_cylinder_small(torch_cuda, precision, spd):
-    say("shell cylinder n=40", "fp32" if precision else "fp64", "spd" if spd else "raw")
+def test_shell_cylinder_small(torch_cuda, precision, spd, scatter):
+    say("shell cylinder n=40", "fp32" if precision else "fp64", "spd" if spd else "raw", "scatter", scatter)
     inp = meshgen.shell_cylinder(n=40, seed=2001)
     mode = ALL | (8 if spd else 0)
-    out, _, _ = run_case(torch_cuda, inp.tris, inp.rest, inp.x, 3, SHELL, precision, mode, patch_faces=96)
+    out, _, _ = run_case(torch_cuda, inp.tris, inp.rest, inp.x, 3, SHELL, precision, mode, patch_faces=96,
+                         scatter=scatter)
     assert not out["nonfinite"]
     say("worst err/scale", out)
 
@@ -166,13 +169,19 @@ def test_energy_is_deterministic(torch_cuda):
 
 
 # ---------------------------------------------------------------- edge cases
-@pytest.mark.parametrize("name", ["two_tris", "octahedron", "nonmanifold", "grid2", "grid3"])
+@pytest.mark.parametrize("name", ["two_tris", "octahedron", "nonmanifold", "grid2", "grid3", "dup_face"])
 def test_tiny_meshes(torch_cuda, name):
     say("tiny", name)
-    tris, pos = meshgen.tiny_meshes()[name]
+    if name == "dup_face":
+        # a face repeated with the opposite orientation: the shared edge's diamond has v2 == v3
+        tris, pos = meshgen.grid(4)
+        tris = np.concatenate([tris, [[0, 1, 5], [1, 0, 5]]]).astype(np.int32)
+    else:
+        tris, pos = meshgen.tiny_meshes()[name]
     x = pos + 0.1 * np.random.default_rng(1).normal(size=pos.shape)
     for precision in (0, 1):
-        out, _, _ = run_case(torch_cuda, tris, pos, x, 3, SHELL, precision, ALL | 8)
+        for scatter in (1, 2):
+            out, _, _ = run_case(torch_cuda, tris, pos, x, 3, SHELL, precision, ALL | 8, scatter=scatter)
 
 
 def test_isolated_vertex_gets_zero_diagonal(torch_cuda):
@@ -191,8 +200,8 @@ def test_single_patch_and_many_patches_agree(torch_cuda):
     torch = torch_cuda
     inp = meshgen.shell_cylinder(n=30, seed=9)
     res = []
-    for pf in (8, 64, 100000):
-        mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, SHELL, 0, patch_faces=pf)
+    for pf, sc in ((8, 2), (64, 2), (100000, 2), (64, 1)):
+        mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, SHELL, 0, patch_faces=pf, scatter=sc)
         e, g, h = prob.eval(torch.from_numpy(inp.x.ravel().copy()).cuda(), ALL | 8)
         res.append((e.cpu().numpy()[0], g.cpu().numpy(), h.cpu().numpy()))
     for e, g, h in res[1:]:
