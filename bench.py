@@ -178,7 +178,8 @@ def main():
         "hbm": {"alg_bytes_per_step": step_bytes, "alg_GBs": step_bytes / (ms_per_step * 1e-3) / 1e9,
                 "frac_of_8TBs": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "stages_ms_per_step": {"fill": stage_ms[0] / n_evals,
-                               **({"fused": term_ms[0] / n_evals} if args.scatter == "patch" else
+                               **({"fused": term_ms[0] / n_evals, "gather_and_fp64_redo": term_ms[1] / n_evals}
+                                  if args.scatter == "patch" else
                                   {["stvk", "bending"][i]: term_ms[i] / n_evals for i in range(len(terms))}),
                                "energy": stage_ms[-1] / n_evals},
         "setup_s": setup_s,

@@ -93,9 +93,10 @@ typedef enum mad_scatter {
     MAD_SCATTER_ATOMIC = 1,  /* one kernel per term; every element adds its gradient and Hessian
                                 entries with device-wide atomics into pre-zeroed outputs (Sec. 5.5) */
     MAD_SCATTER_PATCH = 2    /* one fused kernel over all terms, one workgroup per patch: x staged
-                                in LDS, element contributions summed in LDS, each touched entry then
-                                written once (plain store if no other patch touches it, else one
-                                device-wide atomic add) */
+                                in LDS, element contributions summed in LDS, then every entry written
+                                once: by its patch if no other patch touches it, else by a gather
+                                kernel summing the patches' partials in a fixed order. No global
+                                atomics and no zero fill of the outputs. */
 } mad_scatter;
 
 typedef struct mad_options {
@@ -180,9 +181,12 @@ int32_t mad_problem_status(mad_problem *prob, int32_t *nonfinite, int64_t *fp64_
 int32_t mad_problem_set_profiling(mad_problem *prob, int32_t enable);
 
 /* Synchronise with the recorded events and report, summed over the evaluations recorded since
- * profiling was enabled: ms_out[0] zero fill, ms_out[1 + t] the kernel of term t (in add order),
- * ms_out[1 + n_terms] the energy reduction. *n_stages = n_terms + 2, *n_evals = evaluations.
- * ms_out must hold at least 10 doubles. Records are kept (call set_profiling(1) to clear). */
+ * profiling was enabled, with S = max(n_terms, 2): ms_out[0] zero fills; with MAD_SCATTER_ATOMIC
+ * ms_out[1 + t] the kernel of term t (in add order); with MAD_SCATTER_PATCH ms_out[1] the fused
+ * kernel and ms_out[2] the gather of shared entries plus the FP64 redo of queued FP32 elements;
+ * ms_out[1 + S] the energy
+ * reduction. *n_stages = S + 2, *n_evals = evaluations. ms_out must hold at least 10 doubles.
+ * Records are kept (call set_profiling(1) to clear). */
 int32_t mad_problem_profile(mad_problem *prob, double *ms_out, int32_t *n_stages, int64_t *n_evals);
 
 int32_t mad_problem_destroy(mad_problem *prob);

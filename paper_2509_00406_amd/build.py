@@ -16,7 +16,8 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libmad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "host_patch.cpp", "api.cpp"]
+SOURCES = ["kernels_patch.hip", "kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "host_patch.cpp",
+           "api.cpp"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 (v_pk_*_f32) instructions.
 # -munsafe-fp-atomics: hardware FP32/FP64 atomic add instead of compare-and-swap loops.
@@ -25,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-at
           "-Wall", "-Wno-unused-function", "-pthread", "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 6) -> str:
     os.makedirs(BUILD, exist_ok=True)
     t0 = time.time()
     procs = []

@@ -331,15 +331,50 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
         p->lds_bytes = patch_lds_bytes(p->d, p->prec, 3, L.max_lv, L.max_lb);
         if ((rc = upload(p, (void**)&p->d_lv_ptr, L.lv_ptr.data(), L.lv_ptr.size() * 4, s)) != MAD_OK) return rc;
         if ((rc = upload(p, (void**)&p->d_lv_global, L.lv_global.data(), L.lv_global.size() * 4, s)) != MAD_OK) return rc;
-        if ((rc = upload(p, (void**)&p->d_lv_excl, L.lv_excl.data(), L.lv_excl.size(), s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_lv_halo, L.lv_halo.data(), L.lv_halo.size() * 4, s)) != MAD_OK) return rc;
         if ((rc = upload(p, (void**)&p->d_lb_ptr, L.lb_ptr.data(), L.lb_ptr.size() * 4, s)) != MAD_OK) return rc;
         if ((rc = upload(p, (void**)&p->d_lb_gidx, L.lb_gidx.data(), L.lb_gidx.size() * 4, s)) != MAD_OK) return rc;
         if ((rc = upload(p, (void**)&p->d_lb_gidxT, L.lb_gidxT.data(), L.lb_gidxT.size() * 4, s)) != MAD_OK) return rc;
-        if ((rc = upload(p, (void**)&p->d_lb_excl, L.lb_excl.data(), L.lb_excl.size(), s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_lb_halo, L.lb_halo.data(), L.lb_halo.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_gv_ptr, L.gv_ptr.data(), L.gv_ptr.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_gv_src, L.gv_src.data(), L.gv_src.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_gv_vert, L.gv_vert.data(), L.gv_vert.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_gb_ptr, L.gb_ptr.data(), L.gb_ptr.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_gb_src, L.gb_src.data(), L.gb_src.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_gb_gidx, L.gb_gidx.data(), L.gb_gidx.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_gb_gidxT, L.gb_gidxT.data(), L.gb_gidxT.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload(p, (void**)&p->d_orphan_vert, L.orphan_vert.data(), L.orphan_vert.size() * 4, s)) != MAD_OK)
+            return rc;
+        if ((rc = upload(p, (void**)&p->d_orphan_block, L.orphan_block.data(), L.orphan_block.size() * 4, s)) != MAD_OK)
+            return rc;
+        p->n_gv = (int32_t)L.gv_vert.size();
+        p->n_gb = (int32_t)L.gb_gidx.size();
+        p->n_orphan_vert = (int32_t)L.orphan_vert.size();
+        p->n_orphan_block = (int32_t)L.orphan_block.size();
+        const size_t eb = p->prec == MAD_F32 ? 4 : 8;
+        const size_t nhv = L.gv_src.size(), nhb = L.gb_src.size();
+        MAD_HIP_TRY(hipMalloc(&p->d_halo_g, std::max<size_t>(16, nhv * p->d * eb)));
+        p->owned.push_back(p->d_halo_g);
+        MAD_HIP_TRY(hipMalloc(&p->d_halo_h, std::max<size_t>(16, nhb * p->d * p->d * eb)));
+        p->owned.push_back(p->d_halo_h);
         for (size_t ti = 0; ti < p->terms.size(); ++ti) {
             auto& t = p->terms[ti];
             if ((rc = upload(p, (void**)&t.d_lvert, L.lvert[ti].data(), L.lvert[ti].size() * 2, s)) != MAD_OK) return rc;
             if ((rc = upload(p, (void**)&t.d_lslot, L.lslot[ti].data(), L.lslot[ti].size() * 2, s)) != MAD_OK) return rc;
+        }
+        if (p->prec == MAD_F32) {
+            // queue for FP32 elements redone in FP64: room for every element
+            int64_t total = 0;
+            for (auto& t : p->terms) {
+                if (t.n >= (1ll << 29)) return fail(MAD_E_OVERFLOW, "more than 2^29 elements in one term");
+                total += t.n;
+            }
+            if (total >= INT32_MAX) return fail(MAD_E_OVERFLOW, "more than 2^31 elements");
+            p->fb_cap = (int32_t)std::max<int64_t>(total, 1);
+            MAD_HIP_TRY(hipMalloc((void**)&p->d_fb_list, sizeof(uint32_t) * (size_t)p->fb_cap));
+            p->owned.push_back(p->d_fb_list);
+            MAD_HIP_TRY(hipMalloc((void**)&p->d_fb_count, sizeof(int32_t) * 4));
+            p->owned.push_back(p->d_fb_count);
         }
     }
     int32_t hflags[4];
@@ -396,7 +431,7 @@ int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double*
     const int eb = p->prec == MAD_F32 ? 4 : 8;
     std::vector<hipEvent_t>* ev = nullptr;
     if (p->profiling) {
-        const size_t need = p->terms.size() + 3;
+        const size_t need = std::max<size_t>(p->terms.size(), 2) + 3;
         if ((size_t)p->prof_count >= p->prof_events.size()) {
             std::vector<hipEvent_t> row(need, nullptr);
             for (auto& e : row) MAD_HIP_TRY(hipEventCreate(&e));
@@ -405,8 +440,13 @@ int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double*
         ev = &p->prof_events[(size_t)p->prof_count++];
         MAD_HIP_TRY(hipEventRecord((*ev)[0], s));
     }
-    if (mode & MAD_GRAD) MAD_HIP_TRY(launch_fill(grad, m.nv * d, eb, s));
-    if (mode & MAD_HESS) MAD_HIP_TRY(launch_fill(hess, p->nnzb * d * d, eb, s));
+    const bool fallback_pass = p->scatter == MAD_SCATTER_PATCH && p->prec == MAD_F32 && (mode & MAD_SPD);
+    // the atomic scatter adds into zeroed outputs; the patch scatter writes every entry exactly once
+    if (p->scatter == MAD_SCATTER_ATOMIC) {
+        if (mode & MAD_GRAD) MAD_HIP_TRY(launch_fill(grad, m.nv * d, eb, s));
+        if (mode & MAD_HESS) MAD_HIP_TRY(launch_fill(hess, p->nnzb * d * d, eb, s));
+    }
+    if (fallback_pass) MAD_HIP_TRY(launch_fill(p->d_fb_count, 1, 4, s));
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[1], s));
     const int kmode = (mode & MAD_HESS) ? ((mode & MAD_SPD) ? 3 : 2) : ((mode & MAD_GRAD) ? 1 : 0);
     const int np = p->patches.n;
@@ -425,14 +465,19 @@ int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double*
         L.hess = hess;
         L.lv_ptr = p->d_lv_ptr;
         L.lv_global = p->d_lv_global;
-        L.lv_excl = p->d_lv_excl;
+        L.lv_halo = p->d_lv_halo;
         L.lb_ptr = p->d_lb_ptr;
         L.lb_gidx = p->d_lb_gidx;
         L.lb_gidxT = p->d_lb_gidxT;
-        L.lb_excl = p->d_lb_excl;
+        L.lb_halo = p->d_lb_halo;
+        L.halo_g = p->d_halo_g;
+        L.halo_h = p->d_halo_h;
         L.partial = p->d_partial;
         L.flags = p->d_flags;
         L.fallbacks = p->d_fallbacks;
+        L.fb_list = p->d_fb_list;
+        L.fb_count = p->d_fb_count;
+        L.fb_cap = p->fb_cap;
         L.eps = p->opt.spd_eps;
         L.qmin = p->opt.degenerate_q;
         for (size_t ti = 0; ti < p->terms.size(); ++ti) {
@@ -447,8 +492,56 @@ int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double*
             std::memcpy(A.prm, t.prm, sizeof(A.prm));
         }
         MAD_HIP_TRY(launch_eval_patch(L, s));
+        if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2], s));
+        GatherLaunch G{};
+        G.prec = p->prec;
+        G.var_dim = d;
+        G.want_grad = (mode & MAD_GRAD) ? 1 : 0;
+        G.want_hess = (mode & MAD_HESS) ? 1 : 0;
+        G.grad = grad;
+        G.hess = hess;
+        G.halo_g = p->d_halo_g;
+        G.halo_h = p->d_halo_h;
+        G.gv_ptr = p->d_gv_ptr;
+        G.gv_src = p->d_gv_src;
+        G.gv_vert = p->d_gv_vert;
+        G.gb_ptr = p->d_gb_ptr;
+        G.gb_src = p->d_gb_src;
+        G.gb_gidx = p->d_gb_gidx;
+        G.gb_gidxT = p->d_gb_gidxT;
+        G.orphan_vert = p->d_orphan_vert;
+        G.orphan_block = p->d_orphan_block;
+        G.n_gv = p->n_gv;
+        G.n_gb = p->n_gb;
+        G.n_orphan_vert = p->n_orphan_vert;
+        G.n_orphan_block = p->n_orphan_block;
+        MAD_HIP_TRY(launch_gather(G, s));
+        if (fallback_pass) {
+            FallbackLaunch F{};
+            F.var_dim = d;
+            F.want_grad = L.want_grad;
+            F.x = x;
+            F.grad = grad;
+            F.hess = hess;
+            F.rowptr = p->d_rowptr;
+            F.colidx = p->d_colidx;
+            F.fb_list = p->d_fb_list;
+            F.fb_count = p->d_fb_count;
+            F.fb_cap = p->fb_cap;
+            F.flags = p->d_flags;
+            F.eps = p->opt.spd_eps;
+            for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+                const Term& t = p->terms[ti];
+                F.terms[ti].kind = t.kind;
+                F.terms[ti].n = t.n;
+                F.terms[ti].stencil = t.d_stencil;
+                F.terms[ti].rest = t.d_rest;
+                std::memcpy(F.terms[ti].prm, t.prm, sizeof(t.prm));
+            }
+            MAD_HIP_TRY(launch_fallback(F, s));
+        }
         if (ev)
-            for (size_t ti = 0; ti < p->terms.size(); ++ti) MAD_HIP_TRY(hipEventRecord((*ev)[2 + ti], s));
+            for (size_t k = 3; k < ev->size() - 1; ++k) MAD_HIP_TRY(hipEventRecord((*ev)[k], s));
         n_partial_terms = 1;
     }
     for (size_t ti = 0; p->scatter == MAD_SCATTER_ATOMIC && ti < p->terms.size(); ++ti) {
@@ -481,7 +574,7 @@ int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double*
         MAD_HIP_TRY(launch_energy_reduce(p->d_partial, n_partial_terms, np, p->d_comp_patch_ptr,
                                          std::max(ncomp, 1), m.batched, energy, s));
     }
-    if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2 + p->terms.size()], s));
+    if (ev) MAD_HIP_TRY(hipEventRecord(ev->back(), s));
     return MAD_OK;
 }
 
@@ -494,7 +587,7 @@ int32_t mad_problem_set_profiling(mad_problem* p, int32_t enable) {
 
 int32_t mad_problem_profile(mad_problem* p, double* ms, int32_t* n_stages, int64_t* n_evals) {
     if (!p || !ms) return fail(MAD_E_INVALID_ARG, "NULL argument");
-    const int ns = (int)p->terms.size() + 2;
+    const int ns = (int)std::max<size_t>(p->terms.size(), 2) + 2;
     for (int i = 0; i < 10; ++i) ms[i] = 0.0;
     for (int64_t k = 0; k < p->prof_count; ++k) {
         auto& row = p->prof_events[(size_t)k];

@@ -31,23 +31,91 @@ __device__ __forceinline__ constexpr double helmert(int s, int i) {
 // W = D_NS Q: W[s][i] = Q[s+1][i] - Q[0][i]
 __device__ __forceinline__ constexpr double wmat(int s, int i) { return helmert(s + 1, i) - helmert(0, i); }
 
+// Result of one element: energy, the stencil gradient, and the Hessian kept in reduced form
+// (KR x KR packed): for MODE 2 the raw Hessian in relative coordinates, for MODE 3 the clamped
+// Hessian in Helmert coordinates. hfull() expands any stencil entry on demand.
 template <class Term, typename T>
 struct ElemOut {
     static constexpr int NF = Term::NS * Term::D;
     double f;
     T g[NF];
-    T h[Packed<NF>::N];
+    T hr[Packed<Term::KR>::N];
 };
 
-// ---- symmetric eigen-decomposition: cyclic Jacobi on a packed upper triangle ------------------
-// On return A's diagonal holds the eigenvalues and V's columns the eigenvectors. Returns whether
-// the off-diagonal mass fell below tol relative to the Frobenius norm within max_sweeps.
+// entry (i, j) of the stencil Hessian (i, j in 0..NS*D-1) from the reduced form; te = clamp floor
+template <class Term, int MODE, typename T>
+__device__ __forceinline__ T hfull(const ElemOut<Term, T>& o, int i, int j, T te) {
+    constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
+    const int si = i / D, ci = i % D, sj = j / D, cj = j % D;
+    T acc = T(0);
+    if constexpr (MODE == 2) {
+        // H_x = (D_NS (x) I)^T H_r (D_NS (x) I)
+#pragma unroll
+        for (int a = 1; a < NS; ++a) {
+            if (si != 0 && a != si) continue;
+#pragma unroll
+            for (int b = 1; b < NS; ++b) {
+                if (sj != 0 && b != sj) continue;
+                const T hv = o.hr[Packed<KR>::at((a - 1) * D + ci, (b - 1) * D + cj)];
+                acc += ((si == 0) != (sj == 0)) ? -hv : hv;
+            }
+        }
+    } else {
+        // clamp(H_x) = (Q (x) I) clamp(Hq) (Q (x) I)^T + max(0, eps) T
+#pragma unroll
+        for (int a = 0; a < NS - 1; ++a) {
+            const double qa = helmert(si, a);
+            if (qa == 0.0) continue;
+#pragma unroll
+            for (int b = 0; b < NS - 1; ++b) {
+                const double qb = helmert(sj, b);
+                if (qb == 0.0) continue;
+                acc += T(qa * qb) * o.hr[Packed<KR>::at(a * D + ci, b * D + cj)];
+            }
+        }
+        if (ci == cj) acc += te * T(1.0 / NS);
+    }
+    return acc;
+}
+
+// hardware reciprocal / square root / reciprocal square root: approximate (about 1 ulp) in FP32,
+// IEEE in FP64
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
+
+// ---- symmetric eigen-decomposition: Jacobi rotations in round-robin order --------------------
+// A sweep visits every pair (p, q) once, grouped into rounds of disjoint pairs (circle method
+// over M = N rounded up to even players; pairs with the padding player are skipped). Rotations
+// in one round touch disjoint (p, q) planes, so their parameters depend only on entries no other
+// rotation of the round changes: they are computed together, giving independent instruction
+// streams. The rotation zeroing a_pq uses t = tan(phi) = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)),
+// d = a_qq - a_pp (the smaller root of t^2 + 2 t d / (2 a_pq) - 1 = 0), c = 1/sqrt(1 + t^2),
+// s = t c, and A <- J^T A J, V <- V J with J_pp = J_qq = c, J_pq = s, J_qp = -s.
+// On return A's diagonal holds the eigenvalues and V's columns the eigenvectors. The matrix is
+// scaled to max |a_ij| = 1 first (and the eigenvalues scaled back) so squares cannot overflow.
+// Returns whether the off-diagonal mass fell below tol of the Frobenius norm within max_sweeps.
+__host__ __device__ constexpr int rr_players(int n) { return n + (n & 1); }
+// pair k of round r of the circle method over M players: one of the two members
+__host__ __device__ constexpr int rr_a(int M, int r, int k) { return k == 0 ? M - 1 : (r + k) % (M - 1); }
+__host__ __device__ constexpr int rr_b(int M, int r, int k) { return k == 0 ? r : (r - k + (M - 1)) % (M - 1); }
+
 template <int N, typename T>
 __device__ __forceinline__ bool jacobi_eig(T (&A)[Packed<N>::N], T (&V)[N][N], int max_sweeps, T tol) {
+    constexpr int M = rr_players(N), H = M / 2;
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
         for (int j = 0; j < N; ++j) V[i][j] = (i == j) ? T(1) : T(0);
+    T amax = T(0);
+#pragma unroll
+    for (int i = 0; i < Packed<N>::N; ++i) amax = fmax(amax, fabs(A[i]));
+    const T scale = amax > T(0) ? frcp(amax) : T(1);
+#pragma unroll
+    for (int i = 0; i < Packed<N>::N; ++i) A[i] *= scale;
     bool conv = false;
     for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
         T off = T(0), dg = T(0);
@@ -63,37 +131,53 @@ __device__ __forceinline__ bool jacobi_eig(T (&A)[Packed<N>::N], T (&V)[N][N], i
         }
         if (sweep == max_sweeps) break;
 #pragma unroll
-        for (int p = 0; p < N - 1; ++p)
+        for (int r = 0; r < M - 1; ++r) {
+            T cs[H], sn[H], tn[H];
+            // parameters of the round's rotations (independent of each other)
 #pragma unroll
-            for (int q = p + 1; q < N; ++q) {
+            for (int k = 0; k < H; ++k) {
+                const int a = rr_a(M, r, k), b = rr_b(M, r, k);
+                if (a >= N || b >= N) continue;
+                const int p = a < b ? a : b, q = a < b ? b : a;
                 const T apq = A[Packed<N>::at(p, q)];
-                const T app = A[Packed<N>::at(p, p)];
-                const T aqq = A[Packed<N>::at(q, q)];
-                const T theta = (aqq - app) / (T(2) * apq);
-                T t = T(1) / (fabs(theta) + sqrt(theta * theta + T(1)));
-                t = theta < T(0) ? -t : t;
+                const T d = A[Packed<N>::at(q, q)] - A[Packed<N>::at(p, p)];
+                const T den = fabs(d) + fsqrt(d * d + T(4) * apq * apq);
+                T t = (T(2) * apq) * frcp(den);
+                t = d < T(0) ? -t : t;
                 t = (apq == T(0)) ? T(0) : t;
-                const T c = T(1) / sqrt(t * t + T(1));
-                const T s = t * c;
-                const T tau = s / (T(1) + c);
-                A[Packed<N>::at(p, p)] = app - t * apq;
-                A[Packed<N>::at(q, q)] = aqq + t * apq;
+                const T c = frsq(t * t + T(1));
+                cs[k] = c;
+                sn[k] = t * c;
+                tn[k] = t;
+            }
+#pragma unroll
+            for (int k = 0; k < H; ++k) {
+                const int a = rr_a(M, r, k), b = rr_b(M, r, k);
+                if (a >= N || b >= N) continue;
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                const T c = cs[k], s = sn[k], t = tn[k];
+                const T apq = A[Packed<N>::at(p, q)];
+                A[Packed<N>::at(p, p)] -= t * apq;
+                A[Packed<N>::at(q, q)] += t * apq;
                 A[Packed<N>::at(p, q)] = T(0);
 #pragma unroll
-                for (int r = 0; r < N; ++r) {
-                    if (r == p || r == q) continue;
-                    const T g = A[Packed<N>::at(r, p)], h = A[Packed<N>::at(r, q)];
-                    A[Packed<N>::at(r, p)] = g - s * (h + g * tau);
-                    A[Packed<N>::at(r, q)] = h + s * (g - h * tau);
+                for (int i = 0; i < N; ++i) {
+                    if (i == p || i == q) continue;
+                    const T g = A[Packed<N>::at(i, p)], h = A[Packed<N>::at(i, q)];
+                    A[Packed<N>::at(i, p)] = c * g - s * h;
+                    A[Packed<N>::at(i, q)] = s * g + c * h;
                 }
 #pragma unroll
-                for (int r = 0; r < N; ++r) {
-                    const T g = V[r][p], h = V[r][q];
-                    V[r][p] = g - s * (h + g * tau);
-                    V[r][q] = h + s * (g - h * tau);
+                for (int i = 0; i < N; ++i) {
+                    const T g = V[i][p], h = V[i][q];
+                    V[i][p] = c * g - s * h;
+                    V[i][q] = s * g + c * h;
                 }
             }
+        }
     }
+#pragma unroll
+    for (int i = 0; i < N; ++i) A[Packed<N>::at(i, i)] *= amax > T(0) ? amax : T(1);
     return conv;
 }
 
@@ -112,7 +196,7 @@ template <> struct JacobiTol<double> {
 template <class Term, typename T, int MODE>
 __device__ __forceinline__ bool element_eval(const double* xs, const double* rest, const double* prm, double eps,
                                              ElemOut<Term, T>& out) {
-    constexpr int NS = Term::NS, D = Term::D, KR = Term::KR, NF = NS * D;
+    constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
     double r[KR];
 #pragma unroll
     for (int s = 1; s < NS; ++s)
@@ -158,26 +242,8 @@ __device__ __forceinline__ bool element_eval(const double* xs, const double* res
             out.g[c] = g0;
         }
         if constexpr (MODE == 2) {
-            // H_x = (D_NS (x) I)^T H_r (D_NS (x) I), entry by entry
 #pragma unroll
-            for (int i = 0; i < NF; ++i)
-#pragma unroll
-                for (int j = i; j < NF; ++j) {
-                    const int si = i / D, ci = i % D, sj = j / D, cj = j % D;
-                    T acc = T(0);
-#pragma unroll
-                    for (int a = 1; a < NS; ++a) {
-                        if (si != 0 && a != si) continue;
-#pragma unroll
-                        for (int b = 1; b < NS; ++b) {
-                            if (sj != 0 && b != sj) continue;
-                            const T hv = f.h[Packed<KR>::at((a - 1) * D + ci, (b - 1) * D + cj)];
-                            const bool neg = (si == 0) != (sj == 0);
-                            acc += neg ? -hv : hv;
-                        }
-                    }
-                    out.h[Packed<NF>::at(i, j)] = acc;
-                }
+            for (int i = 0; i < Packed<KR>::N; ++i) out.hr[i] = f.h[i];
             return true;
         } else {
             // Hq = (W (x) I)^T H_r (W (x) I)
@@ -204,33 +270,18 @@ __device__ __forceinline__ bool element_eval(const double* xs, const double* res
             T V[KR][KR];
             const bool conv = jacobi_eig<KR, T>(A, V, JacobiTol<T>::sweeps, JacobiTol<T>::tol);
             const T te = T(eps > 0.0 ? eps : 0.0);
+            // clamp(Hq) = V diag(max(lambda, eps)) V^T, packed
 #pragma unroll
-            for (int i = 0; i < NF; ++i)
-#pragma unroll
-                for (int j = i; j < NF; ++j) out.h[Packed<NF>::at(i, j)] = ((i % D) == (j % D)) ? te / T(NS) : T(0);
+            for (int i = 0; i < Packed<KR>::N; ++i) out.hr[i] = T(0);
 #pragma unroll
             for (int m = 0; m < KR; ++m) {
                 const T lam = A[Packed<KR>::at(m, m)];
                 const T lp = lam > te ? lam : te;
-                T u[NF];
 #pragma unroll
-                for (int s = 0; s < NS; ++s)
+                for (int i = 0; i < KR; ++i) {
+                    const T li = lp * V[i][m];
 #pragma unroll
-                    for (int c = 0; c < D; ++c) {
-                        T acc = T(0);
-#pragma unroll
-                        for (int i = 0; i < NS - 1; ++i) {
-                            const double q = helmert(s, i);
-                            if (q == 0.0) continue;
-                            acc += T(q) * V[i * D + c][m];
-                        }
-                        u[s * D + c] = acc;
-                    }
-#pragma unroll
-                for (int i = 0; i < NF; ++i) {
-                    const T li = lp * u[i];
-#pragma unroll
-                    for (int j = i; j < NF; ++j) out.h[Packed<NF>::at(i, j)] += li * u[j];
+                    for (int j = i; j < KR; ++j) out.hr[Packed<KR>::at(i, j)] += li * V[j][m];
                 }
             }
             return conv;

@@ -5,7 +5,8 @@
 // and the sorted list of upper-triangle blocks (r <= c) its elements add to
 // (the workgroup accumulates them in LDS and writes each once). An entry is
 // "exclusive" when no other patch touches it: it is written with a plain
-// store; shared entries are flushed with a global atomic add.
+// store; a shared entry is written to a halo slot of its own and summed
+// afterwards, in a fixed order, by a gather kernel.
 //
 // Per element, the stencil becomes patch-local vertex indices (u16) and, for
 // each unordered stencil pair s <= t, a local block index (low 14 bits) with
@@ -13,6 +14,7 @@
 // stored (min, max) block; bit 15 = s != t name the same vertex (a degenerate
 // stencil), so both (s, t) and (t, s) add into that diagonal block.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <thread>
 
@@ -117,10 +119,10 @@ int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const 
         L.lb_ptr[p + 1] = L.lb_ptr[p] + (int32_t)pb_r[p].size();
     }
     L.lv_global.resize((size_t)L.lv_ptr[np]);
-    L.lv_excl.resize((size_t)L.lv_ptr[np]);
+    L.lv_halo.resize((size_t)L.lv_ptr[np]);
     L.lb_gidx.resize((size_t)L.lb_ptr[np]);
     L.lb_gidxT.resize((size_t)L.lb_ptr[np]);
-    L.lb_excl.resize((size_t)L.lb_ptr[np]);
+    L.lb_halo.resize((size_t)L.lb_ptr[np]);
     std::vector<int32_t> vcount((size_t)nv, 0), bcount(colidx.size(), 0);
     for (int32_t p = 0; p < np; ++p) {
         for (size_t k = 0; k < pv[p].size(); ++k) {
@@ -136,8 +138,46 @@ int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const 
             bcount[g]++;
         }
     }
-    for (size_t k = 0; k < L.lv_global.size(); ++k) L.lv_excl[k] = vcount[L.lv_global[k]] == 1;
-    for (size_t k = 0; k < L.lb_gidx.size(); ++k) L.lb_excl[k] = bcount[L.lb_gidx[k]] == 1;
+    // halo slots, assigned patch by patch (each patch writes its shared partials contiguously)
+    int32_t nhv = 0, nhb = 0;
+    for (size_t k = 0; k < L.lv_global.size(); ++k) L.lv_halo[k] = vcount[L.lv_global[k]] == 1 ? -1 : nhv++;
+    for (size_t k = 0; k < L.lb_gidx.size(); ++k) L.lb_halo[k] = bcount[L.lb_gidx[k]] == 1 ? -1 : nhb++;
+    // gather lists: for every shared entry its halo slots, in patch order
+    {
+        std::vector<int32_t> first((size_t)nv, -1);
+        std::vector<std::pair<int32_t, int32_t>> vs;   // (vertex, slot)
+        for (size_t k = 0; k < L.lv_global.size(); ++k)
+            if (L.lv_halo[k] >= 0) vs.push_back({L.lv_global[k], L.lv_halo[k]});
+        std::stable_sort(vs.begin(), vs.end(), [](auto& a, auto& b) { return a.first < b.first; });
+        L.gv_ptr.assign(1, 0);
+        for (size_t i = 0; i < vs.size();) {
+            size_t j = i;
+            while (j < vs.size() && vs[j].first == vs[i].first) L.gv_src.push_back(vs[j++].second);
+            L.gv_vert.push_back(vs[i].first);
+            L.gv_ptr.push_back((int32_t)L.gv_src.size());
+            i = j;
+        }
+        std::vector<std::array<int32_t, 3>> bs;         // (block, transposed block, slot)
+        for (size_t k = 0; k < L.lb_gidx.size(); ++k)
+            if (L.lb_halo[k] >= 0) bs.push_back({L.lb_gidx[k], L.lb_gidxT[k], L.lb_halo[k]});
+        std::stable_sort(bs.begin(), bs.end(), [](auto& a, auto& b) { return a[0] < b[0]; });
+        L.gb_ptr.assign(1, 0);
+        for (size_t i = 0; i < bs.size();) {
+            size_t j = i;
+            while (j < bs.size() && bs[j][0] == bs[i][0]) L.gb_src.push_back(bs[j++][2]);
+            L.gb_gidx.push_back(bs[i][0]);
+            L.gb_gidxT.push_back(bs[i][1]);
+            L.gb_ptr.push_back((int32_t)L.gb_src.size());
+            i = j;
+        }
+        for (int64_t v = 0; v < nv; ++v)
+            if (vcount[v] == 0) L.orphan_vert.push_back((int32_t)v);
+        // blocks no patch writes: blocks (r, c) and (c, r) are both written through the upper one
+        std::vector<uint8_t> covered(colidx.size(), 0);
+        for (size_t k = 0; k < L.lb_gidx.size(); ++k) covered[L.lb_gidx[k]] = covered[L.lb_gidxT[k]] = 1;
+        for (size_t b = 0; b < colidx.size(); ++b)
+            if (!covered[b]) L.orphan_block.push_back((int32_t)b);
+    }
     L.max_lv = 0;
     L.max_lb = 0;
     for (int32_t p = 0; p < np; ++p) {

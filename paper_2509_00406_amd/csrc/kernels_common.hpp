@@ -1,0 +1,88 @@
+// Helpers shared by the assembly kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "element.hpp"
+#include "mad_internal.hpp"
+#include "terms.hpp"
+
+namespace mad {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
+
+// triangle quality 4 sqrt(3) A / (l0^2 + l1^2 + l2^2): 1 for equilateral, 0 for degenerate
+__device__ __forceinline__ double tri_quality3(const double* a, const double* b, const double* c) {
+    const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const double e3[3] = {c[0] - b[0], c[1] - b[1], c[2] - b[2]};
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double l2 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2] + e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2] +
+                      e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2];
+    const double area2 = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    return l2 > 0.0 ? 2.0 * 1.7320508075688772 * area2 / l2 : 0.0;
+}
+__device__ __forceinline__ double tri_quality2(const double* a, const double* b, const double* c) {
+    const double e1[2] = {b[0] - a[0], b[1] - a[1]}, e2[2] = {c[0] - a[0], c[1] - a[1]};
+    const double e3[2] = {c[0] - b[0], c[1] - b[1]};
+    const double l2 = e1[0] * e1[0] + e1[1] * e1[1] + e2[0] * e2[0] + e2[1] * e2[1] + e3[0] * e3[0] + e3[1] * e3[1];
+    const double area2 = fabs(e1[0] * e2[1] - e1[1] * e2[0]);
+    return l2 > 0.0 ? 2.0 * 1.7320508075688772 * area2 / l2 : 0.0;
+}
+
+// worst current-triangle quality of an element (diamonds: the worse of its two faces)
+template <class Term> __device__ __forceinline__ double quality(const double* xs) {
+    if constexpr (Term::NS == 3 && Term::D == 3) {
+        return tri_quality3(xs, xs + 3, xs + 6);
+    } else if constexpr (Term::NS == 3 && Term::D == 2) {
+        return tri_quality2(xs, xs + 2, xs + 4);
+    } else if constexpr (Term::NS == 4) {
+        const double q1 = tri_quality3(xs, xs + 3, xs + 6);   // (x0, x1, x2)
+        const double q2 = tri_quality3(xs, xs + 9, xs + 3);   // (x0, x3, x1)
+        return q1 < q2 ? q1 : q2;
+    } else {
+        return 1.0;
+    }
+}
+
+template <class Term, typename T>
+__device__ __forceinline__ bool out_finite(const ElemOut<Term, T>& o, int mode) {
+    constexpr int NF = Term::NS * Term::D;
+    bool ok = finite(o.f);
+    if (mode >= 1) {
+#pragma unroll
+        for (int i = 0; i < NF; ++i) ok = ok && finite(double(o.g[i]));
+    }
+    if (mode >= 2) {
+#pragma unroll
+        for (int i = 0; i < Packed<Term::KR>::N; ++i) ok = ok && finite(double(o.hr[i]));
+    }
+    return ok;
+}
+
+template <class Term, typename T, typename U>
+__device__ __forceinline__ void convert_out(const ElemOut<Term, U>& in, ElemOut<Term, T>& out) {
+    constexpr int NF = Term::NS * Term::D;
+    out.f = in.f;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) out.g[i] = T(in.g[i]);
+#pragma unroll
+    for (int i = 0; i < Packed<Term::KR>::N; ++i) out.hr[i] = T(in.hr[i]);
+}
+
+__device__ __forceinline__ void block_reduce_store(double v, double* red, double* out) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+}  // namespace mad

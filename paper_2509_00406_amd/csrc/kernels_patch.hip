@@ -1,0 +1,377 @@
+// Fused patch assembly: one workgroup per patch evaluates every term's
+// elements of that patch (the term fusion the paper names as future work,
+// Sec. 6 and Sec. 8), with the patch's vertex positions staged in LDS and the
+// element gradients / Hessian blocks summed in LDS (only upper blocks r <= c
+// are kept; the lower block is the transpose). Each entry only this patch
+// touches is then written to HBM once with a plain store; an entry several
+// patches touch is written to a halo slot per patch, and a gather kernel sums
+// those slots in a fixed order and writes the entry once. No global atomics.
+//
+// FP32 elements that are near-degenerate (triangle quality below a threshold)
+// or whose eigen-decomposition did not converge keep their FP64 energy here
+// and are queued; a second, small kernel redoes their derivatives and clamp
+// in FP64 and adds them with atomics.
+#include "kernels_common.hpp"
+
+namespace mad {
+
+__host__ __device__ constexpr size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v) { atomicAdd(p, v); }
+
+
+constexpr uint32_t kFbTermShift = 29;
+constexpr uint32_t kFbElemMask = (1u << kFbTermShift) - 1u;
+
+template <class Term, typename T, int MODE>
+__device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTermArgs& A, int term, int p,
+                                           const double* sx, T* sg, T* sh, double& esum, bool& bad) {
+    constexpr int NS = Term::NS, D = Term::D, NF = NS * D, NR = Term::NREST, DD = D * D;
+    const int beg = A.elem_ptr[p], end = A.elem_ptr[p + 1];
+    const T te = T(L.eps > 0.0 ? L.eps : 0.0);
+    for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) {
+        int lv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) lv[s] = A.lvert[(int64_t)s * A.n + e];
+        double xs[NF];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < D; ++c) xs[s * D + c] = sx[lv[s] * D + c];
+        double rest[NR > 0 ? NR : 1];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) rest[k] = A.rest[(int64_t)k * A.n + e];
+        ElemOut<Term, T> o;
+        if constexpr (MODE == 3 && sizeof(T) == 4) {
+            bool fb = quality<Term>(xs) < L.qmin;
+            if (!fb) fb = !element_eval<Term, T, MODE>(xs, rest, A.prm, L.eps, o);
+            if (fb) {
+                // energy in FP64 here (keeps the reduction deterministic), derivatives queued
+                ElemOut<Term, double> op;
+                element_eval<Term, double, 0>(xs, rest, A.prm, L.eps, op);
+                esum += op.f;
+                bad = bad || !finite(op.f);
+                const int k = atomicAdd(L.fb_count, 1);
+                if (k < L.fb_cap) L.fb_list[k] = ((uint32_t)term << kFbTermShift) | (uint32_t)e;
+                atomicAdd(L.fallbacks, 1ull);
+                continue;
+            }
+        } else {
+            element_eval<Term, T, MODE>(xs, rest, A.prm, L.eps, o);
+        }
+        esum += o.f;
+        bad = bad || !out_finite<Term, T>(o, MODE);
+        if constexpr (MODE >= 1) {
+            if (L.want_grad) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int c = 0; c < D; ++c) lds_add(sg + lv[s] * D + c, o.g[s * D + c]);
+            }
+        }
+        if constexpr (MODE >= 2) {
+            int k = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int t = s; t < NS; ++t, ++k) {
+                    const uint32_t w = A.lslot[(int64_t)k * A.n + e];
+                    T* blk = sh + (int)(w & 0x3fffu) * DD;
+                    const uint32_t flag = w >> 14;
+#pragma unroll
+                    for (int c = 0; c < D; ++c)
+#pragma unroll
+                        for (int c2 = 0; c2 < D; ++c2) {
+                            if (s == t && c2 < c) continue;   // symmetric diagonal block: upper half
+                            const T v = hfull<Term, MODE>(o, s * D + c, t * D + c2, te);
+                            if (s == t) {
+                                lds_add(blk + c * D + c2, v);
+                                if (c2 != c) lds_add(blk + c2 * D + c, v);
+                            } else {
+                                lds_add(blk + ((flag == 1u) ? (c2 * D + c) : (c * D + c2)), v);
+                                if (flag == 2u) lds_add(blk + c2 * D + c, v);   // s, t name one vertex
+                            }
+                        }
+                }
+        }
+    }
+}
+
+template <typename T, int MODE, int D>
+__device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kBlock];
+    constexpr int DD = D * D;
+    const int p = blockIdx.x;
+    const int lv0 = L.lv_ptr[p], nlv = L.lv_ptr[p + 1] - lv0;
+    const int lb0 = L.lb_ptr[p], nlb = L.lb_ptr[p + 1] - lb0;
+    double* sx = reinterpret_cast<double*>(smem);
+    T* sg = reinterpret_cast<T*>(smem + align16((size_t)nlv * D * sizeof(double)));
+    T* sh = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(sg) +
+                                 (MODE >= 1 ? align16((size_t)nlv * D * sizeof(T)) : 0));
+    for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
+        const int v = L.lv_global[lv0 + i / D];
+        sx[i] = L.x[(int64_t)v * D + (i % D)];
+        if constexpr (MODE >= 1) sg[i] = T(0);
+    }
+    if constexpr (MODE >= 2)
+        for (int i = threadIdx.x; i < nlb * DD; i += kBlock) sh[i] = T(0);
+    __syncthreads();
+
+    double esum = 0.0;
+    bool bad = false;
+    for (int t = 0; t < L.n_terms; ++t) {
+        const PatchTermArgs& A = L.terms[t];
+        if constexpr (D == 3) {
+            switch (A.kind) {
+            case K_STVK: patch_term<TermStVK, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
+            case K_BENDING: patch_term<TermBending, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
+            case K_TRI_AREA: patch_term<TermTriArea, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
+            case K_EDGE_SQLEN: patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
+            default: break;
+            }
+        } else if constexpr (D == 2) {
+            if (A.kind == K_SYMDIR) patch_term<TermSymDir, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad);
+        } else {
+            if (A.kind == K_DIRICHLET) patch_term<TermDirichlet, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad);
+        }
+    }
+    if (bad) atomicOr(L.flags, 1);
+    __syncthreads();
+
+    // flush: entries only this patch touches go straight to the output; shared entries go to their
+    // halo slot and are summed by the gather kernel
+    if constexpr (MODE >= 1) {
+        if (L.want_grad) {
+            T* G = static_cast<T*>(L.grad);
+            T* HG = static_cast<T*>(L.halo_g);
+            for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
+                const int k = lv0 + i / D, c = i % D;
+                const int32_t h = L.lv_halo[k];
+                if (h < 0) G[(int64_t)L.lv_global[k] * D + c] = sg[i];
+                else HG[(int64_t)h * D + c] = sg[i];
+            }
+        }
+    }
+    if constexpr (MODE >= 2) {
+        T* H = static_cast<T*>(L.hess);
+        T* HH = static_cast<T*>(L.halo_h);
+        for (int i = threadIdx.x; i < nlb * DD; i += kBlock) {
+            const int b = lb0 + i / DD, k = i % DD;
+            const int32_t h = L.lb_halo[b];
+            const T v = sh[i];
+            if (h >= 0) {
+                HH[(int64_t)h * DD + k] = v;
+            } else {
+                const int32_t g = L.lb_gidx[b], gt = L.lb_gidxT[b];
+                H[(int64_t)g * DD + k] = v;
+                if (gt != g) H[(int64_t)gt * DD + (k % D) * D + k / D] = v;
+            }
+        }
+    }
+    block_reduce_store(esum, red, L.partial + p);
+}
+
+// FP32: the compiler is held to 256 registers so two waves share each SIMD (a few values spill
+// to scratch; the second wave hides the latency of the long dependent rotation chains).
+template <int MODE, int D>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_patch_f32(PatchLaunch L) {
+    eval_patch_body<float, MODE, D>(L);
+}
+template <int MODE, int D>
+__global__ __launch_bounds__(kBlock) void k_eval_patch_f64(PatchLaunch L) {
+    eval_patch_body<double, MODE, D>(L);
+}
+
+// ---- gather of shared entries --------------------------------------------------------------------
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_gather(GatherLaunch G) {
+    constexpr int DD = D * D;
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x, stride = (int64_t)gridDim.x * kBlock;
+    if (G.want_hess) {
+        T* H = static_cast<T*>(G.hess);
+        const T* HH = static_cast<const T*>(G.halo_h);
+        for (int64_t i = tid; i < (int64_t)G.n_gb * DD; i += stride) {
+            const int b = (int)(i / DD), k = (int)(i % DD);
+            T v = T(0);
+            for (int j = G.gb_ptr[b]; j < G.gb_ptr[b + 1]; ++j) v += HH[(int64_t)G.gb_src[j] * DD + k];
+            const int32_t g = G.gb_gidx[b], gt = G.gb_gidxT[b];
+            H[(int64_t)g * DD + k] = v;
+            if (gt != g) H[(int64_t)gt * DD + (k % D) * D + k / D] = v;
+        }
+        for (int64_t i = tid; i < (int64_t)G.n_orphan_block * DD; i += stride)
+            H[(int64_t)G.orphan_block[i / DD] * DD + i % DD] = T(0);
+    }
+    if (G.want_grad) {
+        T* GR = static_cast<T*>(G.grad);
+        const T* HG = static_cast<const T*>(G.halo_g);
+        for (int64_t i = tid; i < (int64_t)G.n_gv * D; i += stride) {
+            const int b = (int)(i / D), c = (int)(i % D);
+            T v = T(0);
+            for (int j = G.gv_ptr[b]; j < G.gv_ptr[b + 1]; ++j) v += HG[(int64_t)G.gv_src[j] * D + c];
+            GR[(int64_t)G.gv_vert[b] * D + c] = v;
+        }
+        for (int64_t i = tid; i < (int64_t)G.n_orphan_vert * D; i += stride)
+            GR[(int64_t)G.orphan_vert[i / D] * D + i % D] = T(0);
+    }
+}
+
+template <typename T>
+static hipError_t launch_gather_t(const GatherLaunch& G, hipStream_t s) {
+    const int64_t work = std::max<int64_t>((int64_t)G.n_gb * G.var_dim * G.var_dim, (int64_t)G.n_gv * G.var_dim);
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + kBlock - 1) / kBlock, 8192));
+    switch (G.var_dim) {
+    case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(blocks), dim3(kBlock), 0, s, G); break;
+    case 2: hipLaunchKernelGGL((k_gather<T, 2>), dim3(blocks), dim3(kBlock), 0, s, G); break;
+    case 3: hipLaunchKernelGGL((k_gather<T, 3>), dim3(blocks), dim3(kBlock), 0, s, G); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherLaunch& G, hipStream_t s) {
+    if (!G.want_grad && !G.want_hess) return hipSuccess;
+    return G.prec == MAD_F32 ? launch_gather_t<float>(G, s) : launch_gather_t<double>(G, s);
+}
+
+// ---- FP64 redo of queued FP32 elements -----------------------------------------------------------
+__device__ __forceinline__ int32_t find_block(const int32_t* rowptr, const int32_t* colidx, int32_t r, int32_t c) {
+    int32_t lo = rowptr[r], hi = rowptr[r + 1] - 1;
+    while (lo <= hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        const int32_t m = colidx[mid];
+        if (m == c) return mid;
+        if (m < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+template <class Term>
+__device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const FallbackTerm& A, int e) {
+    constexpr int NS = Term::NS, D = Term::D, NF = NS * D, NR = Term::NREST, DD = D * D;
+    int vs[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) vs[s] = A.stencil[(int64_t)e * NS + s];
+    double xs[NF];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int c = 0; c < D; ++c) xs[s * D + c] = F.x[(int64_t)vs[s] * D + c];
+    double rest[NR > 0 ? NR : 1];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) rest[k] = A.rest[(int64_t)k * A.n + e];
+    ElemOut<Term, double> o;
+    element_eval<Term, double, 3>(xs, rest, A.prm, F.eps, o);
+    if (!out_finite<Term, double>(o, 3)) atomicOr(F.flags, 1);
+    if (F.want_grad) {
+        float* G = static_cast<float*>(F.grad);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < D; ++c) atomic_add(G + (int64_t)vs[s] * D + c, float(o.g[s * D + c]));
+    }
+    float* H = static_cast<float*>(F.hess);
+    const double te = F.eps > 0.0 ? F.eps : 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            const int32_t b = find_block(F.rowptr, F.colidx, vs[s], vs[t]);
+            if (b < 0) {
+                atomicOr(F.flags + 1, 8);
+                continue;
+            }
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+#pragma unroll
+                for (int c2 = 0; c2 < D; ++c2)
+                    atomic_add(H + (int64_t)b * DD + c * D + c2, float(hfull<Term, 3>(o, s * D + c, t * D + c2, te)));
+        }
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_fallback(FallbackLaunch F) {
+    const int cnt = min(*F.fb_count, F.fb_cap);
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+        const uint32_t w = F.fb_list[i];
+        const int t = (int)(w >> kFbTermShift), e = (int)(w & kFbElemMask);
+        const FallbackTerm& A = F.terms[t];
+        if constexpr (D == 3) {
+            switch (A.kind) {
+            case K_STVK: fallback_elem<TermStVK>(F, A, e); break;
+            case K_BENDING: fallback_elem<TermBending>(F, A, e); break;
+            case K_TRI_AREA: fallback_elem<TermTriArea>(F, A, e); break;
+            case K_EDGE_SQLEN: fallback_elem<TermEdgeSqlen>(F, A, e); break;
+            default: break;
+            }
+        } else if constexpr (D == 2) {
+            if (A.kind == K_SYMDIR) fallback_elem<TermSymDir>(F, A, e);
+        } else {
+            if (A.kind == K_DIRICHLET) fallback_elem<TermDirichlet>(F, A, e);
+        }
+    }
+}
+
+// ---- launchers ----------------------------------------------------------------------------------
+template <typename T, int D>
+static size_t lds_for(int mode, int32_t max_lv, int32_t max_lb) {
+    size_t b = align16((size_t)max_lv * D * sizeof(double));
+    if (mode >= 1) b += align16((size_t)max_lv * D * sizeof(T));
+    if (mode >= 2) b += (size_t)max_lb * D * D * sizeof(T);
+    return b;
+}
+
+size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t max_lb) {
+    const bool f32 = prec == MAD_F32;
+    switch (var_dim) {
+    case 1: return f32 ? lds_for<float, 1>(mode, max_lv, max_lb) : lds_for<double, 1>(mode, max_lv, max_lb);
+    case 2: return f32 ? lds_for<float, 2>(mode, max_lv, max_lb) : lds_for<double, 2>(mode, max_lv, max_lb);
+    default: return f32 ? lds_for<float, 3>(mode, max_lv, max_lb) : lds_for<double, 3>(mode, max_lv, max_lb);
+    }
+}
+
+template <int MODE, int D>
+static void launch_patch_kernel(bool f32, const PatchLaunch& L, hipStream_t s) {
+    dim3 grid(L.n_patch), block(kBlock);
+    if (f32) hipLaunchKernelGGL((k_eval_patch_f32<MODE, D>), grid, block, L.lds_bytes, s, L);
+    else hipLaunchKernelGGL((k_eval_patch_f64<MODE, D>), grid, block, L.lds_bytes, s, L);
+}
+
+template <typename T, int D>
+static hipError_t launch_patch_mode(const PatchLaunch& L, hipStream_t s) {
+    const bool f32 = sizeof(T) == 4;
+    switch (L.mode) {
+    case 0: launch_patch_kernel<0, D>(f32, L, s); break;
+    case 1: launch_patch_kernel<1, D>(f32, L, s); break;
+    case 2: launch_patch_kernel<2, D>(f32, L, s); break;
+    case 3: launch_patch_kernel<3, D>(f32, L, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_patch(const PatchLaunch& L, hipStream_t s) {
+    if (L.n_patch <= 0) return hipSuccess;
+    const bool f32 = L.prec == MAD_F32;
+    switch (L.var_dim) {
+    case 1: return f32 ? launch_patch_mode<float, 1>(L, s) : launch_patch_mode<double, 1>(L, s);
+    case 2: return f32 ? launch_patch_mode<float, 2>(L, s) : launch_patch_mode<double, 2>(L, s);
+    case 3: return f32 ? launch_patch_mode<float, 3>(L, s) : launch_patch_mode<double, 3>(L, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fallback(const FallbackLaunch& F, hipStream_t s) {
+    const dim3 grid(256), block(kBlock);
+    switch (F.var_dim) {
+    case 1: hipLaunchKernelGGL(k_fallback<1>, grid, block, 0, s, F); break;
+    case 2: hipLaunchKernelGGL(k_fallback<2>, grid, block, 0, s, F); break;
+    case 3: hipLaunchKernelGGL(k_fallback<3>, grid, block, 0, s, F); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mad

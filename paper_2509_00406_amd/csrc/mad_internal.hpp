@@ -49,11 +49,15 @@ struct Term {
 // patch-local index structures of the LDS-accumulating assembly (host_patch.cpp)
 struct PatchLocal {
     std::vector<int32_t> lv_ptr, lv_global;          // per patch: touched vertices (sorted)
-    std::vector<uint8_t> lv_excl;                    // vertex touched by this patch only
+    std::vector<int32_t> lv_halo;                    // -1: vertex touched by this patch only; else halo slot
     std::vector<int32_t> lb_ptr, lb_gidx, lb_gidxT;  // per patch: upper blocks (r <= c): (r,c), (c,r)
-    std::vector<uint8_t> lb_excl;                    // block touched by this patch only
+    std::vector<int32_t> lb_halo;                    // -1: block touched by this patch only; else halo slot
     std::vector<std::vector<uint16_t>> lvert;        // per term, SoA [ns][n] local vertex
     std::vector<std::vector<uint16_t>> lslot;        // per term, SoA [ns(ns+1)/2][n] local block + flags
+    // gather of shared entries: per shared vertex / upper block, its halo slots in patch order
+    std::vector<int32_t> gv_ptr, gv_src, gv_vert;
+    std::vector<int32_t> gb_ptr, gb_src, gb_gidx, gb_gidxT;
+    std::vector<int32_t> orphan_vert, orphan_block; // entries no patch touches (isolated vertices)
     int32_t max_lv = 0, max_lb = 0;
 };
 
@@ -84,11 +88,26 @@ struct mad_problem {
     int scatter = MAD_SCATTER_PATCH;
     int32_t* d_lv_ptr = nullptr;
     int32_t* d_lv_global = nullptr;
-    uint8_t* d_lv_excl = nullptr;
+    int32_t* d_lv_halo = nullptr;
     int32_t* d_lb_ptr = nullptr;
     int32_t* d_lb_gidx = nullptr;
     int32_t* d_lb_gidxT = nullptr;
-    uint8_t* d_lb_excl = nullptr;
+    int32_t* d_lb_halo = nullptr;
+    int32_t* d_gv_ptr = nullptr;
+    int32_t* d_gv_src = nullptr;
+    int32_t* d_gv_vert = nullptr;
+    int32_t* d_gb_ptr = nullptr;
+    int32_t* d_gb_src = nullptr;
+    int32_t* d_gb_gidx = nullptr;
+    int32_t* d_gb_gidxT = nullptr;
+    int32_t* d_orphan_vert = nullptr;
+    int32_t* d_orphan_block = nullptr;
+    int32_t n_gv = 0, n_gb = 0, n_orphan_vert = 0, n_orphan_block = 0;
+    void* d_halo_g = nullptr;             // [halo vertex slots][D] partial gradients of shared vertices
+    void* d_halo_h = nullptr;             // [halo block slots][D*D] partial blocks of shared blocks
+    uint32_t* d_fb_list = nullptr;
+    int32_t* d_fb_count = nullptr;
+    int32_t fb_cap = 0;
     size_t lds_bytes = 0;
     int32_t max_lv = 0, max_lb = 0;
     std::vector<void*> owned;             // every device allocation, freed at destroy
@@ -164,18 +183,61 @@ struct PatchLaunch {
     void* hess;
     const int32_t* lv_ptr;
     const int32_t* lv_global;
-    const uint8_t* lv_excl;
+    const int32_t* lv_halo;
     const int32_t* lb_ptr;
     const int32_t* lb_gidx;
     const int32_t* lb_gidxT;
-    const uint8_t* lb_excl;
+    const int32_t* lb_halo;
+    void* halo_g;
+    void* halo_h;
     double* partial;
     int32_t* flags;
     unsigned long long* fallbacks;
+    uint32_t* fb_list;      // queued FP32 elements: term << 29 | element
+    int32_t* fb_count;
+    int32_t fb_cap;
     double eps, qmin;
     PatchTermArgs terms[8];
 };
 hipError_t launch_eval_patch(const PatchLaunch& L, hipStream_t s);
+
+// sum the halo partials of every shared entry in a fixed order and write it once; zero orphans
+struct GatherLaunch {
+    int prec, var_dim, want_grad, want_hess;
+    void* grad;
+    void* hess;
+    const void* halo_g;
+    const void* halo_h;
+    const int32_t *gv_ptr, *gv_src, *gv_vert;
+    const int32_t *gb_ptr, *gb_src, *gb_gidx, *gb_gidxT;
+    const int32_t *orphan_vert, *orphan_block;
+    int32_t n_gv, n_gb, n_orphan_vert, n_orphan_block;
+};
+hipError_t launch_gather(const GatherLaunch& G, hipStream_t s);
+
+// FP64 redo of the queued FP32 elements, added to the FP32 outputs with atomics
+struct FallbackTerm {
+    int kind;
+    int64_t n;
+    const int32_t* stencil;  // [n][ns] global vertices, patch order
+    const double* rest;
+    double prm[4];
+};
+struct FallbackLaunch {
+    int var_dim, want_grad;
+    const double* x;
+    void* grad;
+    void* hess;
+    const int32_t* rowptr;
+    const int32_t* colidx;
+    const uint32_t* fb_list;
+    const int32_t* fb_count;
+    int32_t fb_cap;
+    int32_t* flags;
+    double eps;
+    FallbackTerm terms[8];
+};
+hipError_t launch_fallback(const FallbackLaunch& F, hipStream_t s);
 hipError_t launch_fill(void* ptr, int64_t n_elems, int elem_bytes, hipStream_t s);
 hipError_t launch_energy_reduce(const double* partial, int n_terms, int n_patch, const int32_t* comp_patch_ptr,
                                 int n_comp, bool batched, double* energy, hipStream_t s);
