@@ -1,77 +1,121 @@
 #!/usr/bin/env python3
-"""Benchmark of the hot path: energy + gradient + clamped block-CSR Hessian of
-the elastic-shell objective (StVK membrane per triangle + dihedral bending per
-interior-edge diamond) on a 1024 x 1024-vertex grid rolled into a half
-cylinder with small Gaussian noise (2,093,058 triangles, 3,137,541 diamonds,
-13,606,924 3x3 blocks), FP32 derivative arithmetic, FP64 energy.
+"""Benchmark of the hot path: energy + gradient + SPD-projected block-CSR
+Hessian of the elastic-shell objective (StVK membrane per triangle + dihedral
+bending per interior-edge diamond), FP32 derivative arithmetic, FP64 energy.
+
+Workloads:
+  shell   (default) 1024 x 1024-vertex grid rolled into a half cylinder with
+          N(0, (1e-3 h)^2) noise: 2,093,058 triangles, 3,137,541 diamonds,
+          13,606,924 3x3 blocks.
+  batched 700 geodesic icospheres of lognormal size (one mesh of disjoint
+          components, per-component FP64 energies), layout chosen by the
+          autotuner; also timed as one evaluation per mesh.
 
 One step = one mad_problem_eval(ENERGY | GRAD | HESS | SPD) over the whole
-mesh with inputs resident in HBM (topology, patches and pattern are built
+workload with inputs resident in HBM (topology, patches and pattern are built
 once, outside the timed region). Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--precision f32|f64]
-                  [--n 1024] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps 50] [--warmup 10] [--precision f32|f64]
+                  [--workload shell|batched] [--n 1024] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
-import platform
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 flops per element of the clamped-Hessian element algorithm (counted: see the design doc)
-FLOPS_PER_ELEM = {"stvk": 6.0e3, "bending": 2.6e4}
+# Executed floating-point operations per element of the fused patch kernel on the shell workload
+# (FP32 + FP64 VALU instructions x 64 lanes, FMA = 2), from the rocprofv3 counter pass recorded in
+# profiles/k_eval_patch_shell1024_counters.md. Keyed by precision.
+FLOPS_PER_ELEM = {"f32": None, "f64": None}
 
 # MI355X published peaks used as roofline denominators
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_PEAK_TFLOPS = 157.3
-FP64_VALU_PEAK_TFLOPS = 78.6
+VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+SHELL_TERMS = ((4, (1.0, 1.0)), (5, (1.0, 1.0)))   # StVK (mu, lambda), bending (k_b, h)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--workload", choices=["shell", "batched"], default="shell")
+    ap.add_argument("--n", type=int, default=1024, help="grid side of the shell workload")
+    ap.add_argument("--meshes", type=int, default=700, help="meshes of the batched workload")
     ap.add_argument("--patch-faces", type=int, default=0)
     ap.add_argument("--scatter", choices=["patch", "atomic"], default="patch")
+    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="choose the layout by timing (batched: always)")
+    ap.add_argument("--no-fp64-plain", action="store_true", help="skip the FP64 GPU comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=80, help="grid rows of the oracle timing sample")
+    ap.add_argument("--cpu-elements", type=int, default=300000, help="elements in the oracle timing sample")
+    ap.add_argument("--summarize-counters", metavar="DIR", default=None,
+                    help="summarise a rocprofv3 counter-collection CSV under DIR and exit")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="run only a device-to-device copy of this many bytes (traffic-counter calibration)")
     return ap.parse_args()
 
 
-def alg_bytes(prob_info, precision_bytes):
-    """Algorithmic HBM bytes of one step (read inputs once, write outputs once)."""
-    nv, nt, nd, nnzb = prob_info
+def alg_bytes(nv, nt, nd, nnzb, precision_bytes):
+    """Algorithmic HBM bytes of one step: x, triangles, diamonds, per-element rest data and the
+    pattern read once; gradient, every Hessian value and the energy written once."""
     rd = nv * 3 * 8 + nt * 3 * 4 + nd * 4 * 4 + nt * 5 * 8 + nd * 2 * 8 + (nv + 1) * 4 + nnzb * 4
     wr = nv * 3 * precision_bytes + nnzb * 9 * precision_bytes + 8
     return rd + wr
 
 
-def cpu_baseline(args, terms):
-    """The FP64 oracle timed on a bounded strip of the same workload (first rows of the grid)."""
-    import numpy as np
-    from oracle import oracle as O
+def workload(args):
     from paper_2509_00406_amd import meshgen
-    full = meshgen.shell_cylinder(n=args.n, seed=2001)
-    n = args.n
-    rows = min(args.cpu_rows, n)
-    nv = rows * n
-    sel = np.all(full.tris < nv, axis=1)
-    P = O.Problem(full.tris[sel], full.rest[:nv], nv, 3)
-    for k, prm in terms:
-        P.add_term(k, prm)
+    if args.workload == "shell":
+        inp = meshgen.shell_cylinder(n=args.n, seed=2001)
+        desc = (f"elastic shell StVK+bending, {args.n}x{args.n} grid half cylinder, noise sigma=1e-3 h, "
+                f"SPD-projected Hessians, block-CSR 3x3")
+    else:
+        inp = meshgen.icosphere_batch(n_meshes=args.meshes)
+        desc = (f"batched: {args.meshes} geodesic icospheres (lognormal sizes), StVK+bending, one launch, "
+                f"per-mesh FP64 energies, SPD-projected Hessians, block-CSR 3x3")
+    return inp, desc
+
+
+def cpu_sample(inp, budget):
+    """A bounded piece of the workload for the oracle: leading grid rows of the shell, or the first
+    meshes of the batch, about `budget` elements."""
+    import numpy as np
+    if inp.comp_offsets is None:
+        n = inp.meta["n"]
+        rows = max(2, min(n, int(budget / (5.0 * n))))
+        nv = rows * n
+        what = f"first {rows} of {n} grid rows of the same shell"
+    else:
+        co = inp.comp_offsets
+        k, nv = 0, 0
+        while k < len(co) - 1 and (k == 0 or 5.0 * (co[k + 1] - 0) <= budget):
+            k += 1
+        nv = int(co[k])
+        what = f"first {k} of {len(co) - 1} meshes of the same batch"
+    sel = np.all(inp.tris < nv, axis=1)
+    return inp.tris[sel], inp.rest[:nv], inp.x[:nv], nv, what
+
+
+def cpu_baseline(inp, budget):
+    """The FP64 oracle timed on a bounded sample of the same workload (serial C)."""
+    from oracle import oracle as O
+    tris, rest, x, nv, what = cpu_sample(inp, budget)
+    P = O.Problem(tris, rest, nv, 3)
+    for k, prm in SHELL_TERMS:
+        P.add_term({4: O.STVK, 5: O.BENDING}[k], prm)
     P.build_pattern()
-    n_el = int(sel.sum()) + P.topo.diamonds.shape[0]
+    n_el = int(tris.shape[0]) + int(P.topo.diamonds.shape[0])
     t0 = time.perf_counter()
-    P.eval(full.x[:nv], O.ENERGY | O.GRAD | O.HESS | O.SPD, scales=False)
+    P.eval(x, O.ENERGY | O.GRAD | O.HESS | O.SPD, scales=False)
     dt = time.perf_counter() - t0
     cpu = "unknown"
     try:
@@ -82,77 +126,158 @@ def cpu_baseline(args, terms):
     except OSError:
         pass
     return {"value": n_el / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {rows} of {n} grid rows of the same shell: {n_el} elements "
-                      f"(StVK triangles + bending diamonds), energy+grad+clamped Hessian+assembly, "
-                      f"FP64, serial, {dt:.1f} s on {cpu}; host nproc {os.cpu_count()}"}
+            "sample": f"{what}: {n_el} elements (StVK triangles + bending diamonds), energy + gradient + "
+                      f"SPD-projected Hessian + assembly, FP64, one thread, {dt:.1f} s on {cpu}; "
+                      f"host nproc {os.cpu_count()}"}
+
+
+def summarize_counters(path, n_elements):
+    """Per-dispatch averages of every counter of every kernel in a rocprofv3 counter CSV, plus the
+    FP operation count of the FP32/FP64 VALU counters (each wave instruction counted as 64 lanes,
+    FMA as 2 operations) per element of the shell workload."""
+    import csv
+    import glob
+    from collections import defaultdict
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    out = {}
+    for f in files:
+        agg = defaultdict(lambda: defaultdict(float))
+        disp = defaultdict(set)
+        for r in csv.DictReader(open(f)):
+            agg[r["Kernel_Name"]][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[r["Kernel_Name"]].add(r["Dispatch_Id"])
+        for k, d in agg.items():
+            n = len(disp[k])
+            e = out.setdefault(k, {"dispatches": n})
+            e.update({c: v / n for c, v in d.items()})
+    for k, e in out.items():
+        ops = 0.0
+        for prec in ("F32", "F64"):
+            ops += 2 * e.get(f"SQ_INSTS_VALU_FMA_{prec}", 0.0) + e.get(f"SQ_INSTS_VALU_ADD_{prec}", 0.0) + \
+                   e.get(f"SQ_INSTS_VALU_MUL_{prec}", 0.0) + e.get(f"SQ_INSTS_VALU_TRANS_{prec}", 0.0)
+        if ops:
+            e["fp_ops_per_dispatch"] = 64 * ops
+            e["fp_ops_per_element"] = 64 * ops / n_elements
+    return out
+
+
+def copy_calibration(nbytes):
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "note": "each copy reads and writes this many bytes"}), flush=True)
+
+
+def make_problem(mad, mesh, inp, prec, args, stream):
+    scatter = mad.SCATTER_PATCH if args.scatter == "patch" else mad.SCATTER_ATOMIC
+    prob = mad.Problem(mesh, 3, prec, patch_faces=args.patch_faces, scatter=scatter)
+    for k, prm in SHELL_TERMS:
+        prob.add_term(k, prm, inp.rest)
+    prob.finalize(stream)
+    if args.persistent:
+        lay = prob.layout()
+        prob.set_layout(lay["scatter"], lay["patch_faces"], 1, stream)
+    return prob
+
+
+def time_steps(torch, fn, steps, warmup, stream):
+    """Per-step HIP event times (ms) of `steps` calls after `warmup` untimed ones, and the
+    wall-clock total of the timed region."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for i in range(steps):
+        fn()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)], wall
+
+
+def pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
 
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        print(json.dumps(summarize_counters(args.summarize_counters, 5230599), indent=1))
+        return
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import numpy as np
     import torch
 
-    from paper_2509_00406_amd import mad, meshgen
+    from paper_2509_00406_amd import mad
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     prec = mad.F32 if args.precision == "f32" else mad.F64
     pb = 4 if prec == mad.F32 else 8
-    inp = meshgen.shell_cylinder(n=args.n, seed=2001)
-    terms = [(mad.STVK, (1.0, 1.0)), (mad.BENDING, (1.0, 1.0))]
-    t0 = time.perf_counter()
-    mesh = mad.Mesh(inp.tris, inp.n_verts)
-    scatter = mad.SCATTER_PATCH if args.scatter == "patch" else mad.SCATTER_ATOMIC
-    prob = mad.Problem(mesh, 3, prec, patch_faces=args.patch_faces, scatter=scatter)
-    for k, prm in terms:
-        prob.add_term(k, prm, inp.rest)
+    inp, desc = workload(args)
     stream = torch.cuda.current_stream()
-    prob.finalize(stream)
+    t0 = time.perf_counter()
+    mesh = mad.Mesh(inp.tris, inp.n_verts, inp.comp_offsets)
+    prob = make_problem(mad, mesh, inp, prec, args, stream)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     x = torch.from_numpy(inp.x.ravel().copy()).cuda()
     out = prob.outputs()
     mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
     n_elem = mesh.n_tris + mesh.n_diamonds
+    tune = None
+    if args.autotune or args.workload == "batched":
+        t1 = time.perf_counter()
+        tune = prob.autotune(x, mode, out=out, reps=5, force=True, stream=stream)
+        tune["tune_s"] = time.perf_counter() - t1
+    layout = prob.layout()
 
-    for _ in range(args.warmup):
-        prob.eval(x, mode, out=out, stream=stream)
-    torch.cuda.synchronize()
+    step = lambda: prob.eval(x, mode, out=out, stream=stream)   # noqa: E731
     mad.mad_problem_set_profiling(prob.handle, True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        prob.eval(x, mode, out=out, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    step_ms, wall = time_steps(torch, step, args.steps, args.warmup, stream)
     mad.mad_problem_set_profiling(prob.handle, False)
     stage_ms, n_evals = mad.mad_problem_profile(prob.handle)
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = max(wall * 1e3, gpu_ms) / args.steps
+    # the profile holds warm-up and timed evaluations alike; stage averages are per evaluation
+    ms_per_step = max(wall * 1e3, sum(step_ms)) / args.steps
     nonfinite, fallbacks = prob.status()
 
-    term_ms = stage_ms[1:1 + len(terms)]
-    if args.scatter == "patch":
-        # one fused kernel evaluates both terms of every patch
+    n_terms = len(SHELL_TERMS)
+    if layout["scatter"] == mad.SCATTER_PATCH:
         dom_name = "k_eval_patch (StVK + bending fused)"
-        dom_ms = term_ms[0] / n_evals
-        flops = FLOPS_PER_ELEM["stvk"] * mesh.n_tris + FLOPS_PER_ELEM["bending"] * mesh.n_diamonds
+        dom_ms = stage_ms[1] / n_evals
+        stages = {"fill": stage_ms[0] / n_evals, "fused": stage_ms[1] / n_evals,
+                  "gather_and_fp64_redo": stage_ms[2] / n_evals, "energy": stage_ms[-1] / n_evals}
     else:
+        term_ms = stage_ms[1:1 + n_terms]
         dom = int(np.argmax(term_ms))
         dom_ms = term_ms[dom] / n_evals
         dom_name = ["k_eval<StVK>", "k_eval<bending>"][dom]
-        flops = FLOPS_PER_ELEM["stvk"] * mesh.n_tris if dom == 0 else FLOPS_PER_ELEM["bending"] * mesh.n_diamonds
-    achieved_tf = flops / (dom_ms * 1e-3) / 1e12
-    peak = FP32_VALU_PEAK_TFLOPS if prec == mad.F32 else FP64_VALU_PEAK_TFLOPS
-    step_bytes = alg_bytes((mesh.n_verts, mesh.n_tris, mesh.n_diamonds, prob.nnzb), pb)
+        stages = {"fill": stage_ms[0] / n_evals, "stvk": term_ms[0] / n_evals, "bending": term_ms[1] / n_evals,
+                  "energy": stage_ms[-1] / n_evals}
+    step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, mesh.n_diamonds, prob.nnzb, pb)
+    fpe = FLOPS_PER_ELEM.get(args.precision) if args.workload == "shell" else None
+    peak = VALU_PEAK_TFLOPS[args.precision]
+    if fpe and layout["scatter"] == mad.SCATTER_PATCH:
+        achieved = fpe * n_elem / (dom_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": None, "kernel_ms": dom_ms,
+                    "flops_per_element": fpe}
+    else:
+        roofline = {"bound": "alu", "kernel": dom_name, "achieved": None, "peak": peak, "unit": "TFLOP/s",
+                    "frac": None, "traffic": None, "kernel_ms": dom_ms, "flops_per_element": None}
 
     res = {
         "metric": "elements/s for energy+grad+sparse Hessian assembly",
@@ -162,33 +287,78 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "step_ms_p10_p50_p90": [pct(step_ms, 10), pct(step_ms, 50), pct(step_ms, 90)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": f"elastic shell StVK+bending, {args.n}x{args.n} grid cylinder, sigma=1e-3h, "
-                               f"clamped Hessians, block-CSR 3x3",
-                   "triangles": mesh.n_tris, "diamonds": mesh.n_diamonds, "elements": n_elem,
-                   "nnzb": prob.nnzb, "precision": args.precision, "scatter": args.scatter,
-                   "patches_faces": args.patch_faces or 512},
-        "roofline": {"bound": "alu", "kernel": dom_name, "achieved": achieved_tf, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved_tf / peak, "traffic": None,
-                     "kernel_ms": dom_ms},
+        "config": {"workload": desc, "triangles": mesh.n_tris, "diamonds": mesh.n_diamonds, "elements": n_elem,
+                   "vertices": mesh.n_verts, "nnzb": prob.nnzb, "precision": args.precision,
+                   "layout": layout},
+        "roofline": roofline,
         "hbm": {"alg_bytes_per_step": step_bytes, "alg_GBs": step_bytes / (ms_per_step * 1e-3) / 1e9,
-                "frac_of_8TBs": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "stages_ms_per_step": {"fill": stage_ms[0] / n_evals,
-                               **({"fused": term_ms[0] / n_evals, "gather_and_fp64_redo": term_ms[1] / n_evals}
-                                  if args.scatter == "patch" else
-                                  {["stvk", "bending"][i]: term_ms[i] / n_evals for i in range(len(terms))}),
-                               "energy": stage_ms[-1] / n_evals},
+                "frac_of_peak": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "stages_ms_per_step": stages,
         "setup_s": setup_s,
         "fp64_fallbacks": fallbacks,
         "nonfinite": nonfinite,
     }
+    if tune is not None:
+        res["autotune"] = tune
+    if args.workload == "batched":
+        res["one_launch_per_mesh"] = per_mesh_baseline(torch, mad, inp, prec, stream, ms_per_step, args)
+    if prec == mad.F32 and not args.no_fp64_plain:
+        res["vs_fp64_plain"] = fp64_plain(torch, mad, mesh, inp, args, stream, x, out, ms_per_step)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(args, [(4, (1.0, 1.0)), (5, (1.0, 1.0))])
+        res["cpu_baseline"] = cpu_baseline(inp, args.cpu_elements)
     print(json.dumps(res), flush=True)
+
+
+def fp64_plain(torch, mad, mesh, inp, args, stream, x, out32, ms32):
+    """The same evaluation on the FP64 GPU path: its time, and the FP32 outputs' error against it."""
+    import numpy as np
+    p64 = make_problem(mad, mesh, inp, mad.F64, args, stream)
+    o64 = p64.outputs()
+    mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
+    step_ms, wall = time_steps(torch, lambda: p64.eval(x, mode, out=o64, stream=stream), max(5, args.steps // 5),
+                               2, stream)
+    ms64 = max(wall * 1e3, sum(step_ms)) / len(step_ms)
+    torch.cuda.synchronize()
+    e32, g32, h32 = (t.double() for t in out32)
+    e64, g64, h64 = o64
+    dg = float((g32 - g64).abs().max() / g64.abs().max())
+    dh = float((h32 - h64).abs().max() / h64.abs().max())
+    de = float(abs(e32[0] - e64[0]) / abs(e64[0]))
+    del p64, o64
+    return {"ms_per_step_fp64": ms64, "speedup_fp32_over_fp64": ms64 / ms32,
+            "grad_max_abs_err_over_max": dg, "hess_max_abs_err_over_max": dh, "energy_rel_err": de}
+
+
+def per_mesh_baseline(torch, mad, inp, prec, stream, ms_batched, args):
+    """The batch as one problem per mesh, evaluated one after another on the same stream."""
+    co = inp.comp_offsets
+    probs, xs, outs = [], [], []
+    for c in range(len(co) - 1):
+        lo, hi = int(co[c]), int(co[c + 1])
+        import numpy as np
+        sel = np.all((inp.tris >= lo) & (inp.tris < hi), axis=1)
+        m = mad.Mesh(inp.tris[sel] - lo, hi - lo)
+        p = mad.Problem(m, 3, prec)
+        for k, prm in SHELL_TERMS:
+            p.add_term(k, prm, inp.rest[lo:hi])
+        p.finalize(stream)
+        probs.append((m, p))
+        xs.append(torch.from_numpy(inp.x[lo:hi].ravel().copy()).cuda())
+        outs.append(p.outputs())
+    mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
+
+    def step():
+        for (m, p), xx, o in zip(probs, xs, outs):
+            p.eval(xx, mode, out=o, stream=stream)
+    step_ms, wall = time_steps(torch, step, max(3, args.steps // 10), 1, stream)
+    ms = max(wall * 1e3, sum(step_ms)) / len(step_ms)
+    return {"ms_per_step": ms, "speedup_of_one_launch": ms / ms_batched, "meshes": len(probs)}
 
 
 if __name__ == "__main__":

@@ -147,7 +147,7 @@ int32_t mad_problem_add_term(mad_problem *prob, int32_t kind, const double *para
                              const double *rest_pos_host);
 
 /* Build patches, upload element data and build the block pattern on the GPU (Sec. 6.1), once.
- * Synchronises the stream before returning. */
+ * Starts with the layout of the options (persistent launch off). Synchronises the stream. */
 int32_t mad_problem_finalize(mad_problem *prob, void *stream);
 
 /* Pattern sizes: block rows (= n_verts), nnzb blocks, block_dim (= var_dim). */
@@ -188,6 +188,36 @@ int32_t mad_problem_set_profiling(mad_problem *prob, int32_t enable);
  * reduction. *n_stages = S + 2, *n_evals = evaluations. ms_out must hold at least 10 doubles.
  * Records are kept (call set_profiling(1) to clear). */
 int32_t mad_problem_profile(mad_problem *prob, double *ms_out, int32_t *n_stages, int64_t *n_evals);
+
+/* Current evaluation layout (any output may be NULL): scatter strategy, effective patch target
+ * (after shrinking to fit the LDS budget), persistent launch (0/1) and number of patches. */
+int32_t mad_problem_layout(const mad_problem *prob, int32_t *scatter, int32_t *patch_faces,
+                           int32_t *persistent, int32_t *n_patches);
+
+/* Rebuild the evaluation layout of a finalized problem: scatter (mad_scatter), patch_faces target
+ * (1 .. 2^20; shrunk until the largest patch fits the LDS budget), persistent = 1 for one grid
+ * sized to the device whose workgroups take patches largest-first from a queue (patch scatter
+ * only), 0 for one workgroup per patch. The block pattern and the outputs' layout do not change.
+ * Synchronises the stream. On failure the problem is left unusable (MAD_E_STATE on eval). */
+int32_t mad_problem_set_layout(mad_problem *prob, int32_t scatter, int32_t patch_faces, int32_t persistent,
+                               void *stream);
+
+enum { MAD_TUNE_FORCE = 1 };  /* mad_problem_autotune: re-time even if this problem was tuned before */
+
+/* Choose the layout by timing (batched scheduling and the patch-size study, Sec. 7.1): builds each
+ * candidate layout (patch scatter with patch targets 128, 256, 512, 1024, each with and without the
+ * persistent launch; the atomic scatter at 512), times `reps` evaluations of `mode` on the caller's
+ * x_dev and outputs (arguments as for mad_problem_eval; their contents are overwritten), and keeps
+ * the one with the lowest median time. The choice is cached for the process by a fingerprint of the
+ * device, the connectivity, the terms, the precision and the mode; a later call on an identical
+ * problem applies it without timing unless flags has MAD_TUNE_FORCE. Synchronises the stream.
+ * On failure the problem is left unusable. */
+int32_t mad_problem_autotune(mad_problem *prob, const double *x_dev, uint32_t mode, double *energy_dev,
+                             void *grad_dev, void *hess_dev, int32_t reps, int32_t flags, void *stream);
+
+/* The last autotune's timings as JSON (candidates with their median ms, and the choice). Copies at
+ * most cap - 1 bytes plus a terminating zero into buf (may be NULL); *len = full length. */
+int32_t mad_problem_tune_report(const mad_problem *prob, char *buf, int64_t cap, int64_t *len);
 
 int32_t mad_problem_destroy(mad_problem *prob);
 

@@ -1,0 +1,171 @@
+// One evaluation of a finalized problem on a stream (Sec. 5.5 and Sec. 6.2):
+// zero what the strategy needs zeroed, launch the element kernels, gather the
+// shared entries, redo the queued FP32 elements in FP64, reduce the energy.
+// Called by mad_problem_eval after validation and by the autotuner.
+#include <algorithm>
+#include <cstring>
+
+#include "mad_internal.hpp"
+
+namespace mad {
+
+int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
+                 hipStream_t s) {
+    const mad_mesh& m = *p->mesh;
+    const int d = p->d;
+    const int eb = p->prec == MAD_F32 ? 4 : 8;
+    std::vector<hipEvent_t>* ev = nullptr;
+    if (p->profiling) {
+        const size_t need = std::max<size_t>(p->terms.size(), 2) + 3;
+        if ((size_t)p->prof_count >= p->prof_events.size()) {
+            std::vector<hipEvent_t> row(need, nullptr);
+            for (auto& e : row) MAD_HIP_TRY(hipEventCreate(&e));
+            p->prof_events.push_back(std::move(row));
+        }
+        ev = &p->prof_events[(size_t)p->prof_count++];
+        MAD_HIP_TRY(hipEventRecord((*ev)[0], s));
+    }
+    const bool fallback_pass = p->scatter == MAD_SCATTER_PATCH && p->prec == MAD_F32 && (mode & MAD_SPD);
+    // the atomic scatter adds into zeroed outputs; the patch scatter writes every entry exactly once
+    if (p->scatter == MAD_SCATTER_ATOMIC) {
+        if (mode & MAD_GRAD) MAD_HIP_TRY(launch_fill(grad, m.nv * d, eb, s));
+        if (mode & MAD_HESS) MAD_HIP_TRY(launch_fill(hess, p->nnzb * d * d, eb, s));
+    }
+    if (fallback_pass) MAD_HIP_TRY(launch_fill(p->d_fb_count, 1, 4, s));
+    if (p->scatter == MAD_SCATTER_PATCH && p->persistent) MAD_HIP_TRY(launch_fill(p->d_work_counter, 1, 4, s));
+    if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[1], s));
+    const int kmode = (mode & MAD_HESS) ? ((mode & MAD_SPD) ? 3 : 2) : ((mode & MAD_GRAD) ? 1 : 0);
+    const int np = p->patches.n;
+    int n_partial_terms = (int)p->terms.size();
+    if (p->scatter == MAD_SCATTER_PATCH) {
+        PatchLaunch L{};
+        L.prec = p->prec;
+        L.mode = kmode;
+        L.want_grad = (mode & MAD_GRAD) ? 1 : 0;
+        L.var_dim = d;
+        L.n_terms = (int)p->terms.size();
+        L.n_patch = np;
+        L.lds_bytes = patch_lds_bytes(d, p->prec, kmode, p->max_lv, p->max_lb);
+        L.x = x;
+        L.grad = grad;
+        L.hess = hess;
+        L.lv_ptr = p->d_lv_ptr;
+        L.lv_global = p->d_lv_global;
+        L.lv_halo = p->d_lv_halo;
+        L.lb_ptr = p->d_lb_ptr;
+        L.lb_gidx = p->d_lb_gidx;
+        L.lb_gidxT = p->d_lb_gidxT;
+        L.lb_halo = p->d_lb_halo;
+        L.halo_g = p->d_halo_g;
+        L.halo_h = p->d_halo_h;
+        L.partial = p->d_partial;
+        L.flags = p->d_flags;
+        L.fallbacks = p->d_fallbacks;
+        L.fb_list = p->d_fb_list;
+        L.fb_count = p->d_fb_count;
+        L.fb_cap = p->fb_cap;
+        L.eps = p->opt.spd_eps;
+        L.qmin = p->opt.degenerate_q;
+        L.persistent = p->persistent;
+        L.work_order = p->d_work_order;
+        L.work_counter = p->d_work_counter;
+        L.n_cu = p->n_cu;
+        for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+            const Term& t = p->terms[ti];
+            PatchTermArgs& A = L.terms[ti];
+            A.kind = t.kind;
+            A.n = t.n;
+            A.rest = t.d_rest;
+            A.lvert = t.d_lvert;
+            A.lslot = t.d_lslot;
+            A.elem_ptr = t.d_elem_ptr;
+            std::memcpy(A.prm, t.prm, sizeof(A.prm));
+        }
+        MAD_HIP_TRY(launch_eval_patch(L, s));
+        if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2], s));
+        GatherLaunch G{};
+        G.prec = p->prec;
+        G.var_dim = d;
+        G.want_grad = (mode & MAD_GRAD) ? 1 : 0;
+        G.want_hess = (mode & MAD_HESS) ? 1 : 0;
+        G.grad = grad;
+        G.hess = hess;
+        G.halo_g = p->d_halo_g;
+        G.halo_h = p->d_halo_h;
+        G.gv_ptr = p->d_gv_ptr;
+        G.gv_src = p->d_gv_src;
+        G.gv_vert = p->d_gv_vert;
+        G.gb_ptr = p->d_gb_ptr;
+        G.gb_src = p->d_gb_src;
+        G.gb_gidx = p->d_gb_gidx;
+        G.gb_gidxT = p->d_gb_gidxT;
+        G.orphan_vert = p->d_orphan_vert;
+        G.orphan_block = p->d_orphan_block;
+        G.n_gv = p->n_gv;
+        G.n_gb = p->n_gb;
+        G.n_orphan_vert = p->n_orphan_vert;
+        G.n_orphan_block = p->n_orphan_block;
+        MAD_HIP_TRY(launch_gather(G, s));
+        if (fallback_pass) {
+            FallbackLaunch F{};
+            F.var_dim = d;
+            F.want_grad = L.want_grad;
+            F.x = x;
+            F.grad = grad;
+            F.hess = hess;
+            F.rowptr = p->d_rowptr;
+            F.colidx = p->d_colidx;
+            F.fb_list = p->d_fb_list;
+            F.fb_count = p->d_fb_count;
+            F.fb_cap = p->fb_cap;
+            F.flags = p->d_flags;
+            F.eps = p->opt.spd_eps;
+            for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+                const Term& t = p->terms[ti];
+                F.terms[ti].kind = t.kind;
+                F.terms[ti].n = t.n;
+                F.terms[ti].stencil = t.d_stencil;
+                F.terms[ti].rest = t.d_rest;
+                std::memcpy(F.terms[ti].prm, t.prm, sizeof(t.prm));
+            }
+            MAD_HIP_TRY(launch_fallback(F, s));
+        }
+        if (ev)
+            for (size_t k = 3; k < ev->size() - 1; ++k) MAD_HIP_TRY(hipEventRecord((*ev)[k], s));
+        n_partial_terms = 1;
+    }
+    for (size_t ti = 0; p->scatter == MAD_SCATTER_ATOMIC && ti < p->terms.size(); ++ti) {
+        const Term& t = p->terms[ti];
+        EvalLaunch L{};
+        L.kind = t.kind;
+        L.prec = p->prec;
+        L.mode = kmode;
+        L.want_grad = (mode & MAD_GRAD) ? 1 : 0;
+        L.n_patch = np;
+        L.x = x;
+        L.stencil = t.d_stencil;
+        L.rest = t.d_rest;
+        L.n = t.n;
+        L.elem_ptr = t.d_elem_ptr;
+        L.slots = t.d_slots;
+        L.grad = grad;
+        L.hess = hess;
+        L.partial = p->d_partial + ti * (size_t)np;
+        L.flags = p->d_flags;
+        L.fallbacks = p->d_fallbacks;
+        std::memcpy(L.prm, t.prm, sizeof(L.prm));
+        L.eps = p->opt.spd_eps;
+        L.qmin = p->opt.degenerate_q;
+        MAD_HIP_TRY(launch_eval(L, s));
+        if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2 + ti], s));
+    }
+    if (mode & MAD_ENERGY) {
+        const int ncomp = (int)m.comp_off.size() - 1;
+        MAD_HIP_TRY(launch_energy_reduce(p->d_partial, n_partial_terms, np, p->d_comp_patch_ptr,
+                                         std::max(ncomp, 1), m.batched, energy, s));
+    }
+    if (ev) MAD_HIP_TRY(hipEventRecord(ev->back(), s));
+    return MAD_OK;
+}
+
+}  // namespace mad

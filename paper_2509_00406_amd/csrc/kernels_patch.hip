@@ -79,31 +79,33 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
                     const uint32_t w = A.lslot[(int64_t)k * A.n + e];
                     T* blk = sh + (int)(w & 0x3fffu) * DD;
                     const uint32_t flag = w >> 14;
+                    if (s == t || flag == 2u) {
+                        // lands in a diagonal block, which is symmetric: accumulate its upper half only
+                        // (s != t naming one vertex contributes H_st + H_st^T)
 #pragma unroll
-                    for (int c = 0; c < D; ++c)
+                        for (int c = 0; c < D; ++c)
 #pragma unroll
-                        for (int c2 = 0; c2 < D; ++c2) {
-                            if (s == t && c2 < c) continue;   // symmetric diagonal block: upper half
-                            const T v = hfull<Term, MODE>(o, s * D + c, t * D + c2, te);
-                            if (s == t) {
+                            for (int c2 = c; c2 < D; ++c2) {
+                                T v = hfull<Term, MODE>(o, s * D + c, t * D + c2, te);
+                                if (s != t) v += hfull<Term, MODE>(o, s * D + c2, t * D + c, te);
                                 lds_add(blk + c * D + c2, v);
-                                if (c2 != c) lds_add(blk + c2 * D + c, v);
-                            } else {
-                                lds_add(blk + ((flag == 1u) ? (c2 * D + c) : (c * D + c2)), v);
-                                if (flag == 2u) lds_add(blk + c2 * D + c, v);   // s, t name one vertex
                             }
-                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < D; ++c)
+#pragma unroll
+                            for (int c2 = 0; c2 < D; ++c2)
+                                lds_add(blk + ((flag == 1u) ? (c2 * D + c) : (c * D + c2)),
+                                        hfull<Term, MODE>(o, s * D + c, t * D + c2, te));
+                    }
                 }
         }
     }
 }
 
 template <typename T, int MODE, int D>
-__device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kBlock];
+__device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsigned char* smem, double* red) {
     constexpr int DD = D * D;
-    const int p = blockIdx.x;
     const int lv0 = L.lv_ptr[p], nlv = L.lv_ptr[p + 1] - lv0;
     const int lb0 = L.lb_ptr[p], nlb = L.lb_ptr[p + 1] - lb0;
     double* sx = reinterpret_cast<double*>(smem);
@@ -160,17 +162,41 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
         for (int i = threadIdx.x; i < nlb * DD; i += kBlock) {
             const int b = lb0 + i / DD, k = i % DD;
             const int32_t h = L.lb_halo[b];
-            const T v = sh[i];
+            const int32_t g = L.lb_gidx[b], gt = L.lb_gidxT[b];
+            const int r = k / D, c = k % D;
+            // a diagonal block keeps only its upper half in LDS
+            const T v = (g == gt && c < r) ? sh[(i / DD) * DD + c * D + r] : sh[i];
             if (h >= 0) {
                 HH[(int64_t)h * DD + k] = v;
             } else {
-                const int32_t g = L.lb_gidx[b], gt = L.lb_gidxT[b];
                 H[(int64_t)g * DD + k] = v;
-                if (gt != g) H[(int64_t)gt * DD + (k % D) * D + k / D] = v;
+                if (gt != g) H[(int64_t)gt * DD + c * D + r] = v;
             }
         }
     }
     block_reduce_store(esum, red, L.partial + p);
+}
+
+// One patch per workgroup, or (persistent) a grid sized to the device whose workgroups take
+// patches from a counter in the given order (largest first) until every patch is taken.
+template <typename T, int MODE, int D>
+__device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[kBlock];
+    __shared__ int next;
+    if (!L.persistent) {
+        eval_patch_one<T, MODE, D>(L, blockIdx.x, smem, red);
+        return;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(L.work_counter, 1);
+        __syncthreads();
+        const int k = next;
+        __syncthreads();   // every lane has read `next` before it is overwritten
+        if (k >= L.n_patch) break;
+        eval_patch_one<T, MODE, D>(L, L.work_order[k], smem, red);
+        __syncthreads();   // the flush has read LDS before the next patch clears it
+    }
 }
 
 // FP32: the compiler is held to 256 registers so two waves share each SIMD (a few values spill
@@ -332,11 +358,26 @@ size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t 
     }
 }
 
+// workgroups of a persistent launch: as many as are resident on the device at once
+template <typename K>
+static int persistent_grid(K kernel, const PatchLaunch& L) {
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, L.lds_bytes) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return std::max(1, std::min(L.n_patch, std::max(L.n_cu, 1) * per_cu));
+}
+
 template <int MODE, int D>
 static void launch_patch_kernel(bool f32, const PatchLaunch& L, hipStream_t s) {
-    dim3 grid(L.n_patch), block(kBlock);
-    if (f32) hipLaunchKernelGGL((k_eval_patch_f32<MODE, D>), grid, block, L.lds_bytes, s, L);
-    else hipLaunchKernelGGL((k_eval_patch_f64<MODE, D>), grid, block, L.lds_bytes, s, L);
+    const dim3 block(kBlock);
+    if (f32) {
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f32<MODE, D>, L) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_f32<MODE, D>), grid, block, L.lds_bytes, s, L);
+    } else {
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f64<MODE, D>, L) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_f64<MODE, D>), grid, block, L.lds_bytes, s, L);
+    }
 }
 
 template <typename T, int D>

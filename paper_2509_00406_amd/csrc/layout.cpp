@@ -1,0 +1,261 @@
+// Evaluation layout of a problem: patches, the patch order of every term's
+// elements, and the structures of the chosen scatter strategy. Built at
+// finalize and rebuilt by the autotuner; the block pattern is independent of it.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "mad_internal.hpp"
+
+namespace mad {
+
+// allocate and fill from host memory; waits for the copy (the source is often a temporary)
+static int upload_layout(mad_problem* p, void** dst, const void* src, size_t bytes, hipStream_t s) {
+    MAD_HIP_TRY(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+    p->layout_owned.push_back(*dst);
+    if (bytes) {
+        MAD_HIP_TRY(hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s));
+        MAD_HIP_TRY(hipStreamSynchronize(s));
+    }
+    return MAD_OK;
+}
+
+static int alloc_layout(mad_problem* p, void** dst, size_t bytes) {
+    MAD_HIP_TRY(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+    p->layout_owned.push_back(*dst);
+    return MAD_OK;
+}
+
+// Inside each patch, greedy-colour the term's elements so that no two elements of a colour share a
+// vertex, and store them colour by colour (stable), so that the elements a wave evaluates together
+// rarely add into the same LDS accumulators.
+static void color_within_patches(Term& t, int64_t nv) {
+    std::vector<uint64_t> busy_at((size_t)nv, 0);
+    std::vector<int32_t> color, order, seg;
+    for (size_t q = 0; q + 1 < t.elem_ptr.size(); ++q) {
+        const int32_t b = t.elem_ptr[q], e = t.elem_ptr[q + 1];
+        if (e - b < 2) continue;
+        color.assign((size_t)(e - b), 0);
+        for (int32_t i = b; i < e; ++i) {
+            const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+            uint64_t busy = 0;
+            for (int a = 0; a < t.ns; ++a) busy |= busy_at[st[a]];
+            int c = 0;
+            while (c < 63 && ((busy >> c) & 1ull)) ++c;
+            color[i - b] = c;
+            for (int a = 0; a < t.ns; ++a) busy_at[st[a]] |= 1ull << c;
+        }
+        for (int32_t i = b; i < e; ++i) {
+            const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+            for (int a = 0; a < t.ns; ++a) busy_at[st[a]] = 0;
+        }
+        order.resize((size_t)(e - b));
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return color[x] < color[y]; });
+        seg.assign(t.perm.begin() + b, t.perm.begin() + e);
+        for (int32_t i = 0; i < e - b; ++i) t.perm[b + i] = seg[order[i]];
+    }
+}
+
+// Patch order of every term's elements: faces by their patch, diamonds by their lower face, edges
+// by their first face; inside a patch by colour, then by that face's index.
+static void order_terms(mad_problem* p) {
+    const mad_mesh& m = *p->mesh;
+    const int32_t np = p->patches.n;
+    for (auto& t : p->terms) {
+        std::vector<int32_t> ep((size_t)t.n), key((size_t)t.n);
+        for (int64_t e = 0; e < t.n; ++e) {
+            int32_t f;
+            if (t.kind == MAD_BENDING) f = m.diamond_faces[2 * e];
+            else if (t.kind == MAD_EDGE_SQLEN) f = m.edge_face0[e];
+            else f = (int32_t)e;
+            ep[e] = p->patches.face_patch[f];
+            key[e] = f;
+        }
+        t.perm.resize((size_t)t.n);
+        std::iota(t.perm.begin(), t.perm.end(), 0);
+        std::stable_sort(t.perm.begin(), t.perm.end(), [&](int32_t a, int32_t b) {
+            if (ep[a] != ep[b]) return ep[a] < ep[b];
+            return key[a] < key[b];
+        });
+        t.elem_ptr.assign((size_t)np + 1, 0);
+        for (int64_t e = 0; e < t.n; ++e) t.elem_ptr[ep[e] + 1]++;
+        for (int32_t q = 0; q < np; ++q) t.elem_ptr[q + 1] += t.elem_ptr[q];
+        color_within_patches(t, m.nv);
+    }
+}
+
+// largest per-patch vertex and upper-block counts of the current patching
+static void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb) {
+    const int64_t nv = p->mesh->nv;
+    int32_t mv = 0, mb = 0;
+    std::vector<int32_t> verts;
+    std::vector<int64_t> keys;
+    for (int32_t q = 0; q < p->patches.n; ++q) {
+        verts.clear();
+        keys.clear();
+        for (const auto& t : p->terms)
+            for (int32_t i = t.elem_ptr[q]; i < t.elem_ptr[q + 1]; ++i) {
+                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                for (int a = 0; a < t.ns; ++a) {
+                    verts.push_back(st[a]);
+                    for (int b = a; b < t.ns; ++b)
+                        keys.push_back((int64_t)std::min(st[a], st[b]) * nv + std::max(st[a], st[b]));
+                }
+            }
+        std::sort(verts.begin(), verts.end());
+        std::sort(keys.begin(), keys.end());
+        mv = std::max(mv, (int32_t)(std::unique(verts.begin(), verts.end()) - verts.begin()));
+        mb = std::max(mb, (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin()));
+    }
+    *max_lv = mv;
+    *max_lb = mb;
+}
+
+static void free_layout(mad_problem* p) {
+    for (void* q : p->layout_owned) (void)hipFree(q);
+    p->layout_owned.clear();
+    for (auto& t : p->terms) {
+        t.d_stencil = nullptr;
+        t.d_rest = nullptr;
+        t.d_elem_ptr = nullptr;
+        t.d_slots = nullptr;
+        t.d_lvert = nullptr;
+        t.d_lslot = nullptr;
+    }
+    p->d_lv_ptr = p->d_lv_global = p->d_lv_halo = nullptr;
+    p->d_lb_ptr = p->d_lb_gidx = p->d_lb_gidxT = p->d_lb_halo = nullptr;
+    p->d_gv_ptr = p->d_gv_src = p->d_gv_vert = nullptr;
+    p->d_gb_ptr = p->d_gb_src = p->d_gb_gidx = p->d_gb_gidxT = nullptr;
+    p->d_orphan_vert = p->d_orphan_block = nullptr;
+    p->d_halo_g = p->d_halo_h = nullptr;
+    p->d_fb_list = nullptr;
+    p->d_fb_count = nullptr;
+    p->d_work_order = p->d_work_counter = nullptr;
+    p->d_partial = nullptr;
+    p->d_comp_patch_ptr = nullptr;
+}
+
+// Build the patches and the element order (host), then upload the element arrays. If the pattern
+// already exists, also build the structures of the scatter strategy.
+int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStream_t s) {
+    const mad_mesh& m = *p->mesh;
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    free_layout(p);
+    p->scatter = scatter;
+    p->persistent = scatter == MAD_SCATTER_PATCH ? persistent : 0;
+    build_patches(m, target, p->patches);
+    order_terms(p);
+    if (scatter == MAD_SCATTER_PATCH) {
+        // shrink the patch target until the largest patch's LDS working set fits the budget
+        for (;;) {
+            int32_t mv, mb;
+            patch_extent(p, &mv, &mb);
+            p->lds_bytes = patch_lds_bytes(p->d, p->prec, 3, mv, mb);
+            if (p->lds_bytes <= kLdsBudget) break;
+            if (target <= 1) return fail(MAD_E_UNSUPPORTED, "a single element exceeds the LDS budget");
+            target = std::max(1, (int)(target * 0.75));
+            build_patches(m, target, p->patches);
+            order_terms(p);
+        }
+    }
+    p->opt.patch_faces = target;
+    const int32_t np = p->patches.n;
+    int rc;
+    for (auto& t : p->terms) {
+        std::vector<int32_t> st((size_t)t.n * t.ns);
+        std::vector<double> rs((size_t)t.n * t.nrest);
+        for (int64_t i = 0; i < t.n; ++i) {
+            const int32_t e = t.perm[i];
+            for (int a = 0; a < t.ns; ++a) st[i * t.ns + a] = t.stencil[(int64_t)e * t.ns + a];
+            for (int k = 0; k < t.nrest; ++k) rs[(int64_t)k * t.n + i] = t.rest[(int64_t)e * t.nrest + k];
+        }
+        if ((rc = upload_layout(p, (void**)&t.d_stencil, st.data(), st.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = upload_layout(p, (void**)&t.d_rest, rs.data(), rs.size() * 8, s)) != MAD_OK) return rc;
+        if ((rc = upload_layout(p, (void**)&t.d_elem_ptr, t.elem_ptr.data(), t.elem_ptr.size() * 4, s)) != MAD_OK)
+            return rc;
+    }
+    if ((rc = upload_layout(p, (void**)&p->d_comp_patch_ptr, p->patches.comp_patch_ptr.data(),
+                            p->patches.comp_patch_ptr.size() * 4, s)) != MAD_OK)
+        return rc;
+    if ((rc = alloc_layout(p, (void**)&p->d_partial, sizeof(double) * std::max<size_t>(1, (size_t)np * p->terms.size()))) !=
+        MAD_OK)
+        return rc;
+    // work order of the persistent launch: patches with most elements first
+    {
+        std::vector<int64_t> cnt((size_t)np, 0);
+        for (auto& t : p->terms)
+            for (int32_t q = 0; q < np; ++q) cnt[q] += t.elem_ptr[q + 1] - t.elem_ptr[q];
+        std::vector<int32_t> order((size_t)np);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
+        if ((rc = upload_layout(p, (void**)&p->d_work_order, order.data(), order.size() * 4, s)) != MAD_OK) return rc;
+        if ((rc = alloc_layout(p, (void**)&p->d_work_counter, 16)) != MAD_OK) return rc;
+    }
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    if (p->h_rowptr.empty()) return MAD_OK;   // pattern not built yet (first layout, inside finalize)
+    return build_scatter(p, s);
+}
+
+// Structures of the scatter strategy for the current element order; needs the pattern.
+int build_scatter(mad_problem* p, hipStream_t s) {
+    int rc;
+    if (p->scatter == MAD_SCATTER_ATOMIC) {
+        for (auto& t : p->terms) {
+            if ((rc = alloc_layout(p, (void**)&t.d_slots, sizeof(int32_t) * std::max<int64_t>(1, t.n * t.ns * t.ns))) !=
+                MAD_OK)
+                return rc;
+            MAD_HIP_TRY(launch_slots(t.d_stencil, t.n, t.ns, p->d_rowptr, p->d_colidx, t.d_slots, p->d_flags, s));
+        }
+        MAD_HIP_TRY(hipStreamSynchronize(s));
+        return MAD_OK;
+    }
+    PatchLocal L;
+    if ((rc = build_patch_local(*p, p->h_rowptr, p->h_colidx, L)) != MAD_OK) return rc;
+    p->max_lv = L.max_lv;
+    p->max_lb = L.max_lb;
+    p->lds_bytes = patch_lds_bytes(p->d, p->prec, 3, L.max_lv, L.max_lb);
+    struct Up {
+        void** dst;
+        const std::vector<int32_t>* v;
+    } ups[] = {{(void**)&p->d_lv_ptr, &L.lv_ptr},       {(void**)&p->d_lv_global, &L.lv_global},
+               {(void**)&p->d_lv_halo, &L.lv_halo},     {(void**)&p->d_lb_ptr, &L.lb_ptr},
+               {(void**)&p->d_lb_gidx, &L.lb_gidx},     {(void**)&p->d_lb_gidxT, &L.lb_gidxT},
+               {(void**)&p->d_lb_halo, &L.lb_halo},     {(void**)&p->d_gv_ptr, &L.gv_ptr},
+               {(void**)&p->d_gv_src, &L.gv_src},       {(void**)&p->d_gv_vert, &L.gv_vert},
+               {(void**)&p->d_gb_ptr, &L.gb_ptr},       {(void**)&p->d_gb_src, &L.gb_src},
+               {(void**)&p->d_gb_gidx, &L.gb_gidx},     {(void**)&p->d_gb_gidxT, &L.gb_gidxT},
+               {(void**)&p->d_orphan_vert, &L.orphan_vert}, {(void**)&p->d_orphan_block, &L.orphan_block}};
+    for (auto& u : ups)
+        if ((rc = upload_layout(p, u.dst, u.v->data(), u.v->size() * 4, s)) != MAD_OK) return rc;
+    p->n_gv = (int32_t)L.gv_vert.size();
+    p->n_gb = (int32_t)L.gb_gidx.size();
+    p->n_orphan_vert = (int32_t)L.orphan_vert.size();
+    p->n_orphan_block = (int32_t)L.orphan_block.size();
+    const size_t eb = p->prec == MAD_F32 ? 4 : 8;
+    if ((rc = alloc_layout(p, &p->d_halo_g, L.gv_src.size() * p->d * eb)) != MAD_OK) return rc;
+    if ((rc = alloc_layout(p, &p->d_halo_h, L.gb_src.size() * p->d * p->d * eb)) != MAD_OK) return rc;
+    for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+        auto& t = p->terms[ti];
+        if ((rc = upload_layout(p, (void**)&t.d_lvert, L.lvert[ti].data(), L.lvert[ti].size() * 2, s)) != MAD_OK)
+            return rc;
+        if ((rc = upload_layout(p, (void**)&t.d_lslot, L.lslot[ti].data(), L.lslot[ti].size() * 2, s)) != MAD_OK)
+            return rc;
+    }
+    if (p->prec == MAD_F32) {
+        // queue for FP32 elements redone in FP64: room for every element
+        int64_t total = 0;
+        for (auto& t : p->terms) {
+            if (t.n >= (1ll << 29)) return fail(MAD_E_OVERFLOW, "more than 2^29 elements in one term");
+            total += t.n;
+        }
+        if (total >= INT32_MAX) return fail(MAD_E_OVERFLOW, "more than 2^31 elements");
+        p->fb_cap = (int32_t)std::max<int64_t>(total, 1);
+        if ((rc = alloc_layout(p, (void**)&p->d_fb_list, sizeof(uint32_t) * (size_t)p->fb_cap)) != MAD_OK) return rc;
+        if ((rc = alloc_layout(p, (void**)&p->d_fb_count, 16)) != MAD_OK) return rc;
+    }
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    return MAD_OK;
+}
+
+}  // namespace mad

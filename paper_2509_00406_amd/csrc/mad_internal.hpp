@@ -86,6 +86,13 @@ struct mad_problem {
     int32_t* d_flags = nullptr;           // [0] nonfinite, [1] internal error
     unsigned long long* d_fallbacks = nullptr;
     int scatter = MAD_SCATTER_PATCH;
+    int persistent = 0;                   // patch scatter: persistent grid pulling patches from a queue
+    int n_cu = 0;                         // compute units of the device
+    std::vector<void*> layout_owned;      // device memory of the current layout (freed on relayout)
+    std::vector<int32_t> h_rowptr, h_colidx;  // host copy of the pattern (layout rebuilds)
+    int32_t* d_work_order = nullptr;      // patches, largest first (persistent launch)
+    int32_t* d_work_counter = nullptr;
+    std::string tune_report;              // last autotune table (JSON)
     int32_t* d_lv_ptr = nullptr;
     int32_t* d_lv_global = nullptr;
     int32_t* d_lv_halo = nullptr;
@@ -137,6 +144,12 @@ int build_topology(mad_mesh& m);
 int rest_tri(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);        // [nt][5]
 int rest_diamond(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);    // [nd][2]
 void build_patches(const mad_mesh& m, int target_faces, Patches& p);
+// layout.cpp: (re)build the element order and the scatter structures of a problem
+int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s);
+int build_scatter(mad_problem* p, hipStream_t s);
+int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
+                 hipStream_t s);
+constexpr size_t kLdsBudget = 60 * 1024;  // dynamic LDS per workgroup: two workgroups per CU
 int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& colidx,
                       PatchLocal& L);
 size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t max_lb);
@@ -197,6 +210,10 @@ struct PatchLaunch {
     int32_t* fb_count;
     int32_t fb_cap;
     double eps, qmin;
+    int persistent;
+    const int32_t* work_order;
+    int32_t* work_counter;
+    int n_cu;
     PatchTermArgs terms[8];
 };
 hipError_t launch_eval_patch(const PatchLaunch& L, hipStream_t s);

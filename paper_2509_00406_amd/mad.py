@@ -19,6 +19,7 @@ EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR = 1, 2, 3, 4, 5, 6
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 F64, F32 = 0, 1
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_PATCH = 0, 1, 2
+TUNE_FORCE = 1
 
 STATUS = {0: "MAD_OK", -1: "MAD_E_INVALID_ARG", -2: "MAD_E_BAD_MESH", -3: "MAD_E_DEGENERATE_REST",
           -4: "MAD_E_OVERFLOW", -5: "MAD_E_OOM", -6: "MAD_E_HIP", -7: "MAD_E_STATE", -8: "MAD_E_UNSUPPORTED"}
@@ -62,6 +63,12 @@ _SIGS = {
     "mad_problem_set_profiling": ([C.c_void_p, C.c_int32], C.c_int32),
     "mad_problem_profile": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
                             C.c_int32),
+    "mad_problem_layout": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                            C.POINTER(C.c_int32)], C.c_int32),
+    "mad_problem_set_layout": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p], C.c_int32),
+    "mad_problem_autotune": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                              C.c_int32, C.c_void_p], C.c_int32),
+    "mad_problem_tune_report": ([C.c_void_p, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)], C.c_int32),
     "mad_problem_destroy": ([C.c_void_p], C.c_int32),
 }
 
@@ -204,6 +211,31 @@ def mad_problem_profile(prob) -> tuple[list[float], int]:
     return [ms[i] for i in range(n.value)], k.value
 
 
+def mad_problem_layout(prob) -> dict:
+    sc, pf, pe, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().mad_problem_layout(prob, C.byref(sc), C.byref(pf), C.byref(pe), C.byref(n)), "mad_problem_layout")
+    return {"scatter": sc.value, "patch_faces": pf.value, "persistent": pe.value, "n_patches": n.value}
+
+
+def mad_problem_set_layout(prob, scatter: int, patch_faces: int, persistent: int, stream=None):
+    _check(lib().mad_problem_set_layout(prob, scatter, patch_faces, persistent, _stream(stream)),
+           "mad_problem_set_layout")
+
+
+def mad_problem_autotune(prob, x, mode: int, energy=None, grad=None, hess=None, reps: int = 5, flags: int = 0,
+                         stream=None):
+    _check(lib().mad_problem_autotune(prob, _ptr(x), mode, _ptr(energy), _ptr(grad), _ptr(hess), reps, flags,
+                                      _stream(stream)), "mad_problem_autotune")
+
+
+def mad_problem_tune_report(prob) -> str:
+    n = C.c_int64()
+    _check(lib().mad_problem_tune_report(prob, None, 0, C.byref(n)), "mad_problem_tune_report")
+    buf = C.create_string_buffer(n.value + 1)
+    _check(lib().mad_problem_tune_report(prob, buf, n.value + 1, C.byref(n)), "mad_problem_tune_report")
+    return buf.value.decode()
+
+
 def mad_problem_destroy(prob):
     _check(lib().mad_problem_destroy(prob), "mad_problem_destroy")
 
@@ -272,6 +304,21 @@ class Problem:
 
     def status(self, stream=None):
         return mad_problem_status(self.handle, stream)
+
+    def layout(self) -> dict:
+        return mad_problem_layout(self.handle)
+
+    def set_layout(self, scatter: int, patch_faces: int, persistent: int = 0, stream=None):
+        mad_problem_set_layout(self.handle, scatter, patch_faces, persistent, stream)
+
+    def autotune(self, x, mode: int = ENERGY | GRAD | HESS, out=None, reps: int = 5, force: bool = False,
+                 stream=None) -> dict:
+        """Time the candidate layouts on x and keep the fastest; returns the timing report."""
+        import json
+        energy, grad, hess = out if out is not None else self.outputs(x.device)
+        mad_problem_autotune(self.handle, x, mode, energy if mode & ENERGY else None, grad if mode & GRAD else None,
+                             hess if mode & HESS else None, reps, TUNE_FORCE if force else 0, stream)
+        return json.loads(mad_problem_tune_report(self.handle))
 
     def __del__(self):
         h = getattr(self, "handle", None)
