@@ -262,10 +262,123 @@ static hd e_symdir(int k, const double *xloc, const double *rest) {
     return hd_scale(hd_add(nJ, nJi), area);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Per-triangle shell features and densities (project-defined: the paper has  */
+/* no learned component). z = (E00, E11, E01, dII00, dII11, dII01):           */
+/*   F = Ds Dm^{-1} (3x2), E = (F^T F - I) / 2 (Green strain, rest frame);     */
+/*   N = Dn Dm^{-1} with Dn = [n_b - n_a, n_c - n_a] from passive unit vertex  */
+/*   normals; II = -(N^T F + F^T N) / 2; dII = II - rest II.                   */
+/* rest data (8): Dm^{-1} (4, row-major), rest area, rest II (00, 11, 01).     */
+/* aux (9): the current unit normals of the three vertices (not active).       */
+/* ------------------------------------------------------------------------- */
+static void shell_features(int k, const double *xloc, const double *rest, const double *nrm, hd z[6]) {
+    const double *mi = rest;
+    hd3 xa = lift3(k, xloc, 0), xb = lift3(k, xloc, 1), xc = lift3(k, xloc, 2);
+    hd3 d1 = hd3_sub(xb, xa), d2 = hd3_sub(xc, xa);
+    hd F[3][2];
+    double N[3][2];
+    for (int i = 0; i < 3; ++i) {
+        double dn1 = nrm[3 + i] - nrm[i], dn2 = nrm[6 + i] - nrm[i];
+        for (int j = 0; j < 2; ++j) {
+            F[i][j] = hd_add(hd_scale(d1.c[i], mi[0 * 2 + j]), hd_scale(d2.c[i], mi[1 * 2 + j]));
+            N[i][j] = dn1 * mi[0 * 2 + j] + dn2 * mi[1 * 2 + j];
+        }
+    }
+    /* E[a][b] = (sum_i F[i][a] F[i][b] - delta_ab) / 2; II[a][b] = -(sum_i N[i][a] F[i][b] + F[i][a] N[i][b]) / 2 */
+    static const int A[3] = {0, 1, 0}, B[3] = {0, 1, 1};
+    for (int q = 0; q < 3; ++q) {
+        int a = A[q], b = B[q];
+        hd e = hd_const(k, 0.0), ii = hd_const(k, 0.0);
+        for (int i = 0; i < 3; ++i) {
+            e = hd_add(e, hd_mul(F[i][a], F[i][b]));
+            ii = hd_add(ii, hd_add(hd_scale(F[i][b], N[i][a]), hd_scale(F[i][a], N[i][b])));
+        }
+        z[q] = hd_scale(hd_addc(e, a == b ? -1.0 : 0.0), 0.5);
+        z[3 + q] = hd_addc(hd_scale(ii, -0.5), -rest[5 + q]);
+    }
+}
+
+/* analytic density: W(z) = mu (E00^2 + E11^2 + 2 E01^2) + lambda/2 (E00 + E11)^2
+ *                        + k_b/2 (dII00^2 + dII11^2 + 2 dII01^2); f = rest area * W */
+static hd shell_density(const hd z[6], const double *prm) {
+    double mu = prm[0], lam = prm[1], kb = prm[2];
+    hd trE2 = hd_add(hd_add(hd_sq(z[0]), hd_sq(z[1])), hd_scale(hd_sq(z[2]), 2.0));
+    hd trE = hd_add(z[0], z[1]);
+    hd b2 = hd_add(hd_add(hd_sq(z[3]), hd_sq(z[4])), hd_scale(hd_sq(z[5]), 2.0));
+    return hd_add(hd_add(hd_scale(trE2, mu), hd_scale(hd_sq(trE), 0.5 * lam)), hd_scale(b2, 0.5 * kb));
+}
+
+static hd e_shell_tri(int k, const double *xloc, const double *rest, const double *aux, const double *prm) {
+    hd z[6];
+    shell_features(k, xloc, rest, aux, z);
+    return hd_scale(shell_density(z, prm), rest[4]);
+}
+
+/* softplus(a) = log(1 + e^a), evaluated without overflow; its derivatives are the
+ * logistic sigma(a) and sigma(a) (1 - sigma(a)) */
+static double softplus(double a) { return a > 0.0 ? a + log1p(exp(-a)) : log1p(exp(a)); }
+static double logistic(double a) { return a >= 0.0 ? 1.0 / (1.0 + exp(-a)) : exp(a) / (1.0 + exp(a)); }
+static hd hd_softplus(hd a) {
+    double s = logistic(a.v);
+    return hd_unary(a, softplus(a.v), s, s * (1.0 - s));
+}
+
+/* MLP parameter block: [H, s_out, s_in(6), W1(H x 6), b1(H), W2(H x H), b2(H), w3(H), b3],
+ * psi(z) = s_out (w3 . sp(W2 sp(W1 (s_in * z) + b1) + b2) + b3), sp = softplus */
+#define MLP_HMAX 64
+static int mlp_layout(const double *prm, int *H, const double **sin_, const double **W1, const double **b1,
+                      const double **W2, const double **b2, const double **w3, double *b3) {
+    int h = (int)prm[0];
+    if (h < 1 || h > MLP_HMAX || (double)h != prm[0]) return -1;
+    *H = h;
+    *sin_ = prm + 2;
+    *W1 = prm + 8;
+    *b1 = *W1 + 6 * h;
+    *W2 = *b1 + h;
+    *b2 = *W2 + h * h;
+    *w3 = *b2 + h;
+    *b3 = (*w3)[h];
+    return 0;
+}
+
+static int mlp_psi(const double *prm, const hd z[6], hd *psi) {
+    int H;
+    const double *sin_, *W1, *b1, *W2, *b2, *w3;
+    double b3;
+    if (mlp_layout(prm, &H, &sin_, &W1, &b1, &W2, &b2, &w3, &b3) != 0) return -1;
+    int k = z[0].k;
+    hd xin[6];
+    for (int i = 0; i < 6; ++i) xin[i] = hd_scale(z[i], sin_[i]);
+    hd h1[MLP_HMAX], h2[MLP_HMAX];
+    for (int n = 0; n < H; ++n) {
+        hd a = hd_const(k, b1[n]);
+        for (int i = 0; i < 6; ++i) a = hd_add(a, hd_scale(xin[i], W1[n * 6 + i]));
+        h1[n] = hd_softplus(a);
+    }
+    for (int m = 0; m < H; ++m) {
+        hd a = hd_const(k, b2[m]);
+        for (int n = 0; n < H; ++n) a = hd_add(a, hd_scale(h1[n], W2[m * H + n]));
+        h2[m] = hd_softplus(a);
+    }
+    hd out = hd_const(k, b3);
+    for (int m = 0; m < H; ++m) out = hd_add(out, hd_scale(h2[m], w3[m]));
+    *psi = hd_scale(out, prm[1]);
+    return 0;
+}
+
+/* learned density: f = rest area * psi(z(x)) */
+static int e_mlp(int k, const double *xloc, const double *rest, const double *aux, const double *prm, hd *out) {
+    hd z[6], psi;
+    shell_features(k, xloc, rest, aux, z);
+    if (mlp_psi(prm, z, &psi) != 0) return -1;
+    *out = hd_scale(psi, rest[4]);
+    return 0;
+}
+
 static int kind_stencil(int kind) {
     switch (kind) {
     case OR_EDGE_SQLEN: return 2;
-    case OR_TRI_AREA: case OR_DIRICHLET: case OR_STVK: case OR_SYMDIR: case OR_MLP: return 3;
+    case OR_TRI_AREA: case OR_DIRICHLET: case OR_STVK: case OR_SYMDIR: case OR_MLP: case OR_SHELL_TRI: return 3;
     case OR_BENDING: return 4;
     default: return -1;
     }
@@ -275,14 +388,17 @@ static int kind_vardim(int kind) {
     switch (kind) {
     case OR_DIRICHLET: return 1;
     case OR_SYMDIR: return 2;
-    case OR_EDGE_SQLEN: case OR_TRI_AREA: case OR_STVK: case OR_BENDING: case OR_MLP: return 3;
+    case OR_EDGE_SQLEN: case OR_TRI_AREA: case OR_STVK: case OR_BENDING: case OR_MLP: case OR_SHELL_TRI: return 3;
     default: return -1;
     }
 }
 
 /* evaluate one element with k active variables (k = 0: passive, value only) */
-static int eval_elem(int kind, int k, const double *prm, const double *rest, const double *xloc, hd *out) {
+static int eval_elem(int kind, int k, const double *prm, const double *rest, const double *aux, const double *xloc,
+                     hd *out) {
     switch (kind) {
+    case OR_SHELL_TRI: *out = e_shell_tri(k, xloc, rest, aux, prm); return 0;
+    case OR_MLP: return e_mlp(k, xloc, rest, aux, prm, out);
     case OR_EDGE_SQLEN: *out = e_edge_sqlen(k, xloc); return 0;
     case OR_TRI_AREA: *out = e_tri_area(k, xloc); return 0;
     case OR_DIRICHLET: *out = e_dirichlet(k, xloc, rest); return 0;
@@ -350,14 +466,14 @@ int oracle_spd_project(int n, const double *Ain, double eps, double *out) {
     return 0;
 }
 
-int oracle_element(int kind, const double *params, const double *rest, const double *xloc,
+int oracle_element(int kind, const double *params, const double *rest, const double *aux, const double *xloc,
                    int mode, double spd_eps, double *f, double *g, double *H) {
     int ss = kind_stencil(kind), vd = kind_vardim(kind);
     if (ss < 0 || vd < 0) return -1;
     int k = ss * vd;
     int kk = (mode & (OR_GRAD | OR_HESS)) ? k : 0;
     hd r;
-    if (eval_elem(kind, kk, params, rest, xloc, &r) != 0) return -1;
+    if (eval_elem(kind, kk, params, rest, aux, xloc, &r) != 0) return -1;
     if (f) *f = r.v;
     if (g && (mode & OR_GRAD))
         for (int i = 0; i < k; ++i) g[i] = r.g[i];
@@ -484,6 +600,115 @@ int oracle_rest_diamond(int64_t nd, const int32_t *diamonds, const int32_t *diam
     return 0;
 }
 
+/* area-weighted unit vertex normals: normalize(sum over incident triangles of
+ * (x_b - x_a) x (x_c - x_a)); a vertex with no triangle (or a zero sum) gets 0 */
+int oracle_vertex_normals(int64_t nv, int64_t nt, const int32_t *tris, const double *x, double *out) {
+    memset(out, 0, sizeof(double) * (size_t)(3 * nv));
+    for (int64_t f = 0; f < nt; ++f) {
+        const int32_t *t = tris + 3 * f;
+        const double *a = x + 3 * (int64_t)t[0], *b = x + 3 * (int64_t)t[1], *c = x + 3 * (int64_t)t[2];
+        double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        for (int v = 0; v < 3; ++v)
+            for (int d = 0; d < 3; ++d) out[3 * (int64_t)t[v] + d] += n[d];
+    }
+    for (int64_t v = 0; v < nv; ++v) {
+        double *n = out + 3 * v;
+        double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (l > 0.0)
+            for (int d = 0; d < 3; ++d) n[d] /= l;
+    }
+    return 0;
+}
+
+/* per triangle [Dm^{-1} (4), rest area, rest II (3)]: the features' II evaluated on the rest
+ * mesh with its own vertex normals */
+int oracle_rest_shell(int64_t nv, int64_t nt, const int32_t *tris, const double *rest, double *out) {
+    double *nrm = malloc(sizeof(double) * (size_t)(3 * (nv > 0 ? nv : 1)));
+    if (!nrm) return -4;
+    oracle_vertex_normals(nv, nt, tris, rest, nrm);
+    for (int64_t f = 0; f < nt; ++f) {
+        const int32_t *t = tris + 3 * f;
+        double *o = out + 8 * f;
+        if (rest_frame(rest + 3 * t[0], rest + 3 * t[1], rest + 3 * t[2], o, o + 4) != 0) { free(nrm); return -2; }
+        o[5] = o[6] = o[7] = 0.0;
+        double xl[9], aux[9];
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) {
+                xl[3 * a + d] = rest[3 * (int64_t)t[a] + d];
+                aux[3 * a + d] = nrm[3 * (int64_t)t[a] + d];
+            }
+        hd z[6];
+        shell_features(0, xl, o, aux, z);
+        for (int q = 0; q < 3; ++q) o[5 + q] = z[3 + q].v;
+    }
+    free(nrm);
+    return 0;
+}
+
+/* feature values z [nt][6] at positions x (normals from x over these triangles): the same
+ * formulas as shell_features, in plain doubles (fast enough for millions of samples) */
+int oracle_shell_features(int64_t nv, int64_t nt, const int32_t *tris, const double *rest8, const double *x,
+                          double *z) {
+    double *nrm = malloc(sizeof(double) * (size_t)(3 * (nv > 0 ? nv : 1)));
+    if (!nrm) return -4;
+    oracle_vertex_normals(nv, nt, tris, x, nrm);
+    for (int64_t f = 0; f < nt; ++f) {
+        const int32_t *t = tris + 3 * f;
+        const double *mi = rest8 + 8 * f;
+        const double *xa = x + 3 * (int64_t)t[0], *xb = x + 3 * (int64_t)t[1], *xc = x + 3 * (int64_t)t[2];
+        const double *na = nrm + 3 * (int64_t)t[0], *nb = nrm + 3 * (int64_t)t[1], *nc = nrm + 3 * (int64_t)t[2];
+        double F[3][2], N[3][2];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 2; ++j) {
+                F[i][j] = (xb[i] - xa[i]) * mi[0 * 2 + j] + (xc[i] - xa[i]) * mi[1 * 2 + j];
+                N[i][j] = (nb[i] - na[i]) * mi[0 * 2 + j] + (nc[i] - na[i]) * mi[1 * 2 + j];
+            }
+        static const int A[3] = {0, 1, 0}, B[3] = {0, 1, 1};
+        for (int q = 0; q < 3; ++q) {
+            int a = A[q], b = B[q];
+            double e = 0.0, ii = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                e += F[i][a] * F[i][b];
+                ii += F[i][b] * N[i][a] + F[i][a] * N[i][b];
+            }
+            z[6 * f + q] = 0.5 * (e - (a == b ? 1.0 : 0.0));
+            z[6 * f + 3 + q] = -0.5 * ii - mi[5 + q];
+        }
+    }
+    free(nrm);
+    return 0;
+}
+
+/* the analytic density W and dW/dz at n feature vectors (z seeded as 6 hyper-dual variables) */
+int oracle_shell_density(int64_t n, const double *z, const double *params, double *W, double *dW) {
+    for (int64_t i = 0; i < n; ++i) {
+        hd zz[6];
+        for (int q = 0; q < 6; ++q) zz[q] = hd_var(6, q, z[6 * i + q]);
+        hd w = shell_density(zz, params);
+        W[i] = w.v;
+        if (dW)
+            for (int q = 0; q < 6; ++q) dW[6 * i + q] = w.g[q];
+    }
+    return 0;
+}
+
+/* the network psi(z), and optionally dpsi/dz [n][6] and d2psi/dz2 [n][36] */
+int oracle_mlp_eval(int64_t n, const double *z, const double *params, double *psi, double *dpsi, double *d2psi) {
+    for (int64_t i = 0; i < n; ++i) {
+        hd zz[6], p;
+        for (int q = 0; q < 6; ++q) zz[q] = hd_var(6, q, z[6 * i + q]);
+        if (mlp_psi(params, zz, &p) != 0) return -1;
+        psi[i] = p.v;
+        if (dpsi)
+            for (int q = 0; q < 6; ++q) dpsi[6 * i + q] = p.g[q];
+        if (d2psi)
+            for (int q = 0; q < 6; ++q)
+                for (int r = 0; r < 6; ++r) d2psi[36 * i + 6 * q + r] = p.h[q][r];
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Pattern (Sec. 6.1): sorted unique block pairs, prefix sum to row pointers. */
 /* ------------------------------------------------------------------------- */
@@ -579,7 +804,15 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
         int ss = kind_stencil(kind[t]);
         if (ss < 0 || kind_vardim(kind[t]) != d) { free(fvals); return -1; }
         int k = ss * d;
-        int rest_stride = (kind[t] == OR_BENDING) ? 2 : ((kind[t] == OR_DIRICHLET || kind[t] == OR_STVK || kind[t] == OR_SYMDIR) ? 5 : 0);
+        int shell = kind[t] == OR_SHELL_TRI || kind[t] == OR_MLP;
+        int rest_stride = (kind[t] == OR_BENDING) ? 2
+                          : ((kind[t] == OR_DIRICHLET || kind[t] == OR_STVK || kind[t] == OR_SYMDIR) ? 5 : (shell ? 8 : 0));
+        double *nrm = NULL;
+        if (shell) { /* passive unit vertex normals of the current positions, over this term's triangles */
+            nrm = malloc(sizeof(double) * (size_t)(3 * nv));
+            if (!nrm) { free(fvals); return -4; }
+            oracle_vertex_normals(nv, n_elem[t], stencil[t], x, nrm);
+        }
         for (int64_t e = 0; e < n_elem[t]; ++e) {
             const int32_t *s = stencil[t] + ss * e;
             double xloc[KMAX];
@@ -590,9 +823,17 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
             }
             if (!touches && !(mode & OR_ENERGY)) continue; /* contributes to no requested output */
             const double *rs = rest_stride ? rest[t] + rest_stride * e : NULL;
+            double aux[9];
+            if (shell)
+                for (int a = 0; a < 3; ++a)
+                    for (int c = 0; c < 3; ++c) aux[3 * a + c] = nrm[3 * (int64_t)s[a] + c];
             int want_deriv = touches && (mode & (OR_GRAD | OR_HESS));
             hd r;
-            if (eval_elem(kind[t], want_deriv ? k : 0, params[t], rs, xloc, &r) != 0) { free(fvals); return -1; }
+            if (eval_elem(kind[t], want_deriv ? k : 0, params[t], rs, aux, xloc, &r) != 0) {
+                free(nrm);
+                free(fvals);
+                return -1;
+            }
             fvals[fi++] = r.v;
             abs_sum += fabs(r.v);
             if (!want_deriv) continue;
@@ -619,7 +860,7 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
                     if (row_mask && !row_mask[s[a]]) continue;
                     for (int b = 0; b < ss; ++b) {
                         int64_t blk = find_block(rowptr, colidx, s[a], s[b]);
-                        if (blk < 0) { free(fvals); return -5; }
+                        if (blk < 0) { free(nrm); free(fvals); return -5; }
                         for (int i = 0; i < d; ++i)
                             for (int j = 0; j < d; ++j) {
                                 hess[blk * d * d + i * d + j] += Hp[(a * d + i) * k + (b * d + j)];

@@ -32,7 +32,8 @@ enum {
     OR_STVK = 4,         /* StVK membrane, VarDim 3, k = 9 */
     OR_BENDING = 5,      /* Sec. 7.7 dihedral bending over an edge diamond, VarDim 3, k = 12 */
     OR_SYMDIR = 6,       /* Sec. 7.2 symmetric Dirichlet, VarDim 2, k = 6 */
-    OR_MLP = 7           /* learned per-triangle density, VarDim 3, k = 9 */
+    OR_MLP = 7,          /* learned per-triangle density A psi(z), VarDim 3, k = 9 */
+    OR_SHELL_TRI = 8     /* analytic per-triangle shell density A W(z), VarDim 3, k = 9 */
 };
 
 /* eval mode bits */
@@ -66,8 +67,9 @@ int oracle_pattern(int64_t nv, int n_terms, const int64_t *n_elem, const int *st
 
 /* ---- one element (Sec. 6.2) ---- */
 /* xloc: the stencil DOFs (k = stencil * var_dim values), rest: per-element rest
- * data of the kind, params: the term's constants. Outputs f, g[k], H[k*k]. */
-int oracle_element(int kind, const double *params, const double *rest, const double *xloc,
+ * data of the kind, aux: the three unit vertex normals (kinds OR_SHELL_TRI and
+ * OR_MLP, else unused), params: the term's constants. Outputs f, g[k], H[k*k]. */
+int oracle_element(int kind, const double *params, const double *rest, const double *aux, const double *xloc,
                    int mode, double spd_eps, double *f, double *g, double *H);
 
 /* ---- evaluation + assembly (Eq. 1-2) ---- */
@@ -87,6 +89,21 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
                 const char *row_mask, const int32_t *rowptr, const int32_t *colidx,
                 double *energy, double *esum_abs, double *grad, double *gscale,
                 double *hess, double *hscale);
+
+/* ---- per-triangle shell features and densities (project-defined; no paper counterpart) ----
+ * z = (E00, E11, E01, II00 - rII00, II11 - rII11, II01 - rII01) with F = Ds Dm^{-1},
+ * E = (F^T F - I)/2, N = [n_b - n_a, n_c - n_a] Dm^{-1} from passive unit vertex normals,
+ * II = -(N^T F + F^T N)/2. Kind OR_SHELL_TRI: f = A W(z), params (mu, lambda, k_b),
+ * W = mu (E00^2 + E11^2 + 2 E01^2) + lambda/2 (E00 + E11)^2 + k_b/2 (dII00^2 + dII11^2 + 2 dII01^2).
+ * Kind OR_MLP: f = A psi(z), params [H, s_out, s_in(6), W1(Hx6), b1(H), W2(HxH), b2(H), w3(H), b3],
+ * psi(z) = s_out (w3 . sp(W2 sp(W1 (s_in*z) + b1) + b2) + b3), sp = softplus, H <= 64.
+ * Rest data of both kinds, per triangle: [Dm^{-1} (4), rest area, rest II (3)]. */
+int oracle_vertex_normals(int64_t nv, int64_t nt, const int32_t *tris, const double *x, double *out);
+int oracle_rest_shell(int64_t nv, int64_t nt, const int32_t *tris, const double *rest, double *out);
+int oracle_shell_features(int64_t nv, int64_t nt, const int32_t *tris, const double *rest8, const double *x,
+                          double *z);
+int oracle_shell_density(int64_t n, const double *z, const double *params, double *W, double *dW);
+int oracle_mlp_eval(int64_t n, const double *z, const double *params, double *psi, double *dpsi, double *d2psi);
 
 /* symmetric eigen-clamp of an n x n matrix (cyclic Jacobi, Sec. 7.1 filtering) */
 int oracle_spd_project(int n, const double *A, double eps, double *out);

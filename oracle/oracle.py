@@ -15,11 +15,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR, MLP = 1, 2, 3, 4, 5, 6, 7
+EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI = 1, 2, 3, 4, 5, 6, 7, 8
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 
-STENCIL = {EDGE_SQLEN: 2, TRI_AREA: 3, DIRICHLET: 3, STVK: 3, BENDING: 4, SYMDIR: 3, MLP: 3}
-VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3}
+STENCIL = {EDGE_SQLEN: 2, TRI_AREA: 3, DIRICHLET: 3, STVK: 3, BENDING: 4, SYMDIR: 3, MLP: 3, SHELL_TRI: 3}
+VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3, SHELL_TRI: 3}
 
 
 def build(force: bool = False) -> str:
@@ -139,19 +139,133 @@ def pattern(nv: int, stencils: list[np.ndarray]) -> tuple[np.ndarray, np.ndarray
     return rowptr, colidx
 
 
-def element(kind: int, xloc, rest=None, params=None, mode: int = ENERGY | GRAD | HESS, spd_eps: float = 0.0):
-    """One element: returns (f, g[k], H[k, k])."""
+def element(kind: int, xloc, rest=None, params=None, mode: int = ENERGY | GRAD | HESS, spd_eps: float = 0.0,
+            aux=None):
+    """One element: returns (f, g[k], H[k, k]). aux: the three unit vertex normals of the
+    shell-feature kinds (SHELL_TRI, MLP)."""
     k = STENCIL[kind] * VARDIM[kind]
     xl = np.ascontiguousarray(xloc, dtype=np.float64).ravel()
     assert xl.size == k
     rs = None if rest is None else np.ascontiguousarray(rest, dtype=np.float64).ravel()
     pr = np.ascontiguousarray(params if params is not None else [0.0, 0.0], dtype=np.float64).ravel()
+    ax = None if aux is None else np.ascontiguousarray(aux, dtype=np.float64).ravel()
     f = C.c_double()
     g = np.zeros(k)
     H = np.zeros((k, k))
-    _check(lib().oracle_element(C.c_int(kind), _p(pr), _p(rs), _p(xl), C.c_int(mode), C.c_double(spd_eps),
-                                C.byref(f), _p(g), _p(H)), "element")
+    _check(lib().oracle_element(C.c_int(kind), _p(pr), _p(rs), _p(ax), _p(xl), C.c_int(mode),
+                                C.c_double(spd_eps), C.byref(f), _p(g), _p(H)), "element")
     return f.value, g, H
+
+
+# ---- per-triangle shell features, analytic density and the learned density -----------------------
+def vertex_normals(tris: np.ndarray, x: np.ndarray, nv: int) -> np.ndarray:
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros((nv, 3))
+    _check(lib().oracle_vertex_normals(C.c_int64(nv), C.c_int64(tris.shape[0]), _p(tris), _p(x), _p(out)),
+           "vertex_normals")
+    return out
+
+
+def rest_shell(tris: np.ndarray, rest: np.ndarray, nv: int) -> np.ndarray:
+    """Per-triangle rest data [T, 8] = (Dm^{-1} row-major, rest area, rest II00, II11, II01)."""
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    rest = np.ascontiguousarray(rest, dtype=np.float64)
+    out = np.zeros((tris.shape[0], 8))
+    _check(lib().oracle_rest_shell(C.c_int64(nv), C.c_int64(tris.shape[0]), _p(tris), _p(rest), _p(out)),
+           "rest_shell")
+    return out
+
+
+def shell_features(tris: np.ndarray, rest8: np.ndarray, x: np.ndarray, nv: int) -> np.ndarray:
+    """Feature vectors z [T, 6] at positions x."""
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    z = np.zeros((tris.shape[0], 6))
+    _check(lib().oracle_shell_features(C.c_int64(nv), C.c_int64(tris.shape[0]), _p(tris),
+                                       _p(np.ascontiguousarray(rest8, dtype=np.float64)),
+                                       _p(np.ascontiguousarray(x, dtype=np.float64)), _p(z)), "shell_features")
+    return z
+
+
+def shell_density(z: np.ndarray, params) -> tuple[np.ndarray, np.ndarray]:
+    """Analytic density W(z) and dW/dz (params: mu, lambda, k_b)."""
+    z = np.ascontiguousarray(z, dtype=np.float64).reshape(-1, 6)
+    pr = np.ascontiguousarray(params, dtype=np.float64)
+    W = np.zeros(z.shape[0])
+    dW = np.zeros_like(z)
+    _check(lib().oracle_shell_density(C.c_int64(z.shape[0]), _p(z), _p(pr), _p(W), _p(dW)), "shell_density")
+    return W, dW
+
+
+def mlp_eval(z: np.ndarray, params: np.ndarray, hess: bool = False):
+    """psi(z), dpsi/dz [n, 6] and, if asked, d2psi/dz2 [n, 6, 6] by hyper-dual arithmetic."""
+    z = np.ascontiguousarray(z, dtype=np.float64).reshape(-1, 6)
+    pr = np.ascontiguousarray(params, dtype=np.float64)
+    n = z.shape[0]
+    psi = np.zeros(n)
+    d = np.zeros((n, 6))
+    h = np.zeros((n, 6, 6)) if hess else None
+    _check(lib().oracle_mlp_eval(C.c_int64(n), _p(z), _p(pr), _p(psi), _p(d), _p(h)), "mlp_eval")
+    return (psi, d, h) if hess else (psi, d)
+
+
+MLP_PARTS = ("W1", "b1", "W2", "b2", "w3", "b3")   # trainable parameters, in packing order
+
+
+def mlp_pack(s_out: float, s_in, W1, b1, W2, b2, w3, b3) -> np.ndarray:
+    """The parameter block [H, s_out, s_in(6), W1(H x 6), b1, W2(H x H), b2, w3, b3]."""
+    H = np.asarray(W1).shape[0]
+    return np.concatenate([[float(H), float(s_out)], np.asarray(s_in, float).ravel(), np.asarray(W1, float).ravel(),
+                           np.asarray(b1, float).ravel(), np.asarray(W2, float).ravel(),
+                           np.asarray(b2, float).ravel(), np.asarray(w3, float).ravel(), [float(b3)]])
+
+
+def mlp_unpack(params: np.ndarray) -> dict:
+    p = np.asarray(params, dtype=np.float64)
+    H = int(p[0])
+    o = 8
+    out = {"H": H, "s_out": p[1], "s_in": p[2:8]}
+    for name, size in (("W1", 6 * H), ("b1", H), ("W2", H * H), ("b2", H), ("w3", H), ("b3", 1)):
+        out[name] = p[o:o + size].copy()
+        o += size
+    out["W1"] = out["W1"].reshape(H, 6)
+    out["W2"] = out["W2"].reshape(H, H)
+    out["b3"] = float(out["b3"][0])
+    return out
+
+
+def mlp_loss_grad(params: np.ndarray, z: np.ndarray, W: np.ndarray, dW: np.ndarray, c_e: float, c_g: float,
+                  lam_g: float) -> tuple[float, np.ndarray]:
+    """Training loss and its gradient over the trainable parameters (W1, b1, W2, b2, w3, b3, in
+    packing order), by reverse-mode differentiation in FP64 on the CPU:
+        loss = mean_i (psi(z_i) - W_i)^2 / c_e + lam_g mean_i |dpsi/dz(z_i) - dW_i|^2 / c_g."""
+    import torch
+    u = mlp_unpack(params)
+    T = {k: torch.tensor(u[k], dtype=torch.float64, requires_grad=True) for k in MLP_PARTS}
+    s_in = torch.tensor(u["s_in"], dtype=torch.float64)
+    zz = torch.tensor(np.asarray(z, dtype=np.float64).reshape(-1, 6), requires_grad=True)
+
+    def sp(a):   # softplus, exactly log(1 + e^a)
+        return torch.logaddexp(a, torch.zeros_like(a))
+    h1 = sp((zz * s_in) @ T["W1"].T + T["b1"])
+    h2 = sp(h1 @ T["W2"].T + T["b2"])
+    psi = u["s_out"] * (h2 @ T["w3"] + T["b3"])
+    (dpsi,) = torch.autograd.grad(psi.sum(), zz, create_graph=True)
+    Wt = torch.tensor(np.asarray(W, dtype=np.float64))
+    dWt = torch.tensor(np.asarray(dW, dtype=np.float64).reshape(-1, 6))
+    loss = ((psi - Wt) ** 2).mean() / c_e + lam_g * ((dpsi - dWt) ** 2).sum(dim=1).mean() / c_g
+    grads = torch.autograd.grad(loss, [T[k] for k in MLP_PARTS])
+    return float(loss.detach()), np.concatenate([g.detach().numpy().ravel() for g in grads])
+
+
+def adam_step(theta: np.ndarray, grad: np.ndarray, m: np.ndarray, v: np.ndarray, t: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma and Ba), step number t >= 1; returns (theta, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return theta - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
 def spd_project(A: np.ndarray, eps: float = 0.0) -> np.ndarray:
@@ -208,9 +322,12 @@ class Problem:
     def add_term(self, kind: int, params=(0.0, 0.0)):
         if VARDIM[kind] != self.d:
             raise ValueError("term VarDim does not match the problem")
-        prm = np.zeros(4)
+        prm = np.zeros(max(4, len(params)))
         prm[:len(params)] = params
-        if kind == BENDING:
+        if kind in (SHELL_TRI, MLP):
+            st = self.tris
+            rs = rest_shell(self.tris, self.rest_pos, self.nv)
+        elif kind == BENDING:
             st = self.topo.diamonds
             rs = rest_diamond(self.topo, self.tris, self.rest_pos)
         elif kind in (DIRICHLET, STVK, SYMDIR):

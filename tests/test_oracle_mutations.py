@@ -10,6 +10,7 @@ import pytest
 from oracle import oracle as O
 import tests.test_oracle_elements as TE
 import tests.test_oracle_assembly as TA
+import tests.test_oracle_shell as TS
 
 MUTANTS = {
     "product_rule_drops_cross_term": ("+ a.g[i] * b.g[j] + b.g[i] * a.g[j];", "+ a.g[i] * b.g[j];"),
@@ -37,6 +38,20 @@ MUTANTS = {
     "assembly_transposes_block": ("Hp[(a * d + i) * k + (b * d + j)]", "Hp[(a * d + j) * k + (b * d + i)]"),
     "diamond_wrong_wing": ("d[3] = rec[i + 1].opp;", "d[3] = rec[i].opp;"),
     "neumaier_wrong_sign": ("c += (s - t) + v[i];", "c += (s - t) - v[i];"),
+    "shell_ii_wrong_sign": ("z[3 + q] = hd_addc(hd_scale(ii, -0.5), -rest[5 + q]);",
+                            "z[3 + q] = hd_addc(hd_scale(ii, 0.5), -rest[5 + q]);"),
+    "shell_ii_drops_symmetric_part": ("ii = hd_add(ii, hd_add(hd_scale(F[i][b], N[i][a]), hd_scale(F[i][a], N[i][b])));",
+                                      "ii = hd_add(ii, hd_scale(hd_scale(F[i][b], N[i][a]), 2.0));"),
+    "shell_n_transposed_dminv": ("N[i][j] = dn1 * mi[0 * 2 + j] + dn2 * mi[1 * 2 + j];",
+                                 "N[i][j] = dn1 * mi[j * 2 + 0] + dn2 * mi[j * 2 + 1];"),
+    "shell_plain_ii_wrong_rest": ("z[6 * f + 3 + q] = -0.5 * ii - mi[5 + q];", "z[6 * f + 3 + q] = -0.5 * ii + mi[5 + q];"),
+    "shell_density_drops_factor_two": ("hd b2 = hd_add(hd_add(hd_sq(z[3]), hd_sq(z[4])), hd_scale(hd_sq(z[5]), 2.0));",
+                                       "hd b2 = hd_add(hd_add(hd_sq(z[3]), hd_sq(z[4])), hd_sq(z[5]));"),
+    "softplus_wrong_second": ("return hd_unary(a, softplus(a.v), s, s * (1.0 - s));",
+                              "return hd_unary(a, softplus(a.v), s, s * s);"),
+    "mlp_transposed_w2": ("a = hd_add(a, hd_scale(h1[n], W2[m * H + n]));", "a = hd_add(a, hd_scale(h1[n], W2[n * H + m]));"),
+    "mlp_input_scale_dropped": ("xin[i] = hd_scale(z[i], sin_[i]);", "xin[i] = z[i];"),
+    "normals_not_normalized": ("for (int d = 0; d < 3; ++d) n[d] /= l;", "for (int d = 0; d < 3; ++d) n[d] /= 1.0;"),
 }
 
 PINS = [TE.test_edge_sqlen_closed_form, TE.test_area_gradient_matches_paper_closed_form,
@@ -51,7 +66,13 @@ PINS = [TE.test_edge_sqlen_closed_form, TE.test_area_gradient_matches_paper_clos
         TA.test_topology_two_triangles_diamond_order, lambda: TA.test_pattern_brute_force("grid3"),
         lambda: TA.test_pattern_brute_force("nonmanifold"),
         lambda: TA.test_assembly_equals_dense_sum("grid3", True), TA.test_dirichlet_assembly_is_cotangent_laplacian,
-        TA.test_neumaier_matches_exact_sum]
+        TA.test_neumaier_matches_exact_sum,
+        TS.test_features_vanish_at_rest_and_are_rigid_invariant, TS.test_membrane_part_equals_stvk_element,
+        TS.test_sphere_normals_give_second_form_minus_first_over_radius,
+        TS.test_cylinder_normals_second_form_closed_form, TS.test_plain_features_equal_hyper_dual_features,
+        TS.test_vertex_normals_closed_forms, TS.test_shell_element_fd_and_invariance,
+        TS.test_one_neuron_network_closed_form, TS.test_network_derivatives_fd_and_reverse_mode_agree,
+        TS.test_mlp_element_is_area_times_network_of_features, TS.test_shell_density_closed_form_gradient_by_fd]
 
 
 def run_pins():
