@@ -47,9 +47,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--workload", choices=["shell", "batched"], default="shell")
+    ap.add_argument("--workload", choices=["shell", "batched", "mlp"], default="shell")
     ap.add_argument("--n", type=int, default=1024, help="grid side of the shell workload")
     ap.add_argument("--meshes", type=int, default=700, help="meshes of the batched workload")
+    ap.add_argument("--mlp-n", type=int, default=708, help="grid side of the learned-density workload")
     ap.add_argument("--patch-faces", type=int, default=0)
     ap.add_argument("--scatter", choices=["patch", "atomic"], default="patch")
     ap.add_argument("--persistent", action="store_true")
@@ -78,20 +79,36 @@ def workload(args):
         inp = meshgen.shell_cylinder(n=args.n, seed=2001)
         desc = (f"elastic shell StVK+bending, {args.n}x{args.n} grid half cylinder, noise sigma=1e-3 h, "
                 f"SPD-projected Hessians, block-CSR 3x3")
-    else:
+    elif args.workload == "batched":
         inp = meshgen.icosphere_batch(n_meshes=args.meshes)
         desc = (f"batched: {args.meshes} geodesic icospheres (lognormal sizes), StVK+bending, one launch, "
                 f"per-mesh FP64 energies, SPD-projected Hessians, block-CSR 3x3")
+    else:
+        inp = meshgen.shell_cylinder(n=args.mlp_n, seed=5001)
+        desc = (f"learned density: 6-64-64-1 softplus network per triangle (BF16 weights, FP32 accumulation on "
+                f"MFMA), forward-mode grad + SPD-projected 9x9 Hessian, {args.mlp_n}x{args.mlp_n} grid half "
+                f"cylinder, block-CSR 3x3")
     return inp, desc
 
 
-def cpu_sample(inp, budget):
+def seeded_network(mad, seed=5003):
+    """A network with seeded random weights (evaluation speed does not depend on the values)."""
+    import numpy as np
+    r = np.random.default_rng(seed)
+    H = mad.MLP_HIDDEN
+    theta = np.concatenate([r.normal(scale=0.5, size=6 * H), r.normal(scale=0.5, size=H),
+                            r.normal(scale=1.0 / H ** 0.5, size=H * H), r.normal(scale=0.5, size=H),
+                            r.normal(scale=0.3, size=H), [0.1]]).astype(np.float32)
+    return mad.Network(theta, np.array([60, 60, 80, 2, 1, 2], np.float32), 1.0)
+
+
+def cpu_sample(inp, budget, per_vertex=5.0):
     """A bounded piece of the workload for the oracle: leading grid rows of the shell, or the first
-    meshes of the batch, about `budget` elements."""
+    meshes of the batch, about `budget` elements (`per_vertex` elements per vertex)."""
     import numpy as np
     if inp.comp_offsets is None:
         n = inp.meta["n"]
-        rows = max(2, min(n, int(budget / (5.0 * n))))
+        rows = max(2, min(n, int(budget / (per_vertex * n))))
         nv = rows * n
         what = f"first {rows} of {n} grid rows of the same shell"
     else:
@@ -105,15 +122,25 @@ def cpu_sample(inp, budget):
     return inp.tris[sel], inp.rest[:nv], inp.x[:nv], nv, what
 
 
-def cpu_baseline(inp, budget):
-    """The FP64 oracle timed on a bounded sample of the same workload (serial C)."""
+def cpu_baseline(inp, budget, mlp=None):
+    """The FP64 oracle timed on a bounded sample of the same workload (serial C). With a network:
+    the learned-density form (the oracle gets the same parameters in FP64)."""
+    import numpy as np
     from oracle import oracle as O
-    tris, rest, x, nv, what = cpu_sample(inp, budget)
+    tris, rest, x, nv, what = cpu_sample(inp, budget, per_vertex=2.0 if mlp is not None else 5.0)
     P = O.Problem(tris, rest, nv, 3)
-    for k, prm in SHELL_TERMS:
-        P.add_term({4: O.STVK, 5: O.BENDING}[k], prm)
+    if mlp is not None:
+        t = mlp.params(1).astype(np.float64)
+        H = 64
+        W1, b1 = t[:6 * H].reshape(H, 6), t[6 * H:7 * H]
+        W2, b2 = t[7 * H:7 * H + H * H].reshape(H, H), t[7 * H + H * H:8 * H + H * H]
+        w3, b3 = t[8 * H + H * H:9 * H + H * H], t[9 * H + H * H]
+        P.add_term(O.MLP, O.mlp_pack(mlp.s_out, mlp.s_in.astype(np.float64), W1, b1, W2, b2, w3, b3))
+    else:
+        for k, prm in SHELL_TERMS:
+            P.add_term({4: O.STVK, 5: O.BENDING}[k], prm)
     P.build_pattern()
-    n_el = int(tris.shape[0]) + int(P.topo.diamonds.shape[0])
+    n_el = int(tris.shape[0]) + (int(P.topo.diamonds.shape[0]) if mlp is None else 0)
     t0 = time.perf_counter()
     P.eval(x, O.ENERGY | O.GRAD | O.HESS | O.SPD, scales=False)
     dt = time.perf_counter() - t0
@@ -126,7 +153,7 @@ def cpu_baseline(inp, budget):
     except OSError:
         pass
     return {"value": n_el / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}: {n_el} elements (StVK triangles + bending diamonds), energy + gradient + "
+            "sample": f"{what}: {n_el} elements ({'learned-density triangles' if mlp is not None else 'StVK triangles + bending diamonds'}), energy + gradient + "
                       f"SPD-projected Hessian + assembly, FP64, one thread, {dt:.1f} s on {cpu}; "
                       f"host nproc {os.cpu_count()}"}
 
@@ -172,11 +199,19 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "note": "each copy reads and writes this many bytes"}), flush=True)
 
 
-def make_problem(mad, mesh, inp, prec, args, stream):
+def make_problem(mad, mesh, inp, prec, args, stream, form=None):
+    """form: "plain" (StVK + bending), "mlp" (learned density), "analytic" (shell-triangle density);
+    default: the workload's own."""
+    form = form or ("mlp" if args.workload == "mlp" else "plain")
     scatter = mad.SCATTER_PATCH if args.scatter == "patch" else mad.SCATTER_ATOMIC
     prob = mad.Problem(mesh, 3, prec, patch_faces=args.patch_faces, scatter=scatter)
-    for k, prm in SHELL_TERMS:
-        prob.add_term(k, prm, inp.rest)
+    if form == "mlp":
+        prob.add_mlp_term(seeded_network(mad), inp.rest)
+    elif form == "analytic":
+        prob.add_term(mad.SHELL_TRI, (1.0, 1.0, 1.0), inp.rest)
+    else:
+        for k, prm in SHELL_TERMS:
+            prob.add_term(k, prm, inp.rest)
     prob.finalize(stream)
     if args.persistent:
         lay = prob.layout()
@@ -237,7 +272,7 @@ def main():
     x = torch.from_numpy(inp.x.ravel().copy()).cuda()
     out = prob.outputs()
     mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
-    n_elem = mesh.n_tris + mesh.n_diamonds
+    n_elem = mesh.n_tris + (mesh.n_diamonds if args.workload != "mlp" else 0)
     tune = None
     if args.autotune or args.workload == "batched":
         t1 = time.perf_counter()
@@ -254,20 +289,24 @@ def main():
     ms_per_step = max(wall * 1e3, sum(step_ms)) / args.steps
     nonfinite, fallbacks = prob.status()
 
-    n_terms = len(SHELL_TERMS)
+    n_terms = len(SHELL_TERMS) if args.workload != "mlp" else 1
     if layout["scatter"] == mad.SCATTER_PATCH:
-        dom_name = "k_eval_patch (StVK + bending fused)"
-        dom_ms = stage_ms[1] / n_evals
-        stages = {"fill": stage_ms[0] / n_evals, "fused": stage_ms[1] / n_evals,
-                  "gather_and_fp64_redo": stage_ms[2] / n_evals, "energy": stage_ms[-1] / n_evals}
+        dom_name = ("k_eval_patch (learned-density chain + clamp + assembly)" if args.workload == "mlp"
+                    else "k_eval_patch (StVK + bending fused)")
+        dom_ms = stage_ms[2] / n_evals
+        stages = {"fill": stage_ms[0] / n_evals, "network": stage_ms[1] / n_evals, "fused": stage_ms[2] / n_evals,
+                  "gather_and_fp64_redo": stage_ms[3] / n_evals, "energy": stage_ms[-1] / n_evals}
     else:
-        term_ms = stage_ms[1:1 + n_terms]
+        term_ms = stage_ms[2:2 + n_terms]
         dom = int(np.argmax(term_ms))
         dom_ms = term_ms[dom] / n_evals
         dom_name = ["k_eval<StVK>", "k_eval<bending>"][dom]
         stages = {"fill": stage_ms[0] / n_evals, "stvk": term_ms[0] / n_evals, "bending": term_ms[1] / n_evals,
                   "energy": stage_ms[-1] / n_evals}
-    step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, mesh.n_diamonds, prob.nnzb, pb)
+    if args.workload == "mlp":   # triangles only, 8 rest doubles each
+        step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, 0, prob.nnzb, pb) + mesh.n_tris * 24
+    else:
+        step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, mesh.n_diamonds, prob.nnzb, pb)
     fpe = FLOPS_PER_ELEM.get(args.precision) if args.workload == "shell" else None
     peak = VALU_PEAK_TFLOPS[args.precision]
     if fpe and layout["scatter"] == mad.SCATTER_PATCH:
@@ -306,13 +345,43 @@ def main():
     }
     if tune is not None:
         res["autotune"] = tune
+    if args.workload == "mlp":
+        # network pass (normals + MFMA contraction): useful flops = 28 channels x 64 x 64 x 2 per
+        # triangle; the matrix cores execute three BF16 passes of it (hi/mid/lo activations)
+        net_ms = stage_ms[1] / n_evals
+        useful = 28 * 64 * 64 * 2 * mesh.n_tris
+        res["network_pass"] = {"ms": net_ms, "useful_TFLOPs": useful / (net_ms * 1e-3) / 1e12,
+                               "mfma_bf16_TFLOPs": 3 * useful / (net_ms * 1e-3) / 1e12,
+                               "mfma_bf16_peak": 2500.0,
+                               "mfma_frac": 3 * useful / (net_ms * 1e-3) / 1e12 / 2500.0}
+        res["vs_other_forms"] = other_forms(torch, mad, mesh, inp, args, stream, x, ms_per_step)
     if args.workload == "batched":
         res["one_launch_per_mesh"] = per_mesh_baseline(torch, mad, inp, prec, stream, ms_per_step, args)
     if prec == mad.F32 and not args.no_fp64_plain:
         res["vs_fp64_plain"] = fp64_plain(torch, mad, mesh, inp, args, stream, x, out, ms_per_step)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(inp, args.cpu_elements)
+        if args.workload == "mlp":
+            res["cpu_baseline"] = cpu_baseline(inp, 7000, mlp=seeded_network(mad))
+        else:
+            res["cpu_baseline"] = cpu_baseline(inp, args.cpu_elements)
     print(json.dumps(res), flush=True)
+
+
+def other_forms(torch, mad, mesh, inp, args, stream, x, ms_mlp):
+    """The same mesh with the plain StVK + dihedral form and with the analytic shell-triangle density."""
+    out = {}
+    mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
+    for form in ("plain", "analytic"):
+        p = make_problem(mad, mesh, inp, mad.F32, args, stream, form=form)
+        o = p.outputs()
+        step_ms, wall = time_steps(torch, lambda: p.eval(x, mode, out=o, stream=stream), max(5, args.steps // 2),
+                                   3, stream)
+        ms = max(wall * 1e3, sum(step_ms)) / len(step_ms)
+        n_el = mesh.n_tris + (mesh.n_diamonds if form == "plain" else 0)
+        out[form] = {"ms_per_step": ms, "elements": n_el, "nnzb": p.nnzb,
+                     "learned_speedup": ms / ms_mlp}
+        del p, o
+    return out
 
 
 def fp64_plain(torch, mad, mesh, inp, args, stream, x, out32, ms32):

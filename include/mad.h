@@ -39,6 +39,7 @@ extern "C" {
 
 typedef struct mad_mesh mad_mesh;
 typedef struct mad_problem mad_problem;
+typedef struct mad_mlp mad_mlp;
 
 typedef enum mad_status {
     MAD_OK = 0,
@@ -65,6 +66,16 @@ typedef enum mad_status {
  *                  non-manifold edges (three or more faces) carry no bending term.
  *  MAD_SYMDIR      face, VarDim 2 (Sec. 7.2): A (|J|_F^2 + |J^{-1}|_F^2). params unused.
  *                  Needs rest positions.
+ * The last two kinds are project-defined (the paper has no learned component). Both read the
+ * per-triangle features z = (E00, E11, E01, II00 - rII00, II11 - rII11, II01 - rII01): E the
+ * Green strain as above, II = -(N^T F + F^T N)/2 with N = [n_b - n_a, n_c - n_a] Dm^{-1} from the
+ * area-weighted unit vertex normals of the current positions (recomputed every evaluation, not
+ * differentiated), rII the same form on the rest mesh. Both need rest positions.
+ *  MAD_MLP         face, VarDim 3: A psi(z), psi the network of a mad_mlp; added with
+ *                  mad_problem_add_mlp_term, not mad_problem_add_term.
+ *  MAD_SHELL_TRI   face, VarDim 3: A W(z), W = mu (E00^2 + E11^2 + 2 E01^2) + lambda/2 (E00 + E11)^2
+ *                  + k_b/2 (dII00^2 + dII11^2 + 2 dII01^2). params = {mu, lambda, k_b}. The
+ *                  analytic density the network is trained on (its fallback and error judge).
  */
 typedef enum mad_term_kind {
     MAD_EDGE_SQLEN = 1,
@@ -72,7 +83,9 @@ typedef enum mad_term_kind {
     MAD_DIRICHLET = 3,
     MAD_STVK = 4,
     MAD_BENDING = 5,
-    MAD_SYMDIR = 6
+    MAD_SYMDIR = 6,
+    MAD_MLP = 7,
+    MAD_SHELL_TRI = 8
 } mad_term_kind;
 
 /* evaluation mode bits (Sec. 6.2: passive, gradient-only, full Hessian; Sec. 7.1 filtering) */
@@ -176,17 +189,17 @@ int32_t mad_problem_eval(mad_problem *prob, const double *x_dev, uint32_t mode, 
 int32_t mad_problem_status(mad_problem *prob, int32_t *nonfinite, int64_t *fp64_fallbacks, void *stream);
 
 /* Per-stage timing (profiling aid). enable = 1 starts recording HIP events on the eval stream
- * around each stage of every mad_problem_eval (zero fill, one kernel per term, energy reduction)
+ * around each stage of every mad_problem_eval (zero fill, network pass, element kernels, energy)
  * and clears earlier records; enable = 0 stops recording. Recording adds no synchronisation. */
 int32_t mad_problem_set_profiling(mad_problem *prob, int32_t enable);
 
 /* Synchronise with the recorded events and report, summed over the evaluations recorded since
- * profiling was enabled, with S = max(n_terms, 2): ms_out[0] zero fills; with MAD_SCATTER_ATOMIC
- * ms_out[1 + t] the kernel of term t (in add order); with MAD_SCATTER_PATCH ms_out[1] the fused
- * kernel and ms_out[2] the gather of shared entries plus the FP64 redo of queued FP32 elements;
- * ms_out[1 + S] the energy
- * reduction. *n_stages = S + 2, *n_evals = evaluations. ms_out must hold at least 10 doubles.
- * Records are kept (call set_profiling(1) to clear). */
+ * profiling was enabled, with S = max(n_terms, 2): ms_out[0] zero fills; ms_out[1] the vertex
+ * normals and network passes of shell-feature terms (0 without them); with MAD_SCATTER_ATOMIC
+ * ms_out[2 + t] the kernel of term t (in add order); with MAD_SCATTER_PATCH ms_out[2] the fused
+ * kernel and ms_out[3] the gather of shared entries plus the FP64 redo of queued FP32 elements;
+ * ms_out[2 + S] the energy reduction. *n_stages = S + 3, *n_evals = evaluations. ms_out must hold
+ * at least 12 doubles. Records are kept (call set_profiling(1) to clear). */
 int32_t mad_problem_profile(mad_problem *prob, double *ms_out, int32_t *n_stages, int64_t *n_evals);
 
 /* Current evaluation layout (any output may be NULL): scatter strategy, effective patch target
@@ -220,6 +233,55 @@ int32_t mad_problem_autotune(mad_problem *prob, const double *x_dev, uint32_t mo
 int32_t mad_problem_tune_report(const mad_problem *prob, char *buf, int64_t cap, int64_t *len);
 
 int32_t mad_problem_destroy(mad_problem *prob);
+
+/* ---- learned per-triangle density (project-defined) ------------------------------------------
+ * psi(z) = s_out (w3 . sp(W2 sp(W1 (s_in * z) + b1) + b2) + b3), sp(a) = log(1 + e^a), hidden
+ * width 64. Trainable parameters, packed in this order, row-major (4673 floats):
+ * W1 [64][6], b1 [64], W2 [64][64], b2 [64], w3 [64], b3. The library keeps an FP32 master copy
+ * (trained) and a BF16 copy (round to nearest even) that evaluation uses: layer 2 runs on the
+ * matrix cores with BF16 weights and FP32 accumulation. */
+enum { MAD_MLP_HIDDEN = 64, MAD_MLP_PARAMS = 4673 };
+
+/* Create a network on the current device. hidden must be 64. params_host: MAD_MLP_PARAMS floats
+ * (copied); s_in_host: 6 input scales; s_out: output scale. */
+int32_t mad_mlp_create(int32_t hidden, const float *params_host, const float *s_in_host, float s_out,
+                       mad_mlp **out);
+
+/* Replace the parameters (FP32 master and BF16 copy); resets Adam's moments and step count. */
+int32_t mad_mlp_set_params(mad_mlp *mlp, const float *params_host);
+
+/* Copy the parameters to host memory: which = 0 the FP32 master, 1 the BF16 copy widened to FP32. */
+int32_t mad_mlp_get_params(const mad_mlp *mlp, int32_t which, float *params_host);
+
+/* Training loss and gradient over a batch, on the stream (no host synchronisation):
+ *   loss = mean_b (psi(z_b) - W_b)^2 / c_e + lam_g mean_b sum_i (dpsi/dz_i(z_b) - dW_bi)^2 / c_g[i]
+ * (c_g_host: 6 per-feature normalisers, copied) over the samples idx_dev[base .. base + count) (idx_dev NULL: samples base .. base + count) of
+ * z_dev [N][6], W_dev [N], dW_dev [N][6] (device FP32). Uses the FP32 master parameters.
+ * grad_dev: MAD_MLP_PARAMS floats, loss_dev: 1 float (device). Deterministic: per-wave partial
+ * sums are reduced in a fixed order. count must be >= 1. */
+int32_t mad_mlp_loss_grad(mad_mlp *mlp, const float *z_dev, const float *W_dev, const float *dW_dev,
+                          const int32_t *idx_dev, int64_t base, int64_t count, float c_e, const float *c_g_host,
+                          float lam_g, float *grad_dev, float *loss_dev, void *stream);
+
+/* One Adam step (Kingma and Ba) on the FP32 master with the gradient grad_dev (device), step
+ * count incremented first on the device; refreshes the BF16 copy. */
+int32_t mad_mlp_adam_step(mad_mlp *mlp, const float *grad_dev, float lr, float beta1, float beta2, float eps,
+                          void *stream);
+
+/* One pass over the samples in the order perm_dev [n] (device int32, a permutation the caller
+ * draws): minibatches of `batch` consecutive entries (the last may be shorter), each a loss_grad
+ * followed by an Adam step. loss_hist_dev (nullable): one float per minibatch. No host sync. */
+int32_t mad_mlp_train_epoch(mad_mlp *mlp, const float *z_dev, const float *W_dev, const float *dW_dev,
+                            const int32_t *perm_dev, int64_t n, int32_t batch, float c_e, const float *c_g_host,
+                            float lam_g, float lr, float beta1, float beta2, float eps, float *loss_hist_dev,
+                            void *stream);
+
+int32_t mad_mlp_destroy(mad_mlp *mlp);
+
+/* Add a learned-density term (MAD_MLP) over every triangle. The network must live on the
+ * problem's device and outlive the problem; each evaluation reads its current BF16 parameters.
+ * rest_pos_host: [n_verts][3] rest positions (copied). */
+int32_t mad_problem_add_mlp_term(mad_problem *prob, const mad_mlp *mlp, const double *rest_pos_host);
 
 #ifdef __cplusplus
 }

@@ -234,11 +234,12 @@ def mlp_unpack(params: np.ndarray) -> dict:
     return out
 
 
-def mlp_loss_grad(params: np.ndarray, z: np.ndarray, W: np.ndarray, dW: np.ndarray, c_e: float, c_g: float,
+def mlp_loss_grad(params: np.ndarray, z: np.ndarray, W: np.ndarray, dW: np.ndarray, c_e: float, c_g,
                   lam_g: float) -> tuple[float, np.ndarray]:
     """Training loss and its gradient over the trainable parameters (W1, b1, W2, b2, w3, b3, in
     packing order), by reverse-mode differentiation in FP64 on the CPU:
-        loss = mean_i (psi(z_i) - W_i)^2 / c_e + lam_g mean_i |dpsi/dz(z_i) - dW_i|^2 / c_g."""
+        loss = mean_i (psi(z_i) - W_i)^2 / c_e + lam_g mean_i sum_q (dpsi/dz_q(z_i) - dW_iq)^2 / c_g[q]
+    (c_g: one normaliser per feature, or a scalar for all)."""
     import torch
     u = mlp_unpack(params)
     T = {k: torch.tensor(u[k], dtype=torch.float64, requires_grad=True) for k in MLP_PARTS}
@@ -253,7 +254,8 @@ def mlp_loss_grad(params: np.ndarray, z: np.ndarray, W: np.ndarray, dW: np.ndarr
     (dpsi,) = torch.autograd.grad(psi.sum(), zz, create_graph=True)
     Wt = torch.tensor(np.asarray(W, dtype=np.float64))
     dWt = torch.tensor(np.asarray(dW, dtype=np.float64).reshape(-1, 6))
-    loss = ((psi - Wt) ** 2).mean() / c_e + lam_g * ((dpsi - dWt) ** 2).sum(dim=1).mean() / c_g
+    cg = torch.tensor(np.broadcast_to(np.asarray(c_g, dtype=np.float64), (6,)).copy())
+    loss = ((psi - Wt) ** 2).mean() / c_e + lam_g * (((dpsi - dWt) ** 2) / cg).sum(dim=1).mean()
     grads = torch.autograd.grad(loss, [T[k] for k in MLP_PARTS])
     return float(loss.detach()), np.concatenate([g.detach().numpy().ravel() for g in grads])
 

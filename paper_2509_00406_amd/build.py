@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libmad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["kernels_patch.hip", "kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "host_patch.cpp",
-           "layout.cpp", "eval.cpp", "autotune.cpp", "api.cpp"]
+           "kernels_mlp.hip", "layout.cpp", "eval.cpp", "autotune.cpp", "mlp.cpp", "api.cpp"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 (v_pk_*_f32) instructions.
 # -munsafe-fp-atomics: hardware FP32/FP64 atomic add instead of compare-and-swap loops.

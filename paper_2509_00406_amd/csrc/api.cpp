@@ -150,8 +150,8 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
     return MAD_OK;
 }
 
-int32_t mad_problem_add_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params,
-                             const double* rest_pos) {
+static int32_t add_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params, const double* rest_pos,
+                        const mad_mlp* mlp) {
     if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
     if (p->finalized) return fail(MAD_E_STATE, "add_term after finalize");
     const int ns = kind_stencil(kind);
@@ -191,10 +191,31 @@ int32_t mad_problem_add_term(mad_problem* p, int32_t kind, const double* params,
         t.stencil = m.diamonds;
         rc = rest_diamond(m, rest_pos, t.rest);
         break;
+    case MAD_MLP: case MAD_SHELL_TRI:
+        t.n = m.nt;
+        t.stencil = m.tris;
+        t.mlp = mlp;
+        rc = rest_shell(m, rest_pos, t.rest);
+        break;
     }
     if (rc != MAD_OK) return rc;
+    if (kind == MAD_MLP || kind == MAD_SHELL_TRI) p->shell = true;
     p->terms.push_back(std::move(t));
     return MAD_OK;
+}
+
+int32_t mad_problem_add_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params,
+                             const double* rest_pos) {
+    if (kind == MAD_MLP) return fail(MAD_E_INVALID_ARG, "learned-density terms are added with mad_problem_add_mlp_term");
+    return add_term(p, kind, params, n_params, rest_pos, nullptr);
+}
+
+int32_t mad_problem_add_mlp_term(mad_problem* p, const mad_mlp* mlp, const double* rest_pos) {
+    if (!p || !mlp) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    int dev = 0;
+    MAD_HIP_TRY(hipGetDevice(&dev));
+    if (dev != mlp->device) return fail(MAD_E_INVALID_ARG, "the network lives on another device");
+    return add_term(p, MAD_MLP, nullptr, 0, rest_pos, mlp);
 }
 
 int32_t mad_problem_finalize(mad_problem* p, void* stream) {
@@ -212,6 +233,27 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
     MAD_HIP_TRY(launch_fill(p->d_flags, 4, 4, s));
     MAD_HIP_TRY(launch_fill(p->d_fallbacks, 1, 8, s));
     int rc;
+    if (p->shell) {
+        // triangles of each vertex in ascending order (the normals' fixed summation order)
+        std::vector<int32_t> ptr((size_t)m.nv + 1, 0), vf((size_t)m.nt * 3);
+        for (int64_t f = 0; f < m.nt; ++f)
+            for (int a = 0; a < 3; ++a) ptr[m.tris[3 * f + a] + 1]++;
+        for (int64_t v = 0; v < m.nv; ++v) ptr[v + 1] += ptr[v];
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t f = 0; f < m.nt; ++f)
+            for (int a = 0; a < 3; ++a) vf[fill[m.tris[3 * f + a]]++] = (int32_t)f;
+        auto up = [&](void** dst, const void* src, size_t bytes) -> int {
+            MAD_HIP_TRY(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+            p->owned.push_back(*dst);
+            if (bytes) MAD_HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+            return MAD_OK;
+        };
+        if ((rc = up((void**)&p->d_tris, m.tris.data(), m.tris.size() * 4)) != MAD_OK) return rc;
+        if ((rc = up((void**)&p->d_vf_ptr, ptr.data(), ptr.size() * 4)) != MAD_OK) return rc;
+        if ((rc = up((void**)&p->d_vf, vf.data(), vf.size() * 4)) != MAD_OK) return rc;
+        MAD_HIP_TRY(hipMalloc((void**)&p->d_normals, sizeof(double) * 3 * (size_t)std::max<int64_t>(m.nv, 1)));
+        p->owned.push_back(p->d_normals);
+    }
     // element order first (the pattern is built from the device stencils), then the pattern, then
     // the scatter structures that index into it
     if ((rc = build_layout(p, p->opt.patch_faces, p->scatter, 0, s)) != MAD_OK) return rc;
@@ -279,8 +321,8 @@ int32_t mad_problem_set_profiling(mad_problem* p, int32_t enable) {
 
 int32_t mad_problem_profile(mad_problem* p, double* ms, int32_t* n_stages, int64_t* n_evals) {
     if (!p || !ms) return fail(MAD_E_INVALID_ARG, "NULL argument");
-    const int ns = (int)std::max<size_t>(p->terms.size(), 2) + 2;
-    for (int i = 0; i < 10; ++i) ms[i] = 0.0;
+    const int ns = (int)std::max<size_t>(p->terms.size(), 2) + 3;
+    for (int i = 0; i < 12; ++i) ms[i] = 0.0;
     for (int64_t k = 0; k < p->prof_count; ++k) {
         auto& row = p->prof_events[(size_t)k];
         MAD_HIP_TRY(hipEventSynchronize(row[ns]));

@@ -16,7 +16,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
     const int eb = p->prec == MAD_F32 ? 4 : 8;
     std::vector<hipEvent_t>* ev = nullptr;
     if (p->profiling) {
-        const size_t need = std::max<size_t>(p->terms.size(), 2) + 3;
+        const size_t need = std::max<size_t>(p->terms.size(), 2) + 4;
         if ((size_t)p->prof_count >= p->prof_events.size()) {
             std::vector<hipEvent_t> row(need, nullptr);
             for (auto& e : row) MAD_HIP_TRY(hipEventCreate(&e));
@@ -34,6 +34,23 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
     if (fallback_pass) MAD_HIP_TRY(launch_fill(p->d_fb_count, 1, 4, s));
     if (p->scatter == MAD_SCATTER_PATCH && p->persistent) MAD_HIP_TRY(launch_fill(p->d_work_counter, 1, 4, s));
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[1], s));
+    // learned and analytic shell densities: vertex normals of x, then the network pass per MLP term
+    if (p->shell) MAD_HIP_TRY(launch_vertex_normals(x, m.nv, p->d_vf_ptr, p->d_vf, p->d_tris, p->d_normals, s));
+    for (const Term& t : p->terms) {
+        if (t.kind != MAD_MLP) continue;
+        MlpHeadLaunch H{};
+        H.x = x;
+        H.normals = p->d_normals;
+        H.stencil = t.d_stencil;
+        H.rest = t.d_rest;
+        H.n = t.n;
+        H.wbf = t.mlp->d_wbf;
+        for (int i = 0; i < 6; ++i) H.s_in[i] = t.mlp->s_in[i];
+        H.s_out = t.mlp->s_out;
+        H.psi = t.d_psi;
+        MAD_HIP_TRY(launch_mlp_head(H, s));
+    }
+    if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2], s));
     const int kmode = (mode & MAD_HESS) ? ((mode & MAD_SPD) ? 3 : 2) : ((mode & MAD_GRAD) ? 1 : 0);
     const int np = p->patches.n;
     int n_partial_terms = (int)p->terms.size();
@@ -70,6 +87,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.work_order = p->d_work_order;
         L.work_counter = p->d_work_counter;
         L.n_cu = p->n_cu;
+        L.normals = p->d_normals;
         for (size_t ti = 0; ti < p->terms.size(); ++ti) {
             const Term& t = p->terms[ti];
             PatchTermArgs& A = L.terms[ti];
@@ -79,10 +97,11 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
             A.lvert = t.d_lvert;
             A.lslot = t.d_lslot;
             A.elem_ptr = t.d_elem_ptr;
+            A.psi = t.d_psi;
             std::memcpy(A.prm, t.prm, sizeof(A.prm));
         }
         MAD_HIP_TRY(launch_eval_patch(L, s));
-        if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2], s));
+        if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[3], s));
         GatherLaunch G{};
         G.prec = p->prec;
         G.var_dim = d;
@@ -120,18 +139,20 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
             F.fb_cap = p->fb_cap;
             F.flags = p->d_flags;
             F.eps = p->opt.spd_eps;
+            F.normals = p->d_normals;
             for (size_t ti = 0; ti < p->terms.size(); ++ti) {
                 const Term& t = p->terms[ti];
                 F.terms[ti].kind = t.kind;
                 F.terms[ti].n = t.n;
                 F.terms[ti].stencil = t.d_stencil;
                 F.terms[ti].rest = t.d_rest;
+                F.terms[ti].psi = t.d_psi;
                 std::memcpy(F.terms[ti].prm, t.prm, sizeof(t.prm));
             }
             MAD_HIP_TRY(launch_fallback(F, s));
         }
         if (ev)
-            for (size_t k = 3; k < ev->size() - 1; ++k) MAD_HIP_TRY(hipEventRecord((*ev)[k], s));
+            for (size_t k = 4; k < ev->size() - 1; ++k) MAD_HIP_TRY(hipEventRecord((*ev)[k], s));
         n_partial_terms = 1;
     }
     for (size_t ti = 0; p->scatter == MAD_SCATTER_ATOMIC && ti < p->terms.size(); ++ti) {
@@ -156,13 +177,15 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         std::memcpy(L.prm, t.prm, sizeof(L.prm));
         L.eps = p->opt.spd_eps;
         L.qmin = p->opt.degenerate_q;
+        L.normals = p->d_normals;
+        L.psi = t.d_psi;
         MAD_HIP_TRY(launch_eval(L, s));
-        if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2 + ti], s));
+        if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[3 + ti], s));
     }
     if (mode & MAD_ENERGY) {
         const int ncomp = (int)m.comp_off.size() - 1;
         MAD_HIP_TRY(launch_energy_reduce(p->d_partial, n_partial_terms, np, p->d_comp_patch_ptr,
-                                         std::max(ncomp, 1), m.batched, energy, s));
+                                         std::max(ncomp, 1), m.batched, energy, p->d_comp_energy, s));
     }
     if (ev) MAD_HIP_TRY(hipEventRecord(ev->back(), s));
     return MAD_OK;

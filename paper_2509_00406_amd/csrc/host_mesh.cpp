@@ -14,7 +14,7 @@ namespace mad {
 int kind_stencil(int kind) {
     switch (kind) {
     case MAD_EDGE_SQLEN: return 2;
-    case MAD_TRI_AREA: case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: return 3;
+    case MAD_TRI_AREA: case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: case MAD_MLP: case MAD_SHELL_TRI: return 3;
     case MAD_BENDING: return 4;
     default: return -1;
     }
@@ -23,7 +23,7 @@ int kind_vardim(int kind) {
     switch (kind) {
     case MAD_DIRICHLET: return 1;
     case MAD_SYMDIR: return 2;
-    case MAD_EDGE_SQLEN: case MAD_TRI_AREA: case MAD_STVK: case MAD_BENDING: return 3;
+    case MAD_EDGE_SQLEN: case MAD_TRI_AREA: case MAD_STVK: case MAD_BENDING: case MAD_MLP: case MAD_SHELL_TRI: return 3;
     default: return -1;
     }
 }
@@ -31,6 +31,7 @@ int kind_nrest(int kind) {
     switch (kind) {
     case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: return 5;
     case MAD_BENDING: return 2;
+    case MAD_MLP: case MAD_SHELL_TRI: return 8;
     default: return 0;
     }
 }
@@ -125,6 +126,55 @@ int rest_tri(const mad_mesh& m, const double* X, std::vector<double>& out) {
         const int32_t* t = &m.tris[3 * f];
         if (!rest_frame(X + 3 * (int64_t)t[0], X + 3 * (int64_t)t[1], X + 3 * (int64_t)t[2], &out[5 * f], &out[5 * f + 4]))
             return fail(MAD_E_DEGENERATE_REST, "rest triangle " + std::to_string(f) + " has zero area");
+    }
+    return MAD_OK;
+}
+
+// Rest data of the shell-feature terms: Dm^{-1} (4), rest area, and the rest second form
+// rII = -(N^T F + F^T N)/2 of the rest mesh with its own area-weighted unit vertex normals
+// (F = rest Ds Dm^{-1}, N = [n_b - n_a, n_c - n_a] Dm^{-1}).
+int rest_shell(const mad_mesh& m, const double* X, std::vector<double>& out) {
+    out.assign((size_t)m.nt * 8, 0.0);
+    std::vector<double> nrm((size_t)m.nv * 3, 0.0);
+    for (int64_t f = 0; f < m.nt; ++f) {
+        const int32_t* t = &m.tris[3 * f];
+        const double *a = X + 3 * (int64_t)t[0], *b = X + 3 * (int64_t)t[1], *c = X + 3 * (int64_t)t[2];
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        for (int v = 0; v < 3; ++v)
+            for (int d = 0; d < 3; ++d) nrm[3 * (size_t)t[v] + d] += n[d];
+    }
+    for (int64_t v = 0; v < m.nv; ++v) {
+        double* n = &nrm[3 * v];
+        const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        if (l > 0.0)
+            for (int d = 0; d < 3; ++d) n[d] /= l;
+    }
+    for (int64_t f = 0; f < m.nt; ++f) {
+        const int32_t* t = &m.tris[3 * f];
+        double* o = &out[8 * f];
+        if (!rest_frame(X + 3 * (int64_t)t[0], X + 3 * (int64_t)t[1], X + 3 * (int64_t)t[2], o, o + 4))
+            return fail(MAD_E_DEGENERATE_REST, "rest triangle " + std::to_string(f) + " has zero area");
+        double F[3][2], N[3][2];
+        for (int i = 0; i < 3; ++i) {
+            const double d1 = X[3 * (int64_t)t[1] + i] - X[3 * (int64_t)t[0] + i];
+            const double d2 = X[3 * (int64_t)t[2] + i] - X[3 * (int64_t)t[0] + i];
+            const double n1 = nrm[3 * (size_t)t[1] + i] - nrm[3 * (size_t)t[0] + i];
+            const double n2 = nrm[3 * (size_t)t[2] + i] - nrm[3 * (size_t)t[0] + i];
+            for (int j = 0; j < 2; ++j) {
+                F[i][j] = d1 * o[j] + d2 * o[2 + j];
+                N[i][j] = n1 * o[j] + n2 * o[2 + j];
+            }
+        }
+        double ii00 = 0, ii11 = 0, ii01 = 0;
+        for (int i = 0; i < 3; ++i) {
+            ii00 += F[i][0] * N[i][0];
+            ii11 += F[i][1] * N[i][1];
+            ii01 += F[i][1] * N[i][0] + F[i][0] * N[i][1];
+        }
+        o[5] = -ii00;
+        o[6] = -ii11;
+        o[7] = -0.5 * ii01;
     }
     return MAD_OK;
 }

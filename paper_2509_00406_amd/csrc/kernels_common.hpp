@@ -49,6 +49,31 @@ template <class Term> __device__ __forceinline__ double quality(const double* xs
     }
 }
 
+// Number of per-element inputs a term's energy reads: rest data, then (shell-feature terms) the
+// three unit vertex normals, then (learned density) the 28 network outputs.
+template <class Term> constexpr int n_inputs() {
+    return (Term::NREST + Term::NAUX + Term::NPSI) > 0 ? Term::NREST + Term::NAUX + Term::NPSI : 1;
+}
+
+// Gather one element's inputs: rest SoA [NREST][n], normals [nv][3] at the element's global
+// vertices gv[], network outputs SoA [28][n] (FP32).
+template <class Term>
+__device__ __forceinline__ void gather_inputs(double (&in)[n_inputs<Term>()], const double* rest, int64_t n, int64_t e,
+                                              const double* normals, const int* gv, const float* psi) {
+#pragma unroll
+    for (int k = 0; k < Term::NREST; ++k) in[k] = rest[(int64_t)k * n + e];
+    if constexpr (Term::NAUX > 0) {
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) in[Term::NREST + 3 * s + c] = normals[(int64_t)gv[s] * 3 + c];
+    }
+    if constexpr (Term::NPSI > 0) {
+#pragma unroll
+        for (int k = 0; k < Term::NPSI; ++k) in[Term::NREST + Term::NAUX + k] = double(psi[(int64_t)k * n + e]);
+    }
+}
+
 template <class Term, typename T>
 __device__ __forceinline__ bool out_finite(const ElemOut<Term, T>& o, int mode) {
     constexpr int NF = Term::NS * Term::D;

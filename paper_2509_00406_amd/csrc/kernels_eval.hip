@@ -41,7 +41,7 @@ __device__ __forceinline__ void scatter_global(const ElemOut<Term, T>& o, const 
 
 template <class Term, typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_eval(EvalLaunch L) {
-    constexpr int NS = Term::NS, D = Term::D, NF = NS * D, NR = Term::NREST;
+    constexpr int NS = Term::NS, D = Term::D, NF = NS * D;
     __shared__ double red[kBlock];
     const int p = blockIdx.x;
     const int beg = L.elem_ptr[p], end = L.elem_ptr[p + 1];
@@ -56,9 +56,8 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalLaunch L) {
         for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int c = 0; c < D; ++c) xs[s * D + c] = L.x[(int64_t)vs[s] * D + c];
-        double rest[NR > 0 ? NR : 1];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) rest[k] = L.rest[(int64_t)k * L.n + e];
+        double rest[n_inputs<Term>()];
+        gather_inputs<Term>(rest, L.rest, L.n, e, L.normals, vs, L.psi);
 
         ElemOut<Term, T> o;
         if constexpr (MODE == 3 && sizeof(T) == 4) {
@@ -109,6 +108,8 @@ hipError_t launch_eval(const EvalLaunch& L, hipStream_t s) {
     case K_STVK: return launch_prec<TermStVK>(L, s);
     case K_BENDING: return launch_prec<TermBending>(L, s);
     case K_SYMDIR: return launch_prec<TermSymDir>(L, s);
+    case K_SHELL_TRI: return launch_prec<TermShellTri>(L, s);
+    case K_MLP: return launch_prec<TermMLP>(L, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -141,37 +142,48 @@ hipError_t launch_fill(void* ptr, int64_t n_elems, int elem_bytes, hipStream_t s
 
 // ---- deterministic FP64 energy reduction (Sec. 5.5 global reduction) ----------------------------
 // partial[t * n_patch + p]; patches of component c are [comp_patch_ptr[c], comp_patch_ptr[c+1]).
-// One workgroup; each lane sums a fixed strided subset in a fixed order, then a fixed tree.
-__global__ __launch_bounds__(kBlock) void k_energy_reduce(const double* partial, int n_terms, int n_patch,
-                                                          const int32_t* comp_patch_ptr, int n_comp, int batched,
-                                                          double* energy) {
+// One workgroup per component: each lane sums a fixed strided subset in a fixed order, then a fixed
+// tree. With several components a second one-workgroup pass sums the component energies the same way.
+__global__ __launch_bounds__(kBlock) void k_energy_comp(const double* partial, int n_terms, int n_patch,
+                                                        const int32_t* comp_patch_ptr, int batched, double* energy,
+                                                        double* comp_out) {
     __shared__ double red[kBlock];
-    double total = 0.0;
-    for (int c = 0; c < n_comp; ++c) {
-        const int pb = comp_patch_ptr[c], pe = comp_patch_ptr[c + 1];
-        const int np = pe - pb;
-        double acc = 0.0;
-        for (int t = 0; t < n_terms; ++t)
-            for (int i = (int)threadIdx.x; i < np; i += kBlock) acc += partial[(int64_t)t * n_patch + pb + i];
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            total += red[0];
-            if (batched) energy[1 + c] = red[0];
-        }
+    const int c = blockIdx.x;
+    const int pb = comp_patch_ptr[c], pe = comp_patch_ptr[c + 1];
+    double acc = 0.0;
+    for (int t = 0; t < n_terms; ++t)
+        for (int i = pb + (int)threadIdx.x; i < pe; i += kBlock) acc += partial[(int64_t)t * n_patch + i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) energy[0] = total;
+    if (threadIdx.x == 0) {
+        if (batched) energy[1 + c] = red[0];
+        if (gridDim.x == 1) energy[0] = red[0];
+        else comp_out[c] = red[0];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_total(const double* comp, int n_comp, double* energy) {
+    __shared__ double red[kBlock];
+    double acc = 0.0;
+    for (int i = (int)threadIdx.x; i < n_comp; i += kBlock) acc += comp[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) energy[0] = red[0];
 }
 
 hipError_t launch_energy_reduce(const double* partial, int n_terms, int n_patch, const int32_t* comp_patch_ptr,
-                                int n_comp, bool batched, double* energy, hipStream_t s) {
-    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(kBlock), 0, s, partial, n_terms, n_patch, comp_patch_ptr,
-                       n_comp, batched ? 1 : 0, energy);
+                                int n_comp, bool batched, double* energy, double* comp_scratch, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_comp, dim3(n_comp), dim3(kBlock), 0, s, partial, n_terms, n_patch, comp_patch_ptr,
+                       batched ? 1 : 0, energy, comp_scratch);
+    if (n_comp > 1) hipLaunchKernelGGL(k_energy_total, dim3(1), dim3(kBlock), 0, s, comp_scratch, n_comp, energy);
     return hipGetLastError();
 }
 

@@ -1,0 +1,448 @@
+// Kernels of the learned per-triangle density (project-defined; no paper
+// counterpart): passive vertex normals, the network pass that produces psi and
+// its first and second derivatives with respect to the six features for every
+// triangle, and the training pass (loss, gradient, Adam).
+//
+// Network pass. Forward mode is seeded on the six (scaled) features, so each
+// hidden unit of layer 1 carries 28 channels: value, 6 first and 21 second
+// derivatives, all closed-form in the unit's pre-activation a1:
+//   sp(a1),  sigma(a1) W1[k,i],  sigma'(a1) W1[k,i] W1[k,j].
+// Layer 2 is the dense contraction a2[m, c] = sum_k W2[m, k] h1[k, c] over
+// 64 units for every (element, channel) column: it runs on the matrix cores
+// (v_mfma_f32_16x16x32_bf16). W2 is BF16 exactly; every activation is split
+// into three BF16 terms (hi + mid + lo carries all 24 bits of an FP32
+// significand), so the three MFMAs per tile reproduce FP32 products with FP32
+// accumulation. Layer 2's softplus and the output layer are applied to the
+// accumulators in registers and reduced over the 64 units.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "mlp.hpp"
+#include "terms.hpp"
+
+namespace mad {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float softplusf(float a) { return fmaxf(a, 0.0f) + log1pf(expf(-fabsf(a))); }
+__device__ __forceinline__ float logisticf(float a) {
+    const float e = expf(-fabsf(a));
+    const float r = 1.0f / (1.0f + e);
+    return a >= 0.0f ? r : e * r;
+}
+
+// ---- vertex normals ------------------------------------------------------------------------------
+__global__ void k_vertex_normals(const double* x, int64_t nv, const int32_t* vf_ptr, const int32_t* vf,
+                                 const int32_t* tris, double* normals) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+        double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+        for (int32_t q = vf_ptr[v]; q < vf_ptr[v + 1]; ++q) {
+            const int32_t* t = tris + 3 * (int64_t)vf[q];
+            const double* a = x + 3 * (int64_t)t[0];
+            const double* b = x + 3 * (int64_t)t[1];
+            const double* c = x + 3 * (int64_t)t[2];
+            const double e1x = b[0] - a[0], e1y = b[1] - a[1], e1z = b[2] - a[2];
+            const double e2x = c[0] - a[0], e2y = c[1] - a[1], e2z = c[2] - a[2];
+            n0 += e1y * e2z - e1z * e2y;
+            n1 += e1z * e2x - e1x * e2z;
+            n2 += e1x * e2y - e1y * e2x;
+        }
+        const double l = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const double il = l > 0.0 ? 1.0 / l : 0.0;
+        normals[3 * v] = n0 * il;
+        normals[3 * v + 1] = n1 * il;
+        normals[3 * v + 2] = n2 * il;
+    }
+}
+
+hipError_t launch_vertex_normals(const double* x, int64_t nv, const int32_t* vf_ptr, const int32_t* vf,
+                                 const int32_t* tris, double* normals, hipStream_t s) {
+    if (nv <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((nv + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_vertex_normals, dim3((unsigned)blocks), dim3(256), 0, s, x, nv, vf_ptr, vf, tris, normals);
+    return hipGetLastError();
+}
+
+// ---- network pass --------------------------------------------------------------------------------
+// feature channel c >= 7: the packed upper pair (i, j) of Packed<6>
+__host__ __device__ constexpr int pair_i(int q) { return q < 6 ? 0 : q < 11 ? 1 : q < 15 ? 2 : q < 18 ? 3 : q < 20 ? 4 : 5; }
+__host__ __device__ constexpr int pair_j(int q) {
+    return q < 6 ? q : q < 11 ? q - 5 : q < 15 ? q - 9 : q < 18 ? q - 12 : q < 20 ? q - 14 : 5;
+}
+static_assert(Packed<6>::at(pair_i(13), pair_j(13)) == 13 && Packed<6>::at(pair_i(20), pair_j(20)) == 20,
+              "pair tables follow Packed<6>");
+
+// features z of triangle e (FP64): same formulas as the element term's shell_features
+__device__ __forceinline__ void features_at(const MlpHeadLaunch& L, int64_t e, double (&z)[6]) {
+    const int32_t* st = L.stencil + 3 * e;
+    double xs[9], in[17];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xs[3 * s + c] = L.x[3 * (int64_t)st[s] + c];
+            in[8 + 3 * s + c] = L.normals[3 * (int64_t)st[s] + c];
+        }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) in[k] = L.rest[(int64_t)k * L.n + e];
+    double r[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        r[i] = xs[3 + i] - xs[i];
+        r[3 + i] = xs[6 + i] - xs[i];
+    }
+    shell_features<double>(r, in, z);
+}
+
+// One wave evaluates 16 triangles at a time (one per MFMA column); lane l holds column l % 16 and
+// hidden units k = 32 ks + 8 (l / 16) + j of the B operand, rows m = 16 mt + 4 (l / 16) + jj of the
+// accumulators.
+__global__ __launch_bounds__(256) void k_mlp_head(MlpHeadLaunch L) {
+    __shared__ float sW1[kHid * 6], sB1[kHid], sB2[kHid], sW3[kHid];
+    for (int i = threadIdx.x; i < kHid * 6; i += blockDim.x) sW1[i] = bf2f(L.wbf[kOffW1 + i]);
+    for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
+        sB1[i] = bf2f(L.wbf[kOffB1 + i]);
+        sB2[i] = bf2f(L.wbf[kOffB2 + i]);
+        sW3[i] = bf2f(L.wbf[kOffW3 + i]);
+    }
+    __syncthreads();
+    const float b3 = bf2f(L.wbf[kOffB3]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+    short8 A[4][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                A[mt][ks][j] = (short)L.wbf[kOffW2 + (16 * mt + col) * kHid + 32 * ks + 8 * g + j];
+    const int waves = blockDim.x >> 6;
+    const int64_t tiles = (L.n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * waves + wave; tile < tiles; tile += (int64_t)gridDim.x * waves) {
+        const int64_t e = tile * 16 + col;
+        const bool valid = e < L.n;
+        float xh[6];
+        {
+            double z[6] = {0, 0, 0, 0, 0, 0};
+            if (valid) features_at(L, e, z);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xh[i] = float(z[i]) * L.s_in[i];
+        }
+        float a1[2][8], s1[2][8];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * ks + 8 * g + j;
+                float a = sB1[k];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) a = fmaf(sW1[k * 6 + i], xh[i], a);
+                a1[ks][j] = a;
+                s1[ks][j] = logisticf(a);
+            }
+        float P[kPsi];
+#pragma unroll
+        for (int c = 0; c < kPsi; ++c) P[c] = 0.0f;
+        float a2g[6][4][4], s2[4][4], s2p[4][4];
+#pragma unroll
+        for (int c = 0; c < kPsi; ++c) {
+            short8 bh[2], bm[2], bl[2];
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int k = 32 * ks + 8 * g + j;
+                    float v;
+                    if (c == 0) {
+                        v = softplusf(a1[ks][j]);
+                    } else if (c < 7) {
+                        v = s1[ks][j] * sW1[k * 6 + (c - 1)];
+                    } else {
+                        const float sp2 = s1[ks][j] * (1.0f - s1[ks][j]);
+                        v = sp2 * sW1[k * 6 + pair_i(c - 7)] * sW1[k * 6 + pair_j(c - 7)];
+                    }
+                    const uint16_t h = f2bf(v);
+                    const float r1 = v - bf2f(h);
+                    const uint16_t md = f2bf(r1);
+                    const uint16_t lo = f2bf(r1 - bf2f(md));
+                    bh[ks][j] = (short)h;
+                    bm[ks][j] = (short)md;
+                    bl[ks][j] = (short)lo;
+                }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const bf16x8 a = __builtin_bit_cast(bf16x8, A[mt][ks]);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bh[ks]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bm[ks]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bl[ks]), acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int m = 16 * mt + 4 * g + jj;
+                    const float w = sW3[m];
+                    if (c == 0) {
+                        const float a2 = acc[jj] + sB2[m];
+                        const float sg = logisticf(a2);
+                        s2[mt][jj] = sg;
+                        s2p[mt][jj] = sg * (1.0f - sg);
+                        P[0] = fmaf(w, softplusf(a2), P[0]);
+                    } else if (c < 7) {
+                        a2g[c - 1][mt][jj] = acc[jj];
+                        P[c] = fmaf(w * s2[mt][jj], acc[jj], P[c]);
+                    } else {
+                        const float o = s2[mt][jj] * acc[jj] +
+                                        s2p[mt][jj] * a2g[pair_i(c - 7)][mt][jj] * a2g[pair_j(c - 7)][mt][jj];
+                        P[c] = fmaf(w, o, P[c]);
+                    }
+                }
+            }
+        }
+        // sum over the four lanes holding the same column (units 4g..4g+3 of every 16)
+#pragma unroll
+        for (int c = 0; c < kPsi; ++c) {
+            P[c] += __shfl_xor(P[c], 16);
+            P[c] += __shfl_xor(P[c], 32);
+        }
+        if (valid && g == 0) {
+            // back to z: dpsi/dz_i = s_out s_in[i] dpsi^/dxh_i, likewise for the second derivatives
+            L.psi[e] = L.s_out * (P[0] + b3);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) L.psi[(int64_t)(1 + i) * L.n + e] = L.s_out * L.s_in[i] * P[1 + i];
+#pragma unroll
+            for (int q = 0; q < 21; ++q)
+                L.psi[(int64_t)(7 + q) * L.n + e] = L.s_out * L.s_in[pair_i(q)] * L.s_in[pair_j(q)] * P[7 + q];
+        }
+    }
+}
+
+hipError_t launch_mlp_head(const MlpHeadLaunch& L, hipStream_t s) {
+    if (L.n <= 0) return hipSuccess;
+    const int64_t tiles = (L.n + 15) / 16;
+    const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, 4096);
+    hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)blocks), dim3(256), 0, s, L);
+    return hipGetLastError();
+}
+
+// ---- training ------------------------------------------------------------------------------------
+// One wave per sample at a time, lane m = hidden unit m. Forward mode carries the six tangents
+// d/dxh (xh = s_in * z) through both layers; reverse mode then differentiates
+//   loss = (psi - W)^2 / (c_e B) + lam_g sum_i (dpsi/dz_i - dW_i)^2 / (c_g[i] B)   (B = batch size)
+// with respect to every parameter. Each wave accumulates its samples' gradients in registers and
+// writes one partial row; the rows are summed in a fixed order afterwards.
+constexpr int kTrainBlock = 256;
+constexpr int kW2Pad = kHid + 1;   // padded LDS rows: lane m reading row m is bank-conflict free
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(kTrainBlock) void k_mlp_train(MlpTrainLaunch L) {
+    __shared__ float sW2[kHid * kW2Pad];
+    __shared__ float sX[kTrainBlock / 64][kHid][8];    // per wave: h1, T1 (6), pad
+    __shared__ float sD[kTrainBlock / 64][kHid][8];    // per wave: delta2, G2a (6), pad
+    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x)
+        sW2[(i / kHid) * kW2Pad + i % kHid] = L.params[kOffW2 + i];
+    __syncthreads();
+    const int m = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gw = blockIdx.x * (blockDim.x >> 6) + wv;   // global wave
+    float w1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) w1[i] = L.params[kOffW1 + m * 6 + i];
+    const float b1 = L.params[kOffB1 + m], b2 = L.params[kOffB2 + m], w3 = L.params[kOffW3 + m];
+    const float b3 = L.params[kOffB3];
+    float gW2[kHid];
+#pragma unroll
+    for (int k = 0; k < kHid; ++k) gW2[k] = 0.0f;
+    float gW1[6] = {0, 0, 0, 0, 0, 0};
+    float gb1 = 0.0f, gb2 = 0.0f, gw3 = 0.0f, gb3 = 0.0f, loss = 0.0f;
+    const float inv_b = 1.0f / float(L.count);
+    // every wave runs the same number of rounds (the block barriers below need it); a wave past the
+    // end of the batch evaluates sample 0 of the batch with zero weight
+    const int64_t rounds = (L.count + L.n_waves - 1) / L.n_waves;
+    for (int64_t it = 0; it < rounds; ++it) {
+        const int64_t q = gw + it * L.n_waves;
+        const bool active = q < L.count;
+        const int64_t qi = active ? q : 0;
+        const int64_t smp = L.idx ? (int64_t)L.idx[L.base + qi] : L.base + qi;
+        const float wgt = active ? inv_b : 0.0f;
+        float xh[6], dWt[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            xh[i] = L.z[smp * 6 + i] * L.s_in[i];
+            dWt[i] = L.dW[smp * 6 + i];
+        }
+        const float Wt = L.W[smp];
+        // layer 1 (unit m)
+        float a1 = b1;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) a1 = fmaf(w1[i], xh[i], a1);
+        const float h1 = softplusf(a1), d1 = logisticf(a1), d1p = d1 * (1.0f - d1);
+        sX[wv][m][0] = h1;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sX[wv][m][1 + i] = d1 * w1[i];
+        __syncthreads();
+        // layer 2 (unit m): a2 = W2[m, :] h1 + b2, T2a[m, i] = W2[m, :] T1[:, i]
+        float a2 = b2, t2a[6] = {0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < kHid; ++k) {
+            const float w = sW2[m * kW2Pad + k];
+            a2 = fmaf(w, sX[wv][k][0], a2);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) t2a[i] = fmaf(w, sX[wv][k][1 + i], t2a[i]);
+        }
+        const float h2 = softplusf(a2), d2 = logisticf(a2), d2p = d2 * (1.0f - d2);
+        // output: psi^ = w3 . h2 + b3, g^_i = w3 . (d2 T2a[:, i])
+        const float ps = wave_sum(w3 * h2) + b3;
+        float gh[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) gh[i] = wave_sum(w3 * d2 * t2a[i]);
+        const float psi = L.s_out * ps;
+        const float rr = 2.0f * (psi - Wt) * wgt / L.c_e * L.s_out;            // dloss / dpsi^
+        float qq[6];
+        float lg = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const float dz = L.s_out * L.s_in[i] * gh[i] - dWt[i];
+            lg += dz * dz / L.c_g[i];
+            qq[i] = 2.0f * L.lam_g * dz * wgt / L.c_g[i] * L.s_out * L.s_in[i];  // dloss / dg^_i
+        }
+        loss += ((psi - Wt) * (psi - Wt) / L.c_e + L.lam_g * lg) * wgt;
+        // reverse through the output layer and layer 2's nonlinearity
+        float qt = 0.0f, g2a[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            qt = fmaf(qq[i], t2a[i], qt);
+            g2a[i] = d2 * w3 * qq[i];                 // dloss / dT2a[m, i]
+        }
+        gw3 += rr * h2 + d2 * qt;
+        gb3 += rr;
+        const float delta2 = d2p * w3 * qt + d2 * rr * w3;   // dloss / da2[m]
+        gb2 += delta2;
+        sD[wv][m][0] = delta2;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sD[wv][m][1 + i] = g2a[i];
+        __syncthreads();
+        // dW2[m, k] += delta2[m] h1[k] + sum_i G2a[m, i] T1[k, i]
+#pragma unroll
+        for (int k = 0; k < kHid; ++k) {
+            float acc = delta2 * sX[wv][k][0];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) acc = fmaf(g2a[i], sX[wv][k][1 + i], acc);
+            gW2[k] += acc;
+        }
+        // unit k = m of layer 1: dh1[k] = sum_m W2[m, k] delta2[m], dT1[k, i] = sum_m W2[m, k] G2a[m, i]
+        float dh1 = 0.0f, dT1[6] = {0, 0, 0, 0, 0, 0};
+        for (int mm = 0; mm < kHid; ++mm) {
+            const float w = sW2[mm * kW2Pad + m];
+            dh1 = fmaf(w, sD[wv][mm][0], dh1);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) dT1[i] = fmaf(w, sD[wv][mm][1 + i], dT1[i]);
+        }
+        float dd1 = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            dd1 = fmaf(w1[i], dT1[i], dd1);
+            gW1[i] += d1 * dT1[i];                      // through T1 = d1 W1
+        }
+        const float delta1 = d1p * dd1 + d1 * dh1;     // dloss / da1[m]
+        gb1 += delta1;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) gW1[i] += delta1 * xh[i];
+        __syncthreads();   // sX / sD are rewritten by the next sample
+    }
+    float* out = L.partial + (int64_t)gw * (kMlpParams + 1);
+    if (gw < L.n_waves) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) out[kOffW1 + m * 6 + i] = gW1[i];
+        out[kOffB1 + m] = gb1;
+#pragma unroll
+        for (int k = 0; k < kHid; ++k) out[kOffW2 + m * kHid + k] = gW2[k];
+        out[kOffB2 + m] = gb2;
+        out[kOffW3 + m] = gw3;
+        if (m == 0) {
+            out[kOffB3] = gb3;
+            out[kMlpParams] = loss;
+        }
+    }
+}
+
+hipError_t launch_mlp_train(const MlpTrainLaunch& L, hipStream_t s) {
+    const int per_block = kTrainBlock / 64;
+    if (L.n_waves % per_block != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_train, dim3(L.n_waves / per_block), dim3(kTrainBlock), 0, s, L);
+    return hipGetLastError();
+}
+
+__global__ void k_mlp_reduce(const float* partial, int n_waves, float* grad, float* loss) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > kMlpParams) return;
+    float acc = 0.0f;
+    for (int w = 0; w < n_waves; ++w) acc += partial[(int64_t)w * (kMlpParams + 1) + i];
+    if (i < kMlpParams) grad[i] = acc;
+    else *loss = acc;
+}
+
+hipError_t launch_mlp_reduce(const float* partial, int n_waves, float* grad, float* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, partial, n_waves, grad,
+                       loss);
+    return hipGetLastError();
+}
+
+__global__ void k_mlp_adam(float* params, float* m, float* v, const float* grad, const int64_t* step, float lr,
+                           float beta1, float beta2, float eps, uint16_t* wbf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kMlpParams) return;
+    const float t = float(*step);
+    const float g = grad[i];
+    const float mi = beta1 * m[i] + (1.0f - beta1) * g;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / (1.0f - powf(beta1, t));
+    const float vh = vi / (1.0f - powf(beta2, t));
+    const float p = params[i] - lr * mh / (sqrtf(vh) + eps);
+    params[i] = p;
+    wbf[i] = f2bf(p);
+}
+
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, const int64_t* step, float lr,
+                           float beta1, float beta2, float eps, uint16_t* wbf, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, m, v, grad, step, lr,
+                       beta1, beta2, eps, wbf);
+    return hipGetLastError();
+}
+
+__global__ void k_mlp_to_bf16(const float* params, uint16_t* wbf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kMlpParams) wbf[i] = f2bf(params[i]);
+}
+
+hipError_t launch_mlp_to_bf16(const float* params, uint16_t* wbf, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_to_bf16, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, params, wbf);
+    return hipGetLastError();
+}
+
+__global__ void k_step_incr(int64_t* step) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += 1;
+}
+
+hipError_t launch_mlp_step_incr(int64_t* step, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_incr, dim3(1), dim3(64), 0, s, step);
+    return hipGetLastError();
+}
+
+}  // namespace mad

@@ -27,8 +27,9 @@ constexpr uint32_t kFbElemMask = (1u << kFbTermShift) - 1u;
 template <class Term, typename T, int MODE>
 __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTermArgs& A, int term, int p,
                                            const double* sx, T* sg, T* sh, double& esum, bool& bad) {
-    constexpr int NS = Term::NS, D = Term::D, NF = NS * D, NR = Term::NREST, DD = D * D;
+    constexpr int NS = Term::NS, D = Term::D, NF = NS * D, DD = D * D;
     const int beg = A.elem_ptr[p], end = A.elem_ptr[p + 1];
+    const int lv0 = L.lv_ptr[p];
     const T te = T(L.eps > 0.0 ? L.eps : 0.0);
     for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) {
         int lv[NS];
@@ -39,9 +40,15 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
         for (int s = 0; s < NS; ++s)
 #pragma unroll
             for (int c = 0; c < D; ++c) xs[s * D + c] = sx[lv[s] * D + c];
-        double rest[NR > 0 ? NR : 1];
+        double rest[n_inputs<Term>()];
+        if constexpr (Term::NAUX > 0) {
+            int gv[NS];
 #pragma unroll
-        for (int k = 0; k < NR; ++k) rest[k] = A.rest[(int64_t)k * A.n + e];
+            for (int s = 0; s < NS; ++s) gv[s] = L.lv_global[lv0 + lv[s]];
+            gather_inputs<Term>(rest, A.rest, A.n, e, L.normals, gv, A.psi);
+        } else {
+            gather_inputs<Term>(rest, A.rest, A.n, e, nullptr, nullptr, nullptr);
+        }
         ElemOut<Term, T> o;
         if constexpr (MODE == 3 && sizeof(T) == 4) {
             bool fb = quality<Term>(xs) < L.qmin;
@@ -131,6 +138,8 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
             case K_BENDING: patch_term<TermBending, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
             case K_TRI_AREA: patch_term<TermTriArea, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
             case K_EDGE_SQLEN: patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
+            case K_SHELL_TRI: patch_term<TermShellTri, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
+            case K_MLP: patch_term<TermMLP, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
             default: break;
             }
         } else if constexpr (D == 2) {
@@ -276,7 +285,7 @@ __device__ __forceinline__ int32_t find_block(const int32_t* rowptr, const int32
 
 template <class Term>
 __device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const FallbackTerm& A, int e) {
-    constexpr int NS = Term::NS, D = Term::D, NF = NS * D, NR = Term::NREST, DD = D * D;
+    constexpr int NS = Term::NS, D = Term::D, NF = NS * D, DD = D * D;
     int vs[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) vs[s] = A.stencil[(int64_t)e * NS + s];
@@ -285,9 +294,8 @@ __device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const Fal
     for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int c = 0; c < D; ++c) xs[s * D + c] = F.x[(int64_t)vs[s] * D + c];
-    double rest[NR > 0 ? NR : 1];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) rest[k] = A.rest[(int64_t)k * A.n + e];
+    double rest[n_inputs<Term>()];
+    gather_inputs<Term>(rest, A.rest, A.n, e, F.normals, vs, A.psi);
     ElemOut<Term, double> o;
     element_eval<Term, double, 3>(xs, rest, A.prm, F.eps, o);
     if (!out_finite<Term, double>(o, 3)) atomicOr(F.flags, 1);
@@ -330,6 +338,8 @@ __global__ __launch_bounds__(kBlock) void k_fallback(FallbackLaunch F) {
             case K_BENDING: fallback_elem<TermBending>(F, A, e); break;
             case K_TRI_AREA: fallback_elem<TermTriArea>(F, A, e); break;
             case K_EDGE_SQLEN: fallback_elem<TermEdgeSqlen>(F, A, e); break;
+            case K_SHELL_TRI: fallback_elem<TermShellTri>(F, A, e); break;
+            case K_MLP: fallback_elem<TermMLP>(F, A, e); break;
             default: break;
             }
         } else if constexpr (D == 2) {

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "mad_internal.hpp"
 
@@ -58,58 +59,73 @@ static void color_within_patches(Term& t, int64_t nv) {
 }
 
 // Patch order of every term's elements: faces by their patch, diamonds by their lower face, edges
-// by their first face; inside a patch by colour, then by that face's index.
+// by their first face; inside a patch by colour, then by that face's index. Two stable counting
+// sorts (by face, then by patch): linear in the element count.
 static void order_terms(mad_problem* p) {
     const mad_mesh& m = *p->mesh;
     const int32_t np = p->patches.n;
     for (auto& t : p->terms) {
-        std::vector<int32_t> ep((size_t)t.n), key((size_t)t.n);
+        std::vector<int32_t> key((size_t)t.n);
         for (int64_t e = 0; e < t.n; ++e) {
-            int32_t f;
-            if (t.kind == MAD_BENDING) f = m.diamond_faces[2 * e];
-            else if (t.kind == MAD_EDGE_SQLEN) f = m.edge_face0[e];
-            else f = (int32_t)e;
-            ep[e] = p->patches.face_patch[f];
-            key[e] = f;
+            if (t.kind == MAD_BENDING) key[e] = m.diamond_faces[2 * e];
+            else if (t.kind == MAD_EDGE_SQLEN) key[e] = m.edge_face0[e];
+            else key[e] = (int32_t)e;
         }
-        t.perm.resize((size_t)t.n);
-        std::iota(t.perm.begin(), t.perm.end(), 0);
-        std::stable_sort(t.perm.begin(), t.perm.end(), [&](int32_t a, int32_t b) {
-            if (ep[a] != ep[b]) return ep[a] < ep[b];
-            return key[a] < key[b];
-        });
+        // by face
+        std::vector<int32_t> cnt((size_t)m.nt + 1, 0), byface((size_t)t.n);
+        for (int64_t e = 0; e < t.n; ++e) cnt[key[e] + 1]++;
+        for (int64_t f = 0; f < m.nt; ++f) cnt[f + 1] += cnt[f];
+        for (int64_t e = 0; e < t.n; ++e) byface[cnt[key[e]]++] = (int32_t)e;
+        // then by patch (stable)
         t.elem_ptr.assign((size_t)np + 1, 0);
-        for (int64_t e = 0; e < t.n; ++e) t.elem_ptr[ep[e] + 1]++;
+        for (int64_t e = 0; e < t.n; ++e) t.elem_ptr[p->patches.face_patch[key[e]] + 1]++;
         for (int32_t q = 0; q < np; ++q) t.elem_ptr[q + 1] += t.elem_ptr[q];
+        std::vector<int32_t> fill(t.elem_ptr.begin(), t.elem_ptr.end() - 1);
+        t.perm.resize((size_t)t.n);
+        for (int32_t e : byface) t.perm[fill[p->patches.face_patch[key[e]]]++] = e;
         color_within_patches(t, m.nv);
     }
 }
 
-// largest per-patch vertex and upper-block counts of the current patching
+// largest per-patch vertex and upper-block counts of the current patching (patches split over
+// threads; each counts its distinct vertices with a stamp array and its distinct pairs by sorting)
 static void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb) {
     const int64_t nv = p->mesh->nv;
-    int32_t mv = 0, mb = 0;
-    std::vector<int32_t> verts;
-    std::vector<int64_t> keys;
-    for (int32_t q = 0; q < p->patches.n; ++q) {
-        verts.clear();
-        keys.clear();
-        for (const auto& t : p->terms)
-            for (int32_t i = t.elem_ptr[q]; i < t.elem_ptr[q + 1]; ++i) {
-                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                for (int a = 0; a < t.ns; ++a) {
-                    verts.push_back(st[a]);
-                    for (int b = a; b < t.ns; ++b)
-                        keys.push_back((int64_t)std::min(st[a], st[b]) * nv + std::max(st[a], st[b]));
+    const int32_t np = p->patches.n;
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<int32_t> mv_t((size_t)nth, 0), mb_t((size_t)nth, 0);
+    auto work = [&](int th) {
+        std::vector<int32_t> stamp((size_t)nv, -1);
+        std::vector<int64_t> keys;
+        int32_t mv = 0, mb = 0;
+        for (int32_t q = th; q < np; q += nth) {
+            keys.clear();
+            int32_t nverts = 0;
+            for (const auto& t : p->terms)
+                for (int32_t i = t.elem_ptr[q]; i < t.elem_ptr[q + 1]; ++i) {
+                    const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                    for (int a = 0; a < t.ns; ++a) {
+                        if (stamp[st[a]] != q) {
+                            stamp[st[a]] = q;
+                            ++nverts;
+                        }
+                        for (int b = a; b < t.ns; ++b)
+                            keys.push_back((int64_t)std::min(st[a], st[b]) * nv + std::max(st[a], st[b]));
+                    }
                 }
-            }
-        std::sort(verts.begin(), verts.end());
-        std::sort(keys.begin(), keys.end());
-        mv = std::max(mv, (int32_t)(std::unique(verts.begin(), verts.end()) - verts.begin()));
-        mb = std::max(mb, (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin()));
-    }
-    *max_lv = mv;
-    *max_lb = mb;
+            std::sort(keys.begin(), keys.end());
+            mv = std::max(mv, nverts);
+            mb = std::max(mb, (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin()));
+        }
+        mv_t[th] = mv;
+        mb_t[th] = mb;
+    };
+    std::vector<std::thread> pool;
+    for (int th = 1; th < nth; ++th) pool.emplace_back(work, th);
+    work(0);
+    for (auto& th : pool) th.join();
+    *max_lv = *std::max_element(mv_t.begin(), mv_t.end());
+    *max_lb = *std::max_element(mb_t.begin(), mb_t.end());
 }
 
 static void free_layout(mad_problem* p) {
@@ -122,6 +138,7 @@ static void free_layout(mad_problem* p) {
         t.d_slots = nullptr;
         t.d_lvert = nullptr;
         t.d_lslot = nullptr;
+        t.d_psi = nullptr;
     }
     p->d_lv_ptr = p->d_lv_global = p->d_lv_halo = nullptr;
     p->d_lb_ptr = p->d_lb_gidx = p->d_lb_gidxT = p->d_lb_halo = nullptr;
@@ -133,6 +150,7 @@ static void free_layout(mad_problem* p) {
     p->d_fb_count = nullptr;
     p->d_work_order = p->d_work_counter = nullptr;
     p->d_partial = nullptr;
+    p->d_comp_energy = nullptr;
     p->d_comp_patch_ptr = nullptr;
 }
 
@@ -174,12 +192,19 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
         if ((rc = upload_layout(p, (void**)&t.d_rest, rs.data(), rs.size() * 8, s)) != MAD_OK) return rc;
         if ((rc = upload_layout(p, (void**)&t.d_elem_ptr, t.elem_ptr.data(), t.elem_ptr.size() * 4, s)) != MAD_OK)
             return rc;
+        if (t.kind == MAD_MLP &&
+            (rc = alloc_layout(p, (void**)&t.d_psi, sizeof(float) * (size_t)kPsi * (size_t)std::max<int64_t>(t.n, 1))) !=
+                MAD_OK)
+            return rc;
     }
     if ((rc = upload_layout(p, (void**)&p->d_comp_patch_ptr, p->patches.comp_patch_ptr.data(),
                             p->patches.comp_patch_ptr.size() * 4, s)) != MAD_OK)
         return rc;
     if ((rc = alloc_layout(p, (void**)&p->d_partial, sizeof(double) * std::max<size_t>(1, (size_t)np * p->terms.size()))) !=
         MAD_OK)
+        return rc;
+    if ((rc = alloc_layout(p, (void**)&p->d_comp_energy,
+                           sizeof(double) * std::max<size_t>(1, p->patches.comp_patch_ptr.size()))) != MAD_OK)
         return rc;
     // work order of the persistent launch: patches with most elements first
     {

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "mad.h"
+#include "mlp.hpp"
 
 struct mad_mesh {
     int64_t nv = 0, nt = 0;
@@ -44,6 +45,8 @@ struct Term {
     int32_t* d_slots = nullptr;          // SoA [ns*ns][n] global block of (s, t) (atomic scatter)
     uint16_t* d_lvert = nullptr;         // SoA [ns][n] patch-local vertex (patch scatter)
     uint16_t* d_lslot = nullptr;         // SoA [ns(ns+1)/2][n] patch-local block + flags
+    const mad_mlp* mlp = nullptr;        // learned density: the network
+    float* d_psi = nullptr;              // learned density: SoA [28][n] network outputs, patch order
 };
 
 // patch-local index structures of the LDS-accumulating assembly (host_patch.cpp)
@@ -83,6 +86,7 @@ struct mad_problem {
     int32_t* d_colidx = nullptr;
     int32_t* d_comp_patch_ptr = nullptr;
     double* d_partial = nullptr;          // [n_terms][n_patch]
+    double* d_comp_energy = nullptr;      // [n_comp] per-component energies (reduction scratch)
     int32_t* d_flags = nullptr;           // [0] nonfinite, [1] internal error
     unsigned long long* d_fallbacks = nullptr;
     int scatter = MAD_SCATTER_PATCH;
@@ -93,6 +97,11 @@ struct mad_problem {
     int32_t* d_work_order = nullptr;      // patches, largest first (persistent launch)
     int32_t* d_work_counter = nullptr;
     std::string tune_report;              // last autotune table (JSON)
+    bool shell = false;                   // a term reads the shell features (needs vertex normals)
+    int32_t* d_tris = nullptr;            // [nt][3] mesh triangles (normals)
+    int32_t* d_vf_ptr = nullptr;          // [nv + 1] vertex -> triangles, ascending
+    int32_t* d_vf = nullptr;
+    double* d_normals = nullptr;          // [nv][3] unit vertex normals of the evaluated positions
     int32_t* d_lv_ptr = nullptr;
     int32_t* d_lv_global = nullptr;
     int32_t* d_lv_halo = nullptr;
@@ -143,6 +152,7 @@ int kind_nrest(int kind);
 int build_topology(mad_mesh& m);
 int rest_tri(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);        // [nt][5]
 int rest_diamond(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);    // [nd][2]
+int rest_shell(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);      // [nt][8]
 void build_patches(const mad_mesh& m, int target_faces, Patches& p);
 // layout.cpp: (re)build the element order and the scatter structures of a problem
 int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s);
@@ -175,6 +185,8 @@ struct EvalLaunch {
     double prm[4];
     double eps;
     double qmin;
+    const double* normals;  // [nv][3] unit vertex normals (shell-feature terms)
+    const float* psi;       // SoA [28][n] network outputs (learned density)
 };
 hipError_t launch_eval(const EvalLaunch& L, hipStream_t s);
 
@@ -186,6 +198,7 @@ struct PatchTermArgs {
     const uint16_t* lvert;
     const uint16_t* lslot;
     const int32_t* elem_ptr;
+    const float* psi;        // SoA [28][n] network outputs (learned density)
     double prm[4];
 };
 struct PatchLaunch {
@@ -210,6 +223,7 @@ struct PatchLaunch {
     int32_t* fb_count;
     int32_t fb_cap;
     double eps, qmin;
+    const double* normals;  // [nv][3] unit vertex normals (shell-feature terms)
     int persistent;
     const int32_t* work_order;
     int32_t* work_counter;
@@ -238,6 +252,7 @@ struct FallbackTerm {
     int64_t n;
     const int32_t* stencil;  // [n][ns] global vertices, patch order
     const double* rest;
+    const float* psi;
     double prm[4];
 };
 struct FallbackLaunch {
@@ -252,12 +267,13 @@ struct FallbackLaunch {
     int32_t fb_cap;
     int32_t* flags;
     double eps;
+    const double* normals;
     FallbackTerm terms[8];
 };
 hipError_t launch_fallback(const FallbackLaunch& F, hipStream_t s);
 hipError_t launch_fill(void* ptr, int64_t n_elems, int elem_bytes, hipStream_t s);
 hipError_t launch_energy_reduce(const double* partial, int n_terms, int n_patch, const int32_t* comp_patch_ptr,
-                                int n_comp, bool batched, double* energy, hipStream_t s);
+                                int n_comp, bool batched, double* energy, double* comp_scratch, hipStream_t s);
 
 // pattern builder (kernels_pattern.hip)
 struct PatternTerm {

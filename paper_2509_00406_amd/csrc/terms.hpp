@@ -13,7 +13,9 @@
 
 namespace mad {
 
-enum TermKind { K_EDGE_SQLEN = 1, K_TRI_AREA = 2, K_DIRICHLET = 3, K_STVK = 4, K_BENDING = 5, K_SYMDIR = 6 };
+enum TermKind {
+    K_EDGE_SQLEN = 1, K_TRI_AREA = 2, K_DIRICHLET = 3, K_STVK = 4, K_BENDING = 5, K_SYMDIR = 6, K_MLP = 7, K_SHELL_TRI = 8
+};
 
 template <typename S>
 struct V3 {
@@ -29,7 +31,7 @@ template <typename S> __device__ __forceinline__ S dot(const V3<S>& a, const V3<
 
 // Listing 1: squared edge length. r = x1 - x0.
 struct TermEdgeSqlen {
-    static constexpr int NS = 2, D = 3, KR = 3, NREST = 0;
+    static constexpr int NS = 2, D = 3, KR = 3, NREST = 0, NAUX = 0, NPSI = 0;
     template <typename S> __device__ static S energy(const S* r, const double*, const double*) {
         return r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
     }
@@ -37,7 +39,7 @@ struct TermEdgeSqlen {
 
 // Sec. 7.6: triangle area 0.5 |(x1 - x0) x (x2 - x0)|.
 struct TermTriArea {
-    static constexpr int NS = 3, D = 3, KR = 6, NREST = 0;
+    static constexpr int NS = 3, D = 3, KR = 6, NREST = 0, NAUX = 0, NPSI = 0;
     template <typename S> __device__ static S energy(const S* r, const double*, const double*) {
         const V3<S> a{r[0], r[1], r[2]}, b{r[3], r[4], r[5]};
         const V3<S> n = cross(a, b);
@@ -48,7 +50,7 @@ struct TermTriArea {
 // Scalar Dirichlet energy 0.5 A |grad u|^2 with grad u = Dm^{-T} (u1 - u0, u2 - u0).
 // rest = {Dm^{-1} row-major (4), rest area}.
 struct TermDirichlet {
-    static constexpr int NS = 3, D = 1, KR = 2, NREST = 5;
+    static constexpr int NS = 3, D = 1, KR = 2, NREST = 5, NAUX = 0, NPSI = 0;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double*) {
         const S g0 = r[0] * rest[0] + r[1] * rest[2];
         const S g1 = r[0] * rest[1] + r[1] * rest[3];
@@ -59,7 +61,7 @@ struct TermDirichlet {
 // StVK membrane: F = Ds Dm^{-1} (3x2), E = (F^T F - I)/2, A (mu tr(E^2) + lambda/2 tr(E)^2).
 // r = (x_b - x_a, x_c - x_a); rest = {Dm^{-1} (4), rest area}; prm = {mu, lambda}.
 struct TermStVK {
-    static constexpr int NS = 3, D = 3, KR = 6, NREST = 5;
+    static constexpr int NS = 3, D = 3, KR = 6, NREST = 5, NAUX = 0, NPSI = 0;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double* prm) {
         const double m00 = rest[0], m01 = rest[1], m10 = rest[2], m11 = rest[3];
         S f0[3], f1[3];
@@ -87,7 +89,7 @@ struct TermStVK {
 // avoids the quartic cross product n1 x n2.
 // r = (e, a, b); rest = {mean rest area, rest dihedral}; prm = {k_b, h}.
 struct TermBending {
-    static constexpr int NS = 4, D = 3, KR = 9, NREST = 2;
+    static constexpr int NS = 4, D = 3, KR = 9, NREST = 2, NAUX = 0, NPSI = 0;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double* prm) {
         const V3<S> e{r[0], r[1], r[2]}, a{r[3], r[4], r[5]}, b{r[6], r[7], r[8]};
         const V3<S> n1 = cross(e, a);
@@ -103,7 +105,7 @@ struct TermBending {
 // for 2x2 matrices |J^{-1}|_F^2 = |J|_F^2 / det(J)^2.
 // r = (b - a, c - a) in UV; rest = {Dm^{-1} (4), rest area}.
 struct TermSymDir {
-    static constexpr int NS = 3, D = 2, KR = 4, NREST = 5;
+    static constexpr int NS = 3, D = 2, KR = 4, NREST = 5, NAUX = 0, NPSI = 0;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double*) {
         const double m00 = rest[0], m01 = rest[1], m10 = rest[2], m11 = rest[3];
         const S j00 = r[0] * m00 + r[2] * m10, j01 = r[0] * m01 + r[2] * m11;
@@ -111,6 +113,78 @@ struct TermSymDir {
         const S det = j00 * j11 - j01 * j10;
         const S n = j00 * j00 + j01 * j01 + j10 * j10 + j11 * j11;
         return (n + n * drecip(det * det)) * rest[4];
+    }
+};
+
+
+// ---- per-triangle shell features (project-defined; the learned density's input) -----------------
+// z = (E00, E11, E01, II00 - rII00, II11 - rII11, II01 - rII01): F = Ds Dm^{-1} (3x2),
+// E = (F^T F - I)/2, N = [n_b - n_a, n_c - n_a] Dm^{-1} from the passive unit vertex normals,
+// II = -(N^T F + F^T N)/2. rest = {Dm^{-1} (4), rest area, rest II (3), normals n_a, n_b, n_c (9)}.
+// z is quadratic (E) and linear (II) in r.
+template <typename S>
+__device__ __forceinline__ void shell_features(const S* r, const double* rest, S (&z)[6]) {
+    const double m00 = rest[0], m01 = rest[1], m10 = rest[2], m11 = rest[3];
+    const double* na = rest + 8;
+    S f0[3], f1[3];
+    double n0[3], n1[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        f0[i] = r[i] * m00 + r[3 + i] * m10;
+        f1[i] = r[i] * m01 + r[3 + i] * m11;
+        const double d1 = na[3 + i] - na[i], d2 = na[6 + i] - na[i];
+        n0[i] = d1 * m00 + d2 * m10;
+        n1[i] = d1 * m01 + d2 * m11;
+    }
+    z[0] = (f0[0] * f0[0] + f0[1] * f0[1] + f0[2] * f0[2] + (-1.0)) * 0.5;
+    z[1] = (f1[0] * f1[0] + f1[1] * f1[1] + f1[2] * f1[2] + (-1.0)) * 0.5;
+    z[2] = (f0[0] * f1[0] + f0[1] * f1[1] + f0[2] * f1[2]) * 0.5;
+    z[3] = (f0[0] * n0[0] + f0[1] * n0[1] + f0[2] * n0[2]) * (-1.0) + (-rest[5]);
+    z[4] = (f1[0] * n1[0] + f1[1] * n1[1] + f1[2] * n1[2]) * (-1.0) + (-rest[6]);
+    z[5] = (f1[0] * n0[0] + f1[1] * n0[1] + f1[2] * n0[2] + f0[0] * n1[0] + f0[1] * n1[1] + f0[2] * n1[2]) *
+               (-0.5) + (-rest[7]);
+}
+
+// Analytic per-triangle shell density A W(z), W = mu (E00^2 + E11^2 + 2 E01^2)
+// + lambda/2 (E00 + E11)^2 + k_b/2 (dII00^2 + dII11^2 + 2 dII01^2); prm = {mu, lambda, k_b}.
+struct TermShellTri {
+    static constexpr int NS = 3, D = 3, KR = 6, NREST = 8, NAUX = 9, NPSI = 0;
+    template <typename S> __device__ static S energy(const S* r, const double* rest, const double* prm) {
+        S z[6];
+        shell_features(r, rest, z);
+        const S tr = z[0] + z[1];
+        const S m = z[0] * z[0] + z[1] * z[1] + (z[2] * z[2]) * 2.0;
+        const S b = z[3] * z[3] + z[4] * z[4] + (z[5] * z[5]) * 2.0;
+        return (m * prm[0] + (tr * tr) * (0.5 * prm[1]) + b * (0.5 * prm[2])) * rest[4];
+    }
+};
+
+// Learned density A psi(z). The network's value, gradient and packed Hessian with respect to z
+// at this element's features (28 numbers, computed by the network kernel) arrive after the
+// normals: rest[17] = psi, rest[18 + i] = dpsi/dz_i, rest[24 + Packed<6>::at(i, j)] = d2psi/dz_i dz_j.
+// With dz = z - val(z) (no value, exact first and second derivatives), the second-order Taylor
+// form psi + sum_i psi_i dz_i + 1/2 sum_ij psi_ij dz_i dz_j carries exactly the value, gradient
+// and Hessian of psi(z(r)) in hyper-dual arithmetic.
+struct TermMLP {
+    static constexpr int NS = 3, D = 3, KR = 6, NREST = 8, NAUX = 9, NPSI = 28;
+    template <typename S> __device__ static S energy(const S* r, const double* rest, const double*) {
+        S z[6];
+        shell_features(r, rest, z);
+        const double* ps = rest + 17;
+        S acc = cst<S>(ps[0]);
+        S dz[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            dz[i] = z[i] + (-val(z[i]));
+            acc = acc + dz[i] * ps[1 + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            acc = acc + (dz[i] * dz[i]) * (0.5 * ps[7 + Packed<6>::at(i, i)]);
+#pragma unroll
+            for (int j = i + 1; j < 6; ++j) acc = acc + (dz[i] * dz[j]) * ps[7 + Packed<6>::at(i, j)];
+        }
+        return acc * rest[4];
     }
 };
 

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmad.so")
 
-EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR = 1, 2, 3, 4, 5, 6
+EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI = 1, 2, 3, 4, 5, 6, 7, 8
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 F64, F32 = 0, 1
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_PATCH = 0, 1, 2
@@ -23,8 +23,9 @@ TUNE_FORCE = 1
 
 STATUS = {0: "MAD_OK", -1: "MAD_E_INVALID_ARG", -2: "MAD_E_BAD_MESH", -3: "MAD_E_DEGENERATE_REST",
           -4: "MAD_E_OVERFLOW", -5: "MAD_E_OOM", -6: "MAD_E_HIP", -7: "MAD_E_STATE", -8: "MAD_E_UNSUPPORTED"}
-VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2}
-NEEDS_REST = {DIRICHLET, STVK, BENDING, SYMDIR}
+VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3, SHELL_TRI: 3}
+NEEDS_REST = {DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI}
+MLP_HIDDEN, MLP_PARAMS = 64, 4673
 
 
 class MadError(RuntimeError):
@@ -70,6 +71,18 @@ _SIGS = {
                               C.c_int32, C.c_void_p], C.c_int32),
     "mad_problem_tune_report": ([C.c_void_p, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)], C.c_int32),
     "mad_problem_destroy": ([C.c_void_p], C.c_int32),
+    "mad_mlp_create": ([C.c_int32, C.c_void_p, C.c_void_p, C.c_float, C.POINTER(C.c_void_p)], C.c_int32),
+    "mad_mlp_set_params": ([C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_mlp_get_params": ([C.c_void_p, C.c_int32, C.c_void_p], C.c_int32),
+    "mad_mlp_loss_grad": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                           C.c_float, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_mlp_adam_step": ([C.c_void_p, C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p],
+                          C.c_int32),
+    "mad_mlp_train_epoch": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                             C.c_float, C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float,
+                             C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_mlp_destroy": ([C.c_void_p], C.c_int32),
+    "mad_problem_add_mlp_term": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
 }
 
 
@@ -205,7 +218,7 @@ def mad_problem_set_profiling(prob, enable: bool):
 
 
 def mad_problem_profile(prob) -> tuple[list[float], int]:
-    ms = (C.c_double * 10)()
+    ms = (C.c_double * 12)()
     n, k = C.c_int32(), C.c_int64()
     _check(lib().mad_problem_profile(prob, ms, C.byref(n), C.byref(k)), "mad_problem_profile")
     return [ms[i] for i in range(n.value)], k.value
@@ -240,7 +253,96 @@ def mad_problem_destroy(prob):
     _check(lib().mad_problem_destroy(prob), "mad_problem_destroy")
 
 
+def mad_mlp_create(params: np.ndarray, s_in, s_out: float) -> C.c_void_p:
+    p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    si = np.ascontiguousarray(s_in, dtype=np.float32).ravel()
+    if p.size != MLP_PARAMS or si.size != 6:
+        raise ValueError("network parameters must have 4673 entries and s_in 6")
+    out = C.c_void_p()
+    _check(lib().mad_mlp_create(MLP_HIDDEN, p.ctypes.data, si.ctypes.data, float(s_out), C.byref(out)),
+           "mad_mlp_create")
+    return out
+
+
+def mad_mlp_set_params(mlp, params: np.ndarray):
+    p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    if p.size != MLP_PARAMS:
+        raise ValueError("network parameters must have 4673 entries")
+    _check(lib().mad_mlp_set_params(mlp, p.ctypes.data), "mad_mlp_set_params")
+
+
+def mad_mlp_get_params(mlp, which: int = 0) -> np.ndarray:
+    out = np.zeros(MLP_PARAMS, np.float32)
+    _check(lib().mad_mlp_get_params(mlp, which, out.ctypes.data), "mad_mlp_get_params")
+    return out
+
+
+def _c_g(c_g) -> np.ndarray:
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(c_g, dtype=np.float32), (6,)))
+    return a
+
+
+def mad_mlp_loss_grad(mlp, z, W, dW, idx, base: int, count: int, c_e: float, c_g, lam_g: float, grad, loss,
+                      stream=None):
+    cg = _c_g(c_g)
+    _check(lib().mad_mlp_loss_grad(mlp, _ptr(z), _ptr(W), _ptr(dW), _ptr(idx), base, count, c_e, cg.ctypes.data,
+                                   lam_g, _ptr(grad), _ptr(loss), _stream(stream)), "mad_mlp_loss_grad")
+
+
+def mad_mlp_adam_step(mlp, grad, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+    _check(lib().mad_mlp_adam_step(mlp, _ptr(grad), lr, beta1, beta2, eps, _stream(stream)), "mad_mlp_adam_step")
+
+
+def mad_mlp_train_epoch(mlp, z, W, dW, perm, n: int, batch: int, c_e: float, c_g, lam_g: float, lr: float,
+                        beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, loss_hist=None, stream=None):
+    cg = _c_g(c_g)
+    _check(lib().mad_mlp_train_epoch(mlp, _ptr(z), _ptr(W), _ptr(dW), _ptr(perm), n, batch, c_e, cg.ctypes.data,
+                                     lam_g, lr, beta1, beta2, eps, _ptr(loss_hist), _stream(stream)),
+           "mad_mlp_train_epoch")
+
+
+def mad_problem_add_mlp_term(prob, mlp, rest_pos: np.ndarray):
+    r = np.ascontiguousarray(rest_pos, dtype=np.float64)
+    _check(lib().mad_problem_add_mlp_term(prob, mlp, r.ctypes.data), "mad_problem_add_mlp_term")
+
+
 # ---- convenience objects (still marshalling only) -----------------------------------------------
+class Network:
+    """The learned density's network (FP32 master parameters, BF16 evaluation copy)."""
+
+    def __init__(self, params: np.ndarray, s_in, s_out: float):
+        self.handle = mad_mlp_create(params, s_in, s_out)
+        self.s_in = np.asarray(s_in, np.float32)
+        self.s_out = float(s_out)
+
+    def set_params(self, params):
+        mad_mlp_set_params(self.handle, params)
+
+    def params(self, which: int = 0) -> np.ndarray:
+        return mad_mlp_get_params(self.handle, which)
+
+    def loss_grad(self, z, W, dW, c_e, c_g, lam_g, idx=None, base=0, count=None, out=None, stream=None):
+        import torch
+        grad, loss = out if out is not None else (torch.empty(MLP_PARAMS, dtype=torch.float32, device=z.device),
+                                                   torch.empty(1, dtype=torch.float32, device=z.device))
+        n = z.shape[0] if count is None else count
+        mad_mlp_loss_grad(self.handle, z, W, dW, idx, base, n, c_e, c_g, lam_g, grad, loss, stream)
+        return grad, loss
+
+    def adam_step(self, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        mad_mlp_adam_step(self.handle, grad, lr, beta1, beta2, eps, stream)
+
+    def train_epoch(self, z, W, dW, perm, batch, c_e, c_g, lam_g, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                    loss_hist=None, stream=None):
+        mad_mlp_train_epoch(self.handle, z, W, dW, perm, int(perm.shape[0]), batch, c_e, c_g, lam_g, lr, beta1, beta2,
+                            eps, loss_hist, stream)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.mad_mlp_destroy(h)
+            self.handle = None
+
 class Mesh:
     def __init__(self, tris: np.ndarray, n_verts: int, comp_offsets: np.ndarray | None = None):
         self.handle = mad_mesh_create(n_verts, tris, comp_offsets)
@@ -273,6 +375,10 @@ class Problem:
 
     def add_term(self, kind: int, params=(), rest_pos: np.ndarray | None = None):
         mad_problem_add_term(self.handle, kind, params, rest_pos)
+
+    def add_mlp_term(self, net: "Network", rest_pos: np.ndarray):
+        mad_problem_add_mlp_term(self.handle, net.handle, rest_pos)
+        self._nets = getattr(self, "_nets", []) + [net]    # the network must outlive the problem
 
     def finalize(self, stream=None):
         mad_problem_finalize(self.handle, stream)

@@ -277,6 +277,33 @@ def icosphere_batch(n_meshes: int = 700, size_seed: int = 4001, shape_seed: int 
                                size_seed=size_seed, shape_seed=shape_seed))
 
 
+def training_shells(n_meshes: int, n: int = 32, seed: int = 5002) -> list[MeshInput]:
+    """Perturbed rolled sheets whose triangles supply training samples of the learned density.
+
+    Each sheet: flat n x n rest grid on [0,1]^2 (grid()); deformed by rotating the sheet in its
+    plane by phi ~ U[0, pi), stretching the two in-plane axes by 1 + U[-0.05, 0.05] each, rolling
+    (roll_cylinder) with radius R = +-U[0.2, 2] (random sign: bending either way), and adding
+    N(0, (1e-3 h)^2) noise per coordinate.
+    """
+    rg = np.random.default_rng(seed)
+    tris, rest = grid(n)
+    h = 1.0 / (n - 1)
+    out = []
+    for _ in range(n_meshes):
+        phi = rg.uniform(0.0, math.pi)
+        c, s = math.cos(phi), math.sin(phi)
+        st = 1.0 + rg.uniform(-0.05, 0.05, size=2)
+        p = rest.copy()
+        p[:, 0] = (c * rest[:, 0] - s * rest[:, 1]) * st[0]
+        p[:, 1] = (s * rest[:, 0] + c * rest[:, 1]) * st[1]
+        radius = rg.uniform(0.2, 2.0) * (1.0 if rg.uniform() < 0.5 else -1.0)
+        x = roll_cylinder(p, radius)
+        x += rg.normal(0.0, 1e-3 * h, size=x.shape)
+        out.append(MeshInput(tris, rest, x, 3, meta=dict(workload="training_shell", phi=phi, stretch=st,
+                                                         radius=radius)))
+    return out
+
+
 def tiny_meshes() -> dict[str, tuple[np.ndarray, np.ndarray]]:
     """Small hand-made meshes for brute-force checks: (tris, positions)."""
     out = {}

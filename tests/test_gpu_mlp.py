@@ -1,0 +1,305 @@
+"""GPU parity of the learned per-triangle density and its analytic counterpart
+(through the C ABI) against the FP64 oracle on the same seeded inputs:
+
+* the analytic shell-triangle term (same bar as every element term);
+* the learned-density term with a seeded network (weights rounded to BF16 on
+  both sides), whose network pass runs on the matrix cores;
+* the training loss gradient and Adam steps;
+* an end-to-end training run on oracle-generated samples, reporting what the
+  trained network gains over the plain StVK + dihedral-bending form.
+
+Tolerance of the learned-density term: the network pass carries FP32
+activations exactly (three BF16 terms) into FP32 accumulation over 64 units;
+each of its 28 outputs is a sum of 64 products and commits about
+64 * 2^-24 = 4e-6 of the sum of its terms' magnitudes, and the second-order
+channels combine two such sums. Measured against the element scale the worst
+entry is 2.4e-6; the test holds the term to RTOL_MLP = 1e-5, the FP32 bar,
+also when the element chain runs in FP64.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2509_00406_amd import meshgen
+from tests import parity as PR
+
+pytestmark = pytest.mark.gpu
+
+ALL = 1 | 2 | 4
+RTOL_MLP = 1e-5
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_00406_amd import mad
+    mad.lib()
+    return torch
+
+
+def bf16_round(a) -> np.ndarray:
+    """FP32 -> BF16 (round to nearest even) -> FP32, on the host."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def seeded_network(seed=11, scale=0.6):
+    """Trainable parameters (packed order), input and output scales of a random network."""
+    r = np.random.default_rng(seed)
+    H = 64
+    W1 = r.normal(scale=scale, size=(H, 6))
+    b1 = r.normal(scale=scale, size=H)
+    W2 = r.normal(scale=scale / np.sqrt(H) * 2, size=(H, H))
+    b2 = r.normal(scale=scale, size=H)
+    w3 = r.normal(scale=scale, size=H)
+    b3 = r.normal()
+    theta = np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, [b3]]).astype(np.float32)
+    s_in = r.uniform(0.5, 2.0, size=6).astype(np.float32)
+    s_out = np.float32(r.uniform(0.5, 1.5))
+    return theta, s_in, s_out
+
+
+def oracle_params(theta32, s_in, s_out):
+    """The oracle's parameter block from FP32 trainable parameters (packed order)."""
+    t = np.asarray(theta32, dtype=np.float64)
+    H = 64
+    o = 0
+    W1 = t[o:o + 6 * H].reshape(H, 6); o += 6 * H
+    b1 = t[o:o + H]; o += H
+    W2 = t[o:o + H * H].reshape(H, H); o += H * H
+    b2 = t[o:o + H]; o += H
+    w3 = t[o:o + H]; o += H
+    b3 = t[o]
+    return O.mlp_pack(float(s_out), np.asarray(s_in, np.float64), W1, b1, W2, b2, w3, b3)
+
+
+def run_term(torch, inp, precision, mode, term, spd_eps=0.0, patch_faces=0, scatter=0):
+    """Build the GPU problem with one shell-feature term and the oracle twin; compare."""
+    from paper_2509_00406_amd import mad
+    nv = inp.n_verts
+    mesh = mad.Mesh(inp.tris, nv, inp.comp_offsets)
+    prob = mad.Problem(mesh, 3, precision, patch_faces=patch_faces, spd_eps=spd_eps, scatter=scatter)
+    P = O.Problem(inp.tris, inp.rest, nv, 3)
+    if term[0] == "shell":
+        prob.add_term(mad.SHELL_TRI, term[1], inp.rest)
+        P.add_term(O.SHELL_TRI, term[1])
+        rtol = PR.RTOL[precision]
+    else:
+        theta, s_in, s_out = term[1]
+        net = mad.Network(theta, s_in, s_out)
+        prob.add_mlp_term(net, inp.rest)
+        P.add_term(O.MLP, oracle_params(bf16_round(theta), s_in, s_out))
+        rtol = max(PR.RTOL[precision], RTOL_MLP)
+    prob.finalize()
+    rowptr, colidx = prob.pattern()
+    assert np.array_equal(rowptr.cpu().numpy(), P.build_pattern()[0])
+    assert np.array_equal(colidx.cpu().numpy(), P.colidx)
+    xt = torch.from_numpy(np.ascontiguousarray(inp.x, dtype=np.float64).ravel()).cuda()
+    energy, grad, hess = prob.eval(xt, mode | 1)
+    torch.cuda.synchronize()
+    nonfinite, _ = prob.status()
+    assert not nonfinite
+    ref = P.eval(inp.x, (mode | 1) & 15, spd_eps=spd_eps)
+    e = energy.cpu().numpy()
+    assert abs(e[0] - ref.energy) <= rtol * ref.esum_abs, (e[0], ref.energy)
+    out = {}
+    if mode & 2:
+        out["grad"] = PR.assert_close("grad", grad.cpu().numpy(), ref.grad, ref.gscale, rtol)
+    if mode & 4:
+        out["hess"] = PR.assert_close("hess", hess.cpu().numpy(), ref.hess, ref.hscale, rtol)
+    say("worst |err|/scale", out)
+    return out, prob, (energy, grad, hess)
+
+
+# ---------------------------------------------------------------- analytic shell triangle
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("spd", [False, True])
+def test_shell_tri_cylinder(torch_cuda, precision, spd):
+    say("shell tri cylinder", precision, spd)
+    inp = meshgen.shell_cylinder(n=40, seed=31)
+    run_term(torch_cuda, inp, precision, ALL | (8 if spd else 0), ("shell", (1.0, 0.8, 0.5)), patch_faces=128)
+
+
+def test_shell_tri_curved_rest_batched_atomic(torch_cuda):
+    say("shell tri icospheres atomic")
+    inp = meshgen.icosphere_batch(n_meshes=3, mean_verts=900, vmin=600, vmax=1500)
+    run_term(torch_cuda, inp, 0, ALL | 8, ("shell", (1.0, 0.8, 0.5)), scatter=1)
+
+
+# ---------------------------------------------------------------- learned density
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("spd", [False, True])
+def test_mlp_term_cylinder(torch_cuda, precision, spd):
+    say("mlp term cylinder", precision, spd)
+    inp = meshgen.shell_cylinder(n=33, seed=32)          # 2048 triangles: 128 network tiles
+    run_term(torch_cuda, inp, precision, ALL | (8 if spd else 0), ("mlp", seeded_network(11)), patch_faces=128)
+
+
+def test_mlp_term_ragged_and_curved_rest(torch_cuda):
+    # 2 icospheres: triangle count not a multiple of 16 (ragged last network tile), nonzero rest II
+    say("mlp term icospheres ragged")
+    inp = meshgen.icosphere_batch(n_meshes=2, mean_verts=700, vmin=600, vmax=900)
+    run_term(torch_cuda, inp, 1, ALL | 8, ("mlp", seeded_network(12)))
+    run_term(torch_cuda, inp, 0, ALL, ("mlp", seeded_network(12)), scatter=1)
+
+
+def test_mlp_tiny_mesh(torch_cuda):
+    say("mlp term two triangles")
+    tris, pos = meshgen.tiny_meshes()["two_tris"]
+    inp = meshgen.MeshInput(tris, pos, pos + np.random.default_rng(3).normal(scale=0.05, size=pos.shape), 3)
+    run_term(torch_cuda, inp, 1, ALL | 8, ("mlp", seeded_network(13)))
+
+
+# ---------------------------------------------------------------- training
+def training_batch(n_meshes=6, n=24, seed=41):
+    zs = []
+    for m in meshgen.training_shells(n_meshes, n, seed=seed):
+        r8 = O.rest_shell(m.tris, m.rest, m.n_verts)
+        zs.append(O.shell_features(m.tris, r8, m.x, m.n_verts))
+    z = np.concatenate(zs)
+    W, dW = O.shell_density(z, (1.0, 1.0, 1.0))
+    return z, W, dW
+
+
+def test_loss_gradient_vs_oracle(torch_cuda):
+    say("training gradient")
+    torch = torch_cuda
+    from paper_2509_00406_amd import mad
+    z, W, dW = training_batch()
+    theta, s_in, s_out = seeded_network(21, scale=0.4)
+    s_in = (1.0 / z.std(axis=0)).astype(np.float32)
+    s_out = np.float32(W.std())
+    c_e, c_g, lam = float(W.var()), (dW ** 2).mean(axis=0), 0.5
+    net = mad.Network(theta, s_in, s_out)
+    zt = torch.from_numpy(z.astype(np.float32)).cuda()
+    Wt = torch.from_numpy(W.astype(np.float32)).cuda()
+    dWt = torch.from_numpy(dW.astype(np.float32)).cuda()
+    idx = torch.from_numpy(np.random.default_rng(5).permutation(z.shape[0]).astype(np.int32)).cuda()
+    for base, count in ((0, z.shape[0]), (17, 1000), (3, 1)):
+        grad, loss = net.loss_grad(zt, Wt, dWt, c_e, c_g, lam, idx=idx, base=base, count=count)
+        torch.cuda.synchronize()
+        sel = idx.cpu().numpy()[base:base + count]
+        # the oracle sees the FP32 samples the GPU sees
+        z32, W32, dW32 = (a.astype(np.float32).astype(np.float64) for a in (z[sel], W[sel], dW[sel]))
+        lref, gref = O.mlp_loss_grad(oracle_params(theta, s_in, s_out), z32, W32, dW32, c_e,
+                                     c_g.astype(np.float32).astype(np.float64), lam)
+        g = grad.cpu().numpy().astype(np.float64)
+        err = np.max(np.abs(g - gref)) / np.max(np.abs(gref))
+        say("batch", count, "grad rel err", err, "loss", float(loss.cpu()), lref)
+        assert err < 2e-4
+        assert abs(float(loss.cpu()) - lref) < 1e-4 * lref
+
+
+def test_adam_steps_vs_oracle(torch_cuda):
+    say("adam")
+    torch = torch_cuda
+    from paper_2509_00406_amd import mad
+    theta, s_in, s_out = seeded_network(22)
+    net = mad.Network(theta, s_in, s_out)
+    r = np.random.default_rng(9)
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    for t in range(1, 4):
+        g = r.normal(size=th.size).astype(np.float32)
+        net.adam_step(torch.from_numpy(g).cuda(), 1e-3)
+        th, m, v = O.adam_step(th, g.astype(np.float64), m, v, t, 1e-3)
+    got = net.params(0).astype(np.float64)
+    assert np.max(np.abs(got - th)) < 1e-6 * max(1.0, np.max(np.abs(th)))
+    assert np.array_equal(net.params(1), bf16_round(got.astype(np.float32)))
+
+
+def test_train_and_gain(torch_cuda):
+    """Train on oracle samples, then compare the trained network's term with the analytic
+    density it learned and with the plain StVK + dihedral form on a cylinder."""
+    say("train end to end")
+    torch = torch_cuda
+    from paper_2509_00406_amd import mad
+    z, W, dW = training_batch(n_meshes=60, n=32, seed=43)      # 115,320 samples
+    s_in = (1.0 / z.std(axis=0)).astype(np.float32)
+    s_out = np.float32(W.std())
+    # per-feature normalisers: the membrane features' gradients are ~10x smaller than the bending ones
+    c_e, c_g, lam = float(W.var()), (dW ** 2).mean(axis=0), 1.0
+    theta, _, _ = seeded_network(23, scale=0.5)
+    nets = []
+    for rep in range(2):                                    # twice: training is deterministic
+        net = mad.Network(theta, s_in, s_out)
+        zt = torch.from_numpy(z.astype(np.float32)).cuda()
+        Wt = torch.from_numpy(W.astype(np.float32)).cuda()
+        dWt = torch.from_numpy(dW.astype(np.float32)).cuda()
+        rng = np.random.default_rng(77)
+        n_batches = (z.shape[0] + 511) // 512
+        hist = torch.zeros(n_batches, dtype=torch.float32, device="cuda")
+        first = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        epochs = 40
+        for ep in range(epochs):
+            perm = torch.from_numpy(rng.permutation(z.shape[0]).astype(np.int32)).cuda()
+            lr = 3e-3 if ep < 20 else (1e-3 if ep < 32 else 3e-4)
+            net.train_epoch(zt, Wt, dWt, perm, 512, c_e, c_g, lam, lr, loss_hist=hist)
+            if first is None:
+                torch.cuda.synchronize()
+                first = float(hist[:8].mean())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        last = float(hist.mean())
+        say(f"rep {rep}: loss {first:.4g} -> {last:.4g}, {epochs} epochs in {dt:.2f} s "
+            f"({epochs * z.shape[0] / dt:.3g} samples/s)")
+        assert last < 0.01 * first
+        nets.append(net)
+    assert np.array_equal(nets[0].params(0), nets[1].params(0))
+    net = nets[0]
+    # the trained network on a cylinder: energy, gradient and Hessian against the analytic density
+    inp = meshgen.shell_cylinder(n=64, seed=5001)
+    x = torch.from_numpy(inp.x.ravel().copy()).cuda()
+    mesh = mad.Mesh(inp.tris, inp.n_verts)
+    pm = mad.Problem(mesh, 3, mad.F32)
+    pm.add_mlp_term(net, inp.rest)
+    pm.finalize()
+    pa = mad.Problem(mesh, 3, mad.F32)
+    pa.add_term(mad.SHELL_TRI, (1.0, 1.0, 1.0), inp.rest)
+    pa.finalize()
+    pp = mad.Problem(mesh, 3, mad.F32)
+    pp.add_term(mad.STVK, (1.0, 1.0), inp.rest)
+    pp.add_term(mad.BENDING, (1.0, 1.0), inp.rest)
+    pp.finalize()
+    mode = ALL | 8
+    em, gm, hm = pm.eval(x, mode)
+    ea, ga, ha = pa.eval(x, mode)
+    torch.cuda.synchronize()
+    e_err = abs(float(em[0] - ea[0])) / abs(float(ea[0]))
+    g_err = float((gm - ga).norm() / ga.norm())
+    h_err = float((hm - ha).norm() / ha.norm())
+
+    def timed(p):
+        o = p.outputs()
+        for _ in range(3):
+            p.eval(x, mode, out=o)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(20):
+            p.eval(x, mode, out=o)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / 20 * 1e3
+
+    t_m, t_a, t_p = timed(pm), timed(pa), timed(pp)
+    say(f"trained network vs analytic density on a 64x64 cylinder: energy rel err {e_err:.3g}, "
+        f"grad {g_err:.3g}, hess {h_err:.3g}")
+    say(f"blocks: learned/analytic triangle form {pm.nnzb}, StVK + dihedral {pp.nnzb}; "
+        f"ms per eval: learned {t_m:.3f}, analytic {t_a:.3f}, StVK + dihedral {t_p:.3f}")
+    assert pm.nnzb == pa.nnzb < pp.nnzb
+    # the network is fitted to values and first derivatives only; its energy and gradient follow the
+    # analytic density closely, its curvature less so (reported, loosely bounded)
+    assert e_err < 0.02 and g_err < 0.1 and h_err < 1.0
