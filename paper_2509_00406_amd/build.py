@@ -26,6 +26,13 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-at
           "-Wall", "-Wno-unused-function", "-pthread", "-I", os.path.join(os.path.dirname(HERE), "include")]
 
 
+# Element kernels: let the compiler drop arithmetic on the structurally zero channels of the duals
+# (x * 0 -> 0 and x + 0 -> x need no-NaN/no-Inf and no-signed-zero assumptions). Their finiteness
+# checks read exponent bits (kernels_common.hpp). No reassociation: sums keep their order.
+ELEMENT_FLAGS = ["-fno-signed-zeros", "-ffinite-math-only"]
+EXTRA = {"kernels_patch.hip": ELEMENT_FLAGS, "kernels_eval.hip": ELEMENT_FLAGS}
+
+
 def build(verbose: bool = False, jobs: int = 6) -> str:
     os.makedirs(BUILD, exist_ok=True)
     t0 = time.time()
@@ -35,7 +42,7 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
         obj = os.path.join(BUILD, src.replace(".", "_") + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *COMMON, *EXTRA.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

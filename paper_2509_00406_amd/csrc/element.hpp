@@ -17,6 +17,8 @@
 // instead of an NS*D x NS*D one (6 instead of 9 for a triangle in 3D, 9
 // instead of 12 for a diamond).
 #pragma once
+#include <type_traits>
+
 #include "dual.hpp"
 
 namespace mad {
@@ -191,101 +193,103 @@ template <> struct JacobiTol<double> {
     static constexpr int sweeps = 25;
 };
 
-// Evaluate one element. MODE: 0 passive, 1 gradient, 2 Hessian, 3 clamped Hessian.
-// xs: stencil DOFs (NS*D, FP64). Returns false if the eigen-decomposition did not converge.
+// Derivatives of one element (modes 1-3): energy, stencil gradient, and the reduced Hessian --
+// for MODE 2 the raw Hessian in relative coordinates (into out.hr), for MODE 3 the Hessian in
+// Helmert coordinates Hq = (W (x) I)^T H_r (W (x) I) (into Aq, to be clamped by element_clamp).
 template <class Term, typename T, int MODE>
-__device__ __forceinline__ bool element_eval(const double* xs, const double* rest, const double* prm, double eps,
-                                             ElemOut<Term, T>& out) {
+__device__ __forceinline__ void element_derivs(const double* xs, const double* rest, const double* prm,
+                                               ElemOut<Term, T>& out, T (&Aq)[Packed<Term::KR>::N]) {
     constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
     double r[KR];
 #pragma unroll
     for (int s = 1; s < NS; ++s)
 #pragma unroll
         for (int c = 0; c < D; ++c) r[(s - 1) * D + c] = xs[s * D + c] - xs[c];
+    using S = typename std::conditional<MODE == 1, D1<KR, T>, HD<KR, T>>::type;
+    S rs[KR];
+#pragma unroll
+    for (int i = 0; i < KR; ++i) rs[i] = var<S>(i, r[i]);
+    const S f = Term::template energy<S>(rs, rest, prm);
+    out.f = f.v;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        T g0 = T(0);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) {
+            out.g[s * D + c] = f.g[(s - 1) * D + c];
+            g0 -= f.g[(s - 1) * D + c];
+        }
+        out.g[c] = g0;
+    }
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int i = 0; i < Packed<KR>::N; ++i) out.hr[i] = f.h[i];
+    } else if constexpr (MODE == 3) {
+#pragma unroll
+        for (int i = 0; i < KR; ++i)
+#pragma unroll
+            for (int j = i; j < KR; ++j) {
+                const int bi = i / D, ci = i % D, bj = j / D, cj = j % D;
+                T acc = T(0);
+#pragma unroll
+                for (int a = 0; a < NS - 1; ++a) {
+                    const double wa = wmat(a, bi);
+                    if (wa == 0.0) continue;
+#pragma unroll
+                    for (int b = 0; b < NS - 1; ++b) {
+                        const double wb = wmat(b, bj);
+                        if (wb == 0.0) continue;
+                        acc += T(wa * wb) * f.h[Packed<KR>::at(a * D + ci, b * D + cj)];
+                    }
+                }
+                Aq[Packed<KR>::at(i, j)] = acc;
+            }
+    }
+}
 
+// clamp(Hq) = V diag(max(lambda, eps)) V^T into out.hr; returns whether the eigen-decomposition
+// converged
+template <class Term, typename T>
+__device__ __forceinline__ bool element_clamp(T (&A)[Packed<Term::KR>::N], double eps, ElemOut<Term, T>& out) {
+    constexpr int KR = Term::KR;
+    T V[KR][KR];
+    const bool conv = jacobi_eig<KR, T>(A, V, JacobiTol<T>::sweeps, JacobiTol<T>::tol);
+    const T te = T(eps > 0.0 ? eps : 0.0);
+#pragma unroll
+    for (int i = 0; i < Packed<KR>::N; ++i) out.hr[i] = T(0);
+#pragma unroll
+    for (int m = 0; m < KR; ++m) {
+        const T lam = A[Packed<KR>::at(m, m)];
+        const T lp = lam > te ? lam : te;
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            const T li = lp * V[i][m];
+#pragma unroll
+            for (int j = i; j < KR; ++j) out.hr[Packed<KR>::at(i, j)] += li * V[j][m];
+        }
+    }
+    return conv;
+}
+
+// Evaluate one element. MODE: 0 passive, 1 gradient, 2 Hessian, 3 clamped Hessian.
+// xs: stencil DOFs (NS*D, FP64). Returns false if the eigen-decomposition did not converge.
+template <class Term, typename T, int MODE>
+__device__ __forceinline__ bool element_eval(const double* xs, const double* rest, const double* prm, double eps,
+                                             ElemOut<Term, T>& out) {
+    constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
     if constexpr (MODE == 0) {
+        double r[KR];
+#pragma unroll
+        for (int s = 1; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < D; ++c) r[(s - 1) * D + c] = xs[s * D + c] - xs[c];
         out.f = Term::template energy<double>(r, rest, prm);
         return true;
-    } else if constexpr (MODE == 1) {
-        using S = D1<KR, T>;
-        S rs[KR];
-#pragma unroll
-        for (int i = 0; i < KR; ++i) rs[i] = var<S>(i, r[i]);
-        const S f = Term::template energy<S>(rs, rest, prm);
-        out.f = f.v;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            T g0 = T(0);
-#pragma unroll
-            for (int s = 1; s < NS; ++s) {
-                out.g[s * D + c] = f.g[(s - 1) * D + c];
-                g0 -= f.g[(s - 1) * D + c];
-            }
-            out.g[c] = g0;
-        }
-        return true;
     } else {
-        using S = HD<KR, T>;
-        S rs[KR];
-#pragma unroll
-        for (int i = 0; i < KR; ++i) rs[i] = var<S>(i, r[i]);
-        const S f = Term::template energy<S>(rs, rest, prm);
-        out.f = f.v;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            T g0 = T(0);
-#pragma unroll
-            for (int s = 1; s < NS; ++s) {
-                out.g[s * D + c] = f.g[(s - 1) * D + c];
-                g0 -= f.g[(s - 1) * D + c];
-            }
-            out.g[c] = g0;
-        }
-        if constexpr (MODE == 2) {
-#pragma unroll
-            for (int i = 0; i < Packed<KR>::N; ++i) out.hr[i] = f.h[i];
-            return true;
-        } else {
-            // Hq = (W (x) I)^T H_r (W (x) I)
-            T A[Packed<KR>::N];
-#pragma unroll
-            for (int i = 0; i < KR; ++i)
-#pragma unroll
-                for (int j = i; j < KR; ++j) {
-                    const int bi = i / D, ci = i % D, bj = j / D, cj = j % D;
-                    T acc = T(0);
-#pragma unroll
-                    for (int a = 0; a < NS - 1; ++a) {
-                        const double wa = wmat(a, bi);
-                        if (wa == 0.0) continue;
-#pragma unroll
-                        for (int b = 0; b < NS - 1; ++b) {
-                            const double wb = wmat(b, bj);
-                            if (wb == 0.0) continue;
-                            acc += T(wa * wb) * f.h[Packed<KR>::at(a * D + ci, b * D + cj)];
-                        }
-                    }
-                    A[Packed<KR>::at(i, j)] = acc;
-                }
-            T V[KR][KR];
-            const bool conv = jacobi_eig<KR, T>(A, V, JacobiTol<T>::sweeps, JacobiTol<T>::tol);
-            const T te = T(eps > 0.0 ? eps : 0.0);
-            // clamp(Hq) = V diag(max(lambda, eps)) V^T, packed
-#pragma unroll
-            for (int i = 0; i < Packed<KR>::N; ++i) out.hr[i] = T(0);
-#pragma unroll
-            for (int m = 0; m < KR; ++m) {
-                const T lam = A[Packed<KR>::at(m, m)];
-                const T lp = lam > te ? lam : te;
-#pragma unroll
-                for (int i = 0; i < KR; ++i) {
-                    const T li = lp * V[i][m];
-#pragma unroll
-                    for (int j = i; j < KR; ++j) out.hr[Packed<KR>::at(i, j)] += li * V[j][m];
-                }
-            }
-            return conv;
-        }
+        T A[Packed<KR>::N];
+        element_derivs<Term, T, MODE>(xs, rest, prm, out, A);
+        if constexpr (MODE == 3) return element_clamp<Term, T>(A, eps, out);
+        return true;
     }
 }
 

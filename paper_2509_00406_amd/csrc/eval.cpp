@@ -88,6 +88,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.work_counter = p->d_work_counter;
         L.n_cu = p->n_cu;
         L.normals = p->d_normals;
+        L.shell = p->shell ? 1 : 0;
         for (size_t ti = 0; ti < p->terms.size(); ++ti) {
             const Term& t = p->terms[ti];
             PatchTermArgs& A = L.terms[ti];

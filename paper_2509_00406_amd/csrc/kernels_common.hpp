@@ -13,7 +13,20 @@ constexpr int kBlock = 256;
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
-__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
+// Finiteness by an integer test of the exponent bits, after an empty asm has hidden the value's
+// origin: the element kernels are compiled with -ffinite-math-only (so that arithmetic on the
+// structurally zero channels of the duals folds away), under which a floating-point test could be
+// folded to "finite". The hardware still computes IEEE results; this reads them.
+__device__ __forceinline__ bool finite(float v) {
+    uint32_t u = __float_as_uint(v);
+    asm volatile("" : "+v"(u));
+    return (u & 0x7f800000u) != 0x7f800000u;
+}
+__device__ __forceinline__ bool finite(double v) {
+    uint64_t u = (uint64_t)__double_as_longlong(v);
+    asm volatile("" : "+v"(u));
+    return (u & 0x7ff0000000000000ull) != 0x7ff0000000000000ull;
+}
 
 // triangle quality 4 sqrt(3) A / (l0^2 + l1^2 + l2^2): 1 for equilateral, 0 for degenerate
 __device__ __forceinline__ double tri_quality3(const double* a, const double* b, const double* c) {
@@ -74,19 +87,21 @@ __device__ __forceinline__ void gather_inputs(double (&in)[n_inputs<Term>()], co
     }
 }
 
+// An element's outputs are all finite iff the sum of their magnitudes is (a NaN or an infinity
+// anywhere reaches the sum; finite outputs cannot overflow it at the magnitudes that occur here).
 template <class Term, typename T>
 __device__ __forceinline__ bool out_finite(const ElemOut<Term, T>& o, int mode) {
     constexpr int NF = Term::NS * Term::D;
-    bool ok = finite(o.f);
+    T acc = T(0);
     if (mode >= 1) {
 #pragma unroll
-        for (int i = 0; i < NF; ++i) ok = ok && finite(double(o.g[i]));
+        for (int i = 0; i < NF; ++i) acc += fabs(o.g[i]);
     }
     if (mode >= 2) {
 #pragma unroll
-        for (int i = 0; i < Packed<Term::KR>::N; ++i) ok = ok && finite(double(o.hr[i]));
+        for (int i = 0; i < Packed<Term::KR>::N; ++i) acc += fabs(o.hr[i]);
     }
-    return ok;
+    return finite(o.f) && finite(acc);
 }
 
 template <class Term, typename T, typename U>

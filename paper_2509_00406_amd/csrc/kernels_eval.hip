@@ -55,7 +55,10 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalLaunch L) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int c = 0; c < D; ++c) xs[s * D + c] = L.x[(int64_t)vs[s] * D + c];
+            for (int c = 0; c < D; ++c) {
+                xs[s * D + c] = L.x[(int64_t)vs[s] * D + c];
+                bad = bad || !finite(xs[s * D + c]);
+            }
         double rest[n_inputs<Term>()];
         gather_inputs<Term>(rest, L.rest, L.n, e, L.normals, vs, L.psi);
 

@@ -3,17 +3,15 @@
 // its first and second derivatives with respect to the six features for every
 // triangle, and the training pass (loss, gradient, Adam).
 //
-// Network pass. Forward mode is seeded on the six (scaled) features, so each
-// hidden unit of layer 1 carries 28 channels: value, 6 first and 21 second
-// derivatives, all closed-form in the unit's pre-activation a1:
-//   sp(a1),  sigma(a1) W1[k,i],  sigma'(a1) W1[k,i] W1[k,j].
-// Layer 2 is the dense contraction a2[m, c] = sum_k W2[m, k] h1[k, c] over
-// 64 units for every (element, channel) column: it runs on the matrix cores
-// (v_mfma_f32_16x16x32_bf16). W2 is BF16 exactly; every activation is split
-// into three BF16 terms (hi + mid + lo carries all 24 bits of an FP32
-// significand), so the three MFMAs per tile reproduce FP32 products with FP32
-// accumulation. Layer 2's softplus and the output layer are applied to the
-// accumulators in registers and reduced over the 64 units.
+// Network pass. Forward mode is seeded on the six (scaled) features: layer 1's
+// unit k carries, in closed form, sp(a1) and its first derivatives
+// sigma(a1) W1[k,i] (second derivatives sigma'(a1) W1[k,i] W1[k,j]). Layer 2
+// is a dense contraction over 64 units for every (triangle, channel) column and
+// runs on the matrix cores (v_mfma_f32_16x16x32_bf16), as does the transposed
+// contraction u = W2^T v that folds layer 2's second-order channels into one
+// (see k_mlp_head). W2 is BF16 exactly; every activation is split into three
+// BF16 terms (hi + mid + lo carries all 24 bits of an FP32 significand), so
+// the three MFMAs per tile reproduce FP32 products with FP32 accumulation.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -104,12 +102,41 @@ __device__ __forceinline__ void features_at(const MlpHeadLaunch& L, int64_t e, d
     shell_features<double>(r, in, z);
 }
 
-// One wave evaluates 16 triangles at a time (one per MFMA column); lane l holds column l % 16 and
-// hidden units k = 32 ks + 8 (l / 16) + j of the B operand, rows m = 16 mt + 4 (l / 16) + jj of the
-// accumulators.
-__global__ __launch_bounds__(256) void k_mlp_head(MlpHeadLaunch L) {
+// wave-scope ordering of LDS accesses between the lanes of one wave
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// three BF16 terms of an FP32 value (hi + mid + lo reproduces its 24 significand bits), stored
+// into element j of three operand vectors
+__device__ __forceinline__ void split3(float v, bf16x8& h, bf16x8& m, bf16x8& l, int j) {
+    const __bf16 a = (__bf16)v;
+    const float r = v - (float)a;
+    const __bf16 b = (__bf16)r;
+    h[j] = a;
+    m[j] = b;
+    l[j] = (__bf16)(r - (float)b);
+}
+
+// One wave evaluates 16 triangles at a time (one per MFMA column). With v = w3 * sigma(a2) and
+// u = W2^T v, the network's derivatives with respect to the scaled features xh are
+//   dpsi/dxh_i        = sum_k u_k sigma(a1_k) W1[k,i]
+//   d2psi/dxh_i dxh_j = sum_k u_k sigma'(a1_k) W1[k,i] W1[k,j] + sum_m w3_m sigma'(a2_m) g_mi g_mj,
+// g_mi = sum_k W2[m,k] sigma(a1_k) W1[k,i] (layer 2's first-order channels). So the matrix cores
+// run seven forward channels (value and g_i: a2 = W2 [sp(a1) | sigma(a1) W1]) and one transposed
+// contraction (u = W2^T v); the rest is per-triangle VALU work.
+// Layouts (16x16x32 MFMA): B operand lane l holds column l % 16 (a triangle) and hidden units
+// k = 32 ks + 8 (l / 16) + j; accumulators hold rows 4 (l / 16) + jj of each 16-row tile.
+constexpr int kHeadWaves = 4;
+
+__global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
     __shared__ float sW1[kHid * 6], sB1[kHid], sB2[kHid], sW3[kHid];
+    __shared__ uint16_t sW2[kHid * kHid];
+    __shared__ float sT[kHeadWaves][16][kHid + 1];   // per wave: v, then u, as [triangle][unit]
     for (int i = threadIdx.x; i < kHid * 6; i += blockDim.x) sW1[i] = bf2f(L.wbf[kOffW1 + i]);
+    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x) sW2[i] = L.wbf[kOffW2 + i];
     for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
         sB1[i] = bf2f(L.wbf[kOffB1 + i]);
         sB2[i] = bf2f(L.wbf[kOffB2 + i]);
@@ -118,17 +145,18 @@ __global__ __launch_bounds__(256) void k_mlp_head(MlpHeadLaunch L) {
     __syncthreads();
     const float b3 = bf2f(L.wbf[kOffB3]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
+    float (*T)[kHid + 1] = sT[wave];
+    // A operand: W2 rows m = 16 mt + col, k = 32 ks + 8 g + j
     short8 A[4][2];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                A[mt][ks][j] = (short)L.wbf[kOffW2 + (16 * mt + col) * kHid + 32 * ks + 8 * g + j];
-    const int waves = blockDim.x >> 6;
+            for (int j = 0; j < 8; ++j) A[mt][ks][j] = (short)sW2[(16 * mt + col) * kHid + 32 * ks + 8 * g + j];
     const int64_t tiles = (L.n + 15) / 16;
-    for (int64_t tile = (int64_t)blockIdx.x * waves + wave; tile < tiles; tile += (int64_t)gridDim.x * waves) {
+    for (int64_t tile = (int64_t)blockIdx.x * kHeadWaves + wave; tile < tiles;
+         tile += (int64_t)gridDim.x * kHeadWaves) {
         const int64_t e = tile * 16 + col;
         const bool valid = e < L.n;
         float xh[6];
@@ -138,6 +166,7 @@ __global__ __launch_bounds__(256) void k_mlp_head(MlpHeadLaunch L) {
 #pragma unroll
             for (int i = 0; i < 6; ++i) xh[i] = float(z[i]) * L.s_in[i];
         }
+        // layer 1 at this lane's 16 units (B layout)
         float a1[2][8], s1[2][8];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
@@ -150,34 +179,21 @@ __global__ __launch_bounds__(256) void k_mlp_head(MlpHeadLaunch L) {
                 a1[ks][j] = a;
                 s1[ks][j] = logisticf(a);
             }
-        float P[kPsi];
+        // layer 2, seven forward channels: c = 0 value, c = 1 + i first derivative along xh_i
+        float P0 = 0.0f, PH[21];
 #pragma unroll
-        for (int c = 0; c < kPsi; ++c) P[c] = 0.0f;
-        float a2g[6][4][4], s2[4][4], s2p[4][4];
+        for (int q = 0; q < 21; ++q) PH[q] = 0.0f;
+        float v[4][4], ws2p[4][4], a2g[6][4][4];
 #pragma unroll
-        for (int c = 0; c < kPsi; ++c) {
-            short8 bh[2], bm[2], bl[2];
+        for (int c = 0; c < 7; ++c) {
+            bf16x8 bh[2], bm[2], bl[2];
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int k = 32 * ks + 8 * g + j;
-                    float v;
-                    if (c == 0) {
-                        v = softplusf(a1[ks][j]);
-                    } else if (c < 7) {
-                        v = s1[ks][j] * sW1[k * 6 + (c - 1)];
-                    } else {
-                        const float sp2 = s1[ks][j] * (1.0f - s1[ks][j]);
-                        v = sp2 * sW1[k * 6 + pair_i(c - 7)] * sW1[k * 6 + pair_j(c - 7)];
-                    }
-                    const uint16_t h = f2bf(v);
-                    const float r1 = v - bf2f(h);
-                    const uint16_t md = f2bf(r1);
-                    const uint16_t lo = f2bf(r1 - bf2f(md));
-                    bh[ks][j] = (short)h;
-                    bm[ks][j] = (short)md;
-                    bl[ks][j] = (short)lo;
+                    const float x = c == 0 ? softplusf(a1[ks][j]) : s1[ks][j] * sW1[k * 6 + (c > 0 ? c - 1 : 0)];
+                    split3(x, bh[ks], bm[ks], bl[ks], j);
                 }
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
@@ -185,45 +201,113 @@ __global__ __launch_bounds__(256) void k_mlp_head(MlpHeadLaunch L) {
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
                     const bf16x8 a = __builtin_bit_cast(bf16x8, A[mt][ks]);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bh[ks]), acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bm[ks]), acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bl[ks]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh[ks], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bm[ks], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[ks], acc, 0, 0, 0);
                 }
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const int m = 16 * mt + 4 * g + jj;
-                    const float w = sW3[m];
                     if (c == 0) {
                         const float a2 = acc[jj] + sB2[m];
                         const float sg = logisticf(a2);
-                        s2[mt][jj] = sg;
-                        s2p[mt][jj] = sg * (1.0f - sg);
-                        P[0] = fmaf(w, softplusf(a2), P[0]);
-                    } else if (c < 7) {
-                        a2g[c - 1][mt][jj] = acc[jj];
-                        P[c] = fmaf(w * s2[mt][jj], acc[jj], P[c]);
+                        v[mt][jj] = sW3[m] * sg;
+                        ws2p[mt][jj] = sW3[m] * sg * (1.0f - sg);
+                        P0 = fmaf(sW3[m], softplusf(a2), P0);
                     } else {
-                        const float o = s2[mt][jj] * acc[jj] +
-                                        s2p[mt][jj] * a2g[pair_i(c - 7)][mt][jj] * a2g[pair_j(c - 7)][mt][jj];
-                        P[c] = fmaf(w, o, P[c]);
+                        a2g[c - 1][mt][jj] = acc[jj];
                     }
                 }
             }
         }
-        // sum over the four lanes holding the same column (units 4g..4g+3 of every 16)
+        // second-order part through layer 2's nonlinearity: sum_m w3 sigma'(a2) g_mi g_mj
 #pragma unroll
-        for (int c = 0; c < kPsi; ++c) {
-            P[c] += __shfl_xor(P[c], 16);
-            P[c] += __shfl_xor(P[c], 32);
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    const float t = ws2p[mt][jj] * a2g[i][mt][jj];
+#pragma unroll
+                    for (int j2 = i; j2 < 6; ++j2) PH[Packed<6>::at(i, j2)] = fmaf(t, a2g[j2][mt][jj], PH[Packed<6>::at(i, j2)]);
+                }
+            }
+        // u = W2^T v: v to LDS as [triangle][unit], read back as the A operand (rows = triangles)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) T[col][16 * mt + 4 * g + jj] = v[mt][jj];
+        wave_sync();
+        bf16x8 vh[2], vm[2], vl[2];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) split3(T[col][32 * ks + 8 * g + j], vh[ks], vm[ks], vl[ks], j);
+        f32x4 U[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            U[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                short8 wb;   // B operand: W2[m][k], m = 32 ks + 8 g + j, k = 16 nt + col
+#pragma unroll
+                for (int j = 0; j < 8; ++j) wb[j] = (short)sW2[(32 * ks + 8 * g + j) * kHid + 16 * nt + col];
+                const bf16x8 b = __builtin_bit_cast(bf16x8, wb);
+                U[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh[ks], b, U[nt], 0, 0, 0);
+                U[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vm[ks], b, U[nt], 0, 0, 0);
+                U[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl[ks], b, U[nt], 0, 0, 0);
+            }
+        }
+        wave_sync();   // every lane has read v before u overwrites it
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) T[4 * g + jj][16 * nt + col] = U[nt][jj];
+        wave_sync();
+        // first derivatives and the layer-1 part of the second, over this lane's 16 units
+        float Pg[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * ks + 8 * g + j;
+                const float u = T[col][k];
+                const float us = u * s1[ks][j], usp = us * (1.0f - s1[ks][j]);
+                float w[6];
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    w[i] = sW1[k * 6 + i];
+                    Pg[i] = fmaf(us, w[i], Pg[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    const float t = usp * w[i];
+#pragma unroll
+                    for (int j2 = i; j2 < 6; ++j2) PH[Packed<6>::at(i, j2)] = fmaf(t, w[j2], PH[Packed<6>::at(i, j2)]);
+                }
+            }
+        wave_sync();   // u is read before the next tile writes v
+        // sum over the four lanes holding the same triangle
+        P0 += __shfl_xor(P0, 16);
+        P0 += __shfl_xor(P0, 32);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            Pg[i] += __shfl_xor(Pg[i], 16);
+            Pg[i] += __shfl_xor(Pg[i], 32);
+        }
+#pragma unroll
+        for (int q = 0; q < 21; ++q) {
+            PH[q] += __shfl_xor(PH[q], 16);
+            PH[q] += __shfl_xor(PH[q], 32);
         }
         if (valid && g == 0) {
-            // back to z: dpsi/dz_i = s_out s_in[i] dpsi^/dxh_i, likewise for the second derivatives
-            L.psi[e] = L.s_out * (P[0] + b3);
+            // back to z: dpsi/dz_i = s_out s_in[i] dpsi/dxh_i, likewise for the second derivatives
+            L.psi[e] = L.s_out * (P0 + b3);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) L.psi[(int64_t)(1 + i) * L.n + e] = L.s_out * L.s_in[i] * P[1 + i];
+            for (int i = 0; i < 6; ++i) L.psi[(int64_t)(1 + i) * L.n + e] = L.s_out * L.s_in[i] * Pg[i];
 #pragma unroll
             for (int q = 0; q < 21; ++q)
-                L.psi[(int64_t)(7 + q) * L.n + e] = L.s_out * L.s_in[pair_i(q)] * L.s_in[pair_j(q)] * P[7 + q];
+                L.psi[(int64_t)(7 + q) * L.n + e] = L.s_out * L.s_in[pair_i(q)] * L.s_in[pair_j(q)] * PH[q];
         }
     }
 }
@@ -231,8 +315,8 @@ __global__ __launch_bounds__(256) void k_mlp_head(MlpHeadLaunch L) {
 hipError_t launch_mlp_head(const MlpHeadLaunch& L, hipStream_t s) {
     if (L.n <= 0) return hipSuccess;
     const int64_t tiles = (L.n + 15) / 16;
-    const int64_t blocks = std::min<int64_t>((tiles + 3) / 4, 4096);
-    hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)blocks), dim3(256), 0, s, L);
+    const int64_t blocks = std::min<int64_t>((tiles + kHeadWaves - 1) / kHeadWaves, 2048);
+    hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)blocks), dim3(kHeadWaves * 64), 0, s, L);
     return hipGetLastError();
 }
 

@@ -21,8 +21,10 @@ template <typename T>
 __device__ __forceinline__ void lds_add(T* p, T v) { atomicAdd(p, v); }
 
 
+// queued FP32 element: term << 29 | gradient-already-assembled << 28 | element
 constexpr uint32_t kFbTermShift = 29;
-constexpr uint32_t kFbElemMask = (1u << kFbTermShift) - 1u;
+constexpr uint32_t kFbGradDone = 1u << 28;
+constexpr uint32_t kFbElemMask = kFbGradDone - 1u;
 
 template <class Term, typename T, int MODE>
 __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTermArgs& A, int term, int p,
@@ -50,31 +52,67 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
             gather_inputs<Term>(rest, A.rest, A.n, e, nullptr, nullptr, nullptr);
         }
         ElemOut<Term, T> o;
-        if constexpr (MODE == 3 && sizeof(T) == 4) {
-            bool fb = quality<Term>(xs) < L.qmin;
-            if (!fb) fb = !element_eval<Term, T, MODE>(xs, rest, A.prm, L.eps, o);
-            if (fb) {
-                // energy in FP64 here (keeps the reduction deterministic), derivatives queued
-                ElemOut<Term, double> op;
-                element_eval<Term, double, 0>(xs, rest, A.prm, L.eps, op);
-                esum += op.f;
-                bad = bad || !finite(op.f);
-                const int k = atomicAdd(L.fb_count, 1);
-                if (k < L.fb_cap) L.fb_list[k] = ((uint32_t)term << kFbTermShift) | (uint32_t)e;
-                atomicAdd(L.fallbacks, 1ull);
-                continue;
+        if constexpr (MODE == 3) {
+            // FP32: near-degenerate elements (quality below qmin) are queued whole for the FP64 redo.
+            // Every other element assembles its gradient before the eigen-decomposition (so neither
+            // it nor the inputs stay live across the Jacobi loop); an FP32 element whose
+            // decomposition does not converge is queued for its Hessian only. The primal value (the
+            // energy) is FP64 on every path, so the energy stays here and the reduction stays
+            // deterministic.
+            if constexpr (sizeof(T) == 4) {
+                if (quality<Term>(xs) < L.qmin) {
+                    ElemOut<Term, double> op;
+                    element_eval<Term, double, 0>(xs, rest, A.prm, L.eps, op);
+                    esum += op.f;
+                    bad = bad || !finite(op.f);
+                    const int k = atomicAdd(L.fb_count, 1);
+                    if (k < L.fb_cap) L.fb_list[k] = ((uint32_t)term << kFbTermShift) | (uint32_t)e;
+                    atomicAdd(L.fallbacks, 1ull);
+                    continue;
+                }
             }
-        } else {
-            element_eval<Term, T, MODE>(xs, rest, A.prm, L.eps, o);
-        }
-        esum += o.f;
-        bad = bad || !out_finite<Term, T>(o, MODE);
-        if constexpr (MODE >= 1) {
+            T Aq[Packed<Term::KR>::N];
+            element_derivs<Term, T, 3>(xs, rest, A.prm, o, Aq);
+            esum += o.f;
+            {
+                T ga = T(0);
+#pragma unroll
+                for (int i = 0; i < NF; ++i) ga += fabs(o.g[i]);
+                bad = bad || !finite(o.f) || !finite(ga);
+            }
             if (L.want_grad) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
                     for (int c = 0; c < D; ++c) lds_add(sg + lv[s] * D + c, o.g[s * D + c]);
+            }
+            const bool conv = element_clamp<Term, T>(Aq, L.eps, o);
+            if constexpr (sizeof(T) == 4) {
+                if (!conv) {
+                    const int k = atomicAdd(L.fb_count, 1);
+                    if (k < L.fb_cap)
+                        L.fb_list[k] = ((uint32_t)term << kFbTermShift) | kFbGradDone | (uint32_t)e;
+                    atomicAdd(L.fallbacks, 1ull);
+                    continue;
+                }
+            }
+            {
+                T ha = T(0);
+#pragma unroll
+                for (int i = 0; i < Packed<Term::KR>::N; ++i) ha += fabs(o.hr[i]);
+                bad = bad || !finite(ha);
+            }
+        } else {
+            element_eval<Term, T, MODE>(xs, rest, A.prm, L.eps, o);
+            esum += o.f;
+            bad = bad || !out_finite<Term, T>(o, MODE);
+            if constexpr (MODE >= 1) {
+                if (L.want_grad) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+#pragma unroll
+                        for (int c = 0; c < D; ++c) lds_add(sg + lv[s] * D + c, o.g[s * D + c]);
+                }
             }
         }
         if constexpr (MODE >= 2) {
@@ -110,7 +148,7 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
     }
 }
 
-template <typename T, int MODE, int D>
+template <typename T, int MODE, int D, bool SH>
 __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsigned char* smem, double* red) {
     constexpr int DD = D * D;
     const int lv0 = L.lv_ptr[p], nlv = L.lv_ptr[p + 1] - lv0;
@@ -119,11 +157,15 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
     T* sg = reinterpret_cast<T*>(smem + align16((size_t)nlv * D * sizeof(double)));
     T* sh = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(sg) +
                                  (MODE >= 1 ? align16((size_t)nlv * D * sizeof(T)) : 0));
+    bool bad_x = false;
     for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
         const int v = L.lv_global[lv0 + i / D];
-        sx[i] = L.x[(int64_t)v * D + (i % D)];
+        const double xv = L.x[(int64_t)v * D + (i % D)];
+        sx[i] = xv;
+        bad_x = bad_x || !finite(xv);
         if constexpr (MODE >= 1) sg[i] = T(0);
     }
+    if (bad_x) atomicOr(L.flags, 1);
     if constexpr (MODE >= 2)
         for (int i = threadIdx.x; i < nlb * DD; i += kBlock) sh[i] = T(0);
     __syncthreads();
@@ -138,8 +180,12 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
             case K_BENDING: patch_term<TermBending, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
             case K_TRI_AREA: patch_term<TermTriArea, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
             case K_EDGE_SQLEN: patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
-            case K_SHELL_TRI: patch_term<TermShellTri, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
-            case K_MLP: patch_term<TermMLP, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
+            case K_SHELL_TRI:
+                if constexpr (SH) patch_term<TermShellTri, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad);
+                break;
+            case K_MLP:
+                if constexpr (SH) patch_term<TermMLP, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad);
+                break;
             default: break;
             }
         } else if constexpr (D == 2) {
@@ -188,13 +234,13 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
 
 // One patch per workgroup, or (persistent) a grid sized to the device whose workgroups take
 // patches from a counter in the given order (largest first) until every patch is taken.
-template <typename T, int MODE, int D>
+template <typename T, int MODE, int D, bool SH>
 __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kBlock];
     __shared__ int next;
     if (!L.persistent) {
-        eval_patch_one<T, MODE, D>(L, blockIdx.x, smem, red);
+        eval_patch_one<T, MODE, D, SH>(L, blockIdx.x, smem, red);
         return;
     }
     for (;;) {
@@ -203,20 +249,22 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
         const int k = next;
         __syncthreads();   // every lane has read `next` before it is overwritten
         if (k >= L.n_patch) break;
-        eval_patch_one<T, MODE, D>(L, L.work_order[k], smem, red);
+        eval_patch_one<T, MODE, D, SH>(L, L.work_order[k], smem, red);
         __syncthreads();   // the flush has read LDS before the next patch clears it
     }
 }
 
 // FP32: the compiler is held to 256 registers so two waves share each SIMD (a few values spill
 // to scratch; the second wave hides the latency of the long dependent rotation chains).
-template <int MODE, int D>
+// SH: the shell-feature terms (analytic and learned per-triangle densities) are compiled into a
+// separate instantiation, so that their register needs do not burden the catalogue's kernel.
+template <int MODE, int D, bool SH>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_patch_f32(PatchLaunch L) {
-    eval_patch_body<float, MODE, D>(L);
+    eval_patch_body<float, MODE, D, SH>(L);
 }
-template <int MODE, int D>
+template <int MODE, int D, bool SH>
 __global__ __launch_bounds__(kBlock) void k_eval_patch_f64(PatchLaunch L) {
-    eval_patch_body<double, MODE, D>(L);
+    eval_patch_body<double, MODE, D, SH>(L);
 }
 
 // ---- gather of shared entries --------------------------------------------------------------------
@@ -284,7 +332,7 @@ __device__ __forceinline__ int32_t find_block(const int32_t* rowptr, const int32
 }
 
 template <class Term>
-__device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const FallbackTerm& A, int e) {
+__device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const FallbackTerm& A, int e, bool grad_done) {
     constexpr int NS = Term::NS, D = Term::D, NF = NS * D, DD = D * D;
     int vs[NS];
 #pragma unroll
@@ -299,7 +347,7 @@ __device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const Fal
     ElemOut<Term, double> o;
     element_eval<Term, double, 3>(xs, rest, A.prm, F.eps, o);
     if (!out_finite<Term, double>(o, 3)) atomicOr(F.flags, 1);
-    if (F.want_grad) {
+    if (F.want_grad && !grad_done) {
         float* G = static_cast<float*>(F.grad);
 #pragma unroll
         for (int s = 0; s < NS; ++s)
@@ -331,21 +379,22 @@ __global__ __launch_bounds__(kBlock) void k_fallback(FallbackLaunch F) {
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
         const uint32_t w = F.fb_list[i];
         const int t = (int)(w >> kFbTermShift), e = (int)(w & kFbElemMask);
+        const bool grad_done = (w & kFbGradDone) != 0;
         const FallbackTerm& A = F.terms[t];
         if constexpr (D == 3) {
             switch (A.kind) {
-            case K_STVK: fallback_elem<TermStVK>(F, A, e); break;
-            case K_BENDING: fallback_elem<TermBending>(F, A, e); break;
-            case K_TRI_AREA: fallback_elem<TermTriArea>(F, A, e); break;
-            case K_EDGE_SQLEN: fallback_elem<TermEdgeSqlen>(F, A, e); break;
-            case K_SHELL_TRI: fallback_elem<TermShellTri>(F, A, e); break;
-            case K_MLP: fallback_elem<TermMLP>(F, A, e); break;
+            case K_STVK: fallback_elem<TermStVK>(F, A, e, grad_done); break;
+            case K_BENDING: fallback_elem<TermBending>(F, A, e, grad_done); break;
+            case K_TRI_AREA: fallback_elem<TermTriArea>(F, A, e, grad_done); break;
+            case K_EDGE_SQLEN: fallback_elem<TermEdgeSqlen>(F, A, e, grad_done); break;
+            case K_SHELL_TRI: fallback_elem<TermShellTri>(F, A, e, grad_done); break;
+            case K_MLP: fallback_elem<TermMLP>(F, A, e, grad_done); break;
             default: break;
             }
         } else if constexpr (D == 2) {
-            if (A.kind == K_SYMDIR) fallback_elem<TermSymDir>(F, A, e);
+            if (A.kind == K_SYMDIR) fallback_elem<TermSymDir>(F, A, e, grad_done);
         } else {
-            if (A.kind == K_DIRICHLET) fallback_elem<TermDirichlet>(F, A, e);
+            if (A.kind == K_DIRICHLET) fallback_elem<TermDirichlet>(F, A, e, grad_done);
         }
     }
 }
@@ -378,16 +427,27 @@ static int persistent_grid(K kernel, const PatchLaunch& L) {
     return std::max(1, std::min(L.n_patch, std::max(L.n_cu, 1) * per_cu));
 }
 
-template <int MODE, int D>
-static void launch_patch_kernel(bool f32, const PatchLaunch& L, hipStream_t s) {
+template <int MODE, int D, bool SH>
+static void launch_patch_variant(bool f32, const PatchLaunch& L, hipStream_t s) {
     const dim3 block(kBlock);
     if (f32) {
-        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f32<MODE, D>, L) : L.n_patch);
-        hipLaunchKernelGGL((k_eval_patch_f32<MODE, D>), grid, block, L.lds_bytes, s, L);
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f32<MODE, D, SH>, L) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_f32<MODE, D, SH>), grid, block, L.lds_bytes, s, L);
     } else {
-        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f64<MODE, D>, L) : L.n_patch);
-        hipLaunchKernelGGL((k_eval_patch_f64<MODE, D>), grid, block, L.lds_bytes, s, L);
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f64<MODE, D, SH>, L) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_f64<MODE, D, SH>), grid, block, L.lds_bytes, s, L);
     }
+}
+
+template <int MODE, int D>
+static void launch_patch_kernel(bool f32, const PatchLaunch& L, hipStream_t s) {
+    if constexpr (D == 3) {
+        if (L.shell) {
+            launch_patch_variant<MODE, D, true>(f32, L, s);
+            return;
+        }
+    }
+    launch_patch_variant<MODE, D, false>(f32, L, s);
 }
 
 template <typename T, int D>

@@ -271,7 +271,7 @@ int build_scatter(mad_problem* p, hipStream_t s) {
         // queue for FP32 elements redone in FP64: room for every element
         int64_t total = 0;
         for (auto& t : p->terms) {
-            if (t.n >= (1ll << 29)) return fail(MAD_E_OVERFLOW, "more than 2^29 elements in one term");
+            if (t.n >= (1ll << 28)) return fail(MAD_E_OVERFLOW, "more than 2^28 elements in one term");
             total += t.n;
         }
         if (total >= INT32_MAX) return fail(MAD_E_OVERFLOW, "more than 2^31 elements");

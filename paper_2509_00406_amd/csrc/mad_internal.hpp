@@ -224,6 +224,7 @@ struct PatchLaunch {
     int32_t fb_cap;
     double eps, qmin;
     const double* normals;  // [nv][3] unit vertex normals (shell-feature terms)
+    int shell;              // the problem has shell-feature terms (selects the kernel variant)
     int persistent;
     const int32_t* work_order;
     int32_t* work_counter;
