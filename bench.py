@@ -29,10 +29,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Executed floating-point operations per element of the fused patch kernel on the shell workload
-# (FP32 + FP64 VALU instructions x 64 lanes, FMA = 2), from the rocprofv3 counter pass recorded in
-# profiles/k_eval_patch_shell1024_counters.md. Keyed by precision.
-FLOPS_PER_ELEM = {"f32": None, "f64": None}
+# Executed floating-point operations per element of the fused patch kernel on the 1024^2 shell
+# workload (FP32 + FP64 VALU wave instructions x 64 lanes, FMA = 2), and its HBM traffic per launch
+# (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy), from the rocprofv3 counter
+# passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
+FLOPS_PER_ELEM = {"f32": 17936.0, "f64": None}
+TRAFFIC_BYTES = {"f32": 1.056e9, "f64": None}
 
 # MI355X published peaks used as roofline denominators
 HBM_PEAK_GBS = 8000.0
@@ -307,12 +309,13 @@ def main():
         step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, 0, prob.nnzb, pb) + mesh.n_tris * 24
     else:
         step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, mesh.n_diamonds, prob.nnzb, pb)
-    fpe = FLOPS_PER_ELEM.get(args.precision) if args.workload == "shell" else None
+    default_shell = args.workload == "shell" and args.n == 1024 and layout["scatter"] == mad.SCATTER_PATCH
+    fpe = FLOPS_PER_ELEM.get(args.precision) if default_shell else None
     peak = VALU_PEAK_TFLOPS[args.precision]
-    if fpe and layout["scatter"] == mad.SCATTER_PATCH:
+    if fpe:
         achieved = fpe * n_elem / (dom_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                    "frac": achieved / peak, "traffic": None, "kernel_ms": dom_ms,
+                    "frac": achieved / peak, "traffic": TRAFFIC_BYTES.get(args.precision), "kernel_ms": dom_ms,
                     "flops_per_element": fpe}
     else:
         roofline = {"bound": "alu", "kernel": dom_name, "achieved": None, "peak": peak, "unit": "TFLOP/s",

@@ -47,6 +47,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         H.wbf = t.mlp->d_wbf;
         for (int i = 0; i < 6; ++i) H.s_in[i] = t.mlp->s_in[i];
         H.s_out = t.mlp->s_out;
+        H.xh = t.d_xh;
         H.psi = t.d_psi;
         MAD_HIP_TRY(launch_mlp_head(H, s));
     }

@@ -160,12 +160,8 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
         const int64_t e = tile * 16 + col;
         const bool valid = e < L.n;
         float xh[6];
-        {
-            double z[6] = {0, 0, 0, 0, 0, 0};
-            if (valid) features_at(L, e, z);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) xh[i] = float(z[i]) * L.s_in[i];
-        }
+        for (int i = 0; i < 6; ++i) xh[i] = valid ? L.xh[(int64_t)i * L.n + e] : 0.0f;
         // layer 1 at this lane's 16 units (B layout)
         float a1[2][8], s1[2][8];
 #pragma unroll
@@ -312,8 +308,21 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_mlp_features(MlpHeadLaunch L) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < L.n; e += (int64_t)gridDim.x * blockDim.x) {
+        double z[6];
+        features_at(L, e, z);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) L.xh[(int64_t)i * L.n + e] = float(z[i]) * L.s_in[i];
+    }
+}
+
 hipError_t launch_mlp_head(const MlpHeadLaunch& L, hipStream_t s) {
     if (L.n <= 0) return hipSuccess;
+    {
+        const int64_t blocks = std::min<int64_t>((L.n + 255) / 256, 16384);
+        hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)blocks), dim3(256), 0, s, L);
+    }
     const int64_t tiles = (L.n + 15) / 16;
     const int64_t blocks = std::min<int64_t>((tiles + kHeadWaves - 1) / kHeadWaves, 2048);
     hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)blocks), dim3(kHeadWaves * 64), 0, s, L);

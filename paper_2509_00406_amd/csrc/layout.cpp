@@ -139,6 +139,7 @@ static void free_layout(mad_problem* p) {
         t.d_lvert = nullptr;
         t.d_lslot = nullptr;
         t.d_psi = nullptr;
+        t.d_xh = nullptr;
     }
     p->d_lv_ptr = p->d_lv_global = p->d_lv_halo = nullptr;
     p->d_lb_ptr = p->d_lb_gidx = p->d_lb_gidxT = p->d_lb_halo = nullptr;
@@ -192,10 +193,11 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
         if ((rc = upload_layout(p, (void**)&t.d_rest, rs.data(), rs.size() * 8, s)) != MAD_OK) return rc;
         if ((rc = upload_layout(p, (void**)&t.d_elem_ptr, t.elem_ptr.data(), t.elem_ptr.size() * 4, s)) != MAD_OK)
             return rc;
-        if (t.kind == MAD_MLP &&
-            (rc = alloc_layout(p, (void**)&t.d_psi, sizeof(float) * (size_t)kPsi * (size_t)std::max<int64_t>(t.n, 1))) !=
-                MAD_OK)
-            return rc;
+        if (t.kind == MAD_MLP) {
+            const size_t n = (size_t)std::max<int64_t>(t.n, 1);
+            if ((rc = alloc_layout(p, (void**)&t.d_psi, sizeof(float) * (size_t)kPsi * n)) != MAD_OK) return rc;
+            if ((rc = alloc_layout(p, (void**)&t.d_xh, sizeof(float) * 6 * n)) != MAD_OK) return rc;
+        }
     }
     if ((rc = upload_layout(p, (void**)&p->d_comp_patch_ptr, p->patches.comp_patch_ptr.data(),
                             p->patches.comp_patch_ptr.size() * 4, s)) != MAD_OK)

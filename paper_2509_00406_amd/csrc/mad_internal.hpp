@@ -47,6 +47,7 @@ struct Term {
     uint16_t* d_lslot = nullptr;         // SoA [ns(ns+1)/2][n] patch-local block + flags
     const mad_mlp* mlp = nullptr;        // learned density: the network
     float* d_psi = nullptr;              // learned density: SoA [28][n] network outputs, patch order
+    float* d_xh = nullptr;               // learned density: SoA [6][n] scaled features, patch order
 };
 
 // patch-local index structures of the LDS-accumulating assembly (host_patch.cpp)

@@ -29,8 +29,11 @@ struct MlpHeadLaunch {
     const uint16_t* wbf;      // BF16 parameters, packed order
     float s_in[6];
     float s_out;
+    float* xh;                // SoA [6][n] scaled features s_in * z (written by the feature pass)
     float* psi;               // SoA [28][n]
 };
+// feature pass (one lane per triangle, FP64 features rounded to FP32 and scaled), then the
+// network pass reading them
 hipError_t launch_mlp_head(const MlpHeadLaunch& L, hipStream_t s);
 
 // area-weighted unit vertex normals by a fixed-order gather over each vertex's triangles
