@@ -359,6 +359,18 @@ def main():
                                "mfma_bf16_peak": 2500.0,
                                "mfma_frac": 3 * useful / (net_ms * 1e-3) / 1e12 / 2500.0}
         res["vs_other_forms"] = other_forms(torch, mad, mesh, inp, args, stream, x, ms_per_step)
+    if args.workload == "shell":
+        # the matrix-free mode: y = H v with each element's clamped Hessian applied in LDS, no assembly
+        v = torch.randn_like(x)
+        y = torch.empty_like(out[1])
+        hmode = mad.SPD
+
+        def prod():
+            mad.mad_problem_hvp(prob.handle, x, v, hmode, None, None, y, stream)
+        hv_ms, hv_wall = time_steps(torch, prod, max(10, args.steps // 2), 3, stream)
+        hv = max(hv_wall * 1e3, sum(hv_ms)) / len(hv_ms)
+        res["hvp"] = {"ms_per_product": hv, "elements_per_s": n_elem / (hv * 1e-3),
+                      "note": "clamped Hessian-vector product, matrix-free (no assembly)"}
     if args.workload == "batched":
         res["one_launch_per_mesh"] = per_mesh_baseline(torch, mad, inp, prec, stream, ms_per_step, args)
     if prec == mad.F32 and not args.no_fp64_plain:

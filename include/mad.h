@@ -183,6 +183,15 @@ int32_t mad_problem_copy_pattern(const mad_problem *prob, int32_t *rowptr_dev, i
 int32_t mad_problem_eval(mad_problem *prob, const double *x_dev, uint32_t mode, double *energy_dev,
                          void *grad_dev, void *hess_dev, void *stream);
 
+/* Matrix-free Hessian-vector product (Sec. 5.5, Sec. 6.2 matrix-free mode): y = H(x) v with
+ * H = sum_j S_j^T P(hess f_j) S_j (P the eigenvalue clamp when mode has MAD_SPD, else the
+ * identity), each element's Hessian applied to its slice of v in LDS and the products summed, no
+ * Hessian assembled. v_dev: [n_verts * var_dim] FP64; y_dev: [n_verts * var_dim], FP64 for MAD_F64,
+ * FP32 for MAD_F32, overwritten. mode may add MAD_ENERGY (energy_dev) and MAD_GRAD (grad_dev) from
+ * the same pass; MAD_HESS is not allowed. Asynchronous on stream. */
+int32_t mad_problem_hvp(mad_problem *prob, const double *x_dev, const double *v_dev, uint32_t mode,
+                        double *energy_dev, void *grad_dev, void *y_dev, void *stream);
+
 /* Synchronise the stream and report whether any evaluation since the last call produced a
  * non-finite element energy or derivative (*nonfinite = 1) and how many elements took the FP64
  * fallback (*fp64_fallbacks); both counters are reset. */

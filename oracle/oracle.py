@@ -375,3 +375,20 @@ class Problem:
                                  C.c_int(mode), C.c_double(spd_eps), _p(mask), _p(self.rowptr), _p(self.colidx),
                                  C.byref(e), C.byref(ea), _p(grad), _p(gscale), _p(hess), _p(hscale)), "eval")
         return Result(e.value, ea.value, grad, gscale, hess, hscale)
+
+    def hvp(self, x: np.ndarray, v: np.ndarray, spd: bool = False, spd_eps: float = 0.0):
+        """Hessian-vector product by its definition: the assembled Hessian (clamped per element when
+        spd) times v, block row by block row. Returns (y, yscale) with yscale = |H| scales times |v|
+        (the per-entry tolerance scale of a product: sum over the row's blocks of the oracle's
+        per-entry Hessian scale times |v|)."""
+        r = self.eval(x, ENERGY | HESS | (SPD if spd else 0), spd_eps=spd_eps)
+        d = self.d
+        v = np.asarray(v, dtype=np.float64).reshape(self.nv, d)
+        y = np.zeros((self.nv, d))
+        ys = np.zeros((self.nv, d))
+        for i in range(self.nv):
+            for b in range(self.rowptr[i], self.rowptr[i + 1]):
+                j = self.colidx[b]
+                y[i] += r.hess[b] @ v[j]
+                ys[i] += r.hscale[b] @ np.abs(v[j])
+        return y.ravel(), ys.ravel()

@@ -312,6 +312,18 @@ int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double*
     return eval_problem(p, x, mode, energy, grad, hess, (hipStream_t)stream);
 }
 
+int32_t mad_problem_hvp(mad_problem* p, const double* x, const double* v, uint32_t mode, double* energy, void* grad,
+                        void* y, void* stream) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (!p->finalized) return fail(MAD_E_STATE, "hvp before finalize");
+    if (!x || !v || !y) return fail(MAD_E_INVALID_ARG, "x, v and y must not be NULL");
+    if (mode & ~(uint32_t)(MAD_ENERGY | MAD_GRAD | MAD_SPD))
+        return fail(MAD_E_INVALID_ARG, "hvp mode takes MAD_ENERGY, MAD_GRAD and MAD_SPD only");
+    if ((mode & MAD_ENERGY) && !energy) return fail(MAD_E_INVALID_ARG, "energy output is NULL");
+    if ((mode & MAD_GRAD) && !grad) return fail(MAD_E_INVALID_ARG, "gradient output is NULL");
+    return eval_problem(p, x, mode, energy, grad, nullptr, (hipStream_t)stream, v, y);
+}
+
 int32_t mad_problem_set_profiling(mad_problem* p, int32_t enable) {
     if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
     p->profiling = enable != 0;

@@ -80,6 +80,73 @@ __device__ __forceinline__ T hfull(const ElemOut<Term, T>& o, int i, int j, T te
     return acc;
 }
 
+// Matrix-free product of one element's Hessian with the stencil vector v (Sec. 6.2, matrix-free
+// mode): y = H_x v from the reduced form, without expanding H_x. MODE 2: H_x = (D (x) I)^T H_r (D (x) I),
+// so u = (D (x) I) v (relative coordinates), w = H_r u, y = (D (x) I)^T w. MODE 3: H_x = (Q (x) I) Hc
+// (Q (x) I)^T + te T, so u = (Q (x) I)^T v, w = Hc u, y = (Q (x) I) w + te T v (T the translation projector).
+template <class Term, int MODE, typename T>
+__device__ __forceinline__ void hvp_apply(const ElemOut<Term, T>& o, T te, const T (&v)[Term::NS * Term::D],
+                                          T (&y)[Term::NS * Term::D]) {
+    constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
+    T u[KR], w[KR];
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int s = 1; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < D; ++c) u[(s - 1) * D + c] = v[s * D + c] - v[c];
+    } else {
+#pragma unroll
+        for (int a = 0; a < NS - 1; ++a)
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T acc = T(0);
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const double q = helmert(s, a);
+                    if (q != 0.0) acc += T(q) * v[s * D + c];
+                }
+                u[a * D + c] = acc;
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < KR; ++i) {
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < KR; ++j) acc += o.hr[Packed<KR>::at(i, j)] * u[j];
+        w[i] = acc;
+    }
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            T y0 = T(0);
+#pragma unroll
+            for (int s = 1; s < NS; ++s) {
+                y[s * D + c] = w[(s - 1) * D + c];
+                y0 -= w[(s - 1) * D + c];
+            }
+            y[c] = y0;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            T vs = T(0);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) vs += v[s * D + c];
+            const T tv = te * vs * T(1.0 / NS);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                T acc = tv;
+#pragma unroll
+                for (int a = 0; a < NS - 1; ++a) {
+                    const double q = helmert(s, a);
+                    if (q != 0.0) acc += T(q) * w[a * D + c];
+                }
+                y[s * D + c] = acc;
+            }
+        }
+    }
+}
+
 // hardware reciprocal / square root / reciprocal square root: approximate (about 1 ulp) in FP32,
 // IEEE in FP64
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }

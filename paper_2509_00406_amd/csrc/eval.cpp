@@ -10,7 +10,8 @@
 namespace mad {
 
 int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
-                 hipStream_t s) {
+                 hipStream_t s, const double* v, void* y) {
+    const bool hvp = v != nullptr;
     const mad_mesh& m = *p->mesh;
     const int d = p->d;
     const int eb = p->prec == MAD_F32 ? 4 : 8;
@@ -30,6 +31,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
     if (p->scatter == MAD_SCATTER_ATOMIC) {
         if (mode & MAD_GRAD) MAD_HIP_TRY(launch_fill(grad, m.nv * d, eb, s));
         if (mode & MAD_HESS) MAD_HIP_TRY(launch_fill(hess, p->nnzb * d * d, eb, s));
+        if (hvp) MAD_HIP_TRY(launch_fill(y, m.nv * d, eb, s));
     }
     if (fallback_pass) MAD_HIP_TRY(launch_fill(p->d_fb_count, 1, 4, s));
     if (p->scatter == MAD_SCATTER_PATCH && p->persistent) MAD_HIP_TRY(launch_fill(p->d_work_counter, 1, 4, s));
@@ -52,7 +54,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         MAD_HIP_TRY(launch_mlp_head(H, s));
     }
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2], s));
-    const int kmode = (mode & MAD_HESS) ? ((mode & MAD_SPD) ? 3 : 2) : ((mode & MAD_GRAD) ? 1 : 0);
+    const int kmode = (hvp || (mode & MAD_HESS)) ? ((mode & MAD_SPD) ? 3 : 2) : ((mode & MAD_GRAD) ? 1 : 0);
     const int np = p->patches.n;
     int n_partial_terms = (int)p->terms.size();
     if (p->scatter == MAD_SCATTER_PATCH) {
@@ -63,7 +65,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.var_dim = d;
         L.n_terms = (int)p->terms.size();
         L.n_patch = np;
-        L.lds_bytes = patch_lds_bytes(d, p->prec, kmode, p->max_lv, p->max_lb);
+        L.lds_bytes = patch_lds_bytes(d, p->prec, kmode, p->max_lv, p->max_lb, hvp);
         L.x = x;
         L.grad = grad;
         L.hess = hess;
@@ -90,6 +92,26 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.n_cu = p->n_cu;
         L.normals = p->d_normals;
         L.shell = p->shell ? 1 : 0;
+        L.hvp = hvp ? 1 : 0;
+        L.v = v;
+        L.y = y;
+        L.halo_y = p->d_halo_y;
+        {
+            // relative element cost by kind (reduced dual size, eigen-problem size, network outputs)
+            auto cost = [](int kind) {
+                switch (kind) {
+                case MAD_BENDING: return 6;
+                case MAD_MLP: return 4;
+                case MAD_STVK: case MAD_SHELL_TRI: return 3;
+                case MAD_SYMDIR: return 2;
+                default: return 1;
+                }
+            };
+            const int nt = (int)p->terms.size();
+            for (int k = 0; k < nt; ++k) L.term_order[k] = k;
+            std::stable_sort(L.term_order, L.term_order + nt,
+                             [&](int a, int b) { return cost(p->terms[a].kind) > cost(p->terms[b].kind); });
+        }
         for (size_t ti = 0; ti < p->terms.size(); ++ti) {
             const Term& t = p->terms[ti];
             PatchTermArgs& A = L.terms[ti];
@@ -127,6 +149,13 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         G.n_orphan_vert = p->n_orphan_vert;
         G.n_orphan_block = p->n_orphan_block;
         MAD_HIP_TRY(launch_gather(G, s));
+        if (hvp) {   // the product's shared entries, through the same gather lists
+            G.want_grad = 1;
+            G.want_hess = 0;
+            G.grad = y;
+            G.halo_g = p->d_halo_y;
+            MAD_HIP_TRY(launch_gather(G, s));
+        }
         if (fallback_pass) {
             FallbackLaunch F{};
             F.var_dim = d;
@@ -142,6 +171,9 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
             F.flags = p->d_flags;
             F.eps = p->opt.spd_eps;
             F.normals = p->d_normals;
+            F.hvp = hvp ? 1 : 0;
+            F.v = v;
+            F.y = y;
             for (size_t ti = 0; ti < p->terms.size(); ++ti) {
                 const Term& t = p->terms[ti];
                 F.terms[ti].kind = t.kind;
@@ -181,6 +213,9 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.qmin = p->opt.degenerate_q;
         L.normals = p->d_normals;
         L.psi = t.d_psi;
+        L.hvp = hvp ? 1 : 0;
+        L.v = v;
+        L.y = y;
         MAD_HIP_TRY(launch_eval(L, s));
         if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[3 + ti], s));
     }

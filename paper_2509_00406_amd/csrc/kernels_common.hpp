@@ -125,4 +125,14 @@ __device__ __forceinline__ void block_reduce_store(double v, double* red, double
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// sum of red[0, kBlock) in a fixed tree order; red is already filled and visible to every lane
+__device__ __forceinline__ void block_sum_store(double* red, double* out) {
+#pragma unroll
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
 }  // namespace mad

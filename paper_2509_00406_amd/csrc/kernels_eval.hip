@@ -22,8 +22,23 @@ __device__ __forceinline__ void scatter_global(const ElemOut<Term, T>& o, const 
             for (int c = 0; c < D; ++c) atomic_add(g + (int64_t)vs[s] * D + c, o.g[s * D + c]);
     }
     if constexpr (MODE >= 2) {
-        T* h = static_cast<T*>(L.hess);
         const T te = T(L.eps > 0.0 ? L.eps : 0.0);
+        if (L.hvp) {
+            // matrix-free: y += H_j v_j
+            T vl[NS * D], yl[NS * D];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int c = 0; c < D; ++c) vl[s * D + c] = T(L.v[(int64_t)vs[s] * D + c]);
+            hvp_apply<Term, MODE, T>(o, te, vl, yl);
+            T* y = static_cast<T*>(L.y);
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+#pragma unroll
+                for (int c = 0; c < D; ++c) atomic_add(y + (int64_t)vs[s] * D + c, yl[s * D + c]);
+            return;
+        }
+        T* h = static_cast<T*>(L.hess);
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll

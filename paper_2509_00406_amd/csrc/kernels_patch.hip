@@ -26,14 +26,15 @@ constexpr uint32_t kFbTermShift = 29;
 constexpr uint32_t kFbGradDone = 1u << 28;
 constexpr uint32_t kFbElemMask = kFbGradDone - 1u;
 
+// Elements e_first, e_first + e_step, ... below e_end of one term of patch p.
 template <class Term, typename T, int MODE>
-__device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTermArgs& A, int term, int p,
-                                           const double* sx, T* sg, T* sh, double& esum, bool& bad) {
+__device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTermArgs& A, int term, int p, int e_first,
+                                           int e_step, int e_end, const double* sx, T* sg, T* sh, T* sy, double& esum,
+                                           bool& bad) {
     constexpr int NS = Term::NS, D = Term::D, NF = NS * D, DD = D * D;
-    const int beg = A.elem_ptr[p], end = A.elem_ptr[p + 1];
     const int lv0 = L.lv_ptr[p];
     const T te = T(L.eps > 0.0 ? L.eps : 0.0);
-    for (int e = beg + (int)threadIdx.x; e < end; e += kBlock) {
+    for (int e = e_first; e < e_end; e += e_step) {
         int lv[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) lv[s] = A.lvert[(int64_t)s * A.n + e];
@@ -116,6 +117,20 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
             }
         }
         if constexpr (MODE >= 2) {
+            if (L.hvp) {
+                // matrix-free: y += H_j v_j (sh holds the patch's v, sy its product)
+                T vl[NF], yl[NF];
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int c = 0; c < D; ++c) vl[s * D + c] = sh[lv[s] * D + c];
+                hvp_apply<Term, MODE, T>(o, te, vl, yl);
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+#pragma unroll
+                    for (int c = 0; c < D; ++c) lds_add(sy + lv[s] * D + c, yl[s * D + c]);
+                continue;
+            }
             int k = 0;
 #pragma unroll
             for (int s = 0; s < NS; ++s)
@@ -149,7 +164,8 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
 }
 
 template <typename T, int MODE, int D, bool SH>
-__device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsigned char* smem, double* red) {
+__device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsigned char* smem, double* red,
+                                               int* s_next) {
     constexpr int DD = D * D;
     const int lv0 = L.lv_ptr[p], nlv = L.lv_ptr[p + 1] - lv0;
     const int lb0 = L.lb_ptr[p], nlb = L.lb_ptr[p + 1] - lb0;
@@ -157,6 +173,10 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
     T* sg = reinterpret_cast<T*>(smem + align16((size_t)nlv * D * sizeof(double)));
     T* sh = reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(sg) +
                                  (MODE >= 1 ? align16((size_t)nlv * D * sizeof(T)) : 0));
+    // matrix-free mode: the block area holds the patch's v, then its product y
+    T* sy = (MODE >= 2 && L.hvp) ? sh + align16((size_t)nlv * D * sizeof(T)) / sizeof(T) : nullptr;
+    if (threadIdx.x == 0) *s_next = 0;
+    red[threadIdx.x] = 0.0;   // per-unit energies
     bool bad_x = false;
     for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
         const int v = L.lv_global[lv0 + i / D];
@@ -164,35 +184,75 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         sx[i] = xv;
         bad_x = bad_x || !finite(xv);
         if constexpr (MODE >= 1) sg[i] = T(0);
+        if constexpr (MODE >= 2) {
+            if (L.hvp) {
+                sh[i] = T(L.v[(int64_t)v * D + (i % D)]);
+                sy[i] = T(0);
+            }
+        }
     }
     if (bad_x) atomicOr(L.flags, 1);
     if constexpr (MODE >= 2)
-        for (int i = threadIdx.x; i < nlb * DD; i += kBlock) sh[i] = T(0);
+        if (!L.hvp)
+            for (int i = threadIdx.x; i < nlb * DD; i += kBlock) sh[i] = T(0);
     __syncthreads();
 
-    double esum = 0.0;
     bool bad = false;
-    for (int t = 0; t < L.n_terms; ++t) {
+    // Work units are chunks of 64 consecutive elements of one term; each wave takes the next unit from
+    // an LDS counter, the costliest terms' units first (greedy list scheduling: a wave that finishes
+    // early takes more units, so the four waves of the patch end close together). Which wave runs a
+    // unit varies from run to run, so each unit's energy is summed over its lanes in a fixed order
+    // into a slot of its own, and the slots are summed in a fixed order at the end.
+    static_assert(kMaxPatchUnits <= kBlock, "one energy slot per unit");
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int u = 0;
+        if (lane == 0) u = atomicAdd(s_next, 1);
+        u = __shfl(u, 0);
+        const int unit = u;
+        double esum = 0.0;
+        int t = -1, first = 0, last = 0;
+        for (int k = 0; k < L.n_terms; ++k) {
+            const int tt = L.term_order[k];
+            const int b = L.terms[tt].elem_ptr[p], n = L.terms[tt].elem_ptr[p + 1] - b;
+            const int nc = (n + 63) >> 6;
+            if (u < nc) {
+                t = tt;
+                first = b + (u << 6);
+                last = min(b + n, first + 64);
+                break;
+            }
+            u -= nc;
+        }
+        if (t < 0) break;
         const PatchTermArgs& A = L.terms[t];
+        const int e0 = first + lane;
         if constexpr (D == 3) {
             switch (A.kind) {
-            case K_STVK: patch_term<TermStVK, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
-            case K_BENDING: patch_term<TermBending, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
-            case K_TRI_AREA: patch_term<TermTriArea, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
-            case K_EDGE_SQLEN: patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad); break;
+            case K_STVK: patch_term<TermStVK, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad); break;
+            case K_BENDING: patch_term<TermBending, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad); break;
+            case K_TRI_AREA: patch_term<TermTriArea, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad); break;
+            case K_EDGE_SQLEN:
+                patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
+                break;
             case K_SHELL_TRI:
-                if constexpr (SH) patch_term<TermShellTri, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad);
+                if constexpr (SH) patch_term<TermShellTri, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
                 break;
             case K_MLP:
-                if constexpr (SH) patch_term<TermMLP, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad);
+                if constexpr (SH) patch_term<TermMLP, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
                 break;
             default: break;
             }
         } else if constexpr (D == 2) {
-            if (A.kind == K_SYMDIR) patch_term<TermSymDir, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad);
+            if (A.kind == K_SYMDIR)
+                patch_term<TermSymDir, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
         } else {
-            if (A.kind == K_DIRICHLET) patch_term<TermDirichlet, T, MODE>(L, A, t, p, sx, sg, sh, esum, bad);
+            if (A.kind == K_DIRICHLET)
+                patch_term<TermDirichlet, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) esum += __shfl_down(esum, o);
+        if (lane == 0 && unit < kMaxPatchUnits) red[unit] = esum;
     }
     if (bad) atomicOr(L.flags, 1);
     __syncthreads();
@@ -212,6 +272,22 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         }
     }
     if constexpr (MODE >= 2) {
+        if (L.hvp) {
+            T* Y = static_cast<T*>(L.y);
+            T* HY = static_cast<T*>(L.halo_y);
+            for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
+                const int k = lv0 + i / D, c = i % D;
+                const int32_t h = L.lv_halo[k];
+                if (h < 0) Y[(int64_t)L.lv_global[k] * D + c] = sy[i];
+                else HY[(int64_t)h * D + c] = sy[i];
+            }
+        }
+    }
+    if constexpr (MODE >= 2) {
+        if (L.hvp) {
+            block_sum_store(red, L.partial + p);
+            return;
+        }
         T* H = static_cast<T*>(L.hess);
         T* HH = static_cast<T*>(L.halo_h);
         for (int i = threadIdx.x; i < nlb * DD; i += kBlock) {
@@ -229,7 +305,7 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
             }
         }
     }
-    block_reduce_store(esum, red, L.partial + p);
+    block_sum_store(red, L.partial + p);
 }
 
 // One patch per workgroup, or (persistent) a grid sized to the device whose workgroups take
@@ -238,9 +314,9 @@ template <typename T, int MODE, int D, bool SH>
 __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kBlock];
-    __shared__ int next;
+    __shared__ int next, unit_next;
     if (!L.persistent) {
-        eval_patch_one<T, MODE, D, SH>(L, blockIdx.x, smem, red);
+        eval_patch_one<T, MODE, D, SH>(L, blockIdx.x, smem, red, &unit_next);
         return;
     }
     for (;;) {
@@ -249,7 +325,7 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
         const int k = next;
         __syncthreads();   // every lane has read `next` before it is overwritten
         if (k >= L.n_patch) break;
-        eval_patch_one<T, MODE, D, SH>(L, L.work_order[k], smem, red);
+        eval_patch_one<T, MODE, D, SH>(L, L.work_order[k], smem, red, &unit_next);
         __syncthreads();   // the flush has read LDS before the next patch clears it
     }
 }
@@ -354,8 +430,23 @@ __device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const Fal
 #pragma unroll
             for (int c = 0; c < D; ++c) atomic_add(G + (int64_t)vs[s] * D + c, float(o.g[s * D + c]));
     }
-    float* H = static_cast<float*>(F.hess);
     const double te = F.eps > 0.0 ? F.eps : 0.0;
+    if (F.hvp) {
+        // matrix-free: add H_j v_j to y
+        double vl[NF], yl[NF];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < D; ++c) vl[s * D + c] = F.v[(int64_t)vs[s] * D + c];
+        hvp_apply<Term, 3, double>(o, te, vl, yl);
+        float* Y = static_cast<float*>(F.y);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int c = 0; c < D; ++c) atomic_add(Y + (int64_t)vs[s] * D + c, float(yl[s * D + c]));
+        return;
+    }
+    float* H = static_cast<float*>(F.hess);
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
@@ -401,19 +492,19 @@ __global__ __launch_bounds__(kBlock) void k_fallback(FallbackLaunch F) {
 
 // ---- launchers ----------------------------------------------------------------------------------
 template <typename T, int D>
-static size_t lds_for(int mode, int32_t max_lv, int32_t max_lb) {
+static size_t lds_for(int mode, int32_t max_lv, int32_t max_lb, bool hvp) {
     size_t b = align16((size_t)max_lv * D * sizeof(double));
     if (mode >= 1) b += align16((size_t)max_lv * D * sizeof(T));
-    if (mode >= 2) b += (size_t)max_lb * D * D * sizeof(T);
+    if (mode >= 2) b += hvp ? 2 * align16((size_t)max_lv * D * sizeof(T)) : (size_t)max_lb * D * D * sizeof(T);
     return b;
 }
 
-size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t max_lb) {
+size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t max_lb, bool hvp) {
     const bool f32 = prec == MAD_F32;
     switch (var_dim) {
-    case 1: return f32 ? lds_for<float, 1>(mode, max_lv, max_lb) : lds_for<double, 1>(mode, max_lv, max_lb);
-    case 2: return f32 ? lds_for<float, 2>(mode, max_lv, max_lb) : lds_for<double, 2>(mode, max_lv, max_lb);
-    default: return f32 ? lds_for<float, 3>(mode, max_lv, max_lb) : lds_for<double, 3>(mode, max_lv, max_lb);
+    case 1: return f32 ? lds_for<float, 1>(mode, max_lv, max_lb, hvp) : lds_for<double, 1>(mode, max_lv, max_lb, hvp);
+    case 2: return f32 ? lds_for<float, 2>(mode, max_lv, max_lb, hvp) : lds_for<double, 2>(mode, max_lv, max_lb, hvp);
+    default: return f32 ? lds_for<float, 3>(mode, max_lv, max_lb, hvp) : lds_for<double, 3>(mode, max_lv, max_lb, hvp);
     }
 }
 

@@ -146,7 +146,7 @@ static void free_layout(mad_problem* p) {
     p->d_gv_ptr = p->d_gv_src = p->d_gv_vert = nullptr;
     p->d_gb_ptr = p->d_gb_src = p->d_gb_gidx = p->d_gb_gidxT = nullptr;
     p->d_orphan_vert = p->d_orphan_block = nullptr;
-    p->d_halo_g = p->d_halo_h = nullptr;
+    p->d_halo_g = p->d_halo_h = p->d_halo_y = nullptr;
     p->d_fb_list = nullptr;
     p->d_fb_count = nullptr;
     p->d_work_order = p->d_work_counter = nullptr;
@@ -166,12 +166,19 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
     build_patches(m, target, p->patches);
     order_terms(p);
     if (scatter == MAD_SCATTER_PATCH) {
-        // shrink the patch target until the largest patch's LDS working set fits the budget
+        // shrink the patch target until the largest patch's LDS working set fits the budget and
+        // every patch has at most kMaxPatchUnits work units
         for (;;) {
             int32_t mv, mb;
             patch_extent(p, &mv, &mb);
             p->lds_bytes = patch_lds_bytes(p->d, p->prec, 3, mv, mb);
-            if (p->lds_bytes <= kLdsBudget) break;
+            int32_t mu = 0;
+            for (int32_t q = 0; q < p->patches.n; ++q) {
+                int32_t u = 0;
+                for (const auto& t : p->terms) u += (t.elem_ptr[q + 1] - t.elem_ptr[q] + 63) / 64;
+                mu = std::max(mu, u);
+            }
+            if (p->lds_bytes <= kLdsBudget && mu <= kMaxPatchUnits) break;
             if (target <= 1) return fail(MAD_E_UNSUPPORTED, "a single element exceeds the LDS budget");
             target = std::max(1, (int)(target * 0.75));
             build_patches(m, target, p->patches);
@@ -262,6 +269,7 @@ int build_scatter(mad_problem* p, hipStream_t s) {
     const size_t eb = p->prec == MAD_F32 ? 4 : 8;
     if ((rc = alloc_layout(p, &p->d_halo_g, L.gv_src.size() * p->d * eb)) != MAD_OK) return rc;
     if ((rc = alloc_layout(p, &p->d_halo_h, L.gb_src.size() * p->d * p->d * eb)) != MAD_OK) return rc;
+    if ((rc = alloc_layout(p, &p->d_halo_y, L.gv_src.size() * p->d * eb)) != MAD_OK) return rc;
     for (size_t ti = 0; ti < p->terms.size(); ++ti) {
         auto& t = p->terms[ti];
         if ((rc = upload_layout(p, (void**)&t.d_lvert, L.lvert[ti].data(), L.lvert[ti].size() * 2, s)) != MAD_OK)

@@ -122,6 +122,7 @@ struct mad_problem {
     int32_t n_gv = 0, n_gb = 0, n_orphan_vert = 0, n_orphan_block = 0;
     void* d_halo_g = nullptr;             // [halo vertex slots][D] partial gradients of shared vertices
     void* d_halo_h = nullptr;             // [halo block slots][D*D] partial blocks of shared blocks
+    void* d_halo_y = nullptr;             // [halo vertex slots][D] partial Hessian-vector products
     uint32_t* d_fb_list = nullptr;
     int32_t* d_fb_count = nullptr;
     int32_t fb_cap = 0;
@@ -158,12 +159,15 @@ void build_patches(const mad_mesh& m, int target_faces, Patches& p);
 // layout.cpp: (re)build the element order and the scatter structures of a problem
 int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s);
 int build_scatter(mad_problem* p, hipStream_t s);
+// one evaluation; with v != NULL the matrix-free product y = H v replaces the Hessian (hess NULL)
 int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
-                 hipStream_t s);
+                 hipStream_t s, const double* v = nullptr, void* y = nullptr);
 constexpr size_t kLdsBudget = 60 * 1024;  // dynamic LDS per workgroup: two workgroups per CU
+// work units (64 elements of one term) per patch: the patch kernel keeps one energy slot per unit
+constexpr int kMaxPatchUnits = 256;
 int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& colidx,
                       PatchLocal& L);
-size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t max_lb);
+size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t max_lb, bool hvp = false);
 
 // device launchers (kernels_*.hip); all asynchronous on `stream`
 struct EvalLaunch {
@@ -188,6 +192,9 @@ struct EvalLaunch {
     double qmin;
     const double* normals;  // [nv][3] unit vertex normals (shell-feature terms)
     const float* psi;       // SoA [28][n] network outputs (learned density)
+    int hvp;                // matrix-free mode: atomically add H_j v_j to y
+    const double* v;
+    void* y;
 };
 hipError_t launch_eval(const EvalLaunch& L, hipStream_t s);
 
@@ -226,6 +233,11 @@ struct PatchLaunch {
     double eps, qmin;
     const double* normals;  // [nv][3] unit vertex normals (shell-feature terms)
     int shell;              // the problem has shell-feature terms (selects the kernel variant)
+    int term_order[8];      // terms by decreasing element cost (work units of the costliest first)
+    int hvp;                // matrix-free mode: y = H v instead of assembling H (modes 2, 3)
+    const double* v;        // [nv][D]
+    void* y;                // [nv][D], T
+    void* halo_y;           // [halo vertex slots][D] partial products of shared vertices
     int persistent;
     const int32_t* work_order;
     int32_t* work_counter;
@@ -270,6 +282,9 @@ struct FallbackLaunch {
     int32_t* flags;
     double eps;
     const double* normals;
+    int hvp;                // add H_j v_j to y instead of H_j to the blocks
+    const double* v;
+    void* y;
     FallbackTerm terms[8];
 };
 hipError_t launch_fallback(const FallbackLaunch& F, hipStream_t s);

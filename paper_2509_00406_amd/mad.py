@@ -61,6 +61,8 @@ _SIGS = {
     "mad_problem_eval": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
                          C.c_int32),
     "mad_problem_status": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_void_p], C.c_int32),
+    "mad_problem_hvp": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                         C.c_void_p], C.c_int32),
     "mad_problem_set_profiling": ([C.c_void_p, C.c_int32], C.c_int32),
     "mad_problem_profile": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
                             C.c_int32),
@@ -205,6 +207,11 @@ def mad_problem_copy_pattern(prob, rowptr, colidx, stream=None):
 def mad_problem_eval(prob, x, mode: int, energy=None, grad=None, hess=None, stream=None):
     _check(lib().mad_problem_eval(prob, _ptr(x), mode, _ptr(energy), _ptr(grad), _ptr(hess), _stream(stream)),
            "mad_problem_eval")
+
+
+def mad_problem_hvp(prob, x, v, mode: int, energy=None, grad=None, y=None, stream=None):
+    _check(lib().mad_problem_hvp(prob, _ptr(x), _ptr(v), mode, _ptr(energy), _ptr(grad), _ptr(y), _stream(stream)),
+           "mad_problem_hvp")
 
 
 def mad_problem_status(prob, stream=None) -> tuple[bool, int]:
@@ -410,6 +417,15 @@ class Problem:
 
     def status(self, stream=None):
         return mad_problem_status(self.handle, stream)
+
+    def hvp(self, x, v, mode: int = 0, out=None, stream=None):
+        """y = H(x) v without assembling H (mode: MAD_SPD for the clamped Hessian; ENERGY/GRAD extra)."""
+        import torch
+        energy, grad, _ = out if out is not None else self.outputs(x.device)
+        y = torch.empty_like(grad)
+        mad_problem_hvp(self.handle, x, v, mode, energy if mode & ENERGY else None, grad if mode & GRAD else None, y,
+                        stream)
+        return y, energy, grad
 
     def layout(self) -> dict:
         return mad_problem_layout(self.handle)

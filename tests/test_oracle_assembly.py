@@ -238,3 +238,52 @@ def test_neumaier_matches_exact_sum():
         exact = math.fsum(v)
         assert abs(O.neumaier_sum(v) - exact) <= 2 ** -52 * abs(exact) + 1e-300
     assert O.neumaier_sum(np.array([1e100, 1.0, -1e100])) == 1.0
+
+
+# ---------------------------------------------------------------- Hessian-vector products
+def test_hvp_is_directional_derivative_of_gradient():
+    # H(x) v = d/de g(x + e v) at e = 0: central differences of the oracle's own gradient
+    from paper_2509_00406_amd import meshgen
+    inp = meshgen.shell_cylinder(n=7, seed=17)
+    P = O.Problem(inp.tris, inp.rest, inp.n_verts, 3)
+    P.add_term(O.STVK, (1.0, 0.7))
+    P.add_term(O.BENDING, (0.9, 1.0))
+    x = inp.x.ravel().copy()
+    v = np.random.default_rng(4).normal(size=x.size)
+    y, ys = P.hvp(x, v)
+
+    def g(t):
+        return P.eval(x + t * v, O.GRAD).grad
+    h = 1e-4
+    fd = (4 * (g(h / 2) - g(-h / 2)) / h - (g(h) - g(-h)) / (2 * h)) / 3
+    assert np.max(np.abs(y - fd)) < 1e-6 * np.max(np.abs(y))
+    # linear in v, and symmetric: u.(H v) = v.(H u)
+    u = np.random.default_rng(5).normal(size=x.size)
+    yu, _ = P.hvp(x, u)
+    yuv, _ = P.hvp(x, 2.0 * v - 3.0 * u)
+    assert np.allclose(yuv, 2.0 * y - 3.0 * yu, rtol=1e-12, atol=1e-12 * np.max(np.abs(y)))
+    assert abs(u @ y - v @ yu) < 1e-11 * np.sqrt((u @ u) * (v @ v)) * np.max(np.abs(ys))
+    assert np.all(ys >= np.abs(y) * (1 - 1e-12))
+
+
+def test_hvp_spd_is_psd_and_dense_product():
+    # with the clamp, v.(H v) >= 0 for every v; and the product equals the dense assembled matrix's
+    tris, pos = meshgen.tiny_meshes()["grid3"]
+    x = pos + np.random.default_rng(6).normal(scale=0.2, size=pos.shape)
+    P = O.Problem(tris, pos, pos.shape[0], 3)
+    P.add_term(O.STVK, (1.0, 1.0))
+    P.add_term(O.BENDING, (1.0, 1.0))
+    P.build_pattern()
+    r = P.eval(x, O.HESS | O.SPD)
+    n = pos.shape[0]
+    Hd = np.zeros((3 * n, 3 * n))
+    for i in range(n):
+        for b in range(P.rowptr[i], P.rowptr[i + 1]):
+            j = P.colidx[b]
+            Hd[3 * i:3 * i + 3, 3 * j:3 * j + 3] = r.hess[b]
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        v = rng.normal(size=3 * n)
+        y, _ = P.hvp(x, v, spd=True)
+        assert np.allclose(y, Hd @ v, rtol=0, atol=1e-12 * np.max(np.abs(Hd)) * np.max(np.abs(v)) * 9)
+        assert v @ y >= -1e-10 * np.max(np.abs(Hd)) * (v @ v)
