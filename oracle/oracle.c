@@ -169,6 +169,29 @@ static hd e_edge_sqlen(int k, const double *xloc) {
     return hd3_dot(d, d);
 }
 
+/* Sec. 7.1 mass-spring cloth, spring of edge (x0, x1) with rest length l = rest[0]:
+ * w * (k/2) l^2 (|x0 - x1|^2 / l^2 - 1)^2, params {k, w} (w: the potential's weight h^2). */
+static hd e_spring(int k, const double *xloc, const double *rest, const double *prm) {
+    double l2 = rest[0] * rest[0];
+    hd3 d = hd3_sub(lift3(k, xloc, 0), lift3(k, xloc, 1));
+    hd q = hd_addc(hd_scale(hd3_dot(d, d), 1.0 / l2), -1.0);
+    return hd_scale(hd_sq(q), prm[1] * 0.5 * prm[0] * l2);
+}
+
+/* Sec. 7.1 implicit-Euler inertia plus gravity at one vertex: (m/2) |x - xhat|^2 - w m g.x,
+ * rest = {m, xhat (3)} (xhat = x^n + h v^n), params {w, g (3)}. Not translation invariant. */
+static hd e_inertia(int k, const double *xloc, const double *rest, const double *prm) {
+    double m = rest[0];
+    hd3 x = lift3(k, xloc, 0);
+    hd acc = hd_const(k, 0.0);
+    for (int c = 0; c < 3; ++c) {
+        hd dc = hd_addc(x.c[c], -rest[1 + c]);
+        acc = hd_add(acc, hd_scale(hd_sq(dc), 0.5 * m));
+        acc = hd_add(acc, hd_scale(x.c[c], -prm[0] * m * prm[1 + c]));
+    }
+    return acc;
+}
+
 /* Sec. 7.6: area 0.5 |(x1 - x0) x (x2 - x0)| (Op::FV, k = 9) */
 static hd e_tri_area(int k, const double *xloc) {
     hd3 x0 = lift3(k, xloc, 0), x1 = lift3(k, xloc, 1), x2 = lift3(k, xloc, 2);
@@ -377,7 +400,8 @@ static int e_mlp(int k, const double *xloc, const double *rest, const double *au
 
 static int kind_stencil(int kind) {
     switch (kind) {
-    case OR_EDGE_SQLEN: return 2;
+    case OR_INERTIA: return 1;
+    case OR_EDGE_SQLEN: case OR_SPRING: return 2;
     case OR_TRI_AREA: case OR_DIRICHLET: case OR_STVK: case OR_SYMDIR: case OR_MLP: case OR_SHELL_TRI: return 3;
     case OR_BENDING: return 4;
     default: return -1;
@@ -388,7 +412,8 @@ static int kind_vardim(int kind) {
     switch (kind) {
     case OR_DIRICHLET: return 1;
     case OR_SYMDIR: return 2;
-    case OR_EDGE_SQLEN: case OR_TRI_AREA: case OR_STVK: case OR_BENDING: case OR_MLP: case OR_SHELL_TRI: return 3;
+    case OR_EDGE_SQLEN: case OR_TRI_AREA: case OR_STVK: case OR_BENDING: case OR_MLP: case OR_SHELL_TRI:
+    case OR_SPRING: case OR_INERTIA: return 3;
     default: return -1;
     }
 }
@@ -405,6 +430,8 @@ static int eval_elem(int kind, int k, const double *prm, const double *rest, con
     case OR_STVK: *out = e_stvk(k, xloc, rest, prm); return 0;
     case OR_BENDING: *out = e_bending(k, xloc, rest, prm); return 0;
     case OR_SYMDIR: *out = e_symdir(k, xloc, rest); return 0;
+    case OR_SPRING: *out = e_spring(k, xloc, rest, prm); return 0;
+    case OR_INERTIA: *out = e_inertia(k, xloc, rest, prm); return 0;
     default: return -1;
     }
 }
@@ -807,6 +834,8 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
         int shell = kind[t] == OR_SHELL_TRI || kind[t] == OR_MLP;
         int rest_stride = (kind[t] == OR_BENDING) ? 2
                           : ((kind[t] == OR_DIRICHLET || kind[t] == OR_STVK || kind[t] == OR_SYMDIR) ? 5 : (shell ? 8 : 0));
+        if (kind[t] == OR_SPRING) rest_stride = 1;
+        if (kind[t] == OR_INERTIA) rest_stride = 4;
         double *nrm = NULL;
         if (shell) { /* passive unit vertex normals of the current positions, over this term's triangles */
             nrm = malloc(sizeof(double) * (size_t)(3 * nv));

@@ -33,7 +33,9 @@ enum {
     OR_BENDING = 5,      /* Sec. 7.7 dihedral bending over an edge diamond, VarDim 3, k = 12 */
     OR_SYMDIR = 6,       /* Sec. 7.2 symmetric Dirichlet, VarDim 2, k = 6 */
     OR_MLP = 7,          /* learned per-triangle density A psi(z), VarDim 3, k = 9 */
-    OR_SHELL_TRI = 8     /* analytic per-triangle shell density A W(z), VarDim 3, k = 9 */
+    OR_SHELL_TRI = 8,    /* analytic per-triangle shell density A W(z), VarDim 3, k = 9 */
+    OR_SPRING = 9,       /* Sec. 7.1 mass-spring edge: w k/2 l^2 (|x0 - x1|^2 / l^2 - 1)^2, VarDim 3, k = 6 */
+    OR_INERTIA = 10      /* Sec. 7.1 per-vertex inertia and gravity: m/2 |x - xhat|^2 - w m g.x, VarDim 3, k = 3 */
 };
 
 /* eval mode bits */

@@ -16,10 +16,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI = 1, 2, 3, 4, 5, 6, 7, 8
+SPRING, INERTIA = 9, 10
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 
-STENCIL = {EDGE_SQLEN: 2, TRI_AREA: 3, DIRICHLET: 3, STVK: 3, BENDING: 4, SYMDIR: 3, MLP: 3, SHELL_TRI: 3}
-VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3, SHELL_TRI: 3}
+STENCIL = {EDGE_SQLEN: 2, TRI_AREA: 3, DIRICHLET: 3, STVK: 3, BENDING: 4, SYMDIR: 3, MLP: 3, SHELL_TRI: 3,
+           SPRING: 2, INERTIA: 1}
+VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3, SHELL_TRI: 3,
+          SPRING: 3, INERTIA: 3}
 
 
 def build(force: bool = False) -> str:
@@ -321,12 +324,21 @@ class Problem:
             self._topo = topology(self.tris, self.nv)
         return self._topo
 
-    def add_term(self, kind: int, params=(0.0, 0.0)):
+    def add_term(self, kind: int, params=(0.0, 0.0), vertex_data=None):
+        """vertex_data: for INERTIA, per-vertex (m, xhat_x, xhat_y, xhat_z) [nv, 4]."""
         if VARDIM[kind] != self.d:
             raise ValueError("term VarDim does not match the problem")
         prm = np.zeros(max(4, len(params)))
         prm[:len(params)] = params
-        if kind in (SHELL_TRI, MLP):
+        if kind == SPRING:
+            st = self.topo.edges
+            rs = np.linalg.norm(self.rest_pos[st[:, 0]] - self.rest_pos[st[:, 1]], axis=1)[:, None]
+        elif kind == INERTIA:
+            if vertex_data is None:
+                raise ValueError("INERTIA needs vertex_data [nv, 4]")
+            st = np.arange(self.nv, dtype=np.int32)[:, None]
+            rs = np.ascontiguousarray(vertex_data, dtype=np.float64).reshape(self.nv, 4)
+        elif kind in (SHELL_TRI, MLP):
             st = self.tris
             rs = rest_shell(self.tris, self.rest_pos, self.nv)
         elif kind == BENDING:

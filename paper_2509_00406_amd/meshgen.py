@@ -21,6 +21,11 @@ the shapes and sizes of the evaluated scenes:
 * ``icosphere_batch`` hundreds of geodesic icospheres of lognormal size as
                       disjoint components of one mesh (the many-body shell
                       scene of Sec. 7.7).
+* ``cloth``           mass-spring cloth time step (Sec. 7.1, Table 1 sizes
+                      10^2 ... 1000^2 vertices): flat rest grid, a current
+                      state moved by smooth seeded waves (springs both
+                      stretched and compressed), smooth velocities, uniform
+                      lumped masses and gravity.
 """
 from __future__ import annotations
 
@@ -161,6 +166,45 @@ def warped_grid(n: int = 1001, seed: int = 3001, n_waves: int = 8,
     if not np.all(signed2 > 0):
         raise RuntimeError("warp flipped a triangle")
     return MeshInput(tris, rest, uv, 2, meta=dict(workload="warped_grid", n=n, seed=seed))
+
+
+def _waves(p: np.ndarray, rng, n_waves: int, amplitude: float, dim: int) -> np.ndarray:
+    """sum_k a_k sin(2 pi f_k . p + phi_k): a_k ~ amplitude/n_waves * unit vector in R^dim,
+    f_k = r_k (cos g_k, sin g_k), r_k ~ U[0.5, 2], over the 2D points p."""
+    out = np.zeros((p.shape[0], dim))
+    for _ in range(n_waves):
+        a = rng.normal(size=dim)
+        a *= amplitude / n_waves / np.linalg.norm(a)
+        g, r, phi = rng.uniform(0, 2 * math.pi), rng.uniform(0.5, 2.0), rng.uniform(0, 2 * math.pi)
+        f = r * np.array([math.cos(g), math.sin(g)])
+        out += np.outer(np.sin(2 * math.pi * (p @ f) + phi), a)
+    return out
+
+
+def cloth(n: int = 1000, seed: int = 6001, h: float = 1.0 / 60.0, k: float = 1.0e3,
+          gravity=(0.0, 0.0, -9.81), density: float = 1.0) -> MeshInput:
+    """One implicit-Euler step of a mass-spring cloth (Sec. 7.1) on an n x n grid.
+
+    rest: the flat unit-square grid (springs = mesh edges, rest lengths from it).
+    x (the current iterate x^n): rest + smooth waves of amplitude 0.02 in all three
+    coordinates, so some springs are stretched and others compressed (compressed springs
+    have negative Hessian eigenvalues, which the filtering clamps). v^n: smooth waves of
+    amplitude 0.5. Lumped mass m = density / n^2 per vertex; spring stiffness k = 1e3 makes the
+    springs dominate the inertia, so the unfiltered step Hessian is indefinite. meta holds the per-vertex
+    data vdata = (m, xhat) with xhat = x^n + h v^n, the spring params (k, h^2) and the
+    inertia params (h^2, g).
+    """
+    tris, rest = grid(n)
+    rng = np.random.default_rng(seed)
+    x = rest + _waves(rest[:, :2], rng, 6, 0.02, 3)
+    v = _waves(rest[:, :2], rng, 6, 0.5, 3)
+    m = np.full(n * n, density / (n * n))
+    vdata = np.empty((n * n, 4))
+    vdata[:, 0] = m
+    vdata[:, 1:] = x + h * v
+    w = h * h
+    return MeshInput(tris, rest, x, 3, meta=dict(workload="cloth", n=n, seed=seed, h=h, k=k, vdata=vdata,
+                                                   spring_params=(k, w), inertia_params=(w, *gravity)))
 
 
 # --- geodesic icospheres -------------------------------------------------------------------------

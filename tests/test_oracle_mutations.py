@@ -11,6 +11,7 @@ from oracle import oracle as O
 import tests.test_oracle_elements as TE
 import tests.test_oracle_assembly as TA
 import tests.test_oracle_shell as TS
+import tests.test_oracle_cloth as TC
 
 MUTANTS = {
     "product_rule_drops_cross_term": ("+ a.g[i] * b.g[j] + b.g[i] * a.g[j];", "+ a.g[i] * b.g[j];"),
@@ -52,6 +53,14 @@ MUTANTS = {
     "mlp_transposed_w2": ("a = hd_add(a, hd_scale(h1[n], W2[m * H + n]));", "a = hd_add(a, hd_scale(h1[n], W2[n * H + m]));"),
     "mlp_input_scale_dropped": ("xin[i] = hd_scale(z[i], sin_[i]);", "xin[i] = z[i];"),
     "normals_not_normalized": ("for (int d = 0; d < 3; ++d) n[d] /= l;", "for (int d = 0; d < 3; ++d) n[d] /= 1.0;"),
+    "spring_drops_rest_length_factor": ("return hd_scale(hd_sq(q), prm[1] * 0.5 * prm[0] * l2);",
+                                        "return hd_scale(hd_sq(q), prm[1] * 0.5 * prm[0]);"),
+    "spring_strain_not_normalised": ("hd q = hd_addc(hd_scale(hd3_dot(d, d), 1.0 / l2), -1.0);",
+                                     "hd q = hd_addc(hd3_dot(d, d), -1.0);"),
+    "inertia_gravity_wrong_sign": ("acc = hd_add(acc, hd_scale(x.c[c], -prm[0] * m * prm[1 + c]));",
+                                   "acc = hd_add(acc, hd_scale(x.c[c], prm[0] * m * prm[1 + c]));"),
+    "inertia_drops_half": ("acc = hd_add(acc, hd_scale(hd_sq(dc), 0.5 * m));", "acc = hd_add(acc, hd_scale(hd_sq(dc), m));"),
+    "inertia_rest_stride_wrong": ("if (kind[t] == OR_INERTIA) rest_stride = 4;", "if (kind[t] == OR_INERTIA) rest_stride = 3;"),
 }
 
 PINS = [TE.test_edge_sqlen_closed_form, TE.test_area_gradient_matches_paper_closed_form,
@@ -72,7 +81,9 @@ PINS = [TE.test_edge_sqlen_closed_form, TE.test_area_gradient_matches_paper_clos
         TS.test_cylinder_normals_second_form_closed_form, TS.test_plain_features_equal_hyper_dual_features,
         TS.test_vertex_normals_closed_forms, TS.test_shell_element_fd_and_invariance,
         TS.test_one_neuron_network_closed_form, TS.test_network_derivatives_fd_and_reverse_mode_agree,
-        TS.test_mlp_element_is_area_times_network_of_features, TS.test_shell_density_closed_form_gradient_by_fd]
+        TS.test_mlp_element_is_area_times_network_of_features, TS.test_shell_density_closed_form_gradient_by_fd,
+        lambda: TC.test_spring_matches_closed_form(0.95), TC.test_inertia_matches_closed_form,
+        lambda: TC.test_cloth_step_assembly_matches_dense_closed_form(True, 0.0)]
 
 
 def run_pins():
