@@ -10,6 +10,10 @@ Workloads:
   batched 700 geodesic icospheres of lognormal size (one mesh of disjoint
           components, per-component FP64 energies), layout chosen by the
           autotuner; also timed as one evaluation per mesh.
+  mlp     the learned per-triangle density on a 708 x 708 shell.
+  cloth   mass-spring cloth time step (Sec. 7.1): springs on the 2,996,001 edges
+          of a 1000 x 1000 grid plus inertia and gravity per vertex, filtered
+          Hessian; also timed at the Table 1 sizes 10^2 ... 1000^2 vertices.
 
 One step = one mad_problem_eval(ENERGY | GRAD | HESS | SPD) over the whole
 workload with inputs resident in HBM (topology, patches and pattern are built
@@ -49,7 +53,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--workload", choices=["shell", "batched", "mlp"], default="shell")
+    ap.add_argument("--workload", choices=["shell", "batched", "mlp", "cloth"], default="shell")
+    ap.add_argument("--cloth-n", type=int, default=1000, help="grid side of the cloth workload")
     ap.add_argument("--n", type=int, default=1024, help="grid side of the shell workload")
     ap.add_argument("--meshes", type=int, default=700, help="meshes of the batched workload")
     ap.add_argument("--mlp-n", type=int, default=708, help="grid side of the learned-density workload")
@@ -59,6 +64,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="choose the layout by timing (batched: always)")
     ap.add_argument("--no-fp64-plain", action="store_true", help="skip the FP64 GPU comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sizes", action="store_true", help="cloth: skip the Table 1 size sweep")
     ap.add_argument("--cpu-elements", type=int, default=300000, help="elements in the oracle timing sample")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
                     help="summarise a rocprofv3 counter-collection CSV under DIR and exit")
@@ -85,6 +91,10 @@ def workload(args):
         inp = meshgen.icosphere_batch(n_meshes=args.meshes)
         desc = (f"batched: {args.meshes} geodesic icospheres (lognormal sizes), StVK+bending, one launch, "
                 f"per-mesh FP64 energies, SPD-projected Hessians, block-CSR 3x3")
+    elif args.workload == "cloth":
+        inp = meshgen.cloth(n=args.cloth_n, seed=6001)
+        desc = (f"mass-spring cloth step: springs on every edge + inertia and gravity per vertex, "
+                f"{args.cloth_n}x{args.cloth_n} grid, filtered (SPD-projected) Hessians, block-CSR 3x3")
     else:
         inp = meshgen.shell_cylinder(n=args.mlp_n, seed=5001)
         desc = (f"learned density: 6-64-64-1 softplus network per triangle (BF16 weights, FP32 accumulation on "
@@ -202,12 +212,16 @@ def copy_calibration(nbytes):
 
 
 def make_problem(mad, mesh, inp, prec, args, stream, form=None):
-    """form: "plain" (StVK + bending), "mlp" (learned density), "analytic" (shell-triangle density);
-    default: the workload's own."""
-    form = form or ("mlp" if args.workload == "mlp" else "plain")
+    """form: "plain" (StVK + bending), "mlp" (learned density), "analytic" (shell-triangle density),
+    "cloth" (springs + inertia); default: the workload's own."""
+    form = form or {"mlp": "mlp", "cloth": "cloth"}.get(args.workload, "plain")
     scatter = mad.SCATTER_PATCH if args.scatter == "patch" else mad.SCATTER_ATOMIC
     prob = mad.Problem(mesh, 3, prec, patch_faces=args.patch_faces, scatter=scatter)
-    if form == "mlp":
+    if form == "cloth":
+        import torch
+        prob.add_term(mad.SPRING, inp.meta["spring_params"], inp.rest)
+        prob.add_vertex_term(mad.INERTIA, inp.meta["inertia_params"], torch.from_numpy(inp.meta["vdata"]).cuda())
+    elif form == "mlp":
         prob.add_mlp_term(seeded_network(mad), inp.rest)
     elif form == "analytic":
         prob.add_term(mad.SHELL_TRI, (1.0, 1.0, 1.0), inp.rest)
@@ -274,7 +288,10 @@ def main():
     x = torch.from_numpy(inp.x.ravel().copy()).cuda()
     out = prob.outputs()
     mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
-    n_elem = mesh.n_tris + (mesh.n_diamonds if args.workload != "mlp" else 0)
+    if args.workload == "cloth":
+        n_elem = mesh.n_edges + mesh.n_verts
+    else:
+        n_elem = mesh.n_tris + (mesh.n_diamonds if args.workload != "mlp" else 0)
     tune = None
     if args.autotune or args.workload == "batched":
         t1 = time.perf_counter()
@@ -291,10 +308,11 @@ def main():
     ms_per_step = max(wall * 1e3, sum(step_ms)) / args.steps
     nonfinite, fallbacks = prob.status()
 
-    n_terms = len(SHELL_TERMS) if args.workload != "mlp" else 1
+    n_terms = {"mlp": 1, "cloth": 2}.get(args.workload, len(SHELL_TERMS))
     if layout["scatter"] == mad.SCATTER_PATCH:
-        dom_name = ("k_eval_patch (learned-density chain + clamp + assembly)" if args.workload == "mlp"
-                    else "k_eval_patch (StVK + bending fused)")
+        dom_name = {"mlp": "k_eval_patch (learned-density chain + clamp + assembly)",
+                    "cloth": "k_eval_patch (springs + inertia fused)"}.get(args.workload,
+                                                                          "k_eval_patch (StVK + bending fused)")
         dom_ms = stage_ms[2] / n_evals
         stages = {"fill": stage_ms[0] / n_evals, "network": stage_ms[1] / n_evals, "fused": stage_ms[2] / n_evals,
                   "gather_and_fp64_redo": stage_ms[3] / n_evals, "energy": stage_ms[-1] / n_evals}
@@ -302,17 +320,27 @@ def main():
         term_ms = stage_ms[2:2 + n_terms]
         dom = int(np.argmax(term_ms))
         dom_ms = term_ms[dom] / n_evals
-        dom_name = ["k_eval<StVK>", "k_eval<bending>"][dom]
-        stages = {"fill": stage_ms[0] / n_evals, "stvk": term_ms[0] / n_evals, "bending": term_ms[1] / n_evals,
+        names = (["k_eval<spring>", "k_eval<inertia>"] if args.workload == "cloth"
+                 else ["k_eval<StVK>", "k_eval<bending>"][:n_terms])
+        dom_name = names[dom]
+        stages = {"fill": stage_ms[0] / n_evals, **{nm: t / n_evals for nm, t in zip(names, term_ms)},
                   "energy": stage_ms[-1] / n_evals}
-    if args.workload == "mlp":   # triangles only, 8 rest doubles each
+    if args.workload == "cloth":
+        step_bytes = cloth_alg_bytes(mesh.n_verts, mesh.n_edges, prob.nnzb, pb)
+    elif args.workload == "mlp":   # triangles only, 8 rest doubles each
         step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, 0, prob.nnzb, pb) + mesh.n_tris * 24
     else:
         step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, mesh.n_diamonds, prob.nnzb, pb)
     default_shell = args.workload == "shell" and args.n == 1024 and layout["scatter"] == mad.SCATTER_PATCH
     fpe = FLOPS_PER_ELEM.get(args.precision) if default_shell else None
     peak = VALU_PEAK_TFLOPS[args.precision]
-    if fpe:
+    if args.workload == "cloth":
+        # springs are cheap (one 3x3 reduced Hessian each): the fused kernel is held to its HBM stream
+        achieved = step_bytes / (dom_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": dom_ms,
+                    "alg_bytes_per_launch": step_bytes}
+    elif fpe:
         achieved = fpe * n_elem / (dom_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                     "frac": achieved / peak, "traffic": TRAFFIC_BYTES.get(args.precision), "kernel_ms": dom_ms,
@@ -335,8 +363,9 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": desc, "triangles": mesh.n_tris, "diamonds": mesh.n_diamonds, "elements": n_elem,
-                   "vertices": mesh.n_verts, "nnzb": prob.nnzb, "precision": args.precision,
+        "config": {"workload": desc, **({"springs": mesh.n_edges} if args.workload == "cloth" else
+                                        {"triangles": mesh.n_tris, "diamonds": mesh.n_diamonds}),
+                   "elements": n_elem, "vertices": mesh.n_verts, "nnzb": prob.nnzb, "precision": args.precision,
                    "layout": layout},
         "roofline": roofline,
         "hbm": {"alg_bytes_per_step": step_bytes, "alg_GBs": step_bytes / (ms_per_step * 1e-3) / 1e9,
@@ -373,14 +402,71 @@ def main():
                       "note": "clamped Hessian-vector product, matrix-free (no assembly)"}
     if args.workload == "batched":
         res["one_launch_per_mesh"] = per_mesh_baseline(torch, mad, inp, prec, stream, ms_per_step, args)
+    if args.workload == "cloth" and not args.no_sizes:
+        res["table1_sizes"] = cloth_sizes(torch, mad, args, stream)
     if prec == mad.F32 and not args.no_fp64_plain:
         res["vs_fp64_plain"] = fp64_plain(torch, mad, mesh, inp, args, stream, x, out, ms_per_step)
     if not args.no_cpu_baseline:
         if args.workload == "mlp":
             res["cpu_baseline"] = cpu_baseline(inp, 7000, mlp=seeded_network(mad))
+        elif args.workload == "cloth":
+            res["cpu_baseline"] = cpu_baseline_cloth(inp, 3 * args.cpu_elements)
         else:
             res["cpu_baseline"] = cpu_baseline(inp, args.cpu_elements)
     print(json.dumps(res), flush=True)
+
+
+def cloth_alg_bytes(nv, ne, nnzb, precision_bytes):
+    """Algorithmic HBM bytes of one cloth step: x, per-vertex (m, xhat), edges, spring rest data
+    (l^2, 1/l^2) and the pattern read once; gradient, every Hessian value and the energy written once."""
+    rd = nv * 3 * 8 + nv * 4 * 8 + ne * 2 * 4 + ne * 2 * 8 + (nv + 1) * 4 + nnzb * 4
+    wr = nv * 3 * precision_bytes + nnzb * 9 * precision_bytes + 8
+    return rd + wr
+
+
+# Table 1 of the paper (RTX 4090, precision not stated): grad + Hessian ms per step by vertex count
+PAPER_TABLE1_MS = {10: 0.18, 50: 0.22, 100: 0.25, 500: 3.09, 1000: 11.7}
+
+
+def cloth_sizes(torch, mad, args, stream):
+    """The cloth step at the Table 1 sizes (FP32 and FP64), with the paper's numbers as context."""
+    from paper_2509_00406_amd import meshgen
+    mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
+    rows = []
+    for n in sorted(PAPER_TABLE1_MS):
+        inp = meshgen.cloth(n=n, seed=6001)
+        mesh = mad.Mesh(inp.tris, inp.n_verts)
+        x = torch.from_numpy(inp.x.ravel().copy()).cuda()
+        row = {"vertices": n * n, "springs": mesh.n_edges, "paper_rtx4090_ms": PAPER_TABLE1_MS[n]}
+        for prec, name in ((mad.F32, "f32"), (mad.F64, "f64")):
+            p = make_problem(mad, mesh, inp, prec, args, stream, form="cloth")
+            o = p.outputs()
+            step_ms, wall = time_steps(torch, lambda: p.eval(x, mode, out=o, stream=stream), 20, 3, stream)
+            row[f"ms_{name}"] = max(wall * 1e3, sum(step_ms)) / len(step_ms)
+            del p, o
+        rows.append(row)
+    return rows
+
+
+def cpu_baseline_cloth(inp, budget):
+    """The FP64 oracle on the leading grid rows of the same cloth (serial C)."""
+    import numpy as np
+    from oracle import oracle as O
+    n = inp.meta["n"]
+    rows = max(2, min(n, int(budget / (4.0 * n))))
+    nv = rows * n
+    sel = np.all(inp.tris < nv, axis=1)
+    P = O.Problem(inp.tris[sel], inp.rest[:nv], nv, 3)
+    P.add_term(O.SPRING, inp.meta["spring_params"])
+    P.add_term(O.INERTIA, inp.meta["inertia_params"], vertex_data=inp.meta["vdata"][:nv])
+    P.build_pattern()
+    n_el = int(P.topo.edges.shape[0]) + nv
+    t0 = time.perf_counter()
+    P.eval(inp.x[:nv], O.ENERGY | O.GRAD | O.HESS | O.SPD, scales=False)
+    dt = time.perf_counter() - t0
+    return {"value": n_el / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {rows} of {n} grid rows of the same cloth: {n_el} elements (springs + vertices), "
+                      f"energy + gradient + filtered Hessian + assembly, FP64, one thread, {dt:.1f} s"}
 
 
 def other_forms(torch, mad, mesh, inp, args, stream, x, ms_mlp):

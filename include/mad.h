@@ -76,6 +76,12 @@ typedef enum mad_status {
  *  MAD_SHELL_TRI   face, VarDim 3: A W(z), W = mu (E00^2 + E11^2 + 2 E01^2) + lambda/2 (E00 + E11)^2
  *                  + k_b/2 (dII00^2 + dII11^2 + 2 dII01^2). params = {mu, lambda, k_b}. The
  *                  analytic density the network is trained on (its fallback and error judge).
+ * Mass-spring cloth (Sec. 7.1: implicit Euler, E = 1/2 |x - xhat|_M^2 + h^2 P(x)):
+ *  MAD_SPRING      edge, VarDim 3: w (k/2) l^2 (|x0 - x1|^2 / l^2 - 1)^2, l the rest length.
+ *                  params = {k, w} (w = h^2, the potential's weight). Needs rest positions.
+ *  MAD_INERTIA     vertex (1 vertex), VarDim 3: (m/2) |x - xhat|^2 - w m g.x, params = {w, g_x,
+ *                  g_y, g_z}. Per-vertex m and xhat come from a caller-owned device array read at
+ *                  every evaluation; added with mad_problem_add_vertex_term.
  */
 typedef enum mad_term_kind {
     MAD_EDGE_SQLEN = 1,
@@ -85,7 +91,9 @@ typedef enum mad_term_kind {
     MAD_BENDING = 5,
     MAD_SYMDIR = 6,
     MAD_MLP = 7,
-    MAD_SHELL_TRI = 8
+    MAD_SHELL_TRI = 8,
+    MAD_SPRING = 9,
+    MAD_INERTIA = 10
 } mad_term_kind;
 
 /* evaluation mode bits (Sec. 6.2: passive, gradient-only, full Hessian; Sec. 7.1 filtering) */
@@ -158,6 +166,15 @@ int32_t mad_problem_create(const mad_mesh *mesh, int32_t var_dim, int32_t precis
  * is computed here). Returns MAD_E_DEGENERATE_REST if a rest triangle has zero area. */
 int32_t mad_problem_add_term(mad_problem *prob, int32_t kind, const double *params_host, int32_t n_params,
                              const double *rest_pos_host);
+
+/* Add a per-vertex term (Sec. 7.1, the per-vertex energies of the mass-spring example): one
+ * element per mesh vertex. kind: MAD_INERTIA. vdata_dev: device FP64 [n_verts][4] = {m, xhat_x,
+ * xhat_y, xhat_z} per vertex, on the problem's device, owned by the caller; it is read (not
+ * copied) at every evaluation, so it must stay valid while the problem is evaluated, and the
+ * caller may rewrite it between evaluations (e.g. xhat = x^n + h v^n every time step). Every
+ * vertex must lie on a triangle (MAD_E_UNSUPPORTED otherwise). */
+int32_t mad_problem_add_vertex_term(mad_problem *prob, int32_t kind, const double *params_host, int32_t n_params,
+                                    const double *vdata_dev);
 
 /* Build patches, upload element data and build the block pattern on the GPU (Sec. 6.1), once.
  * Starts with the layout of the options (persistent launch off). Synchronises the stream. */

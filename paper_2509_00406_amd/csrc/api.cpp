@@ -151,7 +151,7 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
 }
 
 static int32_t add_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params, const double* rest_pos,
-                        const mad_mlp* mlp) {
+                        const mad_mlp* mlp, const double* vdata = nullptr) {
     if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
     if (p->finalized) return fail(MAD_E_STATE, "add_term after finalize");
     const int ns = kind_stencil(kind);
@@ -197,6 +197,19 @@ static int32_t add_term(mad_problem* p, int32_t kind, const double* params, int3
         t.mlp = mlp;
         rc = rest_shell(m, rest_pos, t.rest);
         break;
+    case MAD_SPRING:
+        t.n = m.ne();
+        t.stencil = m.edges;
+        rc = rest_spring(m, rest_pos, t.rest);
+        break;
+    case MAD_INERTIA:
+        for (int64_t v = 0; v < m.nv; ++v)
+            if (m.vert_face0[v] < 0) return fail(MAD_E_UNSUPPORTED, "vertex " + std::to_string(v) + " lies on no triangle");
+        t.n = m.nv;
+        t.stencil.resize((size_t)m.nv);
+        std::iota(t.stencil.begin(), t.stencil.end(), 0);
+        t.vdata = vdata;
+        break;
     }
     if (rc != MAD_OK) return rc;
     if (kind == MAD_MLP || kind == MAD_SHELL_TRI) p->shell = true;
@@ -207,7 +220,21 @@ static int32_t add_term(mad_problem* p, int32_t kind, const double* params, int3
 int32_t mad_problem_add_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params,
                              const double* rest_pos) {
     if (kind == MAD_MLP) return fail(MAD_E_INVALID_ARG, "learned-density terms are added with mad_problem_add_mlp_term");
+    if (kind == MAD_INERTIA) return fail(MAD_E_INVALID_ARG, "vertex terms are added with mad_problem_add_vertex_term");
     return add_term(p, kind, params, n_params, rest_pos, nullptr);
+}
+
+int32_t mad_problem_add_vertex_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params,
+                                    const double* vdata) {
+    if (!p || !vdata) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    if (kind != MAD_INERTIA) return fail(MAD_E_INVALID_ARG, "not a vertex term kind");
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, vdata) != hipSuccess || at.type != hipMemoryTypeDevice)
+        return fail(MAD_E_INVALID_ARG, "vdata must be device memory");
+    int dev = 0;
+    MAD_HIP_TRY(hipGetDevice(&dev));
+    if (at.device != dev) return fail(MAD_E_INVALID_ARG, "vdata lives on another device");
+    return add_term(p, kind, params, n_params, nullptr, nullptr, vdata);
 }
 
 int32_t mad_problem_add_mlp_term(mad_problem* p, const mad_mlp* mlp, const double* rest_pos) {

@@ -48,6 +48,7 @@ struct ElemOut {
 template <class Term, int MODE, typename T>
 __device__ __forceinline__ T hfull(const ElemOut<Term, T>& o, int i, int j, T te) {
     constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
+    if constexpr (!Term::TI) return o.hr[Packed<KR>::at(i, j)];   // seeded on the stencil DOFs
     const int si = i / D, ci = i % D, sj = j / D, cj = j % D;
     T acc = T(0);
     if constexpr (MODE == 2) {
@@ -88,6 +89,17 @@ template <class Term, int MODE, typename T>
 __device__ __forceinline__ void hvp_apply(const ElemOut<Term, T>& o, T te, const T (&v)[Term::NS * Term::D],
                                           T (&y)[Term::NS * Term::D]) {
     constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
+    if constexpr (!Term::TI) {
+        // seeded on the stencil DOFs: y = H v (the clamp, if any, is already in hr)
+#pragma unroll
+        for (int i = 0; i < KR; ++i) {
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < KR; ++j) acc += o.hr[Packed<KR>::at(i, j)] * v[j];
+            y[i] = acc;
+        }
+        return;
+    }
     T u[KR], w[KR];
     if constexpr (MODE == 2) {
 #pragma unroll
@@ -268,16 +280,34 @@ __device__ __forceinline__ void element_derivs(const double* xs, const double* r
                                                ElemOut<Term, T>& out, T (&Aq)[Packed<Term::KR>::N]) {
     constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
     double r[KR];
+    if constexpr (Term::TI) {
 #pragma unroll
-    for (int s = 1; s < NS; ++s)
+        for (int s = 1; s < NS; ++s)
 #pragma unroll
-        for (int c = 0; c < D; ++c) r[(s - 1) * D + c] = xs[s * D + c] - xs[c];
+            for (int c = 0; c < D; ++c) r[(s - 1) * D + c] = xs[s * D + c] - xs[c];
+    } else {
+#pragma unroll
+        for (int i = 0; i < KR; ++i) r[i] = xs[i];
+    }
     using S = typename std::conditional<MODE == 1, D1<KR, T>, HD<KR, T>>::type;
     S rs[KR];
 #pragma unroll
     for (int i = 0; i < KR; ++i) rs[i] = var<S>(i, r[i]);
     const S f = Term::template energy<S>(rs, rest, prm);
     out.f = f.v;
+    if constexpr (!Term::TI) {
+        // active variables are the stencil DOFs: no map back, no Helmert reduction
+#pragma unroll
+        for (int i = 0; i < KR; ++i) out.g[i] = f.g[i];
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int i = 0; i < Packed<KR>::N; ++i) out.hr[i] = f.h[i];
+        } else if constexpr (MODE == 3) {
+#pragma unroll
+            for (int i = 0; i < Packed<KR>::N; ++i) Aq[i] = f.h[i];
+        }
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         T g0 = T(0);
@@ -346,10 +376,15 @@ __device__ __forceinline__ bool element_eval(const double* xs, const double* res
     constexpr int NS = Term::NS, D = Term::D, KR = Term::KR;
     if constexpr (MODE == 0) {
         double r[KR];
+        if constexpr (Term::TI) {
 #pragma unroll
-        for (int s = 1; s < NS; ++s)
+            for (int s = 1; s < NS; ++s)
 #pragma unroll
-            for (int c = 0; c < D; ++c) r[(s - 1) * D + c] = xs[s * D + c] - xs[c];
+                for (int c = 0; c < D; ++c) r[(s - 1) * D + c] = xs[s * D + c] - xs[c];
+        } else {
+#pragma unroll
+            for (int i = 0; i < KR; ++i) r[i] = xs[i];
+        }
         out.f = Term::template energy<double>(r, rest, prm);
         return true;
     } else {

@@ -120,8 +120,10 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
             A.rest = t.d_rest;
             A.lvert = t.d_lvert;
             A.lslot = t.d_lslot;
+            A.lseg = t.d_lseg;
             A.elem_ptr = t.d_elem_ptr;
             A.psi = t.d_psi;
+            A.vdata = t.vdata;
             std::memcpy(A.prm, t.prm, sizeof(A.prm));
         }
         MAD_HIP_TRY(launch_eval_patch(L, s));
@@ -181,6 +183,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
                 F.terms[ti].stencil = t.d_stencil;
                 F.terms[ti].rest = t.d_rest;
                 F.terms[ti].psi = t.d_psi;
+                F.terms[ti].vdata = t.vdata;
                 std::memcpy(F.terms[ti].prm, t.prm, sizeof(t.prm));
             }
             MAD_HIP_TRY(launch_fallback(F, s));
@@ -213,6 +216,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.qmin = p->opt.degenerate_q;
         L.normals = p->d_normals;
         L.psi = t.d_psi;
+        L.vdata = t.vdata;
         L.hvp = hvp ? 1 : 0;
         L.v = v;
         L.y = y;

@@ -13,7 +13,8 @@ namespace mad {
 
 int kind_stencil(int kind) {
     switch (kind) {
-    case MAD_EDGE_SQLEN: return 2;
+    case MAD_INERTIA: return 1;
+    case MAD_EDGE_SQLEN: case MAD_SPRING: return 2;
     case MAD_TRI_AREA: case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: case MAD_MLP: case MAD_SHELL_TRI: return 3;
     case MAD_BENDING: return 4;
     default: return -1;
@@ -23,14 +24,15 @@ int kind_vardim(int kind) {
     switch (kind) {
     case MAD_DIRICHLET: return 1;
     case MAD_SYMDIR: return 2;
-    case MAD_EDGE_SQLEN: case MAD_TRI_AREA: case MAD_STVK: case MAD_BENDING: case MAD_MLP: case MAD_SHELL_TRI: return 3;
+    case MAD_EDGE_SQLEN: case MAD_TRI_AREA: case MAD_STVK: case MAD_BENDING: case MAD_MLP: case MAD_SHELL_TRI:
+    case MAD_SPRING: case MAD_INERTIA: return 3;
     default: return -1;
     }
 }
 int kind_nrest(int kind) {
     switch (kind) {
     case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: return 5;
-    case MAD_BENDING: return 2;
+    case MAD_BENDING: case MAD_SPRING: return 2;
     case MAD_MLP: case MAD_SHELL_TRI: return 8;
     default: return 0;
     }
@@ -99,6 +101,10 @@ int build_topology(mad_mesh& m) {
         m.fadj[cur[l.second]++] = l.first;
     }
     for (int64_t f = 0; f < m.nt; ++f) std::sort(m.fadj.begin() + m.fadj_ptr[f], m.fadj.begin() + m.fadj_ptr[f + 1]);
+    // lowest face of every vertex (places a vertex term's element in that face's patch)
+    m.vert_face0.assign((size_t)m.nv, -1);
+    for (int64_t f = m.nt - 1; f >= 0; --f)
+        for (int a = 0; a < 3; ++a) m.vert_face0[m.tris[3 * f + a]] = (int32_t)f;
     return MAD_OK;
 }
 
@@ -208,6 +214,22 @@ int rest_diamond(const mad_mesh& m, const double* X, std::vector<double>& out) {
         out[2 * e] = 0.5 * (a1 + a2);
         const int32_t* d = &m.diamonds[4 * e];
         out[2 * e + 1] = dihedral(X + 3 * (int64_t)d[0], X + 3 * (int64_t)d[1], X + 3 * (int64_t)d[2], X + 3 * (int64_t)d[3]);
+    }
+    return MAD_OK;
+}
+
+// Springs (Sec. 7.1): per edge the rest squared length l^2 and its reciprocal.
+int rest_spring(const mad_mesh& m, const double* X, std::vector<double>& out) {
+    const int64_t ne = m.ne();
+    out.assign((size_t)ne * 2, 0.0);
+    for (int64_t e = 0; e < ne; ++e) {
+        const double* a = X + 3 * (int64_t)m.edges[2 * e];
+        const double* b = X + 3 * (int64_t)m.edges[2 * e + 1];
+        const double l2 = (a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) + (a[2] - b[2]) * (a[2] - b[2]);
+        if (!(l2 > 0.0) || !std::isfinite(l2))
+            return fail(MAD_E_DEGENERATE_REST, "rest edge " + std::to_string(e) + " has zero length");
+        out[2 * e] = l2;
+        out[2 * e + 1] = 1.0 / l2;
     }
     return MAD_OK;
 }

@@ -65,14 +65,16 @@ template <class Term> __device__ __forceinline__ double quality(const double* xs
 // Number of per-element inputs a term's energy reads: rest data, then (shell-feature terms) the
 // three unit vertex normals, then (learned density) the 28 network outputs.
 template <class Term> constexpr int n_inputs() {
-    return (Term::NREST + Term::NAUX + Term::NPSI) > 0 ? Term::NREST + Term::NAUX + Term::NPSI : 1;
+    return (Term::NREST + Term::NAUX + Term::NPSI + Term::NVD) > 0 ? Term::NREST + Term::NAUX + Term::NPSI + Term::NVD
+                                                                    : 1;
 }
 
 // Gather one element's inputs: rest SoA [NREST][n], normals [nv][3] at the element's global
-// vertices gv[], network outputs SoA [28][n] (FP32).
+// vertices gv[], network outputs SoA [28][n] (FP32), the caller's per-vertex data [nv][NVD] at gv[].
 template <class Term>
 __device__ __forceinline__ void gather_inputs(double (&in)[n_inputs<Term>()], const double* rest, int64_t n, int64_t e,
-                                              const double* normals, const int* gv, const float* psi) {
+                                              const double* normals, const int* gv, const float* psi,
+                                              const double* vdata) {
 #pragma unroll
     for (int k = 0; k < Term::NREST; ++k) in[k] = rest[(int64_t)k * n + e];
     if constexpr (Term::NAUX > 0) {
@@ -84,6 +86,13 @@ __device__ __forceinline__ void gather_inputs(double (&in)[n_inputs<Term>()], co
     if constexpr (Term::NPSI > 0) {
 #pragma unroll
         for (int k = 0; k < Term::NPSI; ++k) in[Term::NREST + Term::NAUX + k] = double(psi[(int64_t)k * n + e]);
+    }
+    if constexpr (Term::NVD > 0) {
+        constexpr int B = Term::NREST + Term::NAUX + Term::NPSI;
+#pragma unroll
+        for (int s = 0; s < Term::NS; ++s)
+#pragma unroll
+            for (int k = 0; k < Term::NVD; ++k) in[B + s * Term::NVD + k] = vdata[(int64_t)gv[s] * Term::NVD + k];
     }
 }
 

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalLaunch L) {
                 bad = bad || !finite(xs[s * D + c]);
             }
         double rest[n_inputs<Term>()];
-        gather_inputs<Term>(rest, L.rest, L.n, e, L.normals, vs, L.psi);
+        gather_inputs<Term>(rest, L.rest, L.n, e, L.normals, vs, L.psi, L.vdata);
 
         ElemOut<Term, T> o;
         if constexpr (MODE == 3 && sizeof(T) == 4) {
@@ -128,6 +128,8 @@ hipError_t launch_eval(const EvalLaunch& L, hipStream_t s) {
     case K_SYMDIR: return launch_prec<TermSymDir>(L, s);
     case K_SHELL_TRI: return launch_prec<TermShellTri>(L, s);
     case K_MLP: return launch_prec<TermMLP>(L, s);
+    case K_SPRING: return launch_prec<TermSpring>(L, s);
+    case K_INERTIA: return launch_prec<TermInertia>(L, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -26,15 +26,172 @@ constexpr uint32_t kFbTermShift = 29;
 constexpr uint32_t kFbGradDone = 1u << 28;
 constexpr uint32_t kFbElemMask = kFbGradDone - 1u;
 
-// Elements e_first, e_first + e_step, ... below e_end of one term of patch p.
+// One lock per workgroup over the patch's Hessian blocks in LDS: one wave at a time adds its unit's
+// blocks. Lane 0 takes it for the whole wave (all lanes converged); it is released once the wave's
+// LDS writes have completed. The spin is bounded: past the bound the internal-error flag is raised
+// and the wave goes on without the lock, so every wave ends.
+constexpr int kLockSpins = 1 << 22;
+
+__device__ __forceinline__ bool wave_lock(int* lock, int32_t* flags) {
+    for (int spin = 0; spin < kLockSpins; ++spin) {
+        int got = 0;
+        if ((threadIdx.x & 63) == 0) {
+            int expected = 0;
+            got = __hip_atomic_compare_exchange_strong(lock, &expected, 1, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP)
+                      ? 1
+                      : 0;
+        }
+        got = __shfl(got, 0);
+        if (got) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            return true;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    if ((threadIdx.x & 63) == 0) atomicOr(flags + 1, 16);
+    return false;
+}
+
+__device__ __forceinline__ void wave_unlock(int* lock, bool held) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (held && (threadIdx.x & 63) == 0) __hip_atomic_store(lock, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Add the Hessian blocks of the wave's elements (one per lane, `have` lanes only) into the patch's
+// blocks in LDS with plain read-add-writes: the lanes of one segment touch disjoint blocks, the
+// segments go one after another, and the lock keeps the other waves of the workgroup out. The block
+// values are computed before the lock is taken; under it, a segment reads all its entries, then
+// writes them back summed (one LDS round trip per segment). An element whose stencil names one
+// vertex twice (two pairs landing in one block) makes the wave add pair by pair instead.
+// Called by all 64 lanes of the wave together.
 template <class Term, typename T, int MODE>
-__device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTermArgs& A, int term, int p, int e_first,
-                                           int e_step, int e_end, const double* sx, T* sg, T* sh, T* sy, double& esum,
+__device__ __forceinline__ void add_blocks(const PatchLaunch& L, const PatchTermArgs& A, int e, bool have,
+                                           const ElemOut<Term, T>& o, T te, T* sh, int* lock) {
+    constexpr int NS = Term::NS, D = Term::D, DD = D * D, NP = NS * (NS + 1) / 2;
+    uint32_t wv[NP];
+    int seg = -1;
+    bool degen = false;
+    if (have) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            wv[k] = A.lslot[(int64_t)k * A.n + e];
+            degen = degen || (wv[k] >> 14) == 2u;
+        }
+        seg = A.lseg[e];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) wv[k] = 0u;
+    }
+    const int nseg = wave_max(seg) + 1;
+    if (nseg == 0) return;
+    // entry (k, c, c2) of pair k: the diagonal pairs keep their upper half (c2 >= c)
+    T hv[NP][DD];
+    {
+        int k = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int t = s; t < NS; ++t, ++k)
+#pragma unroll
+                for (int c = 0; c < D; ++c)
+#pragma unroll
+                    for (int c2 = 0; c2 < D; ++c2) {
+                        if (s == t && c2 < c) continue;
+                        hv[k][c * D + c2] = hfull<Term, MODE>(o, s * D + c, t * D + c2, te);
+                    }
+    }
+    const bool held = wave_lock(lock, L.flags);
+    if (__ballot(degen) != 0ull) {
+        // rare: some pair lands in a diagonal block without s == t; add pair by pair
+        int k = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+#pragma unroll
+            for (int t = s; t < NS; ++t, ++k) {
+                T* blk = sh + (int)(wv[k] & 0x3fffu) * DD;
+                const uint32_t flag = wv[k] >> 14;
+                for (int g = 0; g < nseg; ++g) {
+                    if (seg != g) continue;
+                    if (s == t) {
+#pragma unroll
+                        for (int c = 0; c < D; ++c)
+#pragma unroll
+                            for (int c2 = c; c2 < D; ++c2) blk[c * D + c2] += hv[k][c * D + c2];
+                    } else if (flag == 2u) {
+#pragma unroll
+                        for (int c = 0; c < D; ++c)
+#pragma unroll
+                            for (int c2 = c; c2 < D; ++c2) blk[c * D + c2] += hv[k][c * D + c2] + hv[k][c2 * D + c];
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < D; ++c)
+#pragma unroll
+                            for (int c2 = 0; c2 < D; ++c2)
+                                blk[(flag == 1u) ? (c2 * D + c) : (c * D + c2)] += hv[k][c * D + c2];
+                    }
+                }
+            }
+    } else {
+        for (int g = 0; g < nseg; ++g) {
+            if (seg != g) continue;
+            // row by row of the stencil's pairs (s, t >= s): read the row's entries, then write them
+            // back summed
+            int k0 = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                T cur[NS][DD];
+#pragma unroll
+                for (int t = s; t < NS; ++t) {
+                    const int k = k0 + (t - s);
+                    const T* blk = sh + (int)(wv[k] & 0x3fffu) * DD;
+                    const bool tr = (wv[k] >> 14) == 1u;   // block stored as (c, r): the transpose
+#pragma unroll
+                    for (int c = 0; c < D; ++c)
+#pragma unroll
+                        for (int c2 = 0; c2 < D; ++c2) {
+                            if (s == t && c2 < c) continue;
+                            cur[t][c * D + c2] = blk[(s != t && tr) ? (c2 * D + c) : (c * D + c2)];
+                        }
+                }
+#pragma unroll
+                for (int t = s; t < NS; ++t) {
+                    const int k = k0 + (t - s);
+                    T* blk = sh + (int)(wv[k] & 0x3fffu) * DD;
+                    const bool tr = (wv[k] >> 14) == 1u;
+#pragma unroll
+                    for (int c = 0; c < D; ++c)
+#pragma unroll
+                        for (int c2 = 0; c2 < D; ++c2) {
+                            if (s == t && c2 < c) continue;
+                            blk[(s != t && tr) ? (c2 * D + c) : (c * D + c2)] = cur[t][c * D + c2] + hv[k][c * D + c2];
+                        }
+                }
+                k0 += NS - s;
+            }
+        }
+    }
+    wave_unlock(lock, held);
+}
+
+// Element e (one per lane; lanes with e >= e_end have none) of one term of patch p. Called by all
+// 64 lanes of a wave together (the Hessian blocks are added wave by wave, see add_blocks).
+template <class Term, typename T, int MODE>
+__device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTermArgs& A, int term, int p, int e,
+                                           int e_end, const double* sx, T* sg, T* sh, T* sy, int* lock, double& esum,
                                            bool& bad) {
-    constexpr int NS = Term::NS, D = Term::D, NF = NS * D, DD = D * D;
+    constexpr int NS = Term::NS, D = Term::D, NF = NS * D;
     const int lv0 = L.lv_ptr[p];
     const T te = T(L.eps > 0.0 ? L.eps : 0.0);
-    for (int e = e_first; e < e_end; e += e_step) {
+    ElemOut<Term, T> o{};
+    bool blocks = false;   // this lane adds a Hessian into the patch's blocks
+    if (e < e_end) {
         int lv[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) lv[s] = A.lvert[(int64_t)s * A.n + e];
@@ -44,15 +201,14 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
 #pragma unroll
             for (int c = 0; c < D; ++c) xs[s * D + c] = sx[lv[s] * D + c];
         double rest[n_inputs<Term>()];
-        if constexpr (Term::NAUX > 0) {
+        if constexpr (Term::NAUX > 0 || Term::NVD > 0) {
             int gv[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) gv[s] = L.lv_global[lv0 + lv[s]];
-            gather_inputs<Term>(rest, A.rest, A.n, e, L.normals, gv, A.psi);
+            gather_inputs<Term>(rest, A.rest, A.n, e, L.normals, gv, A.psi, A.vdata);
         } else {
-            gather_inputs<Term>(rest, A.rest, A.n, e, nullptr, nullptr, nullptr);
+            gather_inputs<Term>(rest, A.rest, A.n, e, nullptr, nullptr, nullptr, nullptr);
         }
-        ElemOut<Term, T> o;
         if constexpr (MODE == 3) {
             // FP32: near-degenerate elements (quality below qmin) are queued whole for the FP64 redo.
             // Every other element assembles its gradient before the eigen-decomposition (so neither
@@ -60,6 +216,7 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
             // decomposition does not converge is queued for its Hessian only. The primal value (the
             // energy) is FP64 on every path, so the energy stays here and the reduction stays
             // deterministic.
+            bool queued = false;
             if constexpr (sizeof(T) == 4) {
                 if (quality<Term>(xs) < L.qmin) {
                     ElemOut<Term, double> op;
@@ -69,39 +226,37 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
                     const int k = atomicAdd(L.fb_count, 1);
                     if (k < L.fb_cap) L.fb_list[k] = ((uint32_t)term << kFbTermShift) | (uint32_t)e;
                     atomicAdd(L.fallbacks, 1ull);
-                    continue;
+                    queued = true;
                 }
             }
-            T Aq[Packed<Term::KR>::N];
-            element_derivs<Term, T, 3>(xs, rest, A.prm, o, Aq);
-            esum += o.f;
-            {
-                T ga = T(0);
+            if (!queued) {
+                T Aq[Packed<Term::KR>::N];
+                element_derivs<Term, T, 3>(xs, rest, A.prm, o, Aq);
+                esum += o.f;
+                {
+                    T ga = T(0);
 #pragma unroll
-                for (int i = 0; i < NF; ++i) ga += fabs(o.g[i]);
-                bad = bad || !finite(o.f) || !finite(ga);
-            }
-            if (L.want_grad) {
+                    for (int i = 0; i < NF; ++i) ga += fabs(o.g[i]);
+                    bad = bad || !finite(o.f) || !finite(ga);
+                }
+                if (L.want_grad) {
 #pragma unroll
-                for (int s = 0; s < NS; ++s)
+                    for (int s = 0; s < NS; ++s)
 #pragma unroll
-                    for (int c = 0; c < D; ++c) lds_add(sg + lv[s] * D + c, o.g[s * D + c]);
-            }
-            const bool conv = element_clamp<Term, T>(Aq, L.eps, o);
-            if constexpr (sizeof(T) == 4) {
-                if (!conv) {
+                        for (int c = 0; c < D; ++c) lds_add(sg + lv[s] * D + c, o.g[s * D + c]);
+                }
+                const bool conv = element_clamp<Term, T>(Aq, L.eps, o);
+                if (sizeof(T) == 4 && !conv) {
                     const int k = atomicAdd(L.fb_count, 1);
-                    if (k < L.fb_cap)
-                        L.fb_list[k] = ((uint32_t)term << kFbTermShift) | kFbGradDone | (uint32_t)e;
+                    if (k < L.fb_cap) L.fb_list[k] = ((uint32_t)term << kFbTermShift) | kFbGradDone | (uint32_t)e;
                     atomicAdd(L.fallbacks, 1ull);
-                    continue;
-                }
-            }
-            {
-                T ha = T(0);
+                } else {
+                    T ha = T(0);
 #pragma unroll
-                for (int i = 0; i < Packed<Term::KR>::N; ++i) ha += fabs(o.hr[i]);
-                bad = bad || !finite(ha);
+                    for (int i = 0; i < Packed<Term::KR>::N; ++i) ha += fabs(o.hr[i]);
+                    bad = bad || !finite(ha);
+                    blocks = true;
+                }
             }
         } else {
             element_eval<Term, T, MODE>(xs, rest, A.prm, L.eps, o);
@@ -115,9 +270,10 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
                         for (int c = 0; c < D; ++c) lds_add(sg + lv[s] * D + c, o.g[s * D + c]);
                 }
             }
+            blocks = MODE >= 2;
         }
         if constexpr (MODE >= 2) {
-            if (L.hvp) {
+            if (L.hvp && blocks) {
                 // matrix-free: y += H_j v_j (sh holds the patch's v, sy its product)
                 T vl[NF], yl[NF];
 #pragma unroll
@@ -129,43 +285,17 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
                 for (int s = 0; s < NS; ++s)
 #pragma unroll
                     for (int c = 0; c < D; ++c) lds_add(sy + lv[s] * D + c, yl[s * D + c]);
-                continue;
             }
-            int k = 0;
-#pragma unroll
-            for (int s = 0; s < NS; ++s)
-#pragma unroll
-                for (int t = s; t < NS; ++t, ++k) {
-                    const uint32_t w = A.lslot[(int64_t)k * A.n + e];
-                    T* blk = sh + (int)(w & 0x3fffu) * DD;
-                    const uint32_t flag = w >> 14;
-                    if (s == t || flag == 2u) {
-                        // lands in a diagonal block, which is symmetric: accumulate its upper half only
-                        // (s != t naming one vertex contributes H_st + H_st^T)
-#pragma unroll
-                        for (int c = 0; c < D; ++c)
-#pragma unroll
-                            for (int c2 = c; c2 < D; ++c2) {
-                                T v = hfull<Term, MODE>(o, s * D + c, t * D + c2, te);
-                                if (s != t) v += hfull<Term, MODE>(o, s * D + c2, t * D + c, te);
-                                lds_add(blk + c * D + c2, v);
-                            }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < D; ++c)
-#pragma unroll
-                            for (int c2 = 0; c2 < D; ++c2)
-                                lds_add(blk + ((flag == 1u) ? (c2 * D + c) : (c * D + c2)),
-                                        hfull<Term, MODE>(o, s * D + c, t * D + c2, te));
-                    }
-                }
         }
+    }
+    if constexpr (MODE >= 2) {
+        if (!L.hvp) add_blocks<Term, T, MODE>(L, A, e, blocks, o, te, sh, lock);
     }
 }
 
 template <typename T, int MODE, int D, bool SH>
 __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsigned char* smem, double* red,
-                                               int* s_next) {
+                                               int* s_next, int* lock) {
     constexpr int DD = D * D;
     const int lv0 = L.lv_ptr[p], nlv = L.lv_ptr[p + 1] - lv0;
     const int lb0 = L.lb_ptr[p], nlb = L.lb_ptr[p + 1] - lb0;
@@ -175,7 +305,10 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
                                  (MODE >= 1 ? align16((size_t)nlv * D * sizeof(T)) : 0));
     // matrix-free mode: the block area holds the patch's v, then its product y
     T* sy = (MODE >= 2 && L.hvp) ? sh + align16((size_t)nlv * D * sizeof(T)) / sizeof(T) : nullptr;
-    if (threadIdx.x == 0) *s_next = 0;
+    if (threadIdx.x == 0) {
+        *s_next = 0;
+        *lock = 0;
+    }
     red[threadIdx.x] = 0.0;   // per-unit energies
     bool bad_x = false;
     for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
@@ -229,26 +362,30 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         const int e0 = first + lane;
         if constexpr (D == 3) {
             switch (A.kind) {
-            case K_STVK: patch_term<TermStVK, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad); break;
-            case K_BENDING: patch_term<TermBending, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad); break;
-            case K_TRI_AREA: patch_term<TermTriArea, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad); break;
+            case K_STVK: patch_term<TermStVK, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad); break;
+            case K_BENDING: patch_term<TermBending, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad); break;
+            case K_TRI_AREA: patch_term<TermTriArea, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad); break;
             case K_EDGE_SQLEN:
-                patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
+                patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
+                break;
+            case K_SPRING: patch_term<TermSpring, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad); break;
+            case K_INERTIA:
+                patch_term<TermInertia, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
             case K_SHELL_TRI:
-                if constexpr (SH) patch_term<TermShellTri, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
+                if constexpr (SH) patch_term<TermShellTri, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
             case K_MLP:
-                if constexpr (SH) patch_term<TermMLP, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
+                if constexpr (SH) patch_term<TermMLP, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
             default: break;
             }
         } else if constexpr (D == 2) {
             if (A.kind == K_SYMDIR)
-                patch_term<TermSymDir, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
+                patch_term<TermSymDir, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
         } else {
             if (A.kind == K_DIRICHLET)
-                patch_term<TermDirichlet, T, MODE>(L, A, t, p, e0, 64, last, sx, sg, sh, sy, esum, bad);
+                patch_term<TermDirichlet, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) esum += __shfl_down(esum, o);
@@ -314,9 +451,9 @@ template <typename T, int MODE, int D, bool SH>
 __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kBlock];
-    __shared__ int next, unit_next;
+    __shared__ int next, unit_next, block_lock;
     if (!L.persistent) {
-        eval_patch_one<T, MODE, D, SH>(L, blockIdx.x, smem, red, &unit_next);
+        eval_patch_one<T, MODE, D, SH>(L, blockIdx.x, smem, red, &unit_next, &block_lock);
         return;
     }
     for (;;) {
@@ -325,7 +462,7 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
         const int k = next;
         __syncthreads();   // every lane has read `next` before it is overwritten
         if (k >= L.n_patch) break;
-        eval_patch_one<T, MODE, D, SH>(L, L.work_order[k], smem, red, &unit_next);
+        eval_patch_one<T, MODE, D, SH>(L, L.work_order[k], smem, red, &unit_next, &block_lock);
         __syncthreads();   // the flush has read LDS before the next patch clears it
     }
 }
@@ -419,7 +556,7 @@ __device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const Fal
 #pragma unroll
         for (int c = 0; c < D; ++c) xs[s * D + c] = F.x[(int64_t)vs[s] * D + c];
     double rest[n_inputs<Term>()];
-    gather_inputs<Term>(rest, A.rest, A.n, e, F.normals, vs, A.psi);
+    gather_inputs<Term>(rest, A.rest, A.n, e, F.normals, vs, A.psi, A.vdata);
     ElemOut<Term, double> o;
     element_eval<Term, double, 3>(xs, rest, A.prm, F.eps, o);
     if (!out_finite<Term, double>(o, 3)) atomicOr(F.flags, 1);
@@ -478,6 +615,8 @@ __global__ __launch_bounds__(kBlock) void k_fallback(FallbackLaunch F) {
             case K_BENDING: fallback_elem<TermBending>(F, A, e, grad_done); break;
             case K_TRI_AREA: fallback_elem<TermTriArea>(F, A, e, grad_done); break;
             case K_EDGE_SQLEN: fallback_elem<TermEdgeSqlen>(F, A, e, grad_done); break;
+            case K_SPRING: fallback_elem<TermSpring>(F, A, e, grad_done); break;
+            case K_INERTIA: fallback_elem<TermInertia>(F, A, e, grad_done); break;
             case K_SHELL_TRI: fallback_elem<TermShellTri>(F, A, e, grad_done); break;
             case K_MLP: fallback_elem<TermMLP>(F, A, e, grad_done); break;
             default: break;

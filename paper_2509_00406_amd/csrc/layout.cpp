@@ -59,7 +59,7 @@ static void color_within_patches(Term& t, int64_t nv) {
 }
 
 // Patch order of every term's elements: faces by their patch, diamonds by their lower face, edges
-// by their first face; inside a patch by colour, then by that face's index. Two stable counting
+// by their first face, vertices by their lowest face; inside a patch by colour, then by that face's index. Two stable counting
 // sorts (by face, then by patch): linear in the element count.
 static void order_terms(mad_problem* p) {
     const mad_mesh& m = *p->mesh;
@@ -68,7 +68,8 @@ static void order_terms(mad_problem* p) {
         std::vector<int32_t> key((size_t)t.n);
         for (int64_t e = 0; e < t.n; ++e) {
             if (t.kind == MAD_BENDING) key[e] = m.diamond_faces[2 * e];
-            else if (t.kind == MAD_EDGE_SQLEN) key[e] = m.edge_face0[e];
+            else if (t.kind == MAD_EDGE_SQLEN || t.kind == MAD_SPRING) key[e] = m.edge_face0[e];
+            else if (t.kind == MAD_INERTIA) key[e] = m.vert_face0[t.stencil[e]];
             else key[e] = (int32_t)e;
         }
         // by face
@@ -138,6 +139,7 @@ static void free_layout(mad_problem* p) {
         t.d_slots = nullptr;
         t.d_lvert = nullptr;
         t.d_lslot = nullptr;
+        t.d_lseg = nullptr;
         t.d_psi = nullptr;
         t.d_xh = nullptr;
     }
@@ -231,6 +233,34 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
     return build_scatter(p, s);
 }
 
+// Segments of the patch kernel's work units (the 64 consecutive elements of one term in one patch
+// that one wave evaluates together): inside a unit, greedily, each element takes the lowest segment
+// in which no earlier element of the unit shares a vertex with it. Elements of one segment touch
+// disjoint gradient entries and Hessian blocks, so a wave can add a segment's contributions with
+// plain LDS read-add-writes. The colour order inside each patch keeps most units at one or two
+// segments.
+static void unit_segments(const Term& t, int32_t np, int64_t nv, std::vector<uint8_t>& seg) {
+    seg.assign((size_t)std::max<int64_t>(t.n, 1), 0);
+    std::vector<uint64_t> used((size_t)nv, 0);   // segments of the current unit using the vertex
+    for (int32_t q = 0; q < np; ++q)
+        for (int32_t u0 = t.elem_ptr[q]; u0 < t.elem_ptr[q + 1]; u0 += 64) {
+            const int32_t u1 = std::min(u0 + 64, t.elem_ptr[q + 1]);
+            for (int32_t i = u0; i < u1; ++i) {
+                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                uint64_t busy = 0;
+                for (int a = 0; a < t.ns; ++a) busy |= used[st[a]];
+                int sg = 0;
+                while ((busy >> sg) & 1ull) ++sg;   // at most 63: a unit has 64 elements
+                seg[i] = (uint8_t)sg;
+                for (int a = 0; a < t.ns; ++a) used[st[a]] |= 1ull << sg;
+            }
+            for (int32_t i = u0; i < u1; ++i) {
+                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                for (int a = 0; a < t.ns; ++a) used[st[a]] = 0;
+            }
+        }
+}
+
 // Structures of the scatter strategy for the current element order; needs the pattern.
 int build_scatter(mad_problem* p, hipStream_t s) {
     int rc;
@@ -276,6 +306,9 @@ int build_scatter(mad_problem* p, hipStream_t s) {
             return rc;
         if ((rc = upload_layout(p, (void**)&t.d_lslot, L.lslot[ti].data(), L.lslot[ti].size() * 2, s)) != MAD_OK)
             return rc;
+        std::vector<uint8_t> seg;
+        unit_segments(t, (int32_t)p->patches.n, p->mesh->nv, seg);
+        if ((rc = upload_layout(p, (void**)&t.d_lseg, seg.data(), seg.size(), s)) != MAD_OK) return rc;
     }
     if (p->prec == MAD_F32) {
         // queue for FP32 elements redone in FP64: room for every element

@@ -20,6 +20,7 @@ struct mad_mesh {
     std::vector<int32_t> edge_face0;     // [ne] lowest incident face
     std::vector<int32_t> diamonds;       // [nd][4]
     std::vector<int32_t> diamond_faces;  // [nd][2]
+    std::vector<int32_t> vert_face0;     // [nv] lowest face containing the vertex (-1: none)
     // face adjacency across manifold and non-manifold edges (CSR), for patching
     std::vector<int32_t> fadj_ptr, fadj;
     int64_t ne() const { return (int64_t)edge_nf.size(); }
@@ -45,9 +46,11 @@ struct Term {
     int32_t* d_slots = nullptr;          // SoA [ns*ns][n] global block of (s, t) (atomic scatter)
     uint16_t* d_lvert = nullptr;         // SoA [ns][n] patch-local vertex (patch scatter)
     uint16_t* d_lslot = nullptr;         // SoA [ns(ns+1)/2][n] patch-local block + flags
+    uint8_t* d_lseg = nullptr;           // [n] segment of the element inside its 64-element work unit
     const mad_mlp* mlp = nullptr;        // learned density: the network
     float* d_psi = nullptr;              // learned density: SoA [28][n] network outputs, patch order
     float* d_xh = nullptr;               // learned density: SoA [6][n] scaled features, patch order
+    const double* vdata = nullptr;       // vertex terms: the caller's [nv][NVD] device array (not owned)
 };
 
 // patch-local index structures of the LDS-accumulating assembly (host_patch.cpp)
@@ -155,6 +158,7 @@ int build_topology(mad_mesh& m);
 int rest_tri(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);        // [nt][5]
 int rest_diamond(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);    // [nd][2]
 int rest_shell(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);      // [nt][8]
+int rest_spring(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);     // [ne][2]
 void build_patches(const mad_mesh& m, int target_faces, Patches& p);
 // layout.cpp: (re)build the element order and the scatter structures of a problem
 int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s);
@@ -192,6 +196,7 @@ struct EvalLaunch {
     double qmin;
     const double* normals;  // [nv][3] unit vertex normals (shell-feature terms)
     const float* psi;       // SoA [28][n] network outputs (learned density)
+    const double* vdata;    // [nv][NVD] caller's per-vertex data (vertex terms)
     int hvp;                // matrix-free mode: atomically add H_j v_j to y
     const double* v;
     void* y;
@@ -205,8 +210,10 @@ struct PatchTermArgs {
     const double* rest;
     const uint16_t* lvert;
     const uint16_t* lslot;
+    const uint8_t* lseg;     // segment inside the work unit (vertex-disjoint elements share one)
     const int32_t* elem_ptr;
     const float* psi;        // SoA [28][n] network outputs (learned density)
+    const double* vdata;     // [nv][NVD] caller's per-vertex data (vertex terms)
     double prm[4];
 };
 struct PatchLaunch {
@@ -267,6 +274,7 @@ struct FallbackTerm {
     const int32_t* stencil;  // [n][ns] global vertices, patch order
     const double* rest;
     const float* psi;
+    const double* vdata;
     double prm[4];
 };
 struct FallbackLaunch {

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmad.so")
 
 EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI = 1, 2, 3, 4, 5, 6, 7, 8
+SPRING, INERTIA = 9, 10
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 F64, F32 = 0, 1
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_PATCH = 0, 1, 2
@@ -24,7 +25,7 @@ TUNE_FORCE = 1
 STATUS = {0: "MAD_OK", -1: "MAD_E_INVALID_ARG", -2: "MAD_E_BAD_MESH", -3: "MAD_E_DEGENERATE_REST",
           -4: "MAD_E_OVERFLOW", -5: "MAD_E_OOM", -6: "MAD_E_HIP", -7: "MAD_E_STATE", -8: "MAD_E_UNSUPPORTED"}
 VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3, SHELL_TRI: 3}
-NEEDS_REST = {DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI}
+NEEDS_REST = {DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI, SPRING}
 MLP_HIDDEN, MLP_PARAMS = 64, 4673
 
 
@@ -85,6 +86,7 @@ _SIGS = {
                              C.c_void_p, C.c_void_p], C.c_int32),
     "mad_mlp_destroy": ([C.c_void_p], C.c_int32),
     "mad_problem_add_mlp_term": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_problem_add_vertex_term": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p], C.c_int32),
 }
 
 
@@ -181,6 +183,13 @@ def mad_problem_add_term(prob, kind: int, params=(), rest_pos: np.ndarray | None
     rp = None if rest_pos is None else np.ascontiguousarray(rest_pos, dtype=np.float64)
     _check(lib().mad_problem_add_term(prob, kind, _ptr(prm) if prm.size else None, prm.size, _ptr(rp)),
            "mad_problem_add_term")
+
+
+def mad_problem_add_vertex_term(prob, kind: int, params, vdata):
+    """vdata: device FP64 tensor [n_verts, 4] (m, xhat), read at every evaluation (keep it alive)."""
+    prm = np.ascontiguousarray(params, dtype=np.float64)
+    _check(lib().mad_problem_add_vertex_term(prob, kind, _ptr(prm) if prm.size else None, prm.size, _ptr(vdata)),
+           "mad_problem_add_vertex_term")
 
 
 def mad_problem_finalize(prob, stream=None):
@@ -382,6 +391,10 @@ class Problem:
 
     def add_term(self, kind: int, params=(), rest_pos: np.ndarray | None = None):
         mad_problem_add_term(self.handle, kind, params, rest_pos)
+
+    def add_vertex_term(self, kind: int, params, vdata):
+        mad_problem_add_vertex_term(self.handle, kind, params, vdata)
+        self._vdata = getattr(self, "_vdata", []) + [vdata]   # read at every evaluation
 
     def add_mlp_term(self, net: "Network", rest_pos: np.ndarray):
         mad_problem_add_mlp_term(self.handle, net.handle, rest_pos)

@@ -58,3 +58,22 @@ def shell_energy(tris, rest, x, diamonds, diamond_faces, stvk_prm, bend_prm):
     fs = stvk_energies(tris, rest, x, *stvk_prm)
     fb = bending_energies(tris, rest, x, diamonds, diamond_faces, *bend_prm)
     return math.fsum(fs) + math.fsum(fb), float(np.abs(fs).sum() + np.abs(fb).sum())
+
+
+def cloth_energy(tris, rest, x, vdata, spring_params, inertia_params):
+    """Mass-spring time-step energy (Sec. 7.1): springs over the unique mesh edges plus inertia and
+    gravity per vertex. Returns (total, sum of |element energies|)."""
+    e = np.concatenate([tris[:, [0, 1]], tris[:, [1, 2]], tris[:, [2, 0]]]).astype(np.int64)
+    e.sort(axis=1)
+    nv = rest.shape[0]
+    e = np.unique(e[:, 0] * nv + e[:, 1])
+    i, j = e // nv, e % nv
+    k, w = spring_params
+    l2 = np.sum((rest[i] - rest[j]) ** 2, axis=1)
+    d = x[i] - x[j]
+    q = np.sum(d * d, axis=1) / l2 - 1.0
+    fs = w * 0.5 * k * l2 * q * q
+    wg, gx, gy, gz = inertia_params
+    m, xh = vdata[:, 0], vdata[:, 1:]
+    fv = 0.5 * m * np.sum((x - xh) ** 2, axis=1) - wg * m * (x @ np.array([gx, gy, gz]))
+    return math.fsum(fs) + math.fsum(fv), float(np.sum(np.abs(fs)) + np.sum(np.abs(fv)))
