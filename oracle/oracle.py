@@ -142,6 +142,29 @@ def pattern(nv: int, stencils: list[np.ndarray]) -> tuple[np.ndarray, np.ndarray
     return rowptr, colidx
 
 
+def insert_pairs(rowptr: np.ndarray, colidx: np.ndarray, pairs: np.ndarray, nv: int):
+    """Dynamic sparsity (Sec. 6.3 and the CSR update of the appendix), by its definition: the block
+    pattern after new interaction pairs is the union of the old (row, column) set and, for every pair
+    (a, b) with a != b, the blocks (a, b) and (b, a), stored as CSR with every row sorted. Returns
+    (rowptr, colidx, old_to_new) where old_to_new[j] is the new index of old block j.
+    Reading: pairs naming one vertex twice, repeated pairs and pairs already present add nothing."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colidx = np.asarray(colidx, dtype=np.int64)
+    rows = np.repeat(np.arange(nv, dtype=np.int64), np.diff(rowptr))
+    old = rows * nv + colidx
+    pr = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    if pr.size and (pr.min() < 0 or pr.max() >= nv):
+        raise ValueError("pair names a vertex out of range")
+    pr = pr[pr[:, 0] != pr[:, 1]]
+    new = np.concatenate([pr[:, 0] * nv + pr[:, 1], pr[:, 1] * nv + pr[:, 0]])
+    keys = np.union1d(old, new)                      # sorted, unique
+    r, c = keys // nv, keys % nv
+    rp = np.zeros(nv + 1, dtype=np.int64)
+    np.add.at(rp, r + 1, 1)
+    rp = np.cumsum(rp)
+    return rp.astype(np.int32), c.astype(np.int32), np.searchsorted(keys, old).astype(np.int64)
+
+
 def element(kind: int, xloc, rest=None, params=None, mode: int = ENERGY | GRAD | HESS, spd_eps: float = 0.0,
             aux=None):
     """One element: returns (f, g[k], H[k, k]). aux: the three unit vertex normals of the
