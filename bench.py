@@ -37,8 +37,10 @@ sys.path.insert(0, ROOT)
 # workload (FP32 + FP64 VALU wave instructions x 64 lanes, FMA = 2), and its HBM traffic per launch
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy), from the rocprofv3 counter
 # passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
-FLOPS_PER_ELEM = {"f32": 17936.0, "f64": None}
-TRAFFIC_BYTES = {"f32": 1.056e9, "f64": None}
+FLOPS_PER_ELEM = {"f32": 18202.7, "f64": None}
+TRAFFIC_BYTES = {"f32": 1.0639e9, "f64": None}
+# the same for the 1000^2 cloth step (profiles/k_eval_patch_f32_cloth1000_counters.md)
+CLOTH_TRAFFIC_BYTES = {"f32": 0.5311e9, "f64": None}
 
 # MI355X published peaks used as roofline denominators
 HBM_PEAK_GBS = 8000.0
@@ -65,6 +67,7 @@ def parse():
     ap.add_argument("--no-fp64-plain", action="store_true", help="skip the FP64 GPU comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sizes", action="store_true", help="cloth: skip the Table 1 size sweep")
+    ap.add_argument("--no-hvp", action="store_true", help="shell: skip the matrix-free product timing")
     ap.add_argument("--cpu-elements", type=int, default=300000, help="elements in the oracle timing sample")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
                     help="summarise a rocprofv3 counter-collection CSV under DIR and exit")
@@ -300,11 +303,14 @@ def main():
     layout = prob.layout()
 
     step = lambda: prob.eval(x, mode, out=out, stream=stream)   # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # stage events of the timed evaluations only (the warm-up ran above, unprofiled)
     mad.mad_problem_set_profiling(prob.handle, True)
-    step_ms, wall = time_steps(torch, step, args.steps, args.warmup, stream)
+    step_ms, wall = time_steps(torch, step, args.steps, 0, stream)
     mad.mad_problem_set_profiling(prob.handle, False)
     stage_ms, n_evals = mad.mad_problem_profile(prob.handle)
-    # the profile holds warm-up and timed evaluations alike; stage averages are per evaluation
     ms_per_step = max(wall * 1e3, sum(step_ms)) / args.steps
     nonfinite, fallbacks = prob.status()
 
@@ -337,8 +343,10 @@ def main():
     if args.workload == "cloth":
         # springs are cheap (one 3x3 reduced Hessian each): the fused kernel is held to its HBM stream
         achieved = step_bytes / (dom_ms * 1e-3) / 1e9
+        at_1000 = args.cloth_n == 1000 and layout["scatter"] == mad.SCATTER_PATCH
         roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": dom_ms,
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": CLOTH_TRAFFIC_BYTES.get(args.precision) if at_1000 else None, "kernel_ms": dom_ms,
                     "alg_bytes_per_launch": step_bytes}
     elif fpe:
         achieved = fpe * n_elem / (dom_ms * 1e-3) / 1e12
@@ -388,7 +396,7 @@ def main():
                                "mfma_bf16_peak": 2500.0,
                                "mfma_frac": 3 * useful / (net_ms * 1e-3) / 1e12 / 2500.0}
         res["vs_other_forms"] = other_forms(torch, mad, mesh, inp, args, stream, x, ms_per_step)
-    if args.workload == "shell":
+    if args.workload == "shell" and not args.no_hvp:
         # the matrix-free mode: y = H v with each element's clamped Hessian applied in LDS, no assembly
         v = torch.randn_like(x)
         y = torch.empty_like(out[1])
