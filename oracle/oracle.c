@@ -192,6 +192,45 @@ static hd e_inertia(int k, const double *xloc, const double *rest, const double 
     return acc;
 }
 
+/* Residual terms (Sec. 4.1, Eq. 3). Positional residual of one vertex, the paper's ActiveT<3> example:
+ * r = sqrt(w) (x - x_t), rest = {w, x_t (3)}. */
+static int res_position(int k, const double *xloc, const double *rest, hd *out) {
+    hd3 x = lift3(k, xloc, 0);
+    double sw = sqrt(rest[0]);
+    for (int c = 0; c < 3; ++c) out[c] = hd_scale(hd_addc(x.c[c], -rest[1 + c]), sw);
+    return 3;
+}
+
+/* Edge-length residual (least-squares spring): r = sqrt(k_s) (|x0 - x1| - l), rest = {l}, params {k_s} */
+static int res_edge(int k, const double *xloc, const double *rest, const double *prm, hd *out) {
+    hd3 d = hd3_sub(lift3(k, xloc, 0), lift3(k, xloc, 1));
+    out[0] = hd_scale(hd_addc(hd_sqrt(hd3_dot(d, d)), -rest[0]), sqrt(prm[0]));
+    return 1;
+}
+
+/* residuals of one element with k active variables; returns m (0: not a residual kind) */
+static int res_elem(int kind, int k, const double *prm, const double *rest, const double *xloc, hd *out) {
+    switch (kind) {
+    case OR_RES_POSITION: return res_position(k, xloc, rest, out);
+    case OR_RES_EDGE: return res_edge(k, xloc, rest, prm, out);
+    default: return 0;
+    }
+}
+
+/* a residual term as a scalar term: f = 1/2 sum r_i^2, g = sum r_i grad r_i, and the Gauss-Newton
+ * matrix sum grad r_i grad r_i^T in place of the Hessian */
+static hd gauss_newton(int k, const hd *res, int m) {
+    hd out = hd_const(k, 0.0);
+    for (int i = 0; i < m; ++i) {
+        out.v += 0.5 * res[i].v * res[i].v;
+        for (int a = 0; a < k; ++a) {
+            out.g[a] += res[i].v * res[i].g[a];
+            for (int b = 0; b < k; ++b) out.h[a][b] += res[i].g[a] * res[i].g[b];
+        }
+    }
+    return out;
+}
+
 /* Sec. 7.6: area 0.5 |(x1 - x0) x (x2 - x0)| (Op::FV, k = 9) */
 static hd e_tri_area(int k, const double *xloc) {
     hd3 x0 = lift3(k, xloc, 0), x1 = lift3(k, xloc, 1), x2 = lift3(k, xloc, 2);
@@ -400,8 +439,8 @@ static int e_mlp(int k, const double *xloc, const double *rest, const double *au
 
 static int kind_stencil(int kind) {
     switch (kind) {
-    case OR_INERTIA: return 1;
-    case OR_EDGE_SQLEN: case OR_SPRING: return 2;
+    case OR_INERTIA: case OR_RES_POSITION: return 1;
+    case OR_EDGE_SQLEN: case OR_SPRING: case OR_RES_EDGE: return 2;
     case OR_TRI_AREA: case OR_DIRICHLET: case OR_STVK: case OR_SYMDIR: case OR_MLP: case OR_SHELL_TRI: return 3;
     case OR_BENDING: return 4;
     default: return -1;
@@ -413,7 +452,7 @@ static int kind_vardim(int kind) {
     case OR_DIRICHLET: return 1;
     case OR_SYMDIR: return 2;
     case OR_EDGE_SQLEN: case OR_TRI_AREA: case OR_STVK: case OR_BENDING: case OR_MLP: case OR_SHELL_TRI:
-    case OR_SPRING: case OR_INERTIA: return 3;
+    case OR_SPRING: case OR_INERTIA: case OR_RES_POSITION: case OR_RES_EDGE: return 3;
     default: return -1;
     }
 }
@@ -432,6 +471,12 @@ static int eval_elem(int kind, int k, const double *prm, const double *rest, con
     case OR_SYMDIR: *out = e_symdir(k, xloc, rest); return 0;
     case OR_SPRING: *out = e_spring(k, xloc, rest, prm); return 0;
     case OR_INERTIA: *out = e_inertia(k, xloc, rest, prm); return 0;
+    case OR_RES_POSITION: case OR_RES_EDGE: {
+        hd res[3];
+        int m = res_elem(kind, k, prm, rest, xloc, res);
+        *out = gauss_newton(k, res, m);
+        return 0;
+    }
     default: return -1;
     }
 }
@@ -835,7 +880,8 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
         int rest_stride = (kind[t] == OR_BENDING) ? 2
                           : ((kind[t] == OR_DIRICHLET || kind[t] == OR_STVK || kind[t] == OR_SYMDIR) ? 5 : (shell ? 8 : 0));
         if (kind[t] == OR_SPRING) rest_stride = 1;
-        if (kind[t] == OR_INERTIA) rest_stride = 4;
+        if (kind[t] == OR_INERTIA || kind[t] == OR_RES_POSITION) rest_stride = 4;
+        if (kind[t] == OR_RES_EDGE) rest_stride = 1;
         double *nrm = NULL;
         if (shell) { /* passive unit vertex normals of the current positions, over this term's triangles */
             nrm = malloc(sizeof(double) * (size_t)(3 * nv));
@@ -903,5 +949,80 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
     if (energy) *energy = oracle_neumaier_sum(fi, fvals);
     if (esum_abs) *esum_abs = abs_sum;
     free(fvals);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Residual terms and the global sparse Jacobian (Sec. 4.1 Eq. 3, Sec. 6.1).  */
+/* ------------------------------------------------------------------------- */
+int oracle_kind_nres(int kind) {
+    switch (kind) {
+    case OR_RES_POSITION: return 3;
+    case OR_RES_EDGE: return 1;
+    default: return 0;
+    }
+}
+
+static int res_rest_stride(int kind) { return kind == OR_RES_POSITION ? 4 : (kind == OR_RES_EDGE ? 1 : 0); }
+
+int oracle_residual(int kind, const double *params, const double *rest, const double *xloc, double *r, double *J) {
+    int ss = kind_stencil(kind), vd = kind_vardim(kind), m = oracle_kind_nres(kind);
+    if (ss < 0 || vd < 0 || m == 0) return -1;
+    int k = ss * vd;
+    hd res[3];
+    res_elem(kind, k, params, rest, xloc, res);
+    for (int i = 0; i < m; ++i) {
+        if (r) r[i] = res[i].v;
+        if (J)
+            for (int a = 0; a < k; ++a) J[i * k + a] = res[i].g[a];
+    }
+    return 0;
+}
+
+int oracle_jacobian(int64_t nv, int var_dim, int n_terms, const int *kind, const int64_t *n_elem,
+                    const int32_t *const *stencil, const double *const *rest, const double *const *params,
+                    const double *x, double *r, int32_t *rowptr, int32_t *colidx, double *vals) {
+    const int d = var_dim;
+    int64_t row = 0, nz = 0;
+    rowptr[0] = 0;
+    for (int t = 0; t < n_terms; ++t) {
+        int m = oracle_kind_nres(kind[t]);
+        if (m == 0) continue;
+        int ss = kind_stencil(kind[t]);
+        if (ss < 0 || kind_vardim(kind[t]) != d) return -1;
+        int k = ss * d;
+        for (int64_t e = 0; e < n_elem[t]; ++e) {
+            const int32_t *s = stencil[t] + ss * e;
+            double xloc[KMAX], rr[3], J[3 * KMAX];
+            for (int a = 0; a < ss; ++a) {
+                if (s[a] < 0 || s[a] >= nv) return -1;
+                for (int c = 0; c < d; ++c) xloc[a * d + c] = x[(int64_t)s[a] * d + c];
+            }
+            const double *rs = rest[t] ? rest[t] + res_rest_stride(kind[t]) * e : NULL;
+            if (oracle_residual(kind[t], params[t], rs, xloc, rr, J) != 0) return -1;
+            /* columns of the element: stencil DOFs, ascending global index */
+            int64_t col[KMAX];
+            int loc[KMAX];
+            for (int i = 0; i < k; ++i) {
+                col[i] = (int64_t)s[i / d] * d + i % d;
+                loc[i] = i;
+            }
+            for (int i = 1; i < k; ++i)
+                for (int j = i; j > 0 && col[loc[j - 1]] > col[loc[j]]; --j) {
+                    int tmp = loc[j];
+                    loc[j] = loc[j - 1];
+                    loc[j - 1] = tmp;
+                }
+            for (int i = 0; i < m; ++i) {
+                if (r) r[row] = rr[i];
+                for (int j = 0; j < k; ++j) {
+                    if (colidx) colidx[nz] = (int32_t)col[loc[j]];
+                    if (vals) vals[nz] = J[i * k + loc[j]];
+                    ++nz;
+                }
+                rowptr[++row] = (int32_t)nz;
+            }
+        }
+    }
     return 0;
 }

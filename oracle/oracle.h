@@ -35,7 +35,11 @@ enum {
     OR_MLP = 7,          /* learned per-triangle density A psi(z), VarDim 3, k = 9 */
     OR_SHELL_TRI = 8,    /* analytic per-triangle shell density A W(z), VarDim 3, k = 9 */
     OR_SPRING = 9,       /* Sec. 7.1 mass-spring edge: w k/2 l^2 (|x0 - x1|^2 / l^2 - 1)^2, VarDim 3, k = 6 */
-    OR_INERTIA = 10      /* Sec. 7.1 per-vertex inertia and gravity: m/2 |x - xhat|^2 - w m g.x, VarDim 3, k = 3 */
+    OR_INERTIA = 10,     /* Sec. 7.1 per-vertex inertia and gravity: m/2 |x - xhat|^2 - w m g.x, VarDim 3, k = 3 */
+    /* residual terms (Sec. 4.1, Eq. 3): r_j in R^m; as scalar terms they contribute 1/2 |r_j|^2 with the
+     * Gauss-Newton matrix J_j^T J_j in place of the Hessian */
+    OR_RES_POSITION = 11, /* vertex: r = sqrt(w) (x - x_t), m = 3, rest {w, x_t}, VarDim 3, k = 3 */
+    OR_RES_EDGE = 12      /* edge: r = sqrt(k_s) (|x0 - x1| - l), m = 1, rest {l}, params {k_s}, k = 6 */
 };
 
 /* eval mode bits */
@@ -112,6 +116,19 @@ int oracle_spd_project(int n, const double *A, double eps, double *out);
 
 /* Neumaier compensated sum (the energy reduction of Sec. 5.5) */
 double oracle_neumaier_sum(int64_t n, const double *v);
+
+/* ---- residual terms and the sparse Jacobian (Sec. 4.1 Eq. 3, Sec. 6.1) ---- */
+/* residual count m of a kind (0 for scalar kinds) */
+int oracle_kind_nres(int kind);
+/* one element: residuals r[m] and the local Jacobian J[m][k] (row-major, stencil DOF order) */
+int oracle_residual(int kind, const double *params, const double *rest, const double *xloc, double *r, double *J);
+/* Global residual and Jacobian (Eq. 3): rows in term order, then element order (element e of term t owns
+ * rows roff_t + e m_t ... + m_t - 1); each row's columns are the element's stencil DOFs v*var_dim + c,
+ * ascending. Scalar terms own no rows. r[m_total], rowptr[m_total + 1], colidx / vals [nnz]. Pass
+ * colidx = vals = NULL to get rowptr (and so nnz = rowptr[m_total]) only. */
+int oracle_jacobian(int64_t nv, int var_dim, int n_terms, const int *kind, const int64_t *n_elem,
+                    const int32_t *const *stencil, const double *const *rest, const double *const *params,
+                    const double *x, double *r, int32_t *rowptr, int32_t *colidx, double *vals);
 
 #ifdef __cplusplus
 }

@@ -17,12 +17,14 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI = 1, 2, 3, 4, 5, 6, 7, 8
 SPRING, INERTIA = 9, 10
+RES_POSITION, RES_EDGE = 11, 12
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 
 STENCIL = {EDGE_SQLEN: 2, TRI_AREA: 3, DIRICHLET: 3, STVK: 3, BENDING: 4, SYMDIR: 3, MLP: 3, SHELL_TRI: 3,
-           SPRING: 2, INERTIA: 1}
+           SPRING: 2, INERTIA: 1, RES_POSITION: 1, RES_EDGE: 2}
 VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3, SHELL_TRI: 3,
-          SPRING: 3, INERTIA: 3}
+          SPRING: 3, INERTIA: 3, RES_POSITION: 3, RES_EDGE: 3}
+NRES = {RES_POSITION: 3, RES_EDGE: 1}   # residuals per element of the residual kinds
 
 
 def build(force: bool = False) -> str:
@@ -140,6 +142,20 @@ def pattern(nv: int, stencils: list[np.ndarray]) -> tuple[np.ndarray, np.ndarray
     _check(lib().oracle_pattern(C.c_int64(nv), C.c_int(n), ne, ss, ptrs, _p(rowptr), _p(colidx), C.byref(nnzb)),
            "pattern")
     return rowptr, colidx
+
+
+def residual(kind: int, xloc, rest, params=(1.0,)):
+    """One element of a residual kind: (r[m], J[m, k]) in stencil DOF order (Eq. 3's r_j and J_j)."""
+    m = NRES[kind]
+    k = STENCIL[kind] * VARDIM[kind]
+    xl = np.ascontiguousarray(xloc, dtype=np.float64).ravel()
+    rs = np.ascontiguousarray(rest, dtype=np.float64).ravel()
+    pr = np.zeros(4)
+    pr[:len(params)] = params
+    r = np.zeros(m)
+    J = np.zeros((m, k))
+    _check(lib().oracle_residual(C.c_int(kind), _p(pr), _p(rs), _p(xl), _p(r), _p(J)), "residual")
+    return r, J
 
 
 def insert_pairs(rowptr: np.ndarray, colidx: np.ndarray, pairs: np.ndarray, nv: int):
@@ -353,12 +369,12 @@ class Problem:
             raise ValueError("term VarDim does not match the problem")
         prm = np.zeros(max(4, len(params)))
         prm[:len(params)] = params
-        if kind == SPRING:
+        if kind in (SPRING, RES_EDGE):
             st = self.topo.edges
             rs = np.linalg.norm(self.rest_pos[st[:, 0]] - self.rest_pos[st[:, 1]], axis=1)[:, None]
-        elif kind == INERTIA:
+        elif kind in (INERTIA, RES_POSITION):
             if vertex_data is None:
-                raise ValueError("INERTIA needs vertex_data [nv, 4]")
+                raise ValueError("vertex terms need vertex_data [nv, 4]")
             st = np.arange(self.nv, dtype=np.int32)[:, None]
             rs = np.ascontiguousarray(vertex_data, dtype=np.float64).reshape(self.nv, 4)
         elif kind in (SHELL_TRI, MLP):
@@ -410,6 +426,27 @@ class Problem:
                                  C.c_int(mode), C.c_double(spd_eps), _p(mask), _p(self.rowptr), _p(self.colidx),
                                  C.byref(e), C.byref(ea), _p(grad), _p(gscale), _p(hess), _p(hscale)), "eval")
         return Result(e.value, ea.value, grad, gscale, hess, hscale)
+
+    def jacobian(self, x: np.ndarray):
+        """Residual vector and sparse Jacobian of the residual terms (Eq. 3), CSR with scalar entries:
+        (r, rowptr, colidx, vals); rows by term, then element; columns ascending DOF indices."""
+        x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+        n = len(self.terms)
+        kinds = (C.c_int * n)(*[t.kind for t in self.terms])
+        ne = (C.c_int64 * n)(*[t.stencil.shape[0] for t in self.terms])
+        st = (C.c_void_p * n)(*[t.stencil.ctypes.data for t in self.terms])
+        rs = (C.c_void_p * n)(*[(t.rest.ctypes.data if t.rest is not None else None) for t in self.terms])
+        pr = (C.c_void_p * n)(*[t.params.ctypes.data for t in self.terms])
+        m = sum(NRES.get(t.kind, 0) * t.stencil.shape[0] for t in self.terms)
+        rowptr = np.zeros(m + 1, np.int32)
+        args = (C.c_int64(self.nv), C.c_int(self.d), C.c_int(n), kinds, ne, st, rs, pr, _p(x))
+        _check(lib().oracle_jacobian(*args, None, _p(rowptr), None, None), "jacobian")
+        nnz = int(rowptr[-1])
+        r = np.zeros(m)
+        colidx = np.zeros(nnz, np.int32)
+        vals = np.zeros(nnz)
+        _check(lib().oracle_jacobian(*args, _p(r), _p(rowptr), _p(colidx), _p(vals)), "jacobian")
+        return r, rowptr, colidx, vals
 
     def hvp(self, x: np.ndarray, v: np.ndarray, spd: bool = False, spd_eps: float = 0.0):
         """Hessian-vector product by its definition: the assembled Hessian (clamped per element when

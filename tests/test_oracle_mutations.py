@@ -12,6 +12,7 @@ import tests.test_oracle_elements as TE
 import tests.test_oracle_assembly as TA
 import tests.test_oracle_shell as TS
 import tests.test_oracle_cloth as TC
+import tests.test_oracle_residual as TR
 
 MUTANTS = {
     "product_rule_drops_cross_term": ("+ a.g[i] * b.g[j] + b.g[i] * a.g[j];", "+ a.g[i] * b.g[j];"),
@@ -60,7 +61,11 @@ MUTANTS = {
     "inertia_gravity_wrong_sign": ("acc = hd_add(acc, hd_scale(x.c[c], -prm[0] * m * prm[1 + c]));",
                                    "acc = hd_add(acc, hd_scale(x.c[c], prm[0] * m * prm[1 + c]));"),
     "inertia_drops_half": ("acc = hd_add(acc, hd_scale(hd_sq(dc), 0.5 * m));", "acc = hd_add(acc, hd_scale(hd_sq(dc), m));"),
-    "inertia_rest_stride_wrong": ("if (kind[t] == OR_INERTIA) rest_stride = 4;", "if (kind[t] == OR_INERTIA) rest_stride = 3;"),
+    "inertia_rest_stride_wrong": ("if (kind[t] == OR_INERTIA || kind[t] == OR_RES_POSITION) rest_stride = 4;",
+                                  "if (kind[t] == OR_INERTIA || kind[t] == OR_RES_POSITION) rest_stride = 3;"),
+    "res_edge_weight_not_sqrt": ("out[0] = hd_scale(hd_addc(hd_sqrt(hd3_dot(d, d)), -rest[0]), sqrt(prm[0]));",
+                                 "out[0] = hd_scale(hd_addc(hd_sqrt(hd3_dot(d, d)), -rest[0]), prm[0]);"),
+    "gauss_newton_drops_half": ("out.v += 0.5 * res[i].v * res[i].v;", "out.v += res[i].v * res[i].v;"),
 }
 
 PINS = [TE.test_edge_sqlen_closed_form, TE.test_area_gradient_matches_paper_closed_form,
@@ -83,7 +88,10 @@ PINS = [TE.test_edge_sqlen_closed_form, TE.test_area_gradient_matches_paper_clos
         TS.test_one_neuron_network_closed_form, TS.test_network_derivatives_fd_and_reverse_mode_agree,
         TS.test_mlp_element_is_area_times_network_of_features, TS.test_shell_density_closed_form_gradient_by_fd,
         lambda: TC.test_spring_matches_closed_form(0.95), TC.test_inertia_matches_closed_form,
-        lambda: TC.test_cloth_step_assembly_matches_dense_closed_form(True, 0.0)]
+        lambda: TC.test_cloth_step_assembly_matches_dense_closed_form(True, 0.0),
+        TR.test_position_residual_closed_form, TR.test_edge_residual_closed_form_and_fd,
+        lambda: TR.test_residual_kind_as_scalar_term_is_gauss_newton(O.RES_EDGE),
+        TR.test_assembled_jacobian_is_the_stacked_local_jacobians]
 
 
 def run_pins():
