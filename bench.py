@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sizes", action="store_true", help="cloth: skip the Table 1 size sweep")
     ap.add_argument("--no-hvp", action="store_true", help="shell: skip the matrix-free product timing")
+    ap.add_argument("--no-dynamic", action="store_true", help="shell: skip the pair-insertion timing")
+    ap.add_argument("--pairs", type=int, default=100000, help="interaction pairs inserted by the dynamic timing")
     ap.add_argument("--cpu-elements", type=int, default=300000, help="elements in the oracle timing sample")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
                     help="summarise a rocprofv3 counter-collection CSV under DIR and exit")
@@ -408,6 +410,8 @@ def main():
         hv = max(hv_wall * 1e3, sum(hv_ms)) / len(hv_ms)
         res["hvp"] = {"ms_per_product": hv, "elements_per_s": n_elem / (hv * 1e-3),
                       "note": "clamped Hessian-vector product, matrix-free (no assembly)"}
+    if args.workload == "shell" and not args.no_dynamic:
+        res["dynamic_sparsity"] = dynamic_sparsity(torch, mad, mesh, inp, prec, args, stream, x)
     if args.workload == "batched":
         res["one_launch_per_mesh"] = per_mesh_baseline(torch, mad, inp, prec, stream, ms_per_step, args)
     if args.workload == "cloth" and not args.no_sizes:
@@ -475,6 +479,33 @@ def cpu_baseline_cloth(inp, budget):
     return {"value": n_el / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
             "sample": f"first {rows} of {n} grid rows of the same cloth: {n_el} elements (springs + vertices), "
                       f"energy + gradient + filtered Hessian + assembly, FP64, one thread, {dt:.1f} s"}
+
+
+def dynamic_sparsity(torch, mad, mesh, inp, prec, args, stream, x):
+    """Sec. 6.3: insert random interaction pairs into the pattern of a fresh problem (GPU update into the
+    second pattern buffer, wall clock including its final synchronisation), then time evaluations on the
+    grown pattern."""
+    import numpy as np
+    p = mad.Problem(mesh, 3, prec, patch_faces=args.patch_faces)
+    for k, prm in SHELL_TERMS:
+        p.add_term(k, prm, inp.rest)
+    p.reserve_pairs(args.pairs)
+    p.finalize(stream)
+    nnzb0 = p.nnzb
+    pairs = torch.from_numpy(np.ascontiguousarray(
+        np.random.default_rng(7001).integers(0, mesh.n_verts, size=(args.pairs, 2)), dtype=np.int32)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    added = p.insert_pairs(pairs, stream)
+    ms_insert = (time.perf_counter() - t0) * 1e3
+    o = p.outputs()
+    mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
+    step_ms, wall = time_steps(torch, lambda: p.eval(x, mode, out=o, stream=stream), max(5, args.steps // 5), 2,
+                               stream)
+    res = {"pairs": args.pairs, "blocks_before": nnzb0, "blocks_added": added, "ms_insert": ms_insert,
+           "ms_per_step_after": max(wall * 1e3, sum(step_ms)) / len(step_ms)}
+    del p, o
+    return res
 
 
 def other_forms(torch, mad, mesh, inp, args, stream, x, ms_mlp):

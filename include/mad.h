@@ -50,7 +50,8 @@ typedef enum mad_status {
     MAD_E_OOM = -5,             /* device or host allocation failed */
     MAD_E_HIP = -6,             /* a HIP runtime call or kernel launch failed */
     MAD_E_STATE = -7,           /* call out of order (e.g. eval before finalize) */
-    MAD_E_UNSUPPORTED = -8      /* kind/var_dim/precision combination not provided */
+    MAD_E_UNSUPPORTED = -8,     /* kind/var_dim/precision combination not provided */
+    MAD_E_CAPACITY = -9         /* a pattern update would exceed the reserved room */
 } mad_status;
 
 /* Term catalogue. Stencil, VarDim and the params block of each kind:
@@ -82,6 +83,16 @@ typedef enum mad_status {
  *  MAD_INERTIA     vertex (1 vertex), VarDim 3: (m/2) |x - xhat|^2 - w m g.x, params = {w, g_x,
  *                  g_y, g_z}. Per-vertex m and xhat come from a caller-owned device array read at
  *                  every evaluation; added with mad_problem_add_vertex_term.
+ * Residual terms (Sec. 4.1, Eq. 3): each element returns a small residual vector r_j; the residuals
+ * and the sparse Jacobian are read with mad_problem_jacobian. In mad_problem_eval / _hvp they act as
+ * the scalar 1/2 |r_j|^2 whose gradient is J_j^T r_j and whose Hessian slot receives the Gauss-Newton
+ * matrix J_j^T J_j (so the assembled "Hessian" of a residual-only problem is J^T J).
+ *  MAD_RES_POSITION vertex, VarDim 3, 3 residuals: sqrt(w) (x - x_t), the paper's ActiveT<3>
+ *                  positional constraint; per-vertex {w, x_t} (w >= 0; w = 0 leaves a vertex free)
+ *                  from a caller-owned device array [n_verts][4]; added with
+ *                  mad_problem_add_vertex_term. params unused.
+ *  MAD_RES_EDGE    edge, VarDim 3, 1 residual: sqrt(k) (|x0 - x1| - l), l the rest length (a
+ *                  least-squares spring). params = {k}. Needs rest positions.
  */
 typedef enum mad_term_kind {
     MAD_EDGE_SQLEN = 1,
@@ -93,7 +104,9 @@ typedef enum mad_term_kind {
     MAD_MLP = 7,
     MAD_SHELL_TRI = 8,
     MAD_SPRING = 9,
-    MAD_INERTIA = 10
+    MAD_INERTIA = 10,
+    MAD_RES_POSITION = 11,
+    MAD_RES_EDGE = 12
 } mad_term_kind;
 
 /* evaluation mode bits (Sec. 6.2: passive, gradient-only, full Hessian; Sec. 7.1 filtering) */
@@ -167,18 +180,59 @@ int32_t mad_problem_create(const mad_mesh *mesh, int32_t var_dim, int32_t precis
 int32_t mad_problem_add_term(mad_problem *prob, int32_t kind, const double *params_host, int32_t n_params,
                              const double *rest_pos_host);
 
-/* Add a per-vertex term (Sec. 7.1, the per-vertex energies of the mass-spring example): one
- * element per mesh vertex. kind: MAD_INERTIA. vdata_dev: device FP64 [n_verts][4] = {m, xhat_x,
- * xhat_y, xhat_z} per vertex, on the problem's device, owned by the caller; it is read (not
- * copied) at every evaluation, so it must stay valid while the problem is evaluated, and the
- * caller may rewrite it between evaluations (e.g. xhat = x^n + h v^n every time step). Every
- * vertex must lie on a triangle (MAD_E_UNSUPPORTED otherwise). */
+/* Add a per-vertex term (Sec. 7.1, the per-vertex energies of the mass-spring example; Sec. 4.2,
+ * the positional residual): one element per mesh vertex. kind: MAD_INERTIA (vdata_dev: {m, xhat_x,
+ * xhat_y, xhat_z} per vertex) or MAD_RES_POSITION ({w, x_t}). vdata_dev: device FP64 [n_verts][4], on
+ * the problem's device, owned by the caller; it is read (not copied) at every evaluation, so it must
+ * stay valid while the problem is evaluated, and the caller may rewrite it between evaluations (e.g.
+ * xhat = x^n + h v^n every time step). Every vertex must lie on a triangle (MAD_E_UNSUPPORTED
+ * otherwise). */
 int32_t mad_problem_add_vertex_term(mad_problem *prob, int32_t kind, const double *params_host, int32_t n_params,
                                     const double *vdata_dev);
 
 /* Build patches, upload element data and build the block pattern on the GPU (Sec. 6.1), once.
  * Starts with the layout of the options (persistent launch off). Synchronises the stream. */
 int32_t mad_problem_finalize(mad_problem *prob, void *stream);
+
+/* Dynamic sparsity (Sec. 6.3): before mad_problem_finalize, reserve room for interaction pairs. The
+ * pattern is then kept in two device buffers (double buffering: an insertion writes the inactive one and
+ * makes it active), each with capacity for the initial blocks plus 2 * max_pairs; one insertion call takes
+ * at most max_pairs pairs. No allocation happens at insertion time. max_pairs >= 0; 0 turns it off. */
+int32_t mad_problem_reserve_pairs(mad_problem *prob, int64_t max_pairs);
+
+/* Insert the blocks of new interaction pairs into the Hessian pattern, on the GPU (Sec. 6.3 and the CSR
+ * update of the appendix). pairs_dev: device int32 [n_pairs][2] vertex pairs. A pair (a, b), a != b, adds
+ * the blocks (a, b) and (b, a); a pair naming one vertex twice, a repeated pair or one already in the
+ * pattern adds nothing. Rows stay sorted, so the new pattern is unique whatever the order of the pairs.
+ * Blocks are renumbered (a block's index may change, its row and column do not; the library follows its
+ * own references): re-read the pattern and size hess buffers for the new nnzb (mad_problem_pattern_info)
+ * before the next evaluation, which writes zeros into blocks no term touches. *n_added (host, may be
+ * NULL): blocks added. Synchronises the stream (the new block count is read back).
+ * Errors: MAD_E_STATE before finalize or without a reserve; MAD_E_INVALID_ARG if n_pairs exceeds the
+ * reserved max_pairs or a pair names a vertex out of range; MAD_E_CAPACITY if the pattern would outgrow
+ * the reserve. On an error the pattern is unchanged. */
+int32_t mad_problem_insert_pairs(mad_problem *prob, const int32_t *pairs_dev, int64_t n_pairs, int64_t *n_added,
+                                 void *stream);
+
+/* Residual terms and the sparse Jacobian (Sec. 4.1 Eq. 3, Sec. 6.1). The global residual stacks the
+ * residual terms in the order they were added, each term's elements in their original order (element e
+ * of a term with m_t residuals owns rows row_off_t + e m_t ... + m_t - 1: the row ownership P_j of
+ * Eq. 3); scalar terms own no rows. Each row holds the element's stencil DOFs v * var_dim + c in
+ * ascending order (scalar entries: the Jacobian is m x n_verts * var_dim).
+ * mad_problem_jacobian_info: *m rows and *nnz entries. MAD_E_STATE before finalize or without residual
+ * terms; MAD_E_OVERFLOW beyond int32 indexing. */
+int32_t mad_problem_jacobian_info(const mad_problem *prob, int64_t *m, int64_t *nnz);
+
+/* The Jacobian's CSR pattern into rowptr_dev [m + 1] and colidx_dev [nnz] (device int32). Fixed by the
+ * stencils: computed once, valid for every evaluation. Synchronises the stream. */
+int32_t mad_problem_copy_jacobian_pattern(const mad_problem *prob, int32_t *rowptr_dev, int32_t *colidx_dev,
+                                          void *stream);
+
+/* Evaluate the residuals r_dev [m] (FP64) and the Jacobian values vals_dev [nnz] (FP32 for MAD_F32, FP64
+ * for MAD_F64) at x_dev [n_verts * var_dim], in the pattern above. Every entry is written by the element
+ * that owns its row (no atomics); non-finite values raise the flag mad_problem_status reports.
+ * Asynchronous on stream. J^T J and J^T r are what mad_problem_eval assembles for residual terms. */
+int32_t mad_problem_jacobian(mad_problem *prob, const double *x_dev, double *r_dev, void *vals_dev, void *stream);
 
 /* Pattern sizes: block rows (= n_verts), nnzb blocks, block_dim (= var_dim). */
 int32_t mad_problem_pattern_info(const mad_problem *prob, int64_t *n_block_rows, int64_t *nnzb,

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libmad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["kernels_patch.hip", "kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "host_patch.cpp",
-           "kernels_mlp.hip", "layout.cpp", "eval.cpp", "autotune.cpp", "mlp.cpp", "api.cpp"]
+           "kernels_mlp.hip", "kernels_jac.hip", "layout.cpp", "eval.cpp", "autotune.cpp", "mlp.cpp", "api.cpp"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 (v_pk_*_f32) instructions.
 # -munsafe-fp-atomics: hardware FP32/FP64 atomic add instead of compare-and-swap loops.
@@ -30,7 +30,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp-at
 # (x * 0 -> 0 and x + 0 -> x need no-NaN/no-Inf and no-signed-zero assumptions). Their finiteness
 # checks read exponent bits (kernels_common.hpp). No reassociation: sums keep their order.
 ELEMENT_FLAGS = ["-fno-signed-zeros", "-ffinite-math-only"]
-EXTRA = {"kernels_patch.hip": ELEMENT_FLAGS, "kernels_eval.hip": ELEMENT_FLAGS}
+EXTRA = {"kernels_patch.hip": ELEMENT_FLAGS, "kernels_eval.hip": ELEMENT_FLAGS, "kernels_jac.hip": ELEMENT_FLAGS}
 
 
 def build(verbose: bool = False, jobs: int = 6) -> str:

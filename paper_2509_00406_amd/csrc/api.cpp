@@ -202,7 +202,12 @@ static int32_t add_term(mad_problem* p, int32_t kind, const double* params, int3
         t.stencil = m.edges;
         rc = rest_spring(m, rest_pos, t.rest);
         break;
-    case MAD_INERTIA:
+    case MAD_RES_EDGE:
+        t.n = m.ne();
+        t.stencil = m.edges;
+        rc = rest_edge_length(m, rest_pos, t.rest);
+        break;
+    case MAD_INERTIA: case MAD_RES_POSITION:
         for (int64_t v = 0; v < m.nv; ++v)
             if (m.vert_face0[v] < 0) return fail(MAD_E_UNSUPPORTED, "vertex " + std::to_string(v) + " lies on no triangle");
         t.n = m.nv;
@@ -220,14 +225,15 @@ static int32_t add_term(mad_problem* p, int32_t kind, const double* params, int3
 int32_t mad_problem_add_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params,
                              const double* rest_pos) {
     if (kind == MAD_MLP) return fail(MAD_E_INVALID_ARG, "learned-density terms are added with mad_problem_add_mlp_term");
-    if (kind == MAD_INERTIA) return fail(MAD_E_INVALID_ARG, "vertex terms are added with mad_problem_add_vertex_term");
+    if (kind == MAD_INERTIA || kind == MAD_RES_POSITION)
+        return fail(MAD_E_INVALID_ARG, "vertex terms are added with mad_problem_add_vertex_term");
     return add_term(p, kind, params, n_params, rest_pos, nullptr);
 }
 
 int32_t mad_problem_add_vertex_term(mad_problem* p, int32_t kind, const double* params, int32_t n_params,
                                     const double* vdata) {
     if (!p || !vdata) return fail(MAD_E_INVALID_ARG, "NULL argument");
-    if (kind != MAD_INERTIA) return fail(MAD_E_INVALID_ARG, "not a vertex term kind");
+    if (kind != MAD_INERTIA && kind != MAD_RES_POSITION) return fail(MAD_E_INVALID_ARG, "not a vertex term kind");
     hipPointerAttribute_t at{};
     if (hipPointerGetAttributes(&at, vdata) != hipSuccess || at.type != hipMemoryTypeDevice)
         return fail(MAD_E_INVALID_ARG, "vdata must be device memory");
@@ -243,6 +249,69 @@ int32_t mad_problem_add_mlp_term(mad_problem* p, const mad_mlp* mlp, const doubl
     MAD_HIP_TRY(hipGetDevice(&dev));
     if (dev != mlp->device) return fail(MAD_E_INVALID_ARG, "the network lives on another device");
     return add_term(p, MAD_MLP, nullptr, 0, rest_pos, mlp);
+}
+
+// Two pattern buffers with room for the reserved pairs' blocks, the first holding the built pattern, and
+// the scratch of the update (no allocation later, at insertion time).
+static int alloc_dynamic(mad_problem* p, hipStream_t s) {
+    const int64_t nv = p->mesh->nv;
+    const int64_t cap = p->nnzb + 2 * p->pair_reserve;
+    if (cap > INT32_MAX) return fail(MAD_E_OVERFLOW, "reserved block count exceeds int32");
+    p->nnzb_cap = cap;
+    auto dev = [&](void** q, size_t bytes) -> int {
+        if (hipMalloc(q, std::max<size_t>(bytes, 16)) != hipSuccess) return fail(MAD_E_OOM, "pattern reserve");
+        p->owned.push_back(*q);
+        return MAD_OK;
+    };
+    int32_t* colidx_a = nullptr;
+    int rc;
+    if ((rc = dev((void**)&colidx_a, sizeof(int32_t) * cap)) != MAD_OK) return rc;
+    MAD_HIP_TRY(hipMemcpyAsync(colidx_a, p->d_colidx, sizeof(int32_t) * p->nnzb, hipMemcpyDeviceToDevice, s));
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    for (auto it = p->owned.begin(); it != p->owned.end(); ++it)
+        if (*it == (void*)p->d_colidx) {
+            (void)hipFree(*it);
+            p->owned.erase(it);
+            break;
+        }
+    p->d_colidx = colidx_a;
+    DynBuffers& B = p->dyn;
+    const int64_t nb = (std::max<int64_t>(nv, 1) + 2047) / 2048 + 4;
+    if ((rc = dev((void**)&p->d_rowptr_b, sizeof(int32_t) * (nv + 1))) != MAD_OK ||
+        (rc = dev((void**)&p->d_colidx_b, sizeof(int32_t) * cap)) != MAD_OK ||
+        (rc = dev((void**)&p->d_extra_blocks, sizeof(int32_t) * 2 * p->pair_reserve)) != MAD_OK ||
+        (rc = dev((void**)&B.cnt, sizeof(int32_t) * (nv + 1))) != MAD_OK ||
+        (rc = dev((void**)&B.fill, sizeof(int32_t) * (nv + 1))) != MAD_OK ||
+        (rc = dev((void**)&B.coff, sizeof(int32_t) * (nv + 1))) != MAD_OK ||
+        (rc = dev((void**)&B.stage, sizeof(int32_t) * 2 * p->pair_reserve)) != MAD_OK ||
+        (rc = dev((void**)&B.nnew, sizeof(int32_t) * (nv + 1))) != MAD_OK ||
+        (rc = dev((void**)&B.rowcnt, sizeof(int32_t) * (nv + 1))) != MAD_OK ||
+        (rc = dev((void**)&B.noff, sizeof(int32_t) * (nv + 1))) != MAD_OK ||
+        (rc = dev((void**)&B.map, sizeof(int32_t) * cap)) != MAD_OK ||
+        (rc = dev((void**)&B.flags, sizeof(int32_t) * 4)) != MAD_OK ||
+        (rc = dev((void**)&B.rp64, sizeof(int64_t) * (nv + 1))) != MAD_OK ||
+        (rc = dev((void**)&B.scan_tmp, sizeof(int64_t) * (nb + 1))) != MAD_OK)
+        return rc;
+    return MAD_OK;
+}
+
+int32_t mad_problem_reserve_pairs(mad_problem* p, int64_t max_pairs) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (p->finalized) return fail(MAD_E_STATE, "reserve before finalize");
+    if (max_pairs < 0 || max_pairs > INT32_MAX / 4) return fail(MAD_E_INVALID_ARG, "max_pairs out of range");
+    p->pair_reserve = max_pairs;
+    return MAD_OK;
+}
+
+int32_t mad_problem_insert_pairs(mad_problem* p, const int32_t* pairs, int64_t n_pairs, int64_t* n_added,
+                                 void* stream) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (!p->finalized) return fail(MAD_E_STATE, "insert before finalize");
+    if (p->pair_reserve == 0) return fail(MAD_E_STATE, "no pair reserve (mad_problem_reserve_pairs)");
+    if (n_pairs < 0 || n_pairs > p->pair_reserve) return fail(MAD_E_INVALID_ARG, "n_pairs exceeds the reserve");
+    if (n_pairs > 0 && !pairs) return fail(MAD_E_INVALID_ARG, "pairs is NULL");
+    if (n_added) *n_added = 0;
+    return insert_pairs_device(p, pairs, n_pairs, n_added, (hipStream_t)stream);
 }
 
 int32_t mad_problem_finalize(mad_problem* p, void* stream) {
@@ -293,12 +362,81 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
     MAD_HIP_TRY(hipMemcpyAsync(p->h_colidx.data(), p->d_colidx, (size_t)p->nnzb * 4, hipMemcpyDeviceToHost, s));
     MAD_HIP_TRY(hipStreamSynchronize(s));
     p->h_colidx.resize((size_t)p->nnzb);
+    if (p->pair_reserve > 0 && (rc = alloc_dynamic(p, s)) != MAD_OK) return rc;
     if ((rc = build_scatter(p, s)) != MAD_OK) return rc;
     int32_t hflags[4];
     MAD_HIP_TRY(hipMemcpyAsync(hflags, p->d_flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
     MAD_HIP_TRY(hipStreamSynchronize(s));
     if (hflags[1] != 0) return fail(MAD_E_HIP, "internal error: element block missing from the pattern");
     p->finalized = true;
+    return MAD_OK;
+}
+
+// residual terms: the launch description and the global sizes (rows by term, then element)
+static int jac_launch(const mad_problem* p, JacLaunch& L, int64_t* m_out, int64_t* nnz_out) {
+    L = JacLaunch{};
+    L.prec = p->prec;
+    int64_t m = 0, nnz = 0;
+    for (const auto& t : p->terms) {
+        const int nr = kind_nres(t.kind);
+        if (nr == 0) continue;
+        JacTerm& J = L.terms[L.n_terms++];
+        J.kind = t.kind;
+        J.n = t.n;
+        J.stencil = t.d_stencil;
+        J.perm = t.d_perm;
+        J.rest = t.d_rest;
+        J.vdata = t.vdata;
+        std::memcpy(J.prm, t.prm, sizeof(t.prm));
+        J.row_off = m;
+        J.nz_off = nnz;
+        m += t.n * nr;
+        nnz += t.n * nr * t.ns * t.d;
+    }
+    if (m == 0) return fail(MAD_E_STATE, "the problem has no residual terms");
+    if (nnz > INT32_MAX || m > INT32_MAX) return fail(MAD_E_OVERFLOW, "Jacobian exceeds int32 indexing");
+    L.flags = p->d_flags;
+    *m_out = m;
+    *nnz_out = nnz;
+    return MAD_OK;
+}
+
+int32_t mad_problem_jacobian_info(const mad_problem* p, int64_t* m, int64_t* nnz) {
+    if (!p || !m || !nnz) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
+    JacLaunch L;
+    return jac_launch(p, L, m, nnz);
+}
+
+int32_t mad_problem_copy_jacobian_pattern(const mad_problem* p, int32_t* rowptr, int32_t* colidx, void* stream) {
+    if (!p || !rowptr || !colidx) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
+    JacLaunch L;
+    int64_t m = 0, nnz = 0;
+    int rc = jac_launch(p, L, &m, &nnz);
+    if (rc != MAD_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    L.pattern = 1;
+    L.rowptr = rowptr;
+    L.colidx = colidx;
+    MAD_HIP_TRY(launch_jacobian(L, s));
+    const int32_t last = (int32_t)nnz;
+    MAD_HIP_TRY(hipMemcpyAsync(rowptr + m, &last, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    return MAD_OK;
+}
+
+int32_t mad_problem_jacobian(mad_problem* p, const double* x, double* r, void* vals, void* stream) {
+    if (!p || !x || !r || !vals) return fail(MAD_E_INVALID_ARG, "NULL argument");
+    if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
+    JacLaunch L;
+    int64_t m = 0, nnz = 0;
+    int rc = jac_launch(p, L, &m, &nnz);
+    if (rc != MAD_OK) return rc;
+    L.x = x;
+    L.r = r;
+    L.vals = vals;
+    MAD_HIP_TRY(launch_jacobian(L, (hipStream_t)stream));
     return MAD_OK;
 }
 

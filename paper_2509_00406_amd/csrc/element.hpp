@@ -290,10 +290,35 @@ __device__ __forceinline__ void element_derivs(const double* xs, const double* r
         for (int i = 0; i < KR; ++i) r[i] = xs[i];
     }
     using S = typename std::conditional<MODE == 1, D1<KR, T>, HD<KR, T>>::type;
-    S rs[KR];
+    S f;
+    if constexpr (Term::NRES > 0) {
+        // residual term (Eq. 3): first-order duals give r and J; the scalar form is 1/2 |r|^2 with
+        // gradient J^T r and the Gauss-Newton matrix J^T J in place of the Hessian
+        using S1 = D1<KR, T>;
+        S1 q[KR], res[Term::NRES];
 #pragma unroll
-    for (int i = 0; i < KR; ++i) rs[i] = var<S>(i, r[i]);
-    const S f = Term::template energy<S>(rs, rest, prm);
+        for (int i = 0; i < KR; ++i) q[i] = var<S1>(i, r[i]);
+        Term::template residual<S1>(q, rest, prm, res);
+        f = cst<S>(0.0);
+#pragma unroll
+        for (int m = 0; m < Term::NRES; ++m) {
+            f.v += 0.5 * res[m].v * res[m].v;
+            const T rv = T(res[m].v);
+#pragma unroll
+            for (int i = 0; i < KR; ++i) f.g[i] += rv * res[m].g[i];
+            if constexpr (MODE >= 2) {
+#pragma unroll
+                for (int i = 0; i < KR; ++i)
+#pragma unroll
+                    for (int j = i; j < KR; ++j) f.h[Packed<KR>::at(i, j)] += res[m].g[i] * res[m].g[j];
+            }
+        }
+    } else {
+        S rs[KR];
+#pragma unroll
+        for (int i = 0; i < KR; ++i) rs[i] = var<S>(i, r[i]);
+        f = Term::template energy<S>(rs, rest, prm);
+    }
     out.f = f.v;
     if constexpr (!Term::TI) {
         // active variables are the stencil DOFs: no map back, no Helmert reduction

@@ -151,6 +151,8 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         G.n_orphan_vert = p->n_orphan_vert;
         G.n_orphan_block = p->n_orphan_block;
         MAD_HIP_TRY(launch_gather(G, s));
+        if ((mode & MAD_HESS) && p->n_extra > 0)   // blocks of inserted pairs that no term touches
+            MAD_HIP_TRY(launch_zero_blocks(hess, p->d_extra_blocks, p->n_extra, d * d, (int)eb, s));
         if (hvp) {   // the product's shared entries, through the same gather lists
             G.want_grad = 1;
             G.want_hess = 0;

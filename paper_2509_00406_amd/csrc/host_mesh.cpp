@@ -13,8 +13,8 @@ namespace mad {
 
 int kind_stencil(int kind) {
     switch (kind) {
-    case MAD_INERTIA: return 1;
-    case MAD_EDGE_SQLEN: case MAD_SPRING: return 2;
+    case MAD_INERTIA: case MAD_RES_POSITION: return 1;
+    case MAD_EDGE_SQLEN: case MAD_SPRING: case MAD_RES_EDGE: return 2;
     case MAD_TRI_AREA: case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: case MAD_MLP: case MAD_SHELL_TRI: return 3;
     case MAD_BENDING: return 4;
     default: return -1;
@@ -25,14 +25,22 @@ int kind_vardim(int kind) {
     case MAD_DIRICHLET: return 1;
     case MAD_SYMDIR: return 2;
     case MAD_EDGE_SQLEN: case MAD_TRI_AREA: case MAD_STVK: case MAD_BENDING: case MAD_MLP: case MAD_SHELL_TRI:
-    case MAD_SPRING: case MAD_INERTIA: return 3;
+    case MAD_SPRING: case MAD_INERTIA: case MAD_RES_POSITION: case MAD_RES_EDGE: return 3;
     default: return -1;
+    }
+}
+int kind_nres(int kind) {
+    switch (kind) {
+    case MAD_RES_POSITION: return 3;
+    case MAD_RES_EDGE: return 1;
+    default: return 0;
     }
 }
 int kind_nrest(int kind) {
     switch (kind) {
     case MAD_DIRICHLET: case MAD_STVK: case MAD_SYMDIR: return 5;
     case MAD_BENDING: case MAD_SPRING: return 2;
+    case MAD_RES_EDGE: return 1;
     case MAD_MLP: case MAD_SHELL_TRI: return 8;
     default: return 0;
     }
@@ -231,6 +239,17 @@ int rest_spring(const mad_mesh& m, const double* X, std::vector<double>& out) {
         out[2 * e] = l2;
         out[2 * e + 1] = 1.0 / l2;
     }
+    return MAD_OK;
+}
+
+// Edge-length residuals: per edge the rest length l.
+int rest_edge_length(const mad_mesh& m, const double* X, std::vector<double>& out) {
+    std::vector<double> sq;
+    int rc = rest_spring(m, X, sq);
+    if (rc != MAD_OK) return rc;
+    const int64_t ne = m.ne();
+    out.assign((size_t)ne, 0.0);
+    for (int64_t e = 0; e < ne; ++e) out[e] = std::sqrt(sq[2 * e]);
     return MAD_OK;
 }
 

@@ -130,6 +130,8 @@ hipError_t launch_eval(const EvalLaunch& L, hipStream_t s) {
     case K_MLP: return launch_prec<TermMLP>(L, s);
     case K_SPRING: return launch_prec<TermSpring>(L, s);
     case K_INERTIA: return launch_prec<TermInertia>(L, s);
+    case K_RES_EDGE: return launch_prec<TermResEdge>(L, s);
+    case K_RES_POSITION: return launch_prec<TermResPosition>(L, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -142,6 +144,23 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n) {
 __global__ void k_fill_u128(uint4* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// zero block list[i] (words 32-bit words each) of hess
+__global__ void k_zero_blocks(uint32_t* hess, const int32_t* list, int64_t n, int words) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * words) return;
+    const int64_t b = i / words;
+    hess[(int64_t)list[b] * words + (i - b * words)] = 0u;
+}
+
+hipError_t launch_zero_blocks(void* hess, const int32_t* list, int64_t n, int dd, int elem_bytes, hipStream_t s) {
+    const int words = dd * elem_bytes / 4;
+    const int64_t total = n * words;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_blocks, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (uint32_t*)hess, list, n,
+                       words);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(void* ptr, int64_t n_elems, int elem_bytes, hipStream_t s) {

@@ -369,6 +369,12 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
                 patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
             case K_SPRING: patch_term<TermSpring, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad); break;
+            case K_RES_EDGE:
+                patch_term<TermResEdge, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
+                break;
+            case K_RES_POSITION:
+                patch_term<TermResPosition, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
+                break;
             case K_INERTIA:
                 patch_term<TermInertia, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
@@ -617,6 +623,8 @@ __global__ __launch_bounds__(kBlock) void k_fallback(FallbackLaunch F) {
             case K_EDGE_SQLEN: fallback_elem<TermEdgeSqlen>(F, A, e, grad_done); break;
             case K_SPRING: fallback_elem<TermSpring>(F, A, e, grad_done); break;
             case K_INERTIA: fallback_elem<TermInertia>(F, A, e, grad_done); break;
+            case K_RES_EDGE: fallback_elem<TermResEdge>(F, A, e, grad_done); break;
+            case K_RES_POSITION: fallback_elem<TermResPosition>(F, A, e, grad_done); break;
             case K_SHELL_TRI: fallback_elem<TermShellTri>(F, A, e, grad_done); break;
             case K_MLP: fallback_elem<TermMLP>(F, A, e, grad_done); break;
             default: break;

@@ -322,4 +322,153 @@ hipError_t launch_slots(const int32_t* stencil, int64_t n, int ns, const int32_t
     return hipGetLastError();
 }
 
+// ---- dynamic sparsity: blocks of new interaction pairs (Sec. 6.3, CSR update of the appendix) --------
+// The update follows the appendix's count / prefix-sum / copy / insert structure with one change: the
+// new columns of a row are sorted and merged with the old ones instead of appended in atomic order, so
+// every row stays sorted (the layout, the FP64 redo and the callers binary-search rows) and the result is
+// unique, bit for bit, whatever order the atomics ran in.
+
+__device__ __forceinline__ bool has_block(const int32_t* rp, const int32_t* ci, int32_t r, int32_t c) {
+    int32_t lo = rp[r], hi = rp[r + 1] - 1;
+    while (lo <= hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        const int32_t m = ci[mid];
+        if (m == c) return true;
+        if (m < c) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return false;
+}
+
+// pass 0: count each pair's missing blocks per row; pass 1: write them into the row's candidate segment
+__global__ void k_pair_blocks(const int32_t* pairs, int64_t n, int64_t nv, const int32_t* rp, const int32_t* ci,
+                              int32_t* cnt, const int32_t* coff, int32_t* fill, int32_t* stage, int32_t* flags,
+                              int pass) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t a = pairs[2 * i], b = pairs[2 * i + 1];
+    if (a < 0 || b < 0 || a >= nv || b >= nv) {
+        if (pass == 0) atomicOr(flags, 1);
+        return;
+    }
+    if (a == b) return;
+    const int32_t rs[2] = {a, b}, cs[2] = {b, a};
+    for (int k = 0; k < 2; ++k) {
+        if (has_block(rp, ci, rs[k], cs[k])) continue;
+        if (pass == 0) atomicAdd(cnt + rs[k], 1);
+        else stage[coff[rs[k]] + atomicAdd(fill + rs[k], 1)] = cs[k];
+    }
+}
+
+// one lane per row: sort the row's candidate columns, drop repeats; new count and total row count
+__global__ void k_row_unique(int64_t nv, const int32_t* rp, const int32_t* coff, int32_t* stage, int32_t* nnew,
+                             int32_t* rowcnt) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nv) return;
+    int32_t* v = stage + coff[r];
+    const int32_t m = coff[r + 1] - coff[r];
+    for (int32_t i = 1; i < m; ++i) {
+        const int32_t x = v[i];
+        int32_t j = i - 1;
+        while (j >= 0 && v[j] > x) {
+            v[j + 1] = v[j];
+            --j;
+        }
+        v[j + 1] = x;
+    }
+    int32_t k = 0;
+    for (int32_t i = 0; i < m; ++i)
+        if (i == 0 || v[i] != v[i - 1]) v[k++] = v[i];
+    nnew[r] = k;
+    rowcnt[r] = rp[r + 1] - rp[r] + k;
+}
+
+// one lane per row: merge the old and the new columns into the new row; old block j -> map[j]; the new
+// blocks' indices are listed at extra[noff[r] ...]
+__global__ void k_row_merge(int64_t nv, const int32_t* rp, const int32_t* ci, const int32_t* coff,
+                            const int32_t* stage, const int32_t* nnew, const int64_t* rp_new, const int32_t* noff,
+                            int32_t* ci_new, int32_t* map, int32_t* extra) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nv) return;
+    int32_t i = rp[r];
+    const int32_t ie = rp[r + 1];
+    const int32_t* nv_ = stage + coff[r];
+    const int32_t ne = nnew[r];
+    int32_t j = 0;
+    int32_t o = (int32_t)rp_new[r];
+    int32_t x = noff[r];
+    while (i < ie || j < ne) {
+        if (j >= ne || (i < ie && ci[i] < nv_[j])) {
+            map[i] = o;
+            ci_new[o++] = ci[i++];
+        } else {
+            extra[x++] = o;
+            ci_new[o++] = nv_[j++];
+        }
+    }
+}
+
+__global__ void k_remap(int32_t* a, int64_t n, const int32_t* map) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = map[a[i]];
+}
+
+int insert_pairs_device(mad_problem* p, const int32_t* pairs, int64_t n, int64_t* n_added, hipStream_t s) {
+    const int64_t nv = p->mesh->nv;
+    DynBuffers& B = p->dyn;
+    auto T = [&](hipError_t e) { return e; };
+    MAD_HIP_TRY(launch_fill(B.cnt, nv + 1, 4, s));
+    MAD_HIP_TRY(launch_fill(B.fill, nv + 1, 4, s));
+    MAD_HIP_TRY(launch_fill(B.flags, 4, 4, s));
+    if (n > 0)
+        hipLaunchKernelGGL(k_pair_blocks, dim3(blocks_for(n, 256)), dim3(256), 0, s, pairs, n, nv, p->d_rowptr,
+                           p->d_colidx, B.cnt, (const int32_t*)nullptr, B.fill, (int32_t*)nullptr, B.flags, 0);
+    MAD_HIP_TRY(T(hipGetLastError()));
+    MAD_HIP_TRY((scan_exclusive<int32_t, int32_t>(B.cnt, nv, B.coff, B.scan_tmp, s)));
+    if (n > 0)
+        hipLaunchKernelGGL(k_pair_blocks, dim3(blocks_for(n, 256)), dim3(256), 0, s, pairs, n, nv, p->d_rowptr,
+                           p->d_colidx, B.cnt, (const int32_t*)B.coff, B.fill, B.stage, B.flags, 1);
+    hipLaunchKernelGGL(k_row_unique, dim3(blocks_for(nv, 256)), dim3(256), 0, s, nv, p->d_rowptr,
+                       (const int32_t*)B.coff, B.stage, B.nnew, B.rowcnt);
+    MAD_HIP_TRY(T(hipGetLastError()));
+    MAD_HIP_TRY((scan_exclusive<int32_t, int64_t>(B.rowcnt, nv, B.rp64, B.scan_tmp, s)));
+    MAD_HIP_TRY((scan_exclusive<int32_t, int32_t>(B.nnew, nv, B.noff, B.scan_tmp, s)));
+    int64_t total = 0;
+    int32_t added = 0, hflags[4] = {0, 0, 0, 0};
+    MAD_HIP_TRY(hipMemcpyAsync(&total, B.rp64 + nv, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MAD_HIP_TRY(hipMemcpyAsync(&added, B.noff + nv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MAD_HIP_TRY(hipMemcpyAsync(hflags, B.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    if (hflags[0] != 0) return fail(MAD_E_INVALID_ARG, "a pair names a vertex out of range");
+    if (total > p->nnzb_cap) return fail(MAD_E_CAPACITY, "the new blocks exceed the reserve");
+    // write the inactive buffer, then make it the active one
+    hipLaunchKernelGGL(k_i64_to_i32, dim3(blocks_for(nv + 1, 256)), dim3(256), 0, s, B.rp64, p->d_rowptr_b, nv + 1);
+    hipLaunchKernelGGL(k_row_merge, dim3(blocks_for(nv, 256)), dim3(256), 0, s, nv, p->d_rowptr, p->d_colidx,
+                       (const int32_t*)B.coff, (const int32_t*)B.stage, (const int32_t*)B.nnew,
+                       (const int64_t*)B.rp64, (const int32_t*)B.noff, p->d_colidx_b, B.map,
+                       p->d_extra_blocks + p->n_extra);
+    MAD_HIP_TRY(T(hipGetLastError()));
+    // every stored block index of the layout (and the earlier extra blocks) follows its block
+    auto remap = [&](int32_t* a, int64_t m) -> hipError_t {
+        if (!a || m <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_remap, dim3(blocks_for(m, 256)), dim3(256), 0, s, a, m, (const int32_t*)B.map);
+        return hipGetLastError();
+    };
+    MAD_HIP_TRY(remap(p->d_extra_blocks, p->n_extra));
+    MAD_HIP_TRY(remap(p->d_lb_gidx, p->n_lb));
+    MAD_HIP_TRY(remap(p->d_lb_gidxT, p->n_lb));
+    MAD_HIP_TRY(remap(p->d_gb_gidx, p->n_gb));
+    MAD_HIP_TRY(remap(p->d_gb_gidxT, p->n_gb));
+    MAD_HIP_TRY(remap(p->d_orphan_block, p->n_orphan_block));
+    for (auto& t : p->terms) MAD_HIP_TRY(remap(t.d_slots, t.d_slots ? t.n * t.ns * t.ns : 0));
+    MAD_HIP_TRY(hipStreamSynchronize(s));
+    std::swap(p->d_rowptr, p->d_rowptr_b);
+    std::swap(p->d_colidx, p->d_colidx_b);
+    p->nnzb = total;
+    p->n_extra += added;
+    p->host_pattern_stale = true;
+    if (n_added) *n_added = added;
+    return MAD_OK;
+}
+
 }  // namespace mad

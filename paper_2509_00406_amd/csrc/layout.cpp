@@ -68,8 +68,8 @@ static void order_terms(mad_problem* p) {
         std::vector<int32_t> key((size_t)t.n);
         for (int64_t e = 0; e < t.n; ++e) {
             if (t.kind == MAD_BENDING) key[e] = m.diamond_faces[2 * e];
-            else if (t.kind == MAD_EDGE_SQLEN || t.kind == MAD_SPRING) key[e] = m.edge_face0[e];
-            else if (t.kind == MAD_INERTIA) key[e] = m.vert_face0[t.stencil[e]];
+            else if (t.kind == MAD_EDGE_SQLEN || t.kind == MAD_SPRING || t.kind == MAD_RES_EDGE) key[e] = m.edge_face0[e];
+            else if (t.kind == MAD_INERTIA || t.kind == MAD_RES_POSITION) key[e] = m.vert_face0[t.stencil[e]];
             else key[e] = (int32_t)e;
         }
         // by face
@@ -142,9 +142,11 @@ static void free_layout(mad_problem* p) {
         t.d_lseg = nullptr;
         t.d_psi = nullptr;
         t.d_xh = nullptr;
+        t.d_perm = nullptr;
     }
     p->d_lv_ptr = p->d_lv_global = p->d_lv_halo = nullptr;
     p->d_lb_ptr = p->d_lb_gidx = p->d_lb_gidxT = p->d_lb_halo = nullptr;
+    p->n_lb = 0;
     p->d_gv_ptr = p->d_gv_src = p->d_gv_vert = nullptr;
     p->d_gb_ptr = p->d_gb_src = p->d_gb_gidx = p->d_gb_gidxT = nullptr;
     p->d_orphan_vert = p->d_orphan_block = nullptr;
@@ -201,6 +203,9 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
         if ((rc = upload_layout(p, (void**)&t.d_stencil, st.data(), st.size() * 4, s)) != MAD_OK) return rc;
         if ((rc = upload_layout(p, (void**)&t.d_rest, rs.data(), rs.size() * 8, s)) != MAD_OK) return rc;
         if ((rc = upload_layout(p, (void**)&t.d_elem_ptr, t.elem_ptr.data(), t.elem_ptr.size() * 4, s)) != MAD_OK)
+            return rc;
+        if (kind_nres(t.kind) > 0 &&
+            (rc = upload_layout(p, (void**)&t.d_perm, t.perm.data(), t.perm.size() * 4, s)) != MAD_OK)
             return rc;
         if (t.kind == MAD_MLP) {
             const size_t n = (size_t)std::max<int64_t>(t.n, 1);
@@ -264,6 +269,18 @@ static void unit_segments(const Term& t, int32_t np, int64_t nv, std::vector<uin
 // Structures of the scatter strategy for the current element order; needs the pattern.
 int build_scatter(mad_problem* p, hipStream_t s) {
     int rc;
+    if (p->host_pattern_stale) {
+        // pairs were inserted since the host copy was taken: refresh it; the rebuilt structures cover
+        // the inserted blocks (as blocks no element touches), so the extra list starts over
+        p->h_rowptr.resize((size_t)p->mesh->nv + 1);
+        p->h_colidx.resize((size_t)std::max<int64_t>(p->nnzb, 1));
+        MAD_HIP_TRY(hipMemcpyAsync(p->h_rowptr.data(), p->d_rowptr, p->h_rowptr.size() * 4, hipMemcpyDeviceToHost, s));
+        MAD_HIP_TRY(hipMemcpyAsync(p->h_colidx.data(), p->d_colidx, (size_t)p->nnzb * 4, hipMemcpyDeviceToHost, s));
+        MAD_HIP_TRY(hipStreamSynchronize(s));
+        p->h_colidx.resize((size_t)p->nnzb);
+        p->host_pattern_stale = false;
+    }
+    p->n_extra = 0;
     if (p->scatter == MAD_SCATTER_ATOMIC) {
         for (auto& t : p->terms) {
             if ((rc = alloc_layout(p, (void**)&t.d_slots, sizeof(int32_t) * std::max<int64_t>(1, t.n * t.ns * t.ns))) !=
@@ -292,6 +309,7 @@ int build_scatter(mad_problem* p, hipStream_t s) {
                {(void**)&p->d_orphan_vert, &L.orphan_vert}, {(void**)&p->d_orphan_block, &L.orphan_block}};
     for (auto& u : ups)
         if ((rc = upload_layout(p, u.dst, u.v->data(), u.v->size() * 4, s)) != MAD_OK) return rc;
+    p->n_lb = (int64_t)L.lb_gidx.size();
     p->n_gv = (int32_t)L.gv_vert.size();
     p->n_gb = (int32_t)L.gb_gidx.size();
     p->n_orphan_vert = (int32_t)L.orphan_vert.size();

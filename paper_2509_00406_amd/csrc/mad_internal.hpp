@@ -51,6 +51,7 @@ struct Term {
     float* d_psi = nullptr;              // learned density: SoA [28][n] network outputs, patch order
     float* d_xh = nullptr;               // learned density: SoA [6][n] scaled features, patch order
     const double* vdata = nullptr;       // vertex terms: the caller's [nv][NVD] device array (not owned)
+    int32_t* d_perm = nullptr;           // residual terms: [n] patch slot -> element (row ownership)
 };
 
 // patch-local index structures of the LDS-accumulating assembly (host_patch.cpp)
@@ -75,6 +76,21 @@ struct Patches {
     std::vector<int32_t> comp_patch_ptr; // [ncomp + 1]
 };
 
+// scratch of the pattern update for new interaction pairs, sized at finalize from the reserve
+struct DynBuffers {
+    int32_t* cnt = nullptr;      // [nv + 1] candidate blocks per row
+    int32_t* fill = nullptr;     // [nv + 1]
+    int32_t* coff = nullptr;     // [nv + 1] candidate offsets
+    int32_t* stage = nullptr;    // [2 * max_pairs] candidate columns, by row
+    int32_t* nnew = nullptr;     // [nv] distinct new blocks per row
+    int32_t* rowcnt = nullptr;   // [nv] new row lengths
+    int32_t* noff = nullptr;     // [nv + 1]
+    int32_t* map = nullptr;      // [capacity] old block -> new block
+    int32_t* flags = nullptr;    // [4]
+    int64_t* rp64 = nullptr;     // [nv + 1]
+    int64_t* scan_tmp = nullptr;
+};
+
 }  // namespace mad
 
 struct mad_problem {
@@ -86,8 +102,19 @@ struct mad_problem {
     int device = 0;
     mad::Patches patches;
     int64_t nnzb = 0;
-    int32_t* d_rowptr = nullptr;
+    int32_t* d_rowptr = nullptr;          // the active pattern buffer
     int32_t* d_colidx = nullptr;
+    // dynamic sparsity (interaction pairs): a second pattern buffer, both of capacity nnzb_cap; the blocks
+    // added since the last layout build, which no term touches and every Hessian evaluation zeroes
+    int64_t pair_reserve = 0;             // max pairs per insertion (0: no insertion)
+    int64_t nnzb_cap = 0;
+    int32_t* d_rowptr_b = nullptr;
+    int32_t* d_colidx_b = nullptr;
+    int32_t* d_extra_blocks = nullptr;    // [2 * pair_reserve]
+    int64_t n_extra = 0;
+    bool host_pattern_stale = false;      // h_rowptr / h_colidx lag the device pattern
+    mad::DynBuffers dyn;
+    int64_t n_lb = 0;                     // entries of d_lb_gidx / d_lb_gidxT
     int32_t* d_comp_patch_ptr = nullptr;
     double* d_partial = nullptr;          // [n_terms][n_patch]
     double* d_comp_energy = nullptr;      // [n_comp] per-component energies (reduction scratch)
@@ -159,6 +186,7 @@ int rest_tri(const mad_mesh& m, const double* rest_pos, std::vector<double>& out
 int rest_diamond(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);    // [nd][2]
 int rest_shell(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);      // [nt][8]
 int rest_spring(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);     // [ne][2]
+int rest_edge_length(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);  // [ne]
 void build_patches(const mad_mesh& m, int target_faces, Patches& p);
 // layout.cpp: (re)build the element order and the scatter structures of a problem
 int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s);
@@ -311,5 +339,33 @@ int build_pattern_device(int64_t nv, const std::vector<PatternTerm>& terms, int3
                          int64_t* nnzb, std::vector<void*>& owned, hipStream_t s);
 hipError_t launch_slots(const int32_t* stencil, int64_t n, int ns, const int32_t* rowptr, const int32_t* colidx,
                         int32_t* slots, int32_t* flags, hipStream_t s);
+// residual terms: residual vector and row-owned Jacobian (kernels_jac.hip)
+struct JacTerm {
+    int kind;
+    int64_t n;
+    const int32_t* stencil;  // [n][ns] global vertices, patch order
+    const int32_t* perm;     // [n] patch slot -> element (the element owns its rows)
+    const double* rest;      // SoA [nrest][n], patch order
+    const double* vdata;     // [nv][NVD] caller's per-vertex data
+    double prm[4];
+    int64_t row_off, nz_off; // the term's first row and first entry
+};
+struct JacLaunch {
+    int prec, pattern, n_terms;
+    const double* x;
+    double* r;               // [m] FP64
+    void* vals;              // [nnz] T
+    int32_t* rowptr;         // pattern mode: [m + 1] (the last entry is written by the host)
+    int32_t* colidx;         // pattern mode: [nnz]
+    int32_t* flags;
+    JacTerm terms[8];
+};
+hipError_t launch_jacobian(const JacLaunch& L, hipStream_t s);
+int kind_nres(int kind);
+
+// new interaction pairs [n][2] (device) into the pattern (synchronises the stream)
+int insert_pairs_device(mad_problem* p, const int32_t* pairs, int64_t n, int64_t* n_added, hipStream_t s);
+// zero the listed blocks (dd values of elem_bytes each)
+hipError_t launch_zero_blocks(void* hess, const int32_t* list, int64_t n, int dd, int elem_bytes, hipStream_t s);
 
 }  // namespace mad

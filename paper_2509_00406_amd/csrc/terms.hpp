@@ -17,7 +17,7 @@ namespace mad {
 
 enum TermKind {
     K_EDGE_SQLEN = 1, K_TRI_AREA = 2, K_DIRICHLET = 3, K_STVK = 4, K_BENDING = 5, K_SYMDIR = 6, K_MLP = 7, K_SHELL_TRI = 8,
-    K_SPRING = 9, K_INERTIA = 10
+    K_SPRING = 9, K_INERTIA = 10, K_RES_POSITION = 11, K_RES_EDGE = 12
 };
 
 template <typename S>
@@ -34,7 +34,7 @@ template <typename S> __device__ __forceinline__ S dot(const V3<S>& a, const V3<
 
 // Listing 1: squared edge length. r = x1 - x0.
 struct TermEdgeSqlen {
-    static constexpr int NS = 2, D = 3, KR = 3, NREST = 0, NAUX = 0, NPSI = 0, NVD = 0;
+    static constexpr int NS = 2, D = 3, KR = 3, NREST = 0, NAUX = 0, NPSI = 0, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double*, const double*) {
         return r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -44,7 +44,7 @@ struct TermEdgeSqlen {
 // Sec. 7.1 mass-spring cloth, the spring of one edge: w (k/2) l^2 (|r|^2 / l^2 - 1)^2 with r = x1 - x0,
 // l the rest length. rest = {l^2, 1 / l^2}, params = {k, w}.
 struct TermSpring {
-    static constexpr int NS = 2, D = 3, KR = 3, NREST = 2, NAUX = 0, NPSI = 0, NVD = 0;
+    static constexpr int NS = 2, D = 3, KR = 3, NREST = 2, NAUX = 0, NPSI = 0, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double* prm) {
         const S q = (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * rest[1] + (-1.0);
@@ -56,7 +56,7 @@ struct TermSpring {
 // translation invariant (TI = false): the active variables are the vertex's own coordinates x.
 // Per-vertex inputs {m, xhat (3)} come from the caller's vertex array; params = {w, g (3)}.
 struct TermInertia {
-    static constexpr int NS = 1, D = 3, KR = 3, NREST = 0, NAUX = 0, NPSI = 0, NVD = 4;
+    static constexpr int NS = 1, D = 3, KR = 3, NREST = 0, NAUX = 0, NPSI = 0, NVD = 4, NRES = 0;
     static constexpr bool TI = false;
     template <typename S> __device__ static S energy(const S* x, const double* in, const double* prm) {
         const double m = in[0], wm = prm[0] * in[0];
@@ -67,9 +67,43 @@ struct TermInertia {
     }
 };
 
+// Residual terms (Sec. 4.1, Eq. 3): NRES residuals per element. As scalar terms they contribute
+// 1/2 |r|^2, and the element kernels assemble the Gauss-Newton matrix J^T J in place of the Hessian.
+//
+// Positional residual of one vertex (the paper's ActiveT<3> example): r = sqrt(w) (x - x_t), with
+// {w, x_t} from the caller's per-vertex array. Not translation invariant.
+struct TermResPosition {
+    static constexpr int NS = 1, D = 3, KR = 3, NREST = 0, NAUX = 0, NPSI = 0, NVD = 4, NRES = 3;
+    static constexpr bool TI = false;
+    template <typename S> __device__ static void residual(const S* x, const double* in, const double*, S* out) {
+        const double sw = sqrt(in[0]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] = (x[c] + (-in[1 + c])) * sw;
+    }
+    template <typename S> __device__ static S energy(const S* x, const double* in, const double* prm) {
+        S r[3];
+        residual<S>(x, in, prm, r);
+        return (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) * 0.5;
+    }
+};
+
+// Edge-length residual (a least-squares spring): r = sqrt(k) (|x1 - x0| - l), rest = {l}, params = {k}.
+struct TermResEdge {
+    static constexpr int NS = 2, D = 3, KR = 3, NREST = 1, NAUX = 0, NPSI = 0, NVD = 0, NRES = 1;
+    static constexpr bool TI = true;
+    template <typename S> __device__ static void residual(const S* r, const double* rest, const double* prm, S* out) {
+        out[0] = (dsqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]) + (-rest[0])) * sqrt(prm[0]);
+    }
+    template <typename S> __device__ static S energy(const S* r, const double* rest, const double* prm) {
+        S q[1];
+        residual<S>(r, rest, prm, q);
+        return q[0] * q[0] * 0.5;
+    }
+};
+
 // Sec. 7.6: triangle area 0.5 |(x1 - x0) x (x2 - x0)|.
 struct TermTriArea {
-    static constexpr int NS = 3, D = 3, KR = 6, NREST = 0, NAUX = 0, NPSI = 0, NVD = 0;
+    static constexpr int NS = 3, D = 3, KR = 6, NREST = 0, NAUX = 0, NPSI = 0, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double*, const double*) {
         const V3<S> a{r[0], r[1], r[2]}, b{r[3], r[4], r[5]};
@@ -81,7 +115,7 @@ struct TermTriArea {
 // Scalar Dirichlet energy 0.5 A |grad u|^2 with grad u = Dm^{-T} (u1 - u0, u2 - u0).
 // rest = {Dm^{-1} row-major (4), rest area}.
 struct TermDirichlet {
-    static constexpr int NS = 3, D = 1, KR = 2, NREST = 5, NAUX = 0, NPSI = 0, NVD = 0;
+    static constexpr int NS = 3, D = 1, KR = 2, NREST = 5, NAUX = 0, NPSI = 0, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double*) {
         const S g0 = r[0] * rest[0] + r[1] * rest[2];
@@ -93,7 +127,7 @@ struct TermDirichlet {
 // StVK membrane: F = Ds Dm^{-1} (3x2), E = (F^T F - I)/2, A (mu tr(E^2) + lambda/2 tr(E)^2).
 // r = (x_b - x_a, x_c - x_a); rest = {Dm^{-1} (4), rest area}; prm = {mu, lambda}.
 struct TermStVK {
-    static constexpr int NS = 3, D = 3, KR = 6, NREST = 5, NAUX = 0, NPSI = 0, NVD = 0;
+    static constexpr int NS = 3, D = 3, KR = 6, NREST = 5, NAUX = 0, NPSI = 0, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double* prm) {
         const double m00 = rest[0], m01 = rest[1], m10 = rest[2], m11 = rest[3];
@@ -122,7 +156,7 @@ struct TermStVK {
 // avoids the quartic cross product n1 x n2.
 // r = (e, a, b); rest = {mean rest area, rest dihedral}; prm = {k_b, h}.
 struct TermBending {
-    static constexpr int NS = 4, D = 3, KR = 9, NREST = 2, NAUX = 0, NPSI = 0, NVD = 0;
+    static constexpr int NS = 4, D = 3, KR = 9, NREST = 2, NAUX = 0, NPSI = 0, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double* prm) {
         const V3<S> e{r[0], r[1], r[2]}, a{r[3], r[4], r[5]}, b{r[6], r[7], r[8]};
@@ -139,7 +173,7 @@ struct TermBending {
 // for 2x2 matrices |J^{-1}|_F^2 = |J|_F^2 / det(J)^2.
 // r = (b - a, c - a) in UV; rest = {Dm^{-1} (4), rest area}.
 struct TermSymDir {
-    static constexpr int NS = 3, D = 2, KR = 4, NREST = 5, NAUX = 0, NPSI = 0, NVD = 0;
+    static constexpr int NS = 3, D = 2, KR = 4, NREST = 5, NAUX = 0, NPSI = 0, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double*) {
         const double m00 = rest[0], m01 = rest[1], m10 = rest[2], m11 = rest[3];
@@ -183,7 +217,7 @@ __device__ __forceinline__ void shell_features(const S* r, const double* rest, S
 // Analytic per-triangle shell density A W(z), W = mu (E00^2 + E11^2 + 2 E01^2)
 // + lambda/2 (E00 + E11)^2 + k_b/2 (dII00^2 + dII11^2 + 2 dII01^2); prm = {mu, lambda, k_b}.
 struct TermShellTri {
-    static constexpr int NS = 3, D = 3, KR = 6, NREST = 8, NAUX = 9, NPSI = 0, NVD = 0;
+    static constexpr int NS = 3, D = 3, KR = 6, NREST = 8, NAUX = 9, NPSI = 0, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double* prm) {
         S z[6];
@@ -202,7 +236,7 @@ struct TermShellTri {
 // form psi + sum_i psi_i dz_i + 1/2 sum_ij psi_ij dz_i dz_j carries exactly the value, gradient
 // and Hessian of psi(z(r)) in hyper-dual arithmetic.
 struct TermMLP {
-    static constexpr int NS = 3, D = 3, KR = 6, NREST = 8, NAUX = 9, NPSI = 28, NVD = 0;
+    static constexpr int NS = 3, D = 3, KR = 6, NREST = 8, NAUX = 9, NPSI = 28, NVD = 0, NRES = 0;
     static constexpr bool TI = true;
     template <typename S> __device__ static S energy(const S* r, const double* rest, const double*) {
         S z[6];

@@ -17,15 +17,17 @@ LIB_PATH = os.path.join(HERE, "libmad.so")
 
 EDGE_SQLEN, TRI_AREA, DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI = 1, 2, 3, 4, 5, 6, 7, 8
 SPRING, INERTIA = 9, 10
+RES_POSITION, RES_EDGE = 11, 12
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 F64, F32 = 0, 1
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_PATCH = 0, 1, 2
 TUNE_FORCE = 1
 
 STATUS = {0: "MAD_OK", -1: "MAD_E_INVALID_ARG", -2: "MAD_E_BAD_MESH", -3: "MAD_E_DEGENERATE_REST",
-          -4: "MAD_E_OVERFLOW", -5: "MAD_E_OOM", -6: "MAD_E_HIP", -7: "MAD_E_STATE", -8: "MAD_E_UNSUPPORTED"}
+          -4: "MAD_E_OVERFLOW", -5: "MAD_E_OOM", -6: "MAD_E_HIP", -7: "MAD_E_STATE", -8: "MAD_E_UNSUPPORTED",
+          -9: "MAD_E_CAPACITY"}
 VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3, SHELL_TRI: 3}
-NEEDS_REST = {DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI, SPRING}
+NEEDS_REST = {DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI, SPRING, RES_EDGE}
 MLP_HIDDEN, MLP_PARAMS = 64, 4673
 
 
@@ -87,6 +89,11 @@ _SIGS = {
     "mad_mlp_destroy": ([C.c_void_p], C.c_int32),
     "mad_problem_add_mlp_term": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
     "mad_problem_add_vertex_term": ([C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p], C.c_int32),
+    "mad_problem_reserve_pairs": ([C.c_void_p, C.c_int64], C.c_int32),
+    "mad_problem_jacobian_info": ([C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_problem_copy_jacobian_pattern": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_problem_jacobian": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
+    "mad_problem_insert_pairs": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int32),
 }
 
 
@@ -190,6 +197,33 @@ def mad_problem_add_vertex_term(prob, kind: int, params, vdata):
     prm = np.ascontiguousarray(params, dtype=np.float64)
     _check(lib().mad_problem_add_vertex_term(prob, kind, _ptr(prm) if prm.size else None, prm.size, _ptr(vdata)),
            "mad_problem_add_vertex_term")
+
+
+def mad_problem_reserve_pairs(prob, max_pairs: int):
+    _check(lib().mad_problem_reserve_pairs(prob, max_pairs), "mad_problem_reserve_pairs")
+
+
+def mad_problem_insert_pairs(prob, pairs, n_pairs: int, stream=None) -> int:
+    """pairs: device int32 tensor [n_pairs, 2]. Returns the number of blocks added."""
+    added = C.c_int64()
+    _check(lib().mad_problem_insert_pairs(prob, _ptr(pairs), n_pairs, C.byref(added), _stream(stream)),
+           "mad_problem_insert_pairs")
+    return added.value
+
+
+def mad_problem_jacobian_info(prob) -> tuple[int, int]:
+    m, nnz = C.c_int64(), C.c_int64()
+    _check(lib().mad_problem_jacobian_info(prob, C.byref(m), C.byref(nnz)), "mad_problem_jacobian_info")
+    return m.value, nnz.value
+
+
+def mad_problem_copy_jacobian_pattern(prob, rowptr, colidx, stream=None):
+    _check(lib().mad_problem_copy_jacobian_pattern(prob, _ptr(rowptr), _ptr(colidx), _stream(stream)),
+           "mad_problem_copy_jacobian_pattern")
+
+
+def mad_problem_jacobian(prob, x, r, vals, stream=None):
+    _check(lib().mad_problem_jacobian(prob, _ptr(x), _ptr(r), _ptr(vals), _stream(stream)), "mad_problem_jacobian")
 
 
 def mad_problem_finalize(prob, stream=None):
@@ -391,6 +425,33 @@ class Problem:
 
     def add_term(self, kind: int, params=(), rest_pos: np.ndarray | None = None):
         mad_problem_add_term(self.handle, kind, params, rest_pos)
+
+    def reserve_pairs(self, max_pairs: int):
+        mad_problem_reserve_pairs(self.handle, max_pairs)
+
+    def insert_pairs(self, pairs, stream=None) -> int:
+        """Add the blocks of interaction pairs (device int32 [n, 2]); refreshes nnzb."""
+        added = mad_problem_insert_pairs(self.handle, pairs, int(pairs.shape[0]), stream)
+        self.n_rows, self.nnzb, self.block_dim = mad_problem_pattern_info(self.handle)
+        return added
+
+    def jacobian_pattern(self, device="cuda"):
+        import torch
+        m, nnz = mad_problem_jacobian_info(self.handle)
+        rowptr = torch.empty(m + 1, dtype=torch.int32, device=device)
+        colidx = torch.empty(max(nnz, 1), dtype=torch.int32, device=device)
+        mad_problem_copy_jacobian_pattern(self.handle, rowptr, colidx)
+        return rowptr, colidx[:nnz]
+
+    def jacobian(self, x, stream=None):
+        """(r [m] FP64, vals [nnz]) of the residual terms at x (Eq. 3)."""
+        import torch
+        m, nnz = mad_problem_jacobian_info(self.handle)
+        dt = torch.float32 if self.precision == F32 else torch.float64
+        r = torch.empty(m, dtype=torch.float64, device=x.device)
+        vals = torch.empty(max(nnz, 1), dtype=dt, device=x.device)
+        mad_problem_jacobian(self.handle, x, r, vals, stream)
+        return r, vals[:nnz]
 
     def add_vertex_term(self, kind: int, params, vdata):
         mad_problem_add_vertex_term(self.handle, kind, params, vdata)

@@ -108,6 +108,15 @@ def test_problem_validation_errors():
     with pytest.raises(mad.MadError) as e:
         mad.mad_problem_eval(p.handle, np.zeros(27), mad.ENERGY, np.zeros(1), stream=0)
     assert e.value.code == -7                      # eval before finalize
+    with pytest.raises(mad.MadError) as e:
+        p.reserve_pairs(-1)
+    assert e.value.code == -1
+    with pytest.raises(mad.MadError) as e:
+        mad.mad_problem_insert_pairs(p.handle, np.zeros((1, 2), np.int32), 1, stream=0)
+    assert e.value.code == -7                      # insertion before finalize
+    with pytest.raises(mad.MadError) as e:
+        p.add_term(mad.INERTIA, (0.1, 0.0, 0.0, -9.8), None)
+    assert e.value.code == -1                      # vertex terms have their own entry point
     o = mad.mad_options_default()
     o.spd_eps = -1.0
     with pytest.raises(mad.MadError) as e:
