@@ -184,9 +184,72 @@ __host__ __device__ constexpr int rr_players(int n) { return n + (n & 1); }
 __host__ __device__ constexpr int rr_a(int M, int r, int k) { return k == 0 ? M - 1 : (r + k) % (M - 1); }
 __host__ __device__ constexpr int rr_b(int M, int r, int k) { return k == 0 ? r : (r - k + (M - 1)) % (M - 1); }
 
+// off-diagonal mass below tol of the Frobenius norm
+template <int N, typename T>
+__device__ __forceinline__ bool jacobi_converged(const T (&A)[Packed<N>::N], T tol) {
+    T off = T(0), dg = T(0);
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        dg += A[Packed<N>::at(p, p)] * A[Packed<N>::at(p, p)];
+#pragma unroll
+        for (int q = p + 1; q < N; ++q) off += A[Packed<N>::at(p, q)] * A[Packed<N>::at(p, q)];
+    }
+    return off <= tol * tol * (dg + T(2) * off);
+}
+
+// one sweep: every pair once, round by round
+template <int N, typename T>
+__device__ __forceinline__ void jacobi_sweep(T (&A)[Packed<N>::N], T (&V)[N][N]) {
+    constexpr int M = rr_players(N), H = M / 2;
+#pragma unroll
+    for (int r = 0; r < M - 1; ++r) {
+        T cs[H], sn[H], tn[H];
+        // parameters of the round's rotations (independent of each other)
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const int a = rr_a(M, r, k), b = rr_b(M, r, k);
+            if (a >= N || b >= N) continue;
+            const int p = a < b ? a : b, q = a < b ? b : a;
+            const T apq = A[Packed<N>::at(p, q)];
+            const T d = A[Packed<N>::at(q, q)] - A[Packed<N>::at(p, p)];
+            const T den = fabs(d) + fsqrt(d * d + T(4) * apq * apq);
+            T t = (T(2) * apq) * frcp(den);
+            t = d < T(0) ? -t : t;
+            t = (apq == T(0)) ? T(0) : t;
+            const T c = frsq(t * t + T(1));
+            cs[k] = c;
+            sn[k] = t * c;
+            tn[k] = t;
+        }
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const int a = rr_a(M, r, k), b = rr_b(M, r, k);
+            if (a >= N || b >= N) continue;
+            const int p = a < b ? a : b, q = a < b ? b : a;
+            const T c = cs[k], s = sn[k], t = tn[k];
+            const T apq = A[Packed<N>::at(p, q)];
+            A[Packed<N>::at(p, p)] -= t * apq;
+            A[Packed<N>::at(q, q)] += t * apq;
+            A[Packed<N>::at(p, q)] = T(0);
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                if (i == p || i == q) continue;
+                const T g = A[Packed<N>::at(i, p)], h = A[Packed<N>::at(i, q)];
+                A[Packed<N>::at(i, p)] = c * g - s * h;
+                A[Packed<N>::at(i, q)] = s * g + c * h;
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const T g = V[i][p], h = V[i][q];
+                V[i][p] = c * g - s * h;
+                V[i][q] = s * g + c * h;
+            }
+        }
+    }
+}
+
 template <int N, typename T>
 __device__ __forceinline__ bool jacobi_eig(T (&A)[Packed<N>::N], T (&V)[N][N], int max_sweeps, T tol) {
-    constexpr int M = rr_players(N), H = M / 2;
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
@@ -197,64 +260,19 @@ __device__ __forceinline__ bool jacobi_eig(T (&A)[Packed<N>::N], T (&V)[N][N], i
     const T scale = amax > T(0) ? frcp(amax) : T(1);
 #pragma unroll
     for (int i = 0; i < Packed<N>::N; ++i) A[i] *= scale;
-    bool conv = false;
-    for (int sweep = 0; sweep <= max_sweeps; ++sweep) {
-        T off = T(0), dg = T(0);
-#pragma unroll
-        for (int p = 0; p < N; ++p) {
-            dg += A[Packed<N>::at(p, p)] * A[Packed<N>::at(p, p)];
-#pragma unroll
-            for (int q = p + 1; q < N; ++q) off += A[Packed<N>::at(p, q)] * A[Packed<N>::at(p, q)];
-        }
-        if (off <= tol * tol * (dg + T(2) * off)) {
-            conv = true;
-            break;
-        }
-        if (sweep == max_sweeps) break;
-#pragma unroll
-        for (int r = 0; r < M - 1; ++r) {
-            T cs[H], sn[H], tn[H];
-            // parameters of the round's rotations (independent of each other)
-#pragma unroll
-            for (int k = 0; k < H; ++k) {
-                const int a = rr_a(M, r, k), b = rr_b(M, r, k);
-                if (a >= N || b >= N) continue;
-                const int p = a < b ? a : b, q = a < b ? b : a;
-                const T apq = A[Packed<N>::at(p, q)];
-                const T d = A[Packed<N>::at(q, q)] - A[Packed<N>::at(p, p)];
-                const T den = fabs(d) + fsqrt(d * d + T(4) * apq * apq);
-                T t = (T(2) * apq) * frcp(den);
-                t = d < T(0) ? -t : t;
-                t = (apq == T(0)) ? T(0) : t;
-                const T c = frsq(t * t + T(1));
-                cs[k] = c;
-                sn[k] = t * c;
-                tn[k] = t;
+    bool conv = jacobi_converged<N, T>(A, tol);
+    if (!conv && max_sweeps > 0) {
+        // the first sweep on its own: V is still the identity there, so the products with its
+        // structural zeros and ones fold away at compile time (the element kernels are built
+        // without signed zeros and non-finite values)
+        jacobi_sweep<N, T>(A, V);
+        for (int sweep = 1;; ++sweep) {
+            if (jacobi_converged<N, T>(A, tol)) {
+                conv = true;
+                break;
             }
-#pragma unroll
-            for (int k = 0; k < H; ++k) {
-                const int a = rr_a(M, r, k), b = rr_b(M, r, k);
-                if (a >= N || b >= N) continue;
-                const int p = a < b ? a : b, q = a < b ? b : a;
-                const T c = cs[k], s = sn[k], t = tn[k];
-                const T apq = A[Packed<N>::at(p, q)];
-                A[Packed<N>::at(p, p)] -= t * apq;
-                A[Packed<N>::at(q, q)] += t * apq;
-                A[Packed<N>::at(p, q)] = T(0);
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    if (i == p || i == q) continue;
-                    const T g = A[Packed<N>::at(i, p)], h = A[Packed<N>::at(i, q)];
-                    A[Packed<N>::at(i, p)] = c * g - s * h;
-                    A[Packed<N>::at(i, q)] = s * g + c * h;
-                }
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    const T g = V[i][p], h = V[i][q];
-                    V[i][p] = c * g - s * h;
-                    V[i][q] = s * g + c * h;
-                }
-            }
+            if (sweep == max_sweeps) break;
+            jacobi_sweep<N, T>(A, V);
         }
     }
 #pragma unroll
