@@ -293,7 +293,7 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
     }
 }
 
-template <typename T, int MODE, int D, bool SH>
+template <typename T, int MODE, int D, int FAM>
 __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsigned char* smem, double* red,
                                                int* s_next, int* lock) {
     constexpr int DD = D * D;
@@ -362,9 +362,6 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         const int e0 = first + lane;
         if constexpr (D == 3) {
             switch (A.kind) {
-            case K_STVK: patch_term<TermStVK, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad); break;
-            case K_BENDING: patch_term<TermBending, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad); break;
-            case K_TRI_AREA: patch_term<TermTriArea, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad); break;
             case K_EDGE_SQLEN:
                 patch_term<TermEdgeSqlen, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
@@ -378,11 +375,20 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
             case K_INERTIA:
                 patch_term<TermInertia, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
+            case K_STVK:
+                if constexpr (FAM != 2) patch_term<TermStVK, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
+                break;
+            case K_BENDING:
+                if constexpr (FAM != 2) patch_term<TermBending, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
+                break;
+            case K_TRI_AREA:
+                if constexpr (FAM != 2) patch_term<TermTriArea, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
+                break;
             case K_SHELL_TRI:
-                if constexpr (SH) patch_term<TermShellTri, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
+                if constexpr (FAM == 1) patch_term<TermShellTri, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
             case K_MLP:
-                if constexpr (SH) patch_term<TermMLP, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
+                if constexpr (FAM == 1) patch_term<TermMLP, T, MODE>(L, A, t, p, e0, last, sx, sg, sh, sy, lock, esum, bad);
                 break;
             default: break;
             }
@@ -453,13 +459,13 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
 
 // One patch per workgroup, or (persistent) a grid sized to the device whose workgroups take
 // patches from a counter in the given order (largest first) until every patch is taken.
-template <typename T, int MODE, int D, bool SH>
+template <typename T, int MODE, int D, int FAM>
 __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kBlock];
     __shared__ int next, unit_next, block_lock;
     if (!L.persistent) {
-        eval_patch_one<T, MODE, D, SH>(L, blockIdx.x, smem, red, &unit_next, &block_lock);
+        eval_patch_one<T, MODE, D, FAM>(L, blockIdx.x, smem, red, &unit_next, &block_lock);
         return;
     }
     for (;;) {
@@ -468,22 +474,29 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
         const int k = next;
         __syncthreads();   // every lane has read `next` before it is overwritten
         if (k >= L.n_patch) break;
-        eval_patch_one<T, MODE, D, SH>(L, L.work_order[k], smem, red, &unit_next, &block_lock);
+        eval_patch_one<T, MODE, D, FAM>(L, L.work_order[k], smem, red, &unit_next, &block_lock);
         __syncthreads();   // the flush has read LDS before the next patch clears it
     }
 }
 
-// FP32: the compiler is held to 256 registers so two waves share each SIMD (a few values spill
-// to scratch; the second wave hides the latency of the long dependent rotation chains).
-// SH: the shell-feature terms (analytic and learned per-triangle densities) are compiled into a
-// separate instantiation, so that their register needs do not burden the catalogue's kernel.
-template <int MODE, int D, bool SH>
+// FAM: the term family compiled into an instantiation. 0: the catalogue; 1: the catalogue and the
+// shell-feature terms (analytic and learned per-triangle densities), whose register needs would
+// otherwise burden the catalogue's kernel; 2: light terms only (edge, spring, vertex and residual
+// terms: 3 x 3 reduced Hessians), held to fewer registers for more waves per SIMD, since such
+// elements wait on memory more than they compute.
+// FP32 families 0 and 1: the compiler is held to 256 registers so two waves share each SIMD (the
+// second wave hides the latency of the long dependent rotation chains).
+template <int MODE, int D, int FAM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_patch_f32(PatchLaunch L) {
-    eval_patch_body<float, MODE, D, SH>(L);
+    eval_patch_body<float, MODE, D, FAM>(L);
 }
-template <int MODE, int D, bool SH>
+template <int MODE, int D>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_patch_light_f32(PatchLaunch L) {
+    eval_patch_body<float, MODE, D, 2>(L);
+}
+template <int MODE, int D, int FAM>
 __global__ __launch_bounds__(kBlock) void k_eval_patch_f64(PatchLaunch L) {
-    eval_patch_body<double, MODE, D, SH>(L);
+    eval_patch_body<double, MODE, D, FAM>(L);
 }
 
 // ---- gather of shared entries --------------------------------------------------------------------
@@ -665,15 +678,18 @@ static int persistent_grid(K kernel, const PatchLaunch& L) {
     return std::max(1, std::min(L.n_patch, std::max(L.n_cu, 1) * per_cu));
 }
 
-template <int MODE, int D, bool SH>
+template <int MODE, int D, int FAM>
 static void launch_patch_variant(bool f32, const PatchLaunch& L, hipStream_t s) {
     const dim3 block(kBlock);
-    if (f32) {
-        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f32<MODE, D, SH>, L) : L.n_patch);
-        hipLaunchKernelGGL((k_eval_patch_f32<MODE, D, SH>), grid, block, L.lds_bytes, s, L);
+    if (f32 && FAM == 2) {
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_light_f32<MODE, D>, L) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_light_f32<MODE, D>), grid, block, L.lds_bytes, s, L);
+    } else if (f32) {
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f32<MODE, D, FAM>, L) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_f32<MODE, D, FAM>), grid, block, L.lds_bytes, s, L);
     } else {
-        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f64<MODE, D, SH>, L) : L.n_patch);
-        hipLaunchKernelGGL((k_eval_patch_f64<MODE, D, SH>), grid, block, L.lds_bytes, s, L);
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f64<MODE, D, FAM>, L) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_f64<MODE, D, FAM>), grid, block, L.lds_bytes, s, L);
     }
 }
 
@@ -681,11 +697,15 @@ template <int MODE, int D>
 static void launch_patch_kernel(bool f32, const PatchLaunch& L, hipStream_t s) {
     if constexpr (D == 3) {
         if (L.shell) {
-            launch_patch_variant<MODE, D, true>(f32, L, s);
+            launch_patch_variant<MODE, D, 1>(f32, L, s);
+            return;
+        }
+        if (L.light) {
+            launch_patch_variant<MODE, D, 2>(f32, L, s);
             return;
         }
     }
-    launch_patch_variant<MODE, D, false>(f32, L, s);
+    launch_patch_variant<MODE, D, 0>(f32, L, s);
 }
 
 template <typename T, int D>

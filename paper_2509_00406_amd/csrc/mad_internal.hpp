@@ -268,6 +268,7 @@ struct PatchLaunch {
     double eps, qmin;
     const double* normals;  // [nv][3] unit vertex normals (shell-feature terms)
     int shell;              // the problem has shell-feature terms (selects the kernel variant)
+    int light;              // every term is a light term (edge, spring, vertex, residual): the light variant
     int term_order[8];      // terms by decreasing element cost (work units of the costliest first)
     int hvp;                // matrix-free mode: y = H v instead of assembling H (modes 2, 3)
     const double* v;        // [nv][D]
