@@ -135,7 +135,8 @@ typedef enum mad_scatter {
 
 typedef struct mad_options {
     int32_t scatter;         /* mad_scatter; 0 = default */
-    int32_t patch_faces;     /* target faces per patch (Sec. 7.1 patch study); 0 = 512 */
+    int32_t patch_faces;     /* target faces per patch (Sec. 7.1 patch study); 0 = by term mix: 256 when
+                                every term is a spring, inertia, edge-length or residual term, else 512 */
     double spd_eps;          /* eigenvalue floor of MAD_SPD; default 0 (PSD) */
     double degenerate_q;     /* MAD_F32: elements whose triangle quality 4 sqrt(3) A / sum(l^2)
                                 falls below this are evaluated and projected in FP64; 0 = 1e-2 */

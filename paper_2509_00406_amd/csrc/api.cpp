@@ -33,7 +33,7 @@ int32_t mad_options_default(mad_options* opt) {
     if (!opt) return fail(MAD_E_INVALID_ARG, "opt is NULL");
     std::memset(opt, 0, sizeof(*opt));
     opt->scatter = MAD_SCATTER_PATCH;
-    opt->patch_faces = 512;
+    opt->patch_faces = 0;
     opt->spd_eps = 0.0;
     opt->degenerate_q = 1e-2;
     return MAD_OK;
@@ -218,6 +218,9 @@ static int32_t add_term(mad_problem* p, int32_t kind, const double* params, int3
     }
     if (rc != MAD_OK) return rc;
     if (kind == MAD_MLP || kind == MAD_SHELL_TRI) p->shell = true;
+    if (!(kind == MAD_EDGE_SQLEN || kind == MAD_SPRING || kind == MAD_INERTIA || kind == MAD_RES_EDGE ||
+          kind == MAD_RES_POSITION))
+        p->light = false;
     p->terms.push_back(std::move(t));
     return MAD_OK;
 }
@@ -352,6 +355,8 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
     }
     // element order first (the pattern is built from the device stencils), then the pattern, then
     // the scatter structures that index into it
+    // default patch target: smaller patches for cheap elements (more workgroups to hide their latency)
+    if (p->opt.patch_faces == 0) p->opt.patch_faces = p->light ? 256 : 512;
     if ((rc = build_layout(p, p->opt.patch_faces, p->scatter, 0, s)) != MAD_OK) return rc;
     std::vector<PatternTerm> pts;
     for (auto& t : p->terms) pts.push_back({t.d_stencil, t.n, t.ns});

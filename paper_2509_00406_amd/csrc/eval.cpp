@@ -92,12 +92,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.n_cu = p->n_cu;
         L.normals = p->d_normals;
         L.shell = p->shell ? 1 : 0;
-        L.light = 1;
-        for (const auto& t : p->terms) {
-            const int k = t.kind;
-            if (!(k == MAD_EDGE_SQLEN || k == MAD_SPRING || k == MAD_INERTIA || k == MAD_RES_EDGE || k == MAD_RES_POSITION))
-                L.light = 0;
-        }
+        L.light = p->light ? 1 : 0;
         L.hvp = hvp ? 1 : 0;
         L.v = v;
         L.y = y;

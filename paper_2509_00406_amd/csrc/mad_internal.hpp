@@ -129,6 +129,7 @@ struct mad_problem {
     int32_t* d_work_counter = nullptr;
     std::string tune_report;              // last autotune table (JSON)
     bool shell = false;                   // a term reads the shell features (needs vertex normals)
+    bool light = true;                    // every term is a spring, inertia, edge-length or residual term
     int32_t* d_tris = nullptr;            // [nt][3] mesh triangles (normals)
     int32_t* d_vf_ptr = nullptr;          // [nv + 1] vertex -> triangles, ascending
     int32_t* d_vf = nullptr;

@@ -45,7 +45,7 @@ def test_library_is_gfx950_code_object():
 def test_version_and_defaults():
     assert mad.mad_version() == 100
     o = mad.mad_options_default()
-    assert o.patch_faces == 512 and o.spd_eps == 0.0 and o.scatter == mad.SCATTER_PATCH
+    assert o.patch_faces == 0 and o.spd_eps == 0.0 and o.scatter == mad.SCATTER_PATCH
 
 
 @pytest.mark.parametrize("name", ["two_tris", "octahedron", "nonmanifold", "grid5"])
