@@ -176,7 +176,16 @@ __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 // streams. The rotation zeroing a_pq uses t = tan(phi) = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)),
 // d = a_qq - a_pp (the smaller root of t^2 + 2 t d / (2 a_pq) - 1 = 0), c = 1/sqrt(1 + t^2),
 // s = t c, and A <- J^T A J, V <- V J with J_pp = J_qq = c, J_pq = s, J_qp = -s.
-// On return A's diagonal holds the eigenvalues and V's columns the eigenvectors. The matrix is
+//
+// Scaled rotations: the off-diagonal entries and the eigenvector columns are kept with a diagonal
+// scale, a_ij = d_i d_j b_ij (i != j) and V = W diag(d), while the diagonal of A is kept as is. A
+// rotation in the (p, q) plane multiplies d_p and d_q by c; the stored entries then change by one
+// fused multiply-add each, b_ip -= t (d_q / d_p) b_iq and b_iq += t (d_p / d_q) b_ip (the same for
+// W's columns), where the plain rotation needs two products and a multiply-add. The reciprocals
+// e = 1/d are carried along (e <- e sqrt(1 + t^2)), so no division is needed. c >= 1/sqrt(2), so
+// after s sweeps d >= 2^(-s (N - 1) / 2): no underflow in FP32 within the sweep limit, and the
+// stored entries grow by at most the inverse.
+// On return A's diagonal holds the eigenvalues and W diag(d) the eigenvectors. The matrix is
 // scaled to max |a_ij| = 1 first (and the eigenvalues scaled back) so squares cannot overflow.
 // Returns whether the off-diagonal mass fell below tol of the Frobenius norm within max_sweeps.
 __host__ __device__ constexpr int rr_players(int n) { return n + (n & 1); }
@@ -184,95 +193,107 @@ __host__ __device__ constexpr int rr_players(int n) { return n + (n & 1); }
 __host__ __device__ constexpr int rr_a(int M, int r, int k) { return k == 0 ? M - 1 : (r + k) % (M - 1); }
 __host__ __device__ constexpr int rr_b(int M, int r, int k) { return k == 0 ? r : (r - k + (M - 1)) % (M - 1); }
 
-// off-diagonal mass below tol of the Frobenius norm
+// off-diagonal mass (of the unscaled entries) below tol of the Frobenius norm
 template <int N, typename T>
-__device__ __forceinline__ bool jacobi_converged(const T (&A)[Packed<N>::N], T tol) {
+__device__ __forceinline__ bool jacobi_converged(const T (&A)[Packed<N>::N], const T (&dsc)[N], T tol) {
     T off = T(0), dg = T(0);
 #pragma unroll
     for (int p = 0; p < N; ++p) {
         dg += A[Packed<N>::at(p, p)] * A[Packed<N>::at(p, p)];
 #pragma unroll
-        for (int q = p + 1; q < N; ++q) off += A[Packed<N>::at(p, q)] * A[Packed<N>::at(p, q)];
+        for (int q = p + 1; q < N; ++q) {
+            const T a = dsc[p] * dsc[q] * A[Packed<N>::at(p, q)];
+            off += a * a;
+        }
     }
     return off <= tol * tol * (dg + T(2) * off);
 }
 
 // one sweep: every pair once, round by round
 template <int N, typename T>
-__device__ __forceinline__ void jacobi_sweep(T (&A)[Packed<N>::N], T (&V)[N][N]) {
+__device__ __forceinline__ void jacobi_sweep(T (&A)[Packed<N>::N], T (&W)[N][N], T (&dsc)[N], T (&inv)[N]) {
     constexpr int M = rr_players(N), H = M / 2;
 #pragma unroll
     for (int r = 0; r < M - 1; ++r) {
-        T cs[H], sn[H], tn[H];
+        T tn[H], ta[H];
         // parameters of the round's rotations (independent of each other)
 #pragma unroll
         for (int k = 0; k < H; ++k) {
             const int a = rr_a(M, r, k), b = rr_b(M, r, k);
             if (a >= N || b >= N) continue;
             const int p = a < b ? a : b, q = a < b ? b : a;
-            const T apq = A[Packed<N>::at(p, q)];
+            const T apq = dsc[p] * dsc[q] * A[Packed<N>::at(p, q)];
             const T d = A[Packed<N>::at(q, q)] - A[Packed<N>::at(p, p)];
             const T den = fabs(d) + fsqrt(d * d + T(4) * apq * apq);
             T t = (T(2) * apq) * frcp(den);
             t = d < T(0) ? -t : t;
             t = (apq == T(0)) ? T(0) : t;
-            const T c = frsq(t * t + T(1));
-            cs[k] = c;
-            sn[k] = t * c;
             tn[k] = t;
+            ta[k] = t * apq;
         }
 #pragma unroll
         for (int k = 0; k < H; ++k) {
             const int a = rr_a(M, r, k), b = rr_b(M, r, k);
             if (a >= N || b >= N) continue;
             const int p = a < b ? a : b, q = a < b ? b : a;
-            const T c = cs[k], s = sn[k], t = tn[k];
-            const T apq = A[Packed<N>::at(p, q)];
-            A[Packed<N>::at(p, p)] -= t * apq;
-            A[Packed<N>::at(q, q)] += t * apq;
+            const T t = tn[k];
+            const T w = t * t + T(1);
+            const T c = frsq(w);
+            const T u = t * dsc[q] * inv[p], v = t * dsc[p] * inv[q];
+            A[Packed<N>::at(p, p)] -= ta[k];
+            A[Packed<N>::at(q, q)] += ta[k];
             A[Packed<N>::at(p, q)] = T(0);
 #pragma unroll
             for (int i = 0; i < N; ++i) {
                 if (i == p || i == q) continue;
                 const T g = A[Packed<N>::at(i, p)], h = A[Packed<N>::at(i, q)];
-                A[Packed<N>::at(i, p)] = c * g - s * h;
-                A[Packed<N>::at(i, q)] = s * g + c * h;
+                A[Packed<N>::at(i, p)] = g - u * h;
+                A[Packed<N>::at(i, q)] = h + v * g;
             }
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                const T g = V[i][p], h = V[i][q];
-                V[i][p] = c * g - s * h;
-                V[i][q] = s * g + c * h;
+                const T g = W[i][p], h = W[i][q];
+                W[i][p] = g - u * h;
+                W[i][q] = h + v * g;
             }
+            const T ic = w * c;
+            dsc[p] *= c;
+            dsc[q] *= c;
+            inv[p] *= ic;
+            inv[q] *= ic;
         }
     }
 }
 
 template <int N, typename T>
-__device__ __forceinline__ bool jacobi_eig(T (&A)[Packed<N>::N], T (&V)[N][N], int max_sweeps, T tol) {
+__device__ __forceinline__ bool jacobi_eig(T (&A)[Packed<N>::N], T (&W)[N][N], T (&dsc)[N], int max_sweeps, T tol) {
+    T inv[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+    for (int i = 0; i < N; ++i) {
+        dsc[i] = T(1);
+        inv[i] = T(1);
 #pragma unroll
-        for (int j = 0; j < N; ++j) V[i][j] = (i == j) ? T(1) : T(0);
+        for (int j = 0; j < N; ++j) W[i][j] = (i == j) ? T(1) : T(0);
+    }
     T amax = T(0);
 #pragma unroll
     for (int i = 0; i < Packed<N>::N; ++i) amax = fmax(amax, fabs(A[i]));
     const T scale = amax > T(0) ? frcp(amax) : T(1);
 #pragma unroll
     for (int i = 0; i < Packed<N>::N; ++i) A[i] *= scale;
-    bool conv = jacobi_converged<N, T>(A, tol);
+    bool conv = jacobi_converged<N, T>(A, dsc, tol);
     if (!conv && max_sweeps > 0) {
-        // the first sweep on its own: V is still the identity there, so the products with its
-        // structural zeros and ones fold away at compile time (the element kernels are built
-        // without signed zeros and non-finite values)
-        jacobi_sweep<N, T>(A, V);
+        // the first sweep on its own: W is still the identity and the scales one there, so the
+        // products with their structural zeros and ones fold away at compile time (the element
+        // kernels are built without signed zeros and non-finite values)
+        jacobi_sweep<N, T>(A, W, dsc, inv);
         for (int sweep = 1;; ++sweep) {
-            if (jacobi_converged<N, T>(A, tol)) {
+            if (jacobi_converged<N, T>(A, dsc, tol)) {
                 conv = true;
                 break;
             }
             if (sweep == max_sweeps) break;
-            jacobi_sweep<N, T>(A, V);
+            jacobi_sweep<N, T>(A, W, dsc, inv);
         }
     }
 #pragma unroll
@@ -387,20 +408,21 @@ __device__ __forceinline__ void element_derivs(const double* xs, const double* r
     }
 }
 
-// clamp(Hq) = V diag(max(lambda, eps)) V^T into out.hr; returns whether the eigen-decomposition
+// clamp(Hq) = U diag(max(lambda, eps)) U^T into out.hr (U = V diag(dsc)); returns whether the eigen-decomposition
 // converged
 template <class Term, typename T>
 __device__ __forceinline__ bool element_clamp(T (&A)[Packed<Term::KR>::N], double eps, ElemOut<Term, T>& out) {
     constexpr int KR = Term::KR;
-    T V[KR][KR];
-    const bool conv = jacobi_eig<KR, T>(A, V, JacobiTol<T>::sweeps, JacobiTol<T>::tol);
+    T V[KR][KR], dsc[KR];
+    const bool conv = jacobi_eig<KR, T>(A, V, dsc, JacobiTol<T>::sweeps, JacobiTol<T>::tol);
     const T te = T(eps > 0.0 ? eps : 0.0);
 #pragma unroll
     for (int i = 0; i < Packed<KR>::N; ++i) out.hr[i] = T(0);
 #pragma unroll
     for (int m = 0; m < KR; ++m) {
+        // eigenvector m is column m of V times dsc[m]: its scale squared goes with the eigenvalue
         const T lam = A[Packed<KR>::at(m, m)];
-        const T lp = lam > te ? lam : te;
+        const T lp = (lam > te ? lam : te) * (dsc[m] * dsc[m]);
 #pragma unroll
         for (int i = 0; i < KR; ++i) {
             const T li = lp * V[i][m];
