@@ -37,8 +37,8 @@ sys.path.insert(0, ROOT)
 # workload (FP32 + FP64 VALU wave instructions x 64 lanes, FMA = 2), and its HBM traffic per launch
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy), from the rocprofv3 counter
 # passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
-FLOPS_PER_ELEM = {"f32": 18202.7, "f64": None}
-TRAFFIC_BYTES = {"f32": 1.0639e9, "f64": None}
+FLOPS_PER_ELEM = {"f32": 15487.7, "f64": None}
+TRAFFIC_BYTES = {"f32": 1.0643e9, "f64": None}
 # the same for the 1000^2 cloth step at its default layout (profiles/k_eval_patch_f32_cloth1000_counters.md)
 CLOTH_TRAFFIC_BYTES = {"f32": 0.5675e9, "f64": None}
 
