@@ -39,6 +39,28 @@ __device__ __forceinline__ float logisticf(float a) {
     return a >= 0.0f ? r : e * r;
 }
 
+// softplus and logistic of a from one exponential, with the hardware exp2, log2 and reciprocal
+// (a few ulp; used by the network pass): e = exp(-|a|), with the product -|a| log2(e) carried
+// to twice FP32 precision so that e keeps its relative accuracy for large |a|; sigma = 1/(1+e)
+// (a >= 0) or e/(1+e); softplus = max(a, 0) + log1p(e), with log1p(e) = log(u) e / (u - 1),
+// u = 1 + e rounded (accurate to a few ulp; e itself where u rounds to 1).
+__device__ __forceinline__ void softplus_logistic(float a, float& sp, float& sg) {
+    constexpr float kL2E = 1.44269502162933349609375f;          // log2(e) rounded to FP32
+    constexpr float kL2ELo = 1.925963033500011079e-8f;          // log2(e) - kL2E
+    constexpr float kLn2 = 0.693147180559945309f;
+    const float x = -fabsf(a);
+    const float t = x * kL2E;
+    const float tl = fmaf(x, kL2E, -t) + x * kL2ELo;
+    float e = __builtin_amdgcn_exp2f(t);
+    e = fmaf(e, tl * kLn2, e);
+    const float u = 1.0f + e;
+    const float r = __builtin_amdgcn_rcpf(u);
+    sg = a >= 0.0f ? r : e * r;
+    const float um1 = u - 1.0f;
+    const float l1p = um1 == 0.0f ? e : (__builtin_amdgcn_logf(u) * kLn2) * (e * __builtin_amdgcn_rcpf(um1));
+    sp = fmaxf(a, 0.0f) + l1p;
+}
+
 // ---- vertex normals ------------------------------------------------------------------------------
 __global__ void k_vertex_normals(const double* x, int64_t nv, const int32_t* vf_ptr, const int32_t* vf,
                                  const int32_t* tris, double* normals) {
@@ -162,8 +184,9 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
         float xh[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) xh[i] = valid ? L.xh[(int64_t)i * L.n + e] : 0.0f;
-        // layer 1 at this lane's 16 units (B layout)
-        float a1[2][8], s1[2][8];
+        // layer 1 at this lane's 16 units (B layout); sp(a1) goes straight into channel 0's operands
+        float s1[2][8];
+        bf16x8 b0h[2], b0m[2], b0l[2];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
@@ -172,8 +195,10 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
                 float a = sB1[k];
 #pragma unroll
                 for (int i = 0; i < 6; ++i) a = fmaf(sW1[k * 6 + i], xh[i], a);
-                a1[ks][j] = a;
-                s1[ks][j] = logisticf(a);
+                float sp, sg;
+                softplus_logistic(a, sp, sg);
+                s1[ks][j] = sg;
+                split3(sp, b0h[ks], b0m[ks], b0l[ks], j);
             }
         // layer 2, seven forward channels: c = 0 value, c = 1 + i first derivative along xh_i
         float P0 = 0.0f, PH[21];
@@ -183,14 +208,22 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
 #pragma unroll
         for (int c = 0; c < 7; ++c) {
             bf16x8 bh[2], bm[2], bl[2];
+            if (c == 0) {
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int k = 32 * ks + 8 * g + j;
-                    const float x = c == 0 ? softplusf(a1[ks][j]) : s1[ks][j] * sW1[k * 6 + (c > 0 ? c - 1 : 0)];
-                    split3(x, bh[ks], bm[ks], bl[ks], j);
+                for (int ks = 0; ks < 2; ++ks) {
+                    bh[ks] = b0h[ks];
+                    bm[ks] = b0m[ks];
+                    bl[ks] = b0l[ks];
                 }
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int k = 32 * ks + 8 * g + j;
+                        split3(s1[ks][j] * sW1[k * 6 + c - 1], bh[ks], bm[ks], bl[ks], j);
+                    }
+            }
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -206,10 +239,11 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
                     const int m = 16 * mt + 4 * g + jj;
                     if (c == 0) {
                         const float a2 = acc[jj] + sB2[m];
-                        const float sg = logisticf(a2);
+                        float sp, sg;
+                        softplus_logistic(a2, sp, sg);
                         v[mt][jj] = sW3[m] * sg;
                         ws2p[mt][jj] = sW3[m] * sg * (1.0f - sg);
-                        P0 = fmaf(sW3[m], softplusf(a2), P0);
+                        P0 = fmaf(sW3[m], sp, P0);
                     } else {
                         a2g[c - 1][mt][jj] = acc[jj];
                     }
