@@ -216,6 +216,26 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "note": "each copy reads and writes this many bytes"}), flush=True)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second, GB/s): the reachable HBM
+    rate this box shows for a plain stream, beside the published 8 TB/s."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (t0.elapsed_time(t1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def make_problem(mad, mesh, inp, prec, args, stream, form=None):
     """form: "plain" (StVK + bending), "mlp" (learned density), "analytic" (shell-triangle density),
     "cloth" (springs + inertia); default: the workload's own."""
@@ -315,6 +335,7 @@ def main():
     stage_ms, n_evals = mad.mad_problem_profile(prob.handle)
     ms_per_step = max(wall * 1e3, sum(step_ms)) / args.steps
     nonfinite, fallbacks = prob.status()
+    copy_gbs = copy_bandwidth()   # after the timed region
 
     n_terms = {"mlp": 1, "cloth": 2}.get(args.workload, len(SHELL_TERMS))
     if layout["scatter"] == mad.SCATTER_PATCH:
@@ -380,7 +401,8 @@ def main():
                    "layout": layout},
         "roofline": roofline,
         "hbm": {"alg_bytes_per_step": step_bytes, "alg_GBs": step_bytes / (ms_per_step * 1e-3) / 1e9,
-                "frac_of_peak": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                "frac_of_peak": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "copy_GBs": copy_gbs, "frac_of_copy": step_bytes / (ms_per_step * 1e-3) / 1e9 / copy_gbs},
         "stages_ms_per_step": stages,
         "setup_s": setup_s,
         "fp64_fallbacks": fallbacks,
