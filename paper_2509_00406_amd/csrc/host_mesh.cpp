@@ -50,28 +50,37 @@ int kind_nrest(int kind) {
 // An edge with exactly two incident faces yields a diamond (v0, v1, v2, v3): (v0, v1) as the
 // edge is directed in the lower-indexed face f1, v2 opposite in f1, v3 opposite in f2.
 int build_topology(mad_mesh& m) {
-    struct Rec {
-        int32_t lo, hi, face, from, to, opp;
-    };
+    // edge-sides as corner ids c = 3 f + k: the side from tris[c] to the next corner of face f,
+    // opposite the remaining corner
     const int64_t nr = 3 * m.nt;
-    std::vector<Rec> rec((size_t)nr);
-    for (int64_t f = 0; f < m.nt; ++f) {
-        const int32_t* t = &m.tris[3 * f];
-        for (int c = 0; c < 3; ++c) {
-            Rec& r = rec[3 * f + c];
-            r.from = t[c];
-            r.to = t[(c + 1) % 3];
-            r.opp = t[(c + 2) % 3];
-            r.lo = std::min(r.from, r.to);
-            r.hi = std::max(r.from, r.to);
-            r.face = (int32_t)f;
-        }
+    const int32_t* T = m.tris.data();
+    auto from = [&](int64_t c) { return T[c]; };
+    auto to = [&](int64_t c) { return T[c - c % 3 + (c % 3 + 1) % 3]; };
+    auto opp = [&](int64_t c) { return T[c - c % 3 + (c % 3 + 2) % 3]; };
+    auto lo = [&](int64_t c) { return std::min(from(c), to(c)); };
+    auto hi = [&](int64_t c) { return std::max(from(c), to(c)); };
+    // order by (lo, hi, face): a counting sort by lo (ids are generated in face order, so each
+    // bucket keeps ascending faces), then an insertion sort by hi inside each bucket (a vertex's
+    // bucket holds a handful of sides)
+    std::vector<int32_t> rec((size_t)nr);
+    {
+        std::vector<int64_t> start((size_t)m.nv + 1, 0);
+        for (int64_t c = 0; c < nr; ++c) ++start[(size_t)lo(c) + 1];
+        for (int64_t v = 0; v < m.nv; ++v) start[v + 1] += start[v];
+        std::vector<int64_t> fill(start.begin(), start.end() - 1);
+        for (int64_t c = 0; c < nr; ++c) rec[(size_t)fill[lo(c)]++] = (int32_t)c;
+        for (int64_t v = 0; v < m.nv; ++v)
+            for (int64_t a = start[v] + 1; a < start[v + 1]; ++a) {
+                const int32_t x = rec[(size_t)a];
+                const int32_t hx = hi(x);
+                int64_t b = a;
+                while (b > start[v] && hi(rec[(size_t)b - 1]) > hx) {
+                    rec[(size_t)b] = rec[(size_t)b - 1];
+                    --b;
+                }
+                rec[(size_t)b] = x;
+            }
     }
-    std::sort(rec.begin(), rec.end(), [](const Rec& a, const Rec& b) {
-        if (a.lo != b.lo) return a.lo < b.lo;
-        if (a.hi != b.hi) return a.hi < b.hi;
-        return a.face < b.face;
-    });
     m.edges.clear();
     m.edge_nf.clear();
     m.edge_face0.clear();
@@ -79,20 +88,29 @@ int build_topology(mad_mesh& m) {
     m.diamond_faces.clear();
     std::vector<int32_t> deg((size_t)m.nt, 0);
     std::vector<std::pair<int32_t, int32_t>> links;
+    // a closed manifold has 3T/2 edges, each interior one a diamond and a face link
+    m.edges.reserve((size_t)nr + 2);
+    m.edge_nf.reserve((size_t)nr / 2 + 1);
+    m.edge_face0.reserve((size_t)nr / 2 + 1);
+    m.diamonds.reserve((size_t)nr * 2);
+    m.diamond_faces.reserve((size_t)nr);
+    links.reserve((size_t)nr / 2 + 1);
     for (int64_t i = 0; i < nr;) {
+        const int32_t li = lo(rec[i]), hi_i = hi(rec[i]);
         int64_t j = i;
-        while (j < nr && rec[j].lo == rec[i].lo && rec[j].hi == rec[i].hi) ++j;
-        m.edges.push_back(rec[i].lo);
-        m.edges.push_back(rec[i].hi);
+        while (j < nr && lo(rec[j]) == li && hi(rec[j]) == hi_i) ++j;
+        const int32_t f0 = rec[i] / 3;
+        m.edges.push_back(li);
+        m.edges.push_back(hi_i);
         m.edge_nf.push_back((int32_t)(j - i));
-        m.edge_face0.push_back(rec[i].face);
+        m.edge_face0.push_back(f0);
         if (j - i == 2) {
-            m.diamonds.insert(m.diamonds.end(), {rec[i].from, rec[i].to, rec[i].opp, rec[i + 1].opp});
-            m.diamond_faces.insert(m.diamond_faces.end(), {rec[i].face, rec[i + 1].face});
+            m.diamonds.insert(m.diamonds.end(), {from(rec[i]), to(rec[i]), opp(rec[i]), opp(rec[i + 1])});
+            m.diamond_faces.insert(m.diamond_faces.end(), {f0, rec[i + 1] / 3});
         }
         for (int64_t a = i; a < j; ++a)
             for (int64_t b = a + 1; b < j; ++b)
-                if (rec[a].face != rec[b].face) links.push_back({rec[a].face, rec[b].face});
+                if (rec[a] / 3 != rec[b] / 3) links.push_back({rec[a] / 3, rec[b] / 3});
         i = j;
     }
     // face adjacency CSR
