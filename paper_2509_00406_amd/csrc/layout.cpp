@@ -31,36 +31,47 @@ static int alloc_layout(mad_problem* p, void** dst, size_t bytes) {
 // vertex, and store them colour by colour (stable), so that the elements a wave evaluates together
 // rarely add into the same LDS accumulators.
 static void color_within_patches(Term& t, int64_t nv) {
-    std::vector<uint64_t> busy_at((size_t)nv, 0);
-    std::vector<int32_t> color, order, seg;
-    for (size_t q = 0; q + 1 < t.elem_ptr.size(); ++q) {
-        const int32_t b = t.elem_ptr[q], e = t.elem_ptr[q + 1];
-        if (e - b < 2) continue;
-        color.assign((size_t)(e - b), 0);
-        for (int32_t i = b; i < e; ++i) {
-            const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-            uint64_t busy = 0;
-            for (int a = 0; a < t.ns; ++a) busy |= busy_at[st[a]];
-            int c = 0;
-            while (c < 63 && ((busy >> c) & 1ull)) ++c;
-            color[i - b] = c;
-            for (int a = 0; a < t.ns; ++a) busy_at[st[a]] |= 1ull << c;
+    const int32_t np = (int32_t)t.elem_ptr.size() - 1;
+    // patches are independent: split them over threads, each with its own vertex bit array
+    auto work = [&](int32_t q0, int32_t q1) {
+        std::vector<uint64_t> busy_at((size_t)nv, 0);
+        std::vector<int32_t> color, order, seg;
+        for (int32_t q = q0; q < q1; ++q) {
+            const int32_t b = t.elem_ptr[q], e = t.elem_ptr[q + 1];
+            if (e - b < 2) continue;
+            color.assign((size_t)(e - b), 0);
+            for (int32_t i = b; i < e; ++i) {
+                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                uint64_t busy = 0;
+                for (int a = 0; a < t.ns; ++a) busy |= busy_at[st[a]];
+                int c = 0;
+                while (c < 63 && ((busy >> c) & 1ull)) ++c;
+                color[i - b] = c;
+                for (int a = 0; a < t.ns; ++a) busy_at[st[a]] |= 1ull << c;
+            }
+            for (int32_t i = b; i < e; ++i) {
+                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                for (int a = 0; a < t.ns; ++a) busy_at[st[a]] = 0;
+            }
+            order.resize((size_t)(e - b));
+            std::iota(order.begin(), order.end(), 0);
+            std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return color[x] < color[y]; });
+            seg.assign(t.perm.begin() + b, t.perm.begin() + e);
+            for (int32_t i = 0; i < e - b; ++i) t.perm[b + i] = seg[order[i]];
         }
-        for (int32_t i = b; i < e; ++i) {
-            const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-            for (int a = 0; a < t.ns; ++a) busy_at[st[a]] = 0;
-        }
-        order.resize((size_t)(e - b));
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return color[x] < color[y]; });
-        seg.assign(t.perm.begin() + b, t.perm.begin() + e);
-        for (int32_t i = 0; i < e - b; ++i) t.perm[b + i] = seg[order[i]];
-    }
+    };
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int w = 1; w < nth; ++w)
+        pool.emplace_back(work, (int32_t)((int64_t)np * w / nth), (int32_t)((int64_t)np * (w + 1) / nth));
+    work(0, (int32_t)((int64_t)np / nth));
+    for (auto& th : pool) th.join();
 }
 
 // Patch order of every term's elements: faces by their patch, diamonds by their lower face, edges
-// by their first face, vertices by their lowest face; inside a patch by colour, then by that face's index. Two stable counting
-// sorts (by face, then by patch): linear in the element count.
+// by their first face, vertices by their lowest face; inside a patch by that face's index. Two
+// stable counting sorts (by face, then by patch): linear in the element count. The colour order
+// inside each patch (color_within_patches) is applied once the patches are final.
 static void order_terms(mad_problem* p) {
     const mad_mesh& m = *p->mesh;
     const int32_t np = p->patches.n;
@@ -84,7 +95,6 @@ static void order_terms(mad_problem* p) {
         std::vector<int32_t> fill(t.elem_ptr.begin(), t.elem_ptr.end() - 1);
         t.perm.resize((size_t)t.n);
         for (int32_t e : byface) t.perm[fill[p->patches.face_patch[key[e]]]++] = e;
-        color_within_patches(t, m.nv);
     }
 }
 
@@ -167,6 +177,7 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
     free_layout(p);
     p->scatter = scatter;
     p->persistent = scatter == MAD_SCATTER_PATCH ? persistent : 0;
+    // the fit below needs only which elements each patch holds: the colour order comes after it
     build_patches(m, target, p->patches);
     order_terms(p);
     if (scatter == MAD_SCATTER_PATCH) {
@@ -189,6 +200,7 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
             order_terms(p);
         }
     }
+    for (auto& t : p->terms) color_within_patches(t, m.nv);
     p->opt.patch_faces = target;
     const int32_t np = p->patches.n;
     int rc;
