@@ -34,7 +34,7 @@ int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const 
     const int32_t np = P.patches.n;
     const int nt = (int)P.terms.size();
     const int64_t nv = P.mesh->nv;
-    std::vector<std::vector<int32_t>> pv((size_t)np), pb_r((size_t)np), pb_c((size_t)np);
+    std::vector<std::vector<int32_t>> pv((size_t)np), pb_g((size_t)np), pb_gt((size_t)np);
     // per term, per element (patch order): local maps
     L.lvert.assign(nt, {});
     L.lslot.assign(nt, {});
@@ -68,15 +68,18 @@ int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const 
             std::sort(keys.begin(), keys.end());
             keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
             if (keys.size() > (1u << 14) || verts.size() > (1u << 16)) {
-                err.store(1);
+                err.fetch_or(1);
                 continue;
             }
             pv[p] = verts;
-            pb_r[p].resize(keys.size());
-            pb_c[p].resize(keys.size());
+            // global indices of the patch's upper blocks and of their transposes
+            pb_g[p].resize(keys.size());
+            pb_gt[p].resize(keys.size());
             for (size_t k = 0; k < keys.size(); ++k) {
-                pb_r[p][k] = (int32_t)(keys[k] / nv);
-                pb_c[p][k] = (int32_t)(keys[k] % nv);
+                const int32_t r = (int32_t)(keys[k] / nv), c = (int32_t)(keys[k] % nv);
+                pb_g[p][k] = find_block(rowptr, colidx, r, c);
+                pb_gt[p][k] = find_block(rowptr, colidx, c, r);
+                if (pb_g[p][k] < 0 || pb_gt[p][k] < 0) err.fetch_or(2);
             }
             for (int t = 0; t < nt; ++t) {
                 const Term& T = P.terms[t];
@@ -109,6 +112,7 @@ int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const 
         th.emplace_back(work, p0, p1);
     }
     for (auto& x : th) x.join();
+    if (err.load() & 2) return fail(MAD_E_HIP, "internal error: patch block missing from the pattern");
     if (err.load()) return fail(MAD_E_UNSUPPORTED, "a patch touches more than 16384 blocks; use smaller patches");
 
     // concatenate, resolve global block indices, count patch occurrences for exclusivity
@@ -116,7 +120,7 @@ int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const 
     L.lb_ptr.assign((size_t)np + 1, 0);
     for (int32_t p = 0; p < np; ++p) {
         L.lv_ptr[p + 1] = L.lv_ptr[p] + (int32_t)pv[p].size();
-        L.lb_ptr[p + 1] = L.lb_ptr[p] + (int32_t)pb_r[p].size();
+        L.lb_ptr[p + 1] = L.lb_ptr[p] + (int32_t)pb_g[p].size();
     }
     L.lv_global.resize((size_t)L.lv_ptr[np]);
     L.lv_halo.resize((size_t)L.lv_ptr[np]);
@@ -129,13 +133,10 @@ int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const 
             L.lv_global[L.lv_ptr[p] + k] = pv[p][k];
             vcount[pv[p][k]]++;
         }
-        for (size_t k = 0; k < pb_r[p].size(); ++k) {
-            const int32_t g = find_block(rowptr, colidx, pb_r[p][k], pb_c[p][k]);
-            const int32_t gt = find_block(rowptr, colidx, pb_c[p][k], pb_r[p][k]);
-            if (g < 0 || gt < 0) return fail(MAD_E_HIP, "internal error: patch block missing from the pattern");
-            L.lb_gidx[L.lb_ptr[p] + k] = g;
-            L.lb_gidxT[L.lb_ptr[p] + k] = gt;
-            bcount[g]++;
+        for (size_t k = 0; k < pb_g[p].size(); ++k) {
+            L.lb_gidx[L.lb_ptr[p] + k] = pb_g[p][k];
+            L.lb_gidxT[L.lb_ptr[p] + k] = pb_gt[p][k];
+            bcount[pb_g[p][k]]++;
         }
     }
     // halo slots, assigned patch by patch (each patch writes its shared partials contiguously)
