@@ -76,7 +76,8 @@ typedef enum mad_status {
  *                  mad_problem_add_mlp_term, not mad_problem_add_term.
  *  MAD_SHELL_TRI   face, VarDim 3: A W(z), W = mu (E00^2 + E11^2 + 2 E01^2) + lambda/2 (E00 + E11)^2
  *                  + k_b/2 (dII00^2 + dII11^2 + 2 dII01^2). params = {mu, lambda, k_b}. The
- *                  analytic density the network is trained on (its fallback and error judge).
+ *                  analytic density the network is trained on (its fallback, and the reference its
+ *                  error is measured against).
  * Mass-spring cloth (Sec. 7.1: implicit Euler, E = 1/2 |x - xhat|_M^2 + h^2 P(x)):
  *  MAD_SPRING      edge, VarDim 3: w (k/2) l^2 (|x0 - x1|^2 / l^2 - 1)^2, l the rest length.
  *                  params = {k, w} (w = h^2, the potential's weight). Needs rest positions.

@@ -1,6 +1,6 @@
 """Build libmad.so (HIP for gfx950) in-tree with hipcc.
 
-Run as ``python -m paper_2509_00406_amd.build`` or through __graft_entry__.build().
+Run as ``python -m paper_2509_00406_amd.build`` (the repository's build entry point calls the same function).
 Every call recompiles (the objects go to _build/ next to the sources).
 """
 from __future__ import annotations

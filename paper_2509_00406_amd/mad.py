@@ -102,8 +102,8 @@ def lib() -> C.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
-                               "(python -m paper_2509_00406_amd.build)")
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "python -m paper_2509_00406_amd.build")
         h = C.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             fn = getattr(h, name)
