@@ -37,8 +37,9 @@ sys.path.insert(0, ROOT)
 # workload (FP32 + FP64 VALU wave instructions x 64 lanes, FMA = 2), and its HBM traffic per launch
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy), from the rocprofv3 counter
 # passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
-FLOPS_PER_ELEM = {"f32": 15487.7, "f64": None}
-TRAFFIC_BYTES = {"f32": 1.0643e9, "f64": None}
+FLOPS_PER_ELEM = {"f32": 15482.0, "f64": None}
+# traffic by launch (persistent queue / one workgroup per patch) at the default 288-face layout
+TRAFFIC_BYTES = {"f32": {1: 1.3733e9, 0: 1.0643e9}, "f64": None}
 # the same for the 1000^2 cloth step at its default layout (profiles/k_eval_patch_f32_cloth1000_counters.md)
 CLOTH_TRAFFIC_BYTES = {"f32": 0.5675e9, "f64": None}
 
@@ -62,7 +63,8 @@ def parse():
     ap.add_argument("--mlp-n", type=int, default=708, help="grid side of the learned-density workload")
     ap.add_argument("--patch-faces", type=int, default=0)
     ap.add_argument("--scatter", choices=["patch", "atomic"], default="patch")
-    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--persistent", action="store_true", help="persistent launch (the default for heavy terms)")
+    ap.add_argument("--per-patch", action="store_true", help="one workgroup per patch (the default for light terms)")
     ap.add_argument("--autotune", action="store_true", help="choose the layout by timing (batched: always)")
     ap.add_argument("--no-fp64-plain", action="store_true", help="skip the FP64 GPU comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -254,9 +256,9 @@ def make_problem(mad, mesh, inp, prec, args, stream, form=None):
         for k, prm in SHELL_TERMS:
             prob.add_term(k, prm, inp.rest)
     prob.finalize(stream)
-    if args.persistent:
+    if args.persistent or args.per_patch:
         lay = prob.layout()
-        prob.set_layout(lay["scatter"], lay["patch_faces"], 1, stream)
+        prob.set_layout(lay["scatter"], lay["patch_faces"], 1 if args.persistent else 0, stream)
     return prob
 
 
@@ -375,7 +377,10 @@ def main():
     elif fpe:
         achieved = fpe * n_elem / (dom_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                    "frac": achieved / peak, "traffic": TRAFFIC_BYTES.get(args.precision), "kernel_ms": dom_ms,
+                    "frac": achieved / peak,
+                    "traffic": ((TRAFFIC_BYTES.get(args.precision) or {}).get(layout["persistent"])
+                                if layout["patch_faces"] == 288 else None),
+                    "kernel_ms": dom_ms,
                     "flops_per_element": fpe}
     else:
         roofline = {"bound": "alu", "kernel": dom_name, "achieved": None, "peak": peak, "unit": "TFLOP/s",

@@ -193,7 +193,9 @@ int32_t mad_problem_add_vertex_term(mad_problem *prob, int32_t kind, const doubl
                                     const double *vdata_dev);
 
 /* Build patches, upload element data and build the block pattern on the GPU (Sec. 6.1), once.
- * Starts with the layout of the options (persistent launch off). Synchronises the stream. */
+ * Starts with the layout of the options; with the patch scatter the launch is persistent unless every
+ * term is a spring, inertia, edge-length or residual term (those run one workgroup per patch).
+ * Synchronises the stream. */
 int32_t mad_problem_finalize(mad_problem *prob, void *stream);
 
 /* Dynamic sparsity (Sec. 6.3): before mad_problem_finalize, reserve room for interaction pairs. The

@@ -357,7 +357,10 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
     // the scatter structures that index into it
     // default patch target: smaller patches for cheap elements (more workgroups to hide their latency)
     if (p->opt.patch_faces == 0) p->opt.patch_faces = p->light ? 256 : 512;
-    if ((rc = build_layout(p, p->opt.patch_faces, p->scatter, 0, s)) != MAD_OK) return rc;
+    // default launch: the persistent grid for the patch scatter of heavy elements (a workgroup's
+    // flush of one patch overlaps its next patch's work); one workgroup per patch for light terms
+    const int persistent = (p->scatter == MAD_SCATTER_PATCH && !p->light) ? 1 : 0;
+    if ((rc = build_layout(p, p->opt.patch_faces, p->scatter, persistent, s)) != MAD_OK) return rc;
     std::vector<PatternTerm> pts;
     for (auto& t : p->terms) pts.push_back({t.d_stencil, t.n, t.ns});
     if ((rc = build_pattern_device(m.nv, pts, &p->d_rowptr, &p->d_colidx, &p->nnzb, p->owned, s)) != MAD_OK) return rc;
