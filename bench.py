@@ -37,9 +37,9 @@ sys.path.insert(0, ROOT)
 # workload (FP32 + FP64 VALU wave instructions x 64 lanes, FMA = 2), and its HBM traffic per launch
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy), from the rocprofv3 counter
 # passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
-FLOPS_PER_ELEM = {"f32": 15482.0, "f64": None}
-# traffic by launch (persistent queue / one workgroup per patch) at the default 288-face layout
-TRAFFIC_BYTES = {"f32": {1: 1.3733e9, 0: 1.0643e9}, "f64": None}
+FLOPS_PER_ELEM = {"f32": 14924.3, "f64": None}
+# traffic by launch (persistent queue / one workgroup per patch) at the default 384-face layout
+TRAFFIC_BYTES = {"f32": {1: 1.3109e9, 0: 1.0353e9}, "f64": None}
 # the same for the 1000^2 cloth step at its default layout (profiles/k_eval_patch_f32_cloth1000_counters.md)
 CLOTH_TRAFFIC_BYTES = {"f32": 0.5675e9, "f64": None}
 
@@ -379,7 +379,7 @@ def main():
         roofline = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                     "frac": achieved / peak,
                     "traffic": ((TRAFFIC_BYTES.get(args.precision) or {}).get(layout["persistent"])
-                                if layout["patch_faces"] == 288 else None),
+                                if layout["patch_faces"] == 384 else None),
                     "kernel_ms": dom_ms,
                     "flops_per_element": fpe}
     else:

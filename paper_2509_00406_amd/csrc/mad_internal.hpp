@@ -195,7 +195,7 @@ int build_scatter(mad_problem* p, hipStream_t s);
 // one evaluation; with v != NULL the matrix-free product y = H v replaces the Hessian (hess NULL)
 int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
                  hipStream_t s, const double* v = nullptr, void* y = nullptr);
-constexpr size_t kLdsBudget = 60 * 1024;  // dynamic LDS per workgroup: two workgroups per CU
+constexpr size_t kLdsBudget = 76 * 1024;  // dynamic LDS per workgroup: two workgroups in a CU's 160 KB
 // work units (64 elements of one term) per patch: the patch kernel keeps one energy slot per unit
 constexpr int kMaxPatchUnits = 256;
 int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& colidx,
