@@ -14,6 +14,10 @@ Workloads:
   cloth   mass-spring cloth time step (Sec. 7.1): springs on the 2,996,001 edges
           of a 1000 x 1000 grid plus inertia and gravity per vertex, filtered
           Hessian; also timed at the Table 1 sizes 10^2 ... 1000^2 vertices.
+  symdir  symmetric Dirichlet parameterisation energy (Sec. 7.2) on a 1001 x 1001
+          disk-topology grid (2,000,000 triangles) with UVs warped by 8 seeded
+          sinusoids: 2 DOFs per vertex, 2x2 blocks, eigen-clamped 6x6 element
+          Hessians.
 
 One step = one mad_problem_eval(ENERGY | GRAD | HESS | SPD) over the whole
 workload with inputs resident in HBM (topology, patches and pattern are built
@@ -56,7 +60,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--workload", choices=["shell", "batched", "mlp", "cloth"], default="shell")
+    ap.add_argument("--workload", choices=["shell", "batched", "mlp", "cloth", "symdir"], default="shell")
+    ap.add_argument("--symdir-n", type=int, default=1001, help="grid side of the parameterisation workload")
     ap.add_argument("--cloth-n", type=int, default=1000, help="grid side of the cloth workload")
     ap.add_argument("--n", type=int, default=1024, help="grid side of the shell workload")
     ap.add_argument("--meshes", type=int, default=700, help="meshes of the batched workload")
@@ -98,6 +103,10 @@ def workload(args):
         inp = meshgen.icosphere_batch(n_meshes=args.meshes)
         desc = (f"batched: {args.meshes} geodesic icospheres (lognormal sizes), StVK+bending, one launch, "
                 f"per-mesh FP64 energies, SPD-projected Hessians, block-CSR 3x3")
+    elif args.workload == "symdir":
+        inp = meshgen.warped_grid(n=args.symdir_n, seed=3001)
+        desc = (f"symmetric Dirichlet parameterisation, {args.symdir_n}x{args.symdir_n} disk grid, UVs warped by 8 "
+                f"seeded sinusoids (amplitude 0.1), 2 DOFs per vertex, SPD-projected Hessians, block-CSR 2x2")
     elif args.workload == "cloth":
         inp = meshgen.cloth(n=args.cloth_n, seed=6001)
         desc = (f"mass-spring cloth step: springs on every edge + inertia and gravity per vertex, "
@@ -160,21 +169,57 @@ def cpu_baseline(inp, budget, mlp=None):
             P.add_term({4: O.STVK, 5: O.BENDING}[k], prm)
     P.build_pattern()
     n_el = int(tris.shape[0]) + (int(P.topo.diamonds.shape[0]) if mlp is None else 0)
-    t0 = time.perf_counter()
-    P.eval(x, O.ENERGY | O.GRAD | O.HESS | O.SPD, scales=False)
-    dt = time.perf_counter() - t0
-    cpu = "unknown"
+    kind = "learned-density triangles" if mlp is not None else "StVK triangles + bending diamonds"
+    return time_oracle(P, x, n_el, f"{what}: {n_el} elements ({kind}), energy + gradient + SPD-projected Hessian "
+                                   f"+ assembly, FP64")
+
+
+def host_threads():
+    """Threads the oracle may use here: this process's CPU affinity, capped by OMP_NUM_THREADS if set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": n_el / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}: {n_el} elements ({'learned-density triangles' if mlp is not None else 'StVK triangles + bending diamonds'}), energy + gradient + "
-                      f"SPD-projected Hessian + assembly, FP64, one thread, {dt:.1f} s on {cpu}; "
-                      f"host nproc {os.cpu_count()}"}
+    return "unknown"
+
+
+def time_oracle(P, x, n_el, what):
+    """The FP64 oracle on one sample, four ways: its parity build (gcc -O2, no FMA contraction) on all the
+    host threads this process may use (the reported value) and on one thread, and its -O3 -march=native
+    timing build on one and on all threads. The threaded evaluation is bit-identical to the serial one
+    (per-element work in parallel, each block row summed by one thread in the serial order)."""
+    from oracle import oracle as O
+    mode = O.ENERGY | O.GRAD | O.HESS | O.SPD
+    nth = host_threads()
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+    t1 = timed(lambda: P.eval(x, mode, scales=False))
+    tn = timed(lambda: P.eval_par(x, mode, threads=nth))
+    fast = {}
+    try:
+        with O.using(O.load(O.build_fast())):
+            f1 = timed(lambda: P.eval_par(x, mode, threads=1))
+            fn_ = timed(lambda: P.eval_par(x, mode, threads=nth))
+        fast = {"one_thread": n_el / f1, "all_threads": n_el / fn_, "build": "gcc -O3 -march=native -fopenmp"}
+    except Exception as exc:   # a host without a working gcc: report the parity build only
+        fast = {"error": str(exc)[:200]}
+    return {"value": n_el / tn, "unit": "elements/s", "cores": nth, "kind": "oracle",
+            "sample": f"{what}; parity build (gcc -O2 -ffp-contract=off), {nth} threads, {tn:.2f} s "
+                      f"(one thread {t1:.1f} s) on {cpu_model()}; host nproc {os.cpu_count()}",
+            "one_thread": n_el / t1, "o3_native": fast}
 
 
 def summarize_counters(path, n_elements):
@@ -241,10 +286,12 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
 def make_problem(mad, mesh, inp, prec, args, stream, form=None):
     """form: "plain" (StVK + bending), "mlp" (learned density), "analytic" (shell-triangle density),
     "cloth" (springs + inertia); default: the workload's own."""
-    form = form or {"mlp": "mlp", "cloth": "cloth"}.get(args.workload, "plain")
+    form = form or {"mlp": "mlp", "cloth": "cloth", "symdir": "symdir"}.get(args.workload, "plain")
     scatter = mad.SCATTER_PATCH if args.scatter == "patch" else mad.SCATTER_ATOMIC
-    prob = mad.Problem(mesh, 3, prec, patch_faces=args.patch_faces, scatter=scatter)
-    if form == "cloth":
+    prob = mad.Problem(mesh, 2 if form == "symdir" else 3, prec, patch_faces=args.patch_faces, scatter=scatter)
+    if form == "symdir":
+        prob.add_term(mad.SYMDIR, (), inp.rest)
+    elif form == "cloth":
         import torch
         prob.add_term(mad.SPRING, inp.meta["spring_params"], inp.rest)
         prob.add_vertex_term(mad.INERTIA, inp.meta["inertia_params"], torch.from_numpy(inp.meta["vdata"]).cuda())
@@ -317,6 +364,8 @@ def main():
     mode = mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD
     if args.workload == "cloth":
         n_elem = mesh.n_edges + mesh.n_verts
+    elif args.workload == "symdir":
+        n_elem = mesh.n_tris
     else:
         n_elem = mesh.n_tris + (mesh.n_diamonds if args.workload != "mlp" else 0)
     tune = None
@@ -339,10 +388,11 @@ def main():
     nonfinite, fallbacks = prob.status()
     copy_gbs = copy_bandwidth()   # after the timed region
 
-    n_terms = {"mlp": 1, "cloth": 2}.get(args.workload, len(SHELL_TERMS))
+    n_terms = {"mlp": 1, "cloth": 2, "symdir": 1}.get(args.workload, len(SHELL_TERMS))
     if layout["scatter"] == mad.SCATTER_PATCH:
         dom_name = {"mlp": "k_eval_patch (learned-density chain + clamp + assembly)",
-                    "cloth": "k_eval_patch (springs + inertia fused)"}.get(args.workload,
+                    "cloth": "k_eval_patch (springs + inertia fused)",
+                    "symdir": "k_eval_patch (symmetric Dirichlet, 2x2 blocks)"}.get(args.workload,
                                                                           "k_eval_patch (StVK + bending fused)")
         dom_ms = stage_ms[2] / n_evals
         stages = {"fill": stage_ms[0] / n_evals, "network": stage_ms[1] / n_evals, "fused": stage_ms[2] / n_evals,
@@ -352,12 +402,15 @@ def main():
         dom = int(np.argmax(term_ms))
         dom_ms = term_ms[dom] / n_evals
         names = (["k_eval<spring>", "k_eval<inertia>"] if args.workload == "cloth"
+                 else ["k_eval<symdir>"] if args.workload == "symdir"
                  else ["k_eval<StVK>", "k_eval<bending>"][:n_terms])
         dom_name = names[dom]
         stages = {"fill": stage_ms[0] / n_evals, **{nm: t / n_evals for nm, t in zip(names, term_ms)},
                   "energy": stage_ms[-1] / n_evals}
     if args.workload == "cloth":
         step_bytes = cloth_alg_bytes(mesh.n_verts, mesh.n_edges, prob.nnzb, pb)
+    elif args.workload == "symdir":
+        step_bytes = symdir_alg_bytes(mesh.n_verts, mesh.n_tris, prob.nnzb, pb)
     elif args.workload == "mlp":   # triangles only, 8 rest doubles each
         step_bytes = alg_bytes(mesh.n_verts, mesh.n_tris, 0, prob.nnzb, pb) + mesh.n_tris * 24
     else:
@@ -365,7 +418,13 @@ def main():
     default_shell = args.workload == "shell" and args.n == 1024 and layout["scatter"] == mad.SCATTER_PATCH
     fpe = FLOPS_PER_ELEM.get(args.precision) if default_shell else None
     peak = VALU_PEAK_TFLOPS[args.precision]
-    if args.workload == "cloth":
+    if args.workload == "symdir":
+        # a 4x4 reduced Hessian per triangle: few operations per byte, so the HBM stream is the roofline
+        achieved = step_bytes / (dom_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": dom_ms,
+                    "alg_bytes_per_launch": step_bytes}
+    elif args.workload == "cloth":
         # springs are cheap (one 3x3 reduced Hessian each): the fused kernel is held to its HBM stream
         achieved = step_bytes / (dom_ms * 1e-3) / 1e9
         at_1000 = (args.cloth_n == 1000 and layout["scatter"] == mad.SCATTER_PATCH and layout["patch_faces"] == 256
@@ -401,6 +460,7 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": desc, **({"springs": mesh.n_edges} if args.workload == "cloth" else
+                                        {"triangles": mesh.n_tris} if args.workload == "symdir" else
                                         {"triangles": mesh.n_tris, "diamonds": mesh.n_diamonds}),
                    "elements": n_elem, "vertices": mesh.n_verts, "nnzb": prob.nnzb, "precision": args.precision,
                    "layout": layout},
@@ -451,6 +511,8 @@ def main():
             res["cpu_baseline"] = cpu_baseline(inp, 7000, mlp=seeded_network(mad))
         elif args.workload == "cloth":
             res["cpu_baseline"] = cpu_baseline_cloth(inp, 3 * args.cpu_elements)
+        elif args.workload == "symdir":
+            res["cpu_baseline"] = cpu_baseline_symdir(inp, 3 * args.cpu_elements)
         else:
             res["cpu_baseline"] = cpu_baseline(inp, args.cpu_elements)
     print(json.dumps(res), flush=True)
@@ -462,6 +524,31 @@ def cloth_alg_bytes(nv, ne, nnzb, precision_bytes):
     rd = nv * 3 * 8 + nv * 4 * 8 + ne * 2 * 4 + ne * 2 * 8 + (nv + 1) * 4 + nnzb * 4
     wr = nv * 3 * precision_bytes + nnzb * 9 * precision_bytes + 8
     return rd + wr
+
+
+def symdir_alg_bytes(nv, nt, nnzb, precision_bytes):
+    """Algorithmic HBM bytes of one parameterisation step: UVs (2 doubles per vertex), triangles, rest data
+    (Dm^-1 and area: 5 doubles per triangle) and the pattern read once; gradient, every 2x2 Hessian block and
+    the energy written once."""
+    rd = nv * 2 * 8 + nt * 3 * 4 + nt * 5 * 8 + (nv + 1) * 4 + nnzb * 4
+    wr = nv * 2 * precision_bytes + nnzb * 4 * precision_bytes + 8
+    return rd + wr
+
+
+def cpu_baseline_symdir(inp, budget):
+    """The FP64 oracle on the leading grid rows of the same warped grid (serial C)."""
+    import numpy as np
+    from oracle import oracle as O
+    n = inp.meta["n"]
+    rows = max(2, min(n, int(budget / (2.0 * n))))
+    nv = rows * n
+    sel = np.all(inp.tris < nv, axis=1)
+    P = O.Problem(inp.tris[sel], inp.rest[:nv], nv, 2)
+    P.add_term(O.SYMDIR, ())
+    P.build_pattern()
+    n_el = int(sel.sum())
+    return time_oracle(P, inp.x[:nv], n_el, f"first {rows} of {n} grid rows of the same warped grid: {n_el} "
+                                            f"triangles, energy + gradient + SPD-projected Hessian + assembly, FP64")
 
 
 # Table 1 of the paper (RTX 4090, precision not stated): grad + Hessian ms per step by vertex count
@@ -501,12 +588,9 @@ def cpu_baseline_cloth(inp, budget):
     P.add_term(O.INERTIA, inp.meta["inertia_params"], vertex_data=inp.meta["vdata"][:nv])
     P.build_pattern()
     n_el = int(P.topo.edges.shape[0]) + nv
-    t0 = time.perf_counter()
-    P.eval(inp.x[:nv], O.ENERGY | O.GRAD | O.HESS | O.SPD, scales=False)
-    dt = time.perf_counter() - t0
-    return {"value": n_el / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {rows} of {n} grid rows of the same cloth: {n_el} elements (springs + vertices), "
-                      f"energy + gradient + filtered Hessian + assembly, FP64, one thread, {dt:.1f} s"}
+    return time_oracle(P, inp.x[:nv], n_el, f"first {rows} of {n} grid rows of the same cloth: {n_el} elements "
+                                            f"(springs + vertices), energy + gradient + filtered Hessian + assembly, "
+                                            f"FP64")
 
 
 def dynamic_sparsity(torch, mad, mesh, inp, prec, args, stream, x):

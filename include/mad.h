@@ -51,7 +51,10 @@ typedef enum mad_status {
     MAD_E_HIP = -6,             /* a HIP runtime call or kernel launch failed */
     MAD_E_STATE = -7,           /* call out of order (e.g. eval before finalize) */
     MAD_E_UNSUPPORTED = -8,     /* kind/var_dim/precision combination not provided */
-    MAD_E_CAPACITY = -9         /* a pattern update would exceed the reserved room */
+    MAD_E_CAPACITY = -9,        /* a pattern update would exceed the reserved room */
+    MAD_E_INTERNAL = -10        /* a device-side consistency check failed during an evaluation (reported by
+                                   mad_problem_status; the outputs of the evaluations since the previous
+                                   status call are not valid) */
 } mad_status;
 
 /* Term catalogue. Stencil, VarDim and the params block of each kind:
@@ -141,8 +144,15 @@ typedef struct mad_options {
     double spd_eps;          /* eigenvalue floor of MAD_SPD; default 0 (PSD) */
     double degenerate_q;     /* MAD_F32: elements whose triangle quality 4 sqrt(3) A / sum(l^2)
                                 falls below this are evaluated and projected in FP64; 0 = 1e-2 */
-    int32_t reserved[8];     /* must be zero */
+    int32_t lock_spins;      /* bound on each wait for the per-workgroup LDS lock of the patch kernels (spin
+                                iterations); 0 = the default 4,194,304; MAD_LOCK_NO_WAIT gives up at once.
+                                A wait that reaches its bound does not add its Hessian blocks (it never adds
+                                without the lock) and raises the internal-error flag, so mad_problem_status
+                                returns MAD_E_INTERNAL; the kernels still run to completion */
+    int32_t reserved[7];     /* must be zero */
 } mad_options;
+
+enum { MAD_LOCK_NO_WAIT = -1 };  /* mad_options.lock_spins: every lock wait gives up at once */
 
 /* library version (major * 10000 + minor * 100 + patch) */
 int32_t mad_version(void);
@@ -269,7 +279,11 @@ int32_t mad_problem_hvp(mad_problem *prob, const double *x_dev, const double *v_
 
 /* Synchronise the stream and report whether any evaluation since the last call produced a
  * non-finite element energy or derivative (*nonfinite = 1) and how many elements took the FP64
- * fallback (*fp64_fallbacks); both counters are reset. */
+ * fallback (*fp64_fallbacks); both counters are reset. Returns MAD_E_INTERNAL (after filling both
+ * outputs and resetting the counters) if a device-side check failed in one of those evaluations: a
+ * wait for the LDS lock of a patch kernel reached its bound (mad_options.lock_spins), or an element
+ * redone in FP64 found a block missing from the pattern; mad_last_error() names which. The outputs
+ * of those evaluations are then not valid. */
 int32_t mad_problem_status(mad_problem *prob, int32_t *nonfinite, int64_t *fp64_fallbacks, void *stream);
 
 /* Per-stage timing (profiling aid). enable = 1 starts recording HIP events on the eval stream

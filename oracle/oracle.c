@@ -851,6 +851,18 @@ static int64_t find_block(const int32_t *rowptr, const int32_t *colidx, int32_t 
     return -1;
 }
 
+/* doubles of per-element rest data of a kind */
+static int rest_stride_of(int kind) {
+    switch (kind) {
+    case OR_BENDING: return 2;
+    case OR_DIRICHLET: case OR_STVK: case OR_SYMDIR: return 5;
+    case OR_SHELL_TRI: case OR_MLP: return 8;
+    case OR_SPRING: case OR_RES_EDGE: return 1;
+    case OR_INERTIA: case OR_RES_POSITION: return 4;
+    default: return 0;
+    }
+}
+
 int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int64_t *n_elem,
                 const int32_t *const *stencil, const double *const *rest, const double *const *params,
                 const double *x, int mode, double spd_eps, const char *row_mask, const int32_t *rowptr,
@@ -877,11 +889,7 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
         if (ss < 0 || kind_vardim(kind[t]) != d) { free(fvals); return -1; }
         int k = ss * d;
         int shell = kind[t] == OR_SHELL_TRI || kind[t] == OR_MLP;
-        int rest_stride = (kind[t] == OR_BENDING) ? 2
-                          : ((kind[t] == OR_DIRICHLET || kind[t] == OR_STVK || kind[t] == OR_SYMDIR) ? 5 : (shell ? 8 : 0));
-        if (kind[t] == OR_SPRING) rest_stride = 1;
-        if (kind[t] == OR_INERTIA || kind[t] == OR_RES_POSITION) rest_stride = 4;
-        if (kind[t] == OR_RES_EDGE) rest_stride = 1;
+        int rest_stride = rest_stride_of(kind[t]);
         double *nrm = NULL;
         if (shell) { /* passive unit vertex normals of the current positions, over this term's triangles */
             nrm = malloc(sizeof(double) * (size_t)(3 * nv));
@@ -953,6 +961,145 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
 }
 
 /* ------------------------------------------------------------------------- */
+/* The same evaluation spread over threads (CPU baseline timing).             */
+/* ------------------------------------------------------------------------- */
+/* Phase 1 evaluates the elements in parallel into per-element storage (the same element code as
+ * oracle_eval). Phase 2 sums every block row in one thread, from the elements touching its vertex in the
+ * serial order (terms in add order, elements ascending, stencil slots ascending), starting from zero: each
+ * output entry is the same sequence of additions as in oracle_eval, so the results are bit-identical to
+ * it in the same build. The energy is the same Neumaier sum over the element energies in order. */
+int oracle_eval_par(int64_t nv, int var_dim, int n_terms, const int *kind, const int64_t *n_elem,
+                    const int32_t *const *stencil, const double *const *rest, const double *const *params,
+                    const double *x, int mode, double spd_eps, const int32_t *rowptr, const int32_t *colidx,
+                    int threads, double *energy, double *esum_abs, double *grad, double *hess) {
+    const int d = var_dim;
+    if (n_terms <= 0 || n_terms > 16) return -1;
+    int64_t eoff[17], goff[17], hoff[17];
+    int ks[16], sss[16];
+    eoff[0] = goff[0] = hoff[0] = 0;
+    for (int t = 0; t < n_terms; ++t) {
+        sss[t] = kind_stencil(kind[t]);
+        if (sss[t] < 0 || kind_vardim(kind[t]) != d) return -1;
+        ks[t] = sss[t] * d;
+        eoff[t + 1] = eoff[t] + n_elem[t];
+        goff[t + 1] = goff[t] + ((mode & OR_GRAD) ? n_elem[t] * ks[t] : 0);
+        hoff[t + 1] = hoff[t] + ((mode & OR_HESS) ? n_elem[t] * ks[t] * ks[t] : 0);
+    }
+    const int64_t total = eoff[n_terms];
+    const int want_deriv = (mode & (OR_GRAD | OR_HESS)) != 0;
+    double *fvals = malloc(sizeof(double) * (size_t)(total > 0 ? total : 1));
+    double *gl = malloc(sizeof(double) * (size_t)(goff[n_terms] > 0 ? goff[n_terms] : 1));
+    double *hl = malloc(sizeof(double) * (size_t)(hoff[n_terms] > 0 ? hoff[n_terms] : 1));
+    double *nrm = malloc(sizeof(double) * (size_t)(3 * nv * n_terms > 0 ? 3 * nv * n_terms : 1));
+    int err = 0;
+    if (!fvals || !gl || !hl || !nrm) err = -4;
+    for (int t = 0; !err && t < n_terms; ++t)
+        if (kind[t] == OR_SHELL_TRI || kind[t] == OR_MLP)
+            oracle_vertex_normals(nv, n_elem[t], stencil[t], x, nrm + 3 * nv * t);
+#pragma omp parallel for schedule(dynamic, 256) num_threads(threads) if (!err)
+    for (int64_t i = 0; i < total; ++i) {
+        int t = 0;
+        while (i >= eoff[t + 1]) ++t;
+        const int64_t e = i - eoff[t];
+        const int ss = sss[t], k = ks[t];
+        const int32_t *s = stencil[t] + ss * e;
+        double xloc[KMAX], aux[9];
+        for (int a = 0; a < ss; ++a)
+            for (int c = 0; c < d; ++c) xloc[a * d + c] = x[(int64_t)s[a] * d + c];
+        if (kind[t] == OR_SHELL_TRI || kind[t] == OR_MLP)
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) aux[3 * a + c] = nrm[3 * nv * t + 3 * (int64_t)s[a] + c];
+        const int rsd = rest_stride_of(kind[t]);
+        hd r;
+        if (eval_elem(kind[t], want_deriv ? k : 0, params[t], rsd ? rest[t] + rsd * e : NULL, aux, xloc, &r) != 0) {
+#pragma omp atomic write
+            err = -1;
+            continue;
+        }
+        fvals[i] = r.v;
+        if (mode & OR_GRAD)
+            for (int q = 0; q < k; ++q) gl[goff[t] + e * k + q] = r.g[q];
+        if (mode & OR_HESS) {
+            double Hl[KMAX * KMAX];
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b) Hl[a * k + b] = r.h[a][b];
+            double *Hp = hl + hoff[t] + e * k * k;
+            if (mode & OR_SPD) oracle_spd_project(k, Hl, spd_eps, Hp);
+            else memcpy(Hp, Hl, sizeof(double) * k * k);
+        }
+    }
+    /* vertex -> (element, slot) incidence in the serial order */
+    int64_t *iptr = NULL, *inc = NULL;
+    if (!err && want_deriv) {
+        iptr = calloc((size_t)nv + 1, sizeof(int64_t));
+        int64_t slots = 0;
+        for (int t = 0; t < n_terms; ++t) slots += n_elem[t] * sss[t];
+        inc = malloc(sizeof(int64_t) * (size_t)(slots > 0 ? slots : 1));
+        if (!iptr || !inc) err = -4;
+        for (int t = 0; !err && t < n_terms; ++t)
+            for (int64_t j = 0; j < n_elem[t] * sss[t]; ++j) iptr[stencil[t][j] + 1]++;
+        for (int64_t v = 0; !err && v < nv; ++v) iptr[v + 1] += iptr[v];
+        int64_t *fill = err ? NULL : malloc(sizeof(int64_t) * (size_t)(nv > 0 ? nv : 1));
+        if (!err && !fill) err = -4;
+        if (!err) {
+            memcpy(fill, iptr, sizeof(int64_t) * (size_t)nv);
+            for (int t = 0; t < n_terms; ++t)
+                for (int64_t e = 0; e < n_elem[t]; ++e)
+                    for (int a = 0; a < sss[t]; ++a)
+                        inc[fill[stencil[t][sss[t] * e + a]]++] = ((eoff[t] + e) << 4) | a;
+        }
+        free(fill);
+    }
+    if (!err && (mode & OR_GRAD) && grad) memset(grad, 0, sizeof(double) * (size_t)(nv * d));
+    if (!err && (mode & OR_HESS) && hess) memset(hess, 0, sizeof(double) * (size_t)(rowptr[nv] * d * d));
+    if (!err && want_deriv) {
+#pragma omp parallel for schedule(dynamic, 512) num_threads(threads)
+        for (int64_t v = 0; v < nv; ++v) {
+            for (int64_t q = iptr[v]; q < iptr[v + 1]; ++q) {
+                const int64_t i = inc[q] >> 4;
+                const int a = (int)(inc[q] & 15);
+                int t = 0;
+                while (i >= eoff[t + 1]) ++t;
+                const int64_t e = i - eoff[t];
+                const int ss = sss[t], k = ks[t];
+                const int32_t *s = stencil[t] + ss * e;
+                if ((mode & OR_GRAD) && grad)
+                    for (int c = 0; c < d; ++c) grad[v * d + c] += gl[goff[t] + e * k + a * d + c];
+                if ((mode & OR_HESS) && hess) {
+                    const double *Hp = hl + hoff[t] + e * k * k;
+                    for (int b = 0; b < ss; ++b) {
+                        int64_t blk = find_block(rowptr, colidx, (int32_t)v, s[b]);
+                        if (blk < 0) {
+#pragma omp atomic write
+                            err = -5;
+                            continue;
+                        }
+                        for (int ii = 0; ii < d; ++ii)
+                            for (int jj = 0; jj < d; ++jj)
+                                hess[blk * d * d + ii * d + jj] += Hp[(a * d + ii) * k + (b * d + jj)];
+                    }
+                }
+            }
+        }
+    }
+    if (!err) {
+        if (energy) *energy = oracle_neumaier_sum(total, fvals);
+        if (esum_abs) {
+            double abs_sum = 0.0;
+            for (int64_t i = 0; i < total; ++i) abs_sum += fabs(fvals[i]);
+            *esum_abs = abs_sum;
+        }
+    }
+    free(fvals);
+    free(gl);
+    free(hl);
+    free(nrm);
+    free(iptr);
+    free(inc);
+    return err;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Residual terms and the global sparse Jacobian (Sec. 4.1 Eq. 3, Sec. 6.1).  */
 /* ------------------------------------------------------------------------- */
 int oracle_kind_nres(int kind) {
@@ -967,7 +1114,7 @@ static int res_rest_stride(int kind) { return kind == OR_RES_POSITION ? 4 : (kin
 
 int oracle_residual(int kind, const double *params, const double *rest, const double *xloc, double *r, double *J) {
     int ss = kind_stencil(kind), vd = kind_vardim(kind), m = oracle_kind_nres(kind);
-    if (ss < 0 || vd < 0 || m == 0) return -1;
+    if (ss < 0 || vd < 0 || m == 0 || m > 3) return -1;
     int k = ss * vd;
     hd res[3];
     res_elem(kind, k, params, rest, xloc, res);

@@ -96,6 +96,14 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
                 double *energy, double *esum_abs, double *grad, double *gscale,
                 double *hess, double *hscale);
 
+/* The same evaluation over `threads` OpenMP threads (no row mask, no scales): elements in parallel, then
+ * each block row summed by one thread in the serial order, so the outputs are bit-identical to
+ * oracle_eval in the same build. Used to time the oracle on all host cores. */
+int oracle_eval_par(int64_t nv, int var_dim, int n_terms, const int *kind, const int64_t *n_elem,
+                    const int32_t *const *stencil, const double *const *rest, const double *const *params,
+                    const double *x, int mode, double spd_eps, const int32_t *rowptr, const int32_t *colidx,
+                    int threads, double *energy, double *esum_abs, double *grad, double *hess);
+
 /* ---- per-triangle shell features and densities (project-defined; no paper counterpart) ----
  * z = (E00, E11, E01, II00 - rII00, II11 - rII11, II01 - rII01) with F = Ds Dm^{-1},
  * E = (F^T F - I)/2, N = [n_b - n_a, n_c - n_a] Dm^{-1} from passive unit vertex normals,

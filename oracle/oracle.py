@@ -28,15 +28,42 @@ NRES = {RES_POSITION: 3, RES_EDGE: 1}   # residuals per element of the residual 
 
 
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (serial, -O2, no fast-math)."""
+    """Compile liboracle.so with gcc (-O2, no FMA contraction, no fast-math): the parity reference. OpenMP
+    is enabled for oracle_eval_par only; oracle_eval stays serial."""
     src = os.path.join(HERE, "oracle.c")
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
             os.path.getmtime(src), os.path.getmtime(os.path.join(HERE, "oracle.h"))):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
-                               "-ffp-contract=off", "-o", tmp, src, "-lm"])
+                               "-ffp-contract=off", "-fopenmp", "-o", tmp, src, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
+
+
+def build_fast() -> str:
+    """A timing build of the same source for the host it runs on (-O3 -march=native, the compiler's
+    default FMA contraction): used only to time the oracle, never as the parity reference. Built on first
+    use on each host (the file name carries a hash of the CPU model, so a copy built elsewhere is not
+    reused)."""
+    import hashlib
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    tag = hashlib.sha1(model.encode()).hexdigest()[:10]
+    src = os.path.join(HERE, "oracle.c")
+    path = os.path.join(HERE, f"liboracle_fast_{tag}.so")
+    if not os.path.exists(path) or os.path.getmtime(path) < max(
+            os.path.getmtime(src), os.path.getmtime(os.path.join(HERE, "oracle.h"))):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-o", tmp,
+                               src, "-lm"])
+        os.replace(tmp, path)
+    return path
 
 
 _lib = None
@@ -426,6 +453,31 @@ class Problem:
                                  C.c_int(mode), C.c_double(spd_eps), _p(mask), _p(self.rowptr), _p(self.colidx),
                                  C.byref(e), C.byref(ea), _p(grad), _p(gscale), _p(hess), _p(hscale)), "eval")
         return Result(e.value, ea.value, grad, gscale, hess, hscale)
+
+    def eval_par(self, x: np.ndarray, mode: int = ENERGY | GRAD | HESS, spd_eps: float = 0.0,
+                 threads: int = 1) -> Result:
+        """oracle_eval_par: the same evaluation over `threads` OpenMP threads (bit-identical to eval in the
+        same build; no row mask, no scales)."""
+        if self.rowptr is None:
+            self.build_pattern()
+        x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+        assert x.size == self.nv * self.d
+        n = len(self.terms)
+        kinds = (C.c_int * n)(*[t.kind for t in self.terms])
+        ne = (C.c_int64 * n)(*[t.stencil.shape[0] for t in self.terms])
+        st = (C.c_void_p * n)(*[t.stencil.ctypes.data for t in self.terms])
+        rs = (C.c_void_p * n)(*[(t.rest.ctypes.data if t.rest is not None else None) for t in self.terms])
+        pr = (C.c_void_p * n)(*[t.params.ctypes.data for t in self.terms])
+        d = self.d
+        nnzb = int(self.rowptr[-1])
+        grad = np.zeros(self.nv * d) if mode & GRAD else None
+        hess = np.zeros((nnzb, d, d)) if mode & HESS else None
+        e = C.c_double()
+        ea = C.c_double()
+        _check(lib().oracle_eval_par(C.c_int64(self.nv), C.c_int(d), C.c_int(n), kinds, ne, st, rs, pr, _p(x),
+                                     C.c_int(mode), C.c_double(spd_eps), _p(self.rowptr), _p(self.colidx),
+                                     C.c_int(int(threads)), C.byref(e), C.byref(ea), _p(grad), _p(hess)), "eval_par")
+        return Result(e.value, ea.value, grad, None, hess, None)
 
     def jacobian(self, x: np.ndarray):
         """Residual vector and sparse Jacobian of the residual terms (Eq. 3), CSR with scalar entries:

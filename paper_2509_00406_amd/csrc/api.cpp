@@ -127,7 +127,7 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
     mad_options o;
     mad_options_default(&o);
     if (opt) {
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 7; ++i)
             if (opt->reserved[i] != 0) return fail(MAD_E_INVALID_ARG, "reserved option fields must be zero");
         if (opt->scatter != MAD_SCATTER_AUTO && opt->scatter != MAD_SCATTER_ATOMIC && opt->scatter != MAD_SCATTER_PATCH)
             return fail(MAD_E_INVALID_ARG, "bad scatter mode");
@@ -138,6 +138,8 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
         if (opt->patch_faces > 0) o.patch_faces = opt->patch_faces;
         o.spd_eps = opt->spd_eps;
         if (opt->degenerate_q > 0.0) o.degenerate_q = opt->degenerate_q;
+        if (opt->lock_spins < MAD_LOCK_NO_WAIT) return fail(MAD_E_INVALID_ARG, "lock_spins must be >= -1");
+        o.lock_spins = opt->lock_spins;
     }
     mad_problem* p = new (std::nothrow) mad_problem();
     if (!p) return fail(MAD_E_OOM, "problem");
@@ -375,7 +377,7 @@ int32_t mad_problem_finalize(mad_problem* p, void* stream) {
     int32_t hflags[4];
     MAD_HIP_TRY(hipMemcpyAsync(hflags, p->d_flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
     MAD_HIP_TRY(hipStreamSynchronize(s));
-    if (hflags[1] != 0) return fail(MAD_E_HIP, "internal error: element block missing from the pattern");
+    if (hflags[1] != 0) return fail(MAD_E_INTERNAL, "element block missing from the pattern");
     p->finalized = true;
     return MAD_OK;
 }
@@ -536,6 +538,14 @@ int32_t mad_problem_status(mad_problem* p, int32_t* nonfinite, int64_t* fallback
     MAD_HIP_TRY(hipStreamSynchronize(s));
     if (nonfinite) *nonfinite = hf[0] != 0;
     if (fallbacks) *fallbacks = (int64_t)hb;
+    if (hf[1] != 0) {
+        std::string what;
+        if (hf[1] & kFlagLockTimeout) what += " a wait for the LDS lock of a patch kernel reached its bound;";
+        if (hf[1] & kFlagRedoBlockMissing) what += " an element redone in FP64 found a block missing from the pattern;";
+        if (hf[1] & kFlagSlotMissing) what += " an element block is missing from the pattern;";
+        return fail(MAD_E_INTERNAL, "device-side check failed (flags " + std::to_string(hf[1]) + "):" + what +
+                                        " the outputs since the previous status call are not valid");
+    }
     return MAD_OK;
 }
 

@@ -91,7 +91,7 @@ int32_t mad_problem_set_layout(mad_problem* p, int32_t scatter, int32_t patch_fa
     if (scatter != MAD_SCATTER_AUTO && scatter != MAD_SCATTER_ATOMIC && scatter != MAD_SCATTER_PATCH)
         return fail(MAD_E_INVALID_ARG, "bad scatter mode");
     if (patch_faces < 1 || patch_faces > (1 << 20)) return fail(MAD_E_INVALID_ARG, "bad patch_faces");
-    if (persistent != 0 && persistent != 1) return fail(MAD_E_INVALID_ARG, "persistent must be 0 or 1");
+    if (persistent < 0 || persistent > 2) return fail(MAD_E_INVALID_ARG, "persistent must be 0, 1 or 2");
     if (scatter == MAD_SCATTER_ATOMIC && persistent) return fail(MAD_E_UNSUPPORTED, "persistent needs the patch scatter");
     const int sc = scatter == MAD_SCATTER_AUTO ? MAD_SCATTER_PATCH : scatter;
     const int rc = build_layout(p, patch_faces, sc, persistent, (hipStream_t)stream);

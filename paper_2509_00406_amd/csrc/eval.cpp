@@ -86,6 +86,8 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.fb_cap = p->fb_cap;
         L.eps = p->opt.spd_eps;
         L.qmin = p->opt.degenerate_q;
+        L.lock_spins = p->opt.lock_spins == MAD_LOCK_NO_WAIT ? 0
+                       : (p->opt.lock_spins > 0 ? p->opt.lock_spins : kDefaultLockSpins);
         L.persistent = p->persistent;
         L.work_order = p->d_work_order;
         L.work_counter = p->d_work_counter;

@@ -28,12 +28,11 @@ constexpr uint32_t kFbElemMask = kFbGradDone - 1u;
 
 // One lock per workgroup over the patch's Hessian blocks in LDS: one wave at a time adds its unit's
 // blocks. Lane 0 takes it for the whole wave (all lanes converged); it is released once the wave's
-// LDS writes have completed. The spin is bounded: past the bound the internal-error flag is raised
-// and the wave goes on without the lock, so every wave ends.
-constexpr int kLockSpins = 1 << 22;
-
-__device__ __forceinline__ bool wave_lock(int* lock, int32_t* flags) {
-    for (int spin = 0; spin < kLockSpins; ++spin) {
+// LDS writes have completed. The spin is bounded (`spins` attempts, a launch parameter): past the bound
+// the internal-error flag is raised and the wave adds nothing, so every wave ends and no block is ever
+// added without the lock.
+__device__ __forceinline__ bool wave_lock(int* lock, int32_t* flags, int spins) {
+    for (int spin = 0; spin < spins; ++spin) {
         int got = 0;
         if ((threadIdx.x & 63) == 0) {
             int expected = 0;
@@ -49,7 +48,7 @@ __device__ __forceinline__ bool wave_lock(int* lock, int32_t* flags) {
         }
         __builtin_amdgcn_s_sleep(2);
     }
-    if ((threadIdx.x & 63) == 0) atomicOr(flags + 1, 16);
+    if ((threadIdx.x & 63) == 0) atomicOr(flags + 1, kFlagLockTimeout);
     return false;
 }
 
@@ -107,7 +106,8 @@ __device__ __forceinline__ void add_blocks(const PatchLaunch& L, const PatchTerm
                         hv[k][c * D + c2] = hfull<Term, MODE>(o, s * D + c, t * D + c2, te);
                     }
     }
-    const bool held = wave_lock(lock, L.flags);
+    const bool held = wave_lock(lock, L.flags, L.lock_spins);
+    if (!held) return;   // flagged: the evaluation's Hessian is reported invalid
     if (__ballot(degen) != 0ull) {
         // rare: some pair lands in a diagonal block without s == t; add pair by pair
         int k = 0;
@@ -609,7 +609,7 @@ __device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const Fal
         for (int t = 0; t < NS; ++t) {
             const int32_t b = find_block(F.rowptr, F.colidx, vs[s], vs[t]);
             if (b < 0) {
-                atomicOr(F.flags + 1, 8);
+                atomicOr(F.flags + 1, kFlagRedoBlockMissing);
                 continue;
             }
 #pragma unroll

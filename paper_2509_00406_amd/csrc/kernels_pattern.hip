@@ -306,7 +306,7 @@ __global__ void k_slots(const int32_t* stencil, int64_t n, int ns, const int32_t
                 else hi = mid - 1;
             }
             if (found < 0) {
-                atomicOr(flags + 1, 4);
+                atomicOr(flags + 1, kFlagSlotMissing);
                 found = rowptr[r];
             }
             slots[(int64_t)(a * ns + b) * n + e] = found;

@@ -234,14 +234,23 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
     if ((rc = alloc_layout(p, (void**)&p->d_comp_energy,
                            sizeof(double) * std::max<size_t>(1, p->patches.comp_patch_ptr.size()))) != MAD_OK)
         return rc;
-    // work order of the persistent launch: patches with most elements first
+    // work order of the persistent launch. persistent == 1: patches in index order, which is spatial
+    // order (neighbouring patches share halo vertices and output cache lines, so they run close in time),
+    // grouped into four size classes with the largest class first (no large patch starts last).
+    // persistent == 2: strictly by decreasing element count.
     {
         std::vector<int64_t> cnt((size_t)np, 0);
         for (auto& t : p->terms)
             for (int32_t q = 0; q < np; ++q) cnt[q] += t.elem_ptr[q + 1] - t.elem_ptr[q];
+        const int64_t cmax = np > 0 ? *std::max_element(cnt.begin(), cnt.end()) : 0;
         std::vector<int32_t> order((size_t)np);
         std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
+        if (persistent == 2) {
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cnt[a] > cnt[b]; });
+        } else {
+            auto cls = [&](int32_t q) { return (cnt[q] * 4) / (cmax + 1); };
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cls(a) > cls(b); });
+        }
         if ((rc = upload_layout(p, (void**)&p->d_work_order, order.data(), order.size() * 4, s)) != MAD_OK) return rc;
         if ((rc = alloc_layout(p, (void**)&p->d_work_counter, 16)) != MAD_OK) return rc;
     }

@@ -118,7 +118,7 @@ struct mad_problem {
     int32_t* d_comp_patch_ptr = nullptr;
     double* d_partial = nullptr;          // [n_terms][n_patch]
     double* d_comp_energy = nullptr;      // [n_comp] per-component energies (reduction scratch)
-    int32_t* d_flags = nullptr;           // [0] nonfinite, [1] internal error
+    int32_t* d_flags = nullptr;           // [0] nonfinite, [1] internal-error bits (kFlag*)
     unsigned long long* d_fallbacks = nullptr;
     int scatter = MAD_SCATTER_PATCH;
     int persistent = 0;                   // patch scatter: persistent grid pulling patches from a queue
@@ -167,6 +167,12 @@ struct mad_problem {
 };
 
 namespace mad {
+
+// bits of a problem's internal-error flag word (d_flags[1]); mad_problem_status turns any into MAD_E_INTERNAL
+constexpr int32_t kFlagSlotMissing = 4;        // atomic scatter: an element block is not in the pattern
+constexpr int32_t kFlagRedoBlockMissing = 8;   // FP64 redo: an element block is not in the pattern
+constexpr int32_t kFlagLockTimeout = 16;       // patch kernel: a wait for the LDS lock reached its bound
+constexpr int32_t kDefaultLockSpins = 1 << 22;
 
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
@@ -275,6 +281,7 @@ struct PatchLaunch {
     const double* v;        // [nv][D]
     void* y;                // [nv][D], T
     void* halo_y;           // [halo vertex slots][D] partial products of shared vertices
+    int lock_spins;         // bound on each LDS-lock wait (0: give up at once)
     int persistent;
     const int32_t* work_order;
     int32_t* work_counter;

@@ -25,7 +25,8 @@ TUNE_FORCE = 1
 
 STATUS = {0: "MAD_OK", -1: "MAD_E_INVALID_ARG", -2: "MAD_E_BAD_MESH", -3: "MAD_E_DEGENERATE_REST",
           -4: "MAD_E_OVERFLOW", -5: "MAD_E_OOM", -6: "MAD_E_HIP", -7: "MAD_E_STATE", -8: "MAD_E_UNSUPPORTED",
-          -9: "MAD_E_CAPACITY"}
+          -9: "MAD_E_CAPACITY", -10: "MAD_E_INTERNAL"}
+LOCK_NO_WAIT = -1
 VARDIM = {EDGE_SQLEN: 3, TRI_AREA: 3, DIRICHLET: 1, STVK: 3, BENDING: 3, SYMDIR: 2, MLP: 3, SHELL_TRI: 3}
 NEEDS_REST = {DIRICHLET, STVK, BENDING, SYMDIR, MLP, SHELL_TRI, SPRING, RES_EDGE}
 MLP_HIDDEN, MLP_PARAMS = 64, 4673
@@ -39,7 +40,7 @@ class MadError(RuntimeError):
 
 class mad_options(C.Structure):
     _fields_ = [("scatter", C.c_int32), ("patch_faces", C.c_int32), ("spd_eps", C.c_double),
-                ("degenerate_q", C.c_double), ("reserved", C.c_int32 * 8)]
+                ("degenerate_q", C.c_double), ("lock_spins", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
 _lib = None
@@ -412,9 +413,11 @@ class Problem:
     """mesh + var_dim + precision -> terms -> finalize -> eval (Sec. 4.2 programming model)."""
 
     def __init__(self, mesh: Mesh, var_dim: int, precision: int = F64, patch_faces: int = 0,
-                 spd_eps: float = 0.0, degenerate_q: float = 0.0, scatter: int = SCATTER_AUTO):
+                 spd_eps: float = 0.0, degenerate_q: float = 0.0, scatter: int = SCATTER_AUTO,
+                 lock_spins: int = 0):
         o = mad_options_default()
         o.scatter = scatter
+        o.lock_spins = lock_spins
         o.patch_faces = patch_faces
         o.spd_eps = spd_eps
         o.degenerate_q = degenerate_q

@@ -127,3 +127,17 @@ def test_problem_validation_errors():
     with pytest.raises(mad.MadError) as e:
         mad.mad_problem_create(m.handle, 3, mad.F64, o)
     assert e.value.code == -1
+    o = mad.mad_options_default()
+    o.lock_spins = -2                              # below MAD_LOCK_NO_WAIT
+    with pytest.raises(mad.MadError) as e:
+        mad.mad_problem_create(m.handle, 3, mad.F64, o)
+    assert e.value.code == -1
+    o.lock_spins = mad.LOCK_NO_WAIT
+    mad.mad_problem_destroy(mad.mad_problem_create(m.handle, 3, mad.F64, o))
+
+
+def test_status_codes_mirror_header():
+    txt = open(os.path.join(ROOT, "include", "mad.h")).read()
+    codes = {int(v): k for k, v in re.findall(r"\b(MAD_(?:OK|E_[A-Z_]+))\s*=\s*(-?\d+)", txt)}
+    assert codes == mad.STATUS
+    assert re.search(r"MAD_LOCK_NO_WAIT\s*=\s*-1\b", txt) and mad.LOCK_NO_WAIT == -1

@@ -61,8 +61,8 @@ MUTANTS = {
     "inertia_gravity_wrong_sign": ("acc = hd_add(acc, hd_scale(x.c[c], -prm[0] * m * prm[1 + c]));",
                                    "acc = hd_add(acc, hd_scale(x.c[c], prm[0] * m * prm[1 + c]));"),
     "inertia_drops_half": ("acc = hd_add(acc, hd_scale(hd_sq(dc), 0.5 * m));", "acc = hd_add(acc, hd_scale(hd_sq(dc), m));"),
-    "inertia_rest_stride_wrong": ("if (kind[t] == OR_INERTIA || kind[t] == OR_RES_POSITION) rest_stride = 4;",
-                                  "if (kind[t] == OR_INERTIA || kind[t] == OR_RES_POSITION) rest_stride = 3;"),
+    "inertia_rest_stride_wrong": ("case OR_INERTIA: case OR_RES_POSITION: return 4;",
+                                  "case OR_INERTIA: case OR_RES_POSITION: return 3;"),
     "res_edge_weight_not_sqrt": ("out[0] = hd_scale(hd_addc(hd_sqrt(hd3_dot(d, d)), -rest[0]), sqrt(prm[0]));",
                                  "out[0] = hd_scale(hd_addc(hd_sqrt(hd3_dot(d, d)), -rest[0]), prm[0]);"),
     "gauss_newton_drops_half": ("out.v += 0.5 * res[i].v * res[i].v;", "out.v += res[i].v * res[i].v;"),
