@@ -170,15 +170,18 @@ __device__ __forceinline__ double frsq(double x) { return 1.0 / sqrt(x); }
 
 // ---- symmetric eigen-decomposition: Jacobi rotations in round-robin order --------------------
 // A sweep visits every pair (p, q) once, grouped into rounds of disjoint pairs (circle method
-// over M = N rounded up to even players; pairs with the padding player are skipped). Rotations
+// over M = N rounded up to even players; pairs with the padding player are skipped): the parallel
+// ordering of R. P. Brent and F. T. Luk, "The solution of singular-value and symmetric eigenvalue
+// problems on multiprocessor arrays" (SIAM J. Sci. Stat. Comput., 1985). Rotations
 // in one round touch disjoint (p, q) planes, so their parameters depend only on entries no other
 // rotation of the round changes: they are computed together, giving independent instruction
 // streams. The rotation zeroing a_pq uses t = tan(phi) = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)),
 // d = a_qq - a_pp (the smaller root of t^2 + 2 t d / (2 a_pq) - 1 = 0), c = 1/sqrt(1 + t^2),
 // s = t c, and A <- J^T A J, V <- V J with J_pp = J_qq = c, J_pq = s, J_qp = -s.
 //
-// Scaled rotations: the off-diagonal entries and the eigenvector columns are kept with a diagonal
-// scale, a_ij = d_i d_j b_ij (i != j) and V = W diag(d), while the diagonal of A is kept as is. A
+// Scaled rotations (the idea of the fast Givens transformation of W. M. Gentleman, 1973, and
+// S. Hammarling, 1974, applied to Jacobi rotations): the off-diagonal entries and the eigenvector
+// columns are kept with a diagonal scale, a_ij = d_i d_j b_ij (i != j) and V = W diag(d), while the diagonal of A is kept as is. A
 // rotation in the (p, q) plane multiplies d_p and d_q by c; the stored entries then change by one
 // fused multiply-add each, b_ip -= t (d_q / d_p) b_iq and b_iq += t (d_p / d_q) b_ip (the same for
 // W's columns), where the plain rotation needs two products and a multiply-add. The reciprocals
