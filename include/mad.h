@@ -51,7 +51,8 @@ typedef enum mad_status {
     MAD_E_HIP = -6,             /* a HIP runtime call or kernel launch failed */
     MAD_E_STATE = -7,           /* call out of order (e.g. eval before finalize) */
     MAD_E_UNSUPPORTED = -8,     /* kind/var_dim/precision combination not provided */
-    MAD_E_CAPACITY = -9,        /* a pattern update would exceed the reserved room */
+    MAD_E_CAPACITY = -9,        /* a pattern update would exceed the reserved room, or an evaluation would
+                                   exceed the static scratch of mad_problem_eval_static */
     MAD_E_INTERNAL = -10        /* a device-side consistency check failed during an evaluation (reported by
                                    mad_problem_status; the outputs of the evaluations since the previous
                                    status call are not valid) */
@@ -267,6 +268,22 @@ int32_t mad_problem_copy_pattern(const mad_problem *prob, int32_t *rowptr_dev, i
  * Asynchronous on stream: no host synchronisation. The energy is a deterministic FP64 sum. */
 int32_t mad_problem_eval(mad_problem *prob, const double *x_dev, uint32_t mode, double *energy_dev,
                          void *grad_dev, void *hess_dev, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops with a
+ * fixed memory budget): mad_problem_eval with the same arguments, outputs and errors, that allocates
+ * nothing. Every buffer the evaluation writes and reads back within itself (per-patch energies, queue
+ * counters, halo partials of entries several patches share, the queue of FP32 elements redone in FP64,
+ * vertex normals, network outputs) is taken from a static device array of 64 MiB that each GPU holds
+ * from the library's load until the process ends, instead of from the problem's buffers. The problem
+ * must live on the current device (MAD_E_INVALID_ARG otherwise). MAD_E_CAPACITY, before any launch, if
+ * the problem needs more than 64 MiB of it (at the default patches the elastic shell of a 724 x 724 vertex
+ * grid, 1M triangles, needs 36 MB; the 1024 x 1024 one, 72 MB, does not fit); the FP64 redo queue takes what is left, and an evaluation that queues more elements
+ * than that is reported by mad_problem_status as MAD_E_INTERNAL. The array keeps the last call's
+ * contents; each call initialises what it reads. Calls on one GPU share its array: calls that overlap
+ * on one GPU (other streams, other threads) race and must be ordered by the caller. Per-stage profiling
+ * (mad_problem_set_profiling) does not record these calls. Asynchronous on stream. */
+int32_t mad_problem_eval_static(mad_problem *prob, const double *x_dev, uint32_t mode, double *energy_dev,
+                                void *grad_dev, void *hess_dev, void *stream);
 
 /* Matrix-free Hessian-vector product (Sec. 5.5, Sec. 6.2 matrix-free mode): y = H(x) v with
  * H = sum_j S_j^T P(hess f_j) S_j (P the eigenvalue clamp when mode has MAD_SPD, else the

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libmad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["kernels_patch.hip", "kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "host_patch.cpp",
-           "kernels_mlp.hip", "kernels_jac.hip", "layout.cpp", "eval.cpp", "autotune.cpp", "mlp.cpp", "api.cpp"]
+           "kernels_mlp.hip", "kernels_jac.hip", "layout.cpp", "eval.cpp", "autotune.cpp", "mlp.cpp", "api.cpp",
+           "eval_static.hip"]
 
 # -packed-fp32-ops: keep the compiler from forming packed FP32 (v_pk_*_f32) instructions.
 # -munsafe-fp-atomics: hardware FP32/FP64 atomic add instead of compare-and-swap loops.

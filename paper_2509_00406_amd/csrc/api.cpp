@@ -23,6 +23,23 @@ int fail(int code, const std::string& msg) {
 
 using namespace mad;
 
+namespace mad {
+
+int check_eval_args(const mad_problem* p, const double* x, uint32_t mode, const double* energy, const void* grad,
+                    const void* hess) {
+    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
+    if (!p->finalized) return fail(MAD_E_STATE, "eval before finalize");
+    if (!x) return fail(MAD_E_INVALID_ARG, "x is NULL");
+    if (mode & ~15u) return fail(MAD_E_INVALID_ARG, "unknown mode bits");
+    if ((mode & MAD_ENERGY) && !energy) return fail(MAD_E_INVALID_ARG, "energy output is NULL");
+    if ((mode & MAD_GRAD) && !grad) return fail(MAD_E_INVALID_ARG, "gradient output is NULL");
+    if ((mode & MAD_HESS) && !hess) return fail(MAD_E_INVALID_ARG, "Hessian output is NULL");
+    if ((mode & MAD_SPD) && !(mode & MAD_HESS)) return fail(MAD_E_INVALID_ARG, "MAD_SPD needs MAD_HESS");
+    return MAD_OK;
+}
+
+}  // namespace mad
+
 extern "C" {
 
 int32_t mad_version(void) { return 100; }
@@ -476,14 +493,8 @@ int32_t mad_problem_copy_pattern(const mad_problem* p, int32_t* rowptr, int32_t*
 
 int32_t mad_problem_eval(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
                          void* stream) {
-    if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
-    if (!p->finalized) return fail(MAD_E_STATE, "eval before finalize");
-    if (!x) return fail(MAD_E_INVALID_ARG, "x is NULL");
-    if (mode & ~15u) return fail(MAD_E_INVALID_ARG, "unknown mode bits");
-    if ((mode & MAD_ENERGY) && !energy) return fail(MAD_E_INVALID_ARG, "energy output is NULL");
-    if ((mode & MAD_GRAD) && !grad) return fail(MAD_E_INVALID_ARG, "gradient output is NULL");
-    if ((mode & MAD_HESS) && !hess) return fail(MAD_E_INVALID_ARG, "Hessian output is NULL");
-    if ((mode & MAD_SPD) && !(mode & MAD_HESS)) return fail(MAD_E_INVALID_ARG, "MAD_SPD needs MAD_HESS");
+    const int rc = check_eval_args(p, x, mode, energy, grad, hess);
+    if (rc != MAD_OK) return rc;
     return eval_problem(p, x, mode, energy, grad, hess, (hipStream_t)stream);
 }
 
@@ -543,6 +554,7 @@ int32_t mad_problem_status(mad_problem* p, int32_t* nonfinite, int64_t* fallback
         if (hf[1] & kFlagLockTimeout) what += " a wait for the LDS lock of a patch kernel reached its bound;";
         if (hf[1] & kFlagRedoBlockMissing) what += " an element redone in FP64 found a block missing from the pattern;";
         if (hf[1] & kFlagSlotMissing) what += " an element block is missing from the pattern;";
+        if (hf[1] & kFlagQueueOverflow) what += " the FP64 redo queue of the static scratch overflowed;";
         return fail(MAD_E_INTERNAL, "device-side check failed (flags " + std::to_string(hf[1]) + "):" + what +
                                         " the outputs since the previous status call are not valid");
     }

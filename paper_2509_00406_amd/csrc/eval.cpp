@@ -9,8 +9,28 @@
 
 namespace mad {
 
+EvalScratch own_scratch(const mad_problem* p) {
+    EvalScratch sc;
+    sc.partial = p->d_partial;
+    sc.comp_energy = p->d_comp_energy;
+    sc.work_counter = p->d_work_counter;
+    sc.fb_count = p->d_fb_count;
+    sc.fb_list = p->d_fb_list;
+    sc.fb_cap = p->fb_cap;
+    sc.halo_g = p->d_halo_g;
+    sc.halo_h = p->d_halo_h;
+    sc.halo_y = p->d_halo_y;
+    sc.normals = p->d_normals;
+    for (size_t ti = 0; ti < p->terms.size() && ti < 8; ++ti) {
+        sc.psi[ti] = p->terms[ti].d_psi;
+        sc.xh[ti] = p->terms[ti].d_xh;
+    }
+    return sc;
+}
+
 int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
-                 hipStream_t s, const double* v, void* y) {
+                 hipStream_t s, const double* v, void* y, const EvalScratch* scp) {
+    const EvalScratch sc = scp ? *scp : own_scratch(p);
     const bool hvp = v != nullptr;
     const mad_mesh& m = *p->mesh;
     const int d = p->d;
@@ -33,24 +53,25 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         if (mode & MAD_HESS) MAD_HIP_TRY(launch_fill(hess, p->nnzb * d * d, eb, s));
         if (hvp) MAD_HIP_TRY(launch_fill(y, m.nv * d, eb, s));
     }
-    if (fallback_pass) MAD_HIP_TRY(launch_fill(p->d_fb_count, 1, 4, s));
-    if (p->scatter == MAD_SCATTER_PATCH && p->persistent) MAD_HIP_TRY(launch_fill(p->d_work_counter, 1, 4, s));
+    if (fallback_pass) MAD_HIP_TRY(launch_fill(sc.fb_count, 1, 4, s));
+    if (p->scatter == MAD_SCATTER_PATCH && p->persistent) MAD_HIP_TRY(launch_fill(sc.work_counter, 1, 4, s));
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[1], s));
     // learned and analytic shell densities: vertex normals of x, then the network pass per MLP term
-    if (p->shell) MAD_HIP_TRY(launch_vertex_normals(x, m.nv, p->d_vf_ptr, p->d_vf, p->d_tris, p->d_normals, s));
-    for (const Term& t : p->terms) {
+    if (p->shell) MAD_HIP_TRY(launch_vertex_normals(x, m.nv, p->d_vf_ptr, p->d_vf, p->d_tris, sc.normals, s));
+    for (size_t ti = 0; ti < p->terms.size(); ++ti) {
+        const Term& t = p->terms[ti];
         if (t.kind != MAD_MLP) continue;
         MlpHeadLaunch H{};
         H.x = x;
-        H.normals = p->d_normals;
+        H.normals = sc.normals;
         H.stencil = t.d_stencil;
         H.rest = t.d_rest;
         H.n = t.n;
         H.wbf = t.mlp->d_wbf;
         for (int i = 0; i < 6; ++i) H.s_in[i] = t.mlp->s_in[i];
         H.s_out = t.mlp->s_out;
-        H.xh = t.d_xh;
-        H.psi = t.d_psi;
+        H.xh = sc.xh[ti];
+        H.psi = sc.psi[ti];
         MAD_HIP_TRY(launch_mlp_head(H, s));
     }
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2], s));
@@ -76,29 +97,29 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.lb_gidx = p->d_lb_gidx;
         L.lb_gidxT = p->d_lb_gidxT;
         L.lb_halo = p->d_lb_halo;
-        L.halo_g = p->d_halo_g;
-        L.halo_h = p->d_halo_h;
-        L.partial = p->d_partial;
+        L.halo_g = sc.halo_g;
+        L.halo_h = sc.halo_h;
+        L.partial = sc.partial;
         L.flags = p->d_flags;
         L.fallbacks = p->d_fallbacks;
-        L.fb_list = p->d_fb_list;
-        L.fb_count = p->d_fb_count;
-        L.fb_cap = p->fb_cap;
+        L.fb_list = sc.fb_list;
+        L.fb_count = sc.fb_count;
+        L.fb_cap = sc.fb_cap;
         L.eps = p->opt.spd_eps;
         L.qmin = p->opt.degenerate_q;
         L.lock_spins = p->opt.lock_spins == MAD_LOCK_NO_WAIT ? 0
                        : (p->opt.lock_spins > 0 ? p->opt.lock_spins : kDefaultLockSpins);
         L.persistent = p->persistent;
         L.work_order = p->d_work_order;
-        L.work_counter = p->d_work_counter;
+        L.work_counter = sc.work_counter;
         L.n_cu = p->n_cu;
-        L.normals = p->d_normals;
+        L.normals = sc.normals;
         L.shell = p->shell ? 1 : 0;
         L.light = p->light ? 1 : 0;
         L.hvp = hvp ? 1 : 0;
         L.v = v;
         L.y = y;
-        L.halo_y = p->d_halo_y;
+        L.halo_y = sc.halo_y;
         {
             // relative element cost by kind (reduced dual size, eigen-problem size, network outputs)
             auto cost = [](int kind) {
@@ -125,7 +146,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
             A.lslot = t.d_lslot;
             A.lseg = t.d_lseg;
             A.elem_ptr = t.d_elem_ptr;
-            A.psi = t.d_psi;
+            A.psi = sc.psi[ti];
             A.vdata = t.vdata;
             std::memcpy(A.prm, t.prm, sizeof(A.prm));
         }
@@ -138,8 +159,8 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         G.want_hess = (mode & MAD_HESS) ? 1 : 0;
         G.grad = grad;
         G.hess = hess;
-        G.halo_g = p->d_halo_g;
-        G.halo_h = p->d_halo_h;
+        G.halo_g = sc.halo_g;
+        G.halo_h = sc.halo_h;
         G.gv_ptr = p->d_gv_ptr;
         G.gv_src = p->d_gv_src;
         G.gv_vert = p->d_gv_vert;
@@ -160,7 +181,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
             G.want_grad = 1;
             G.want_hess = 0;
             G.grad = y;
-            G.halo_g = p->d_halo_y;
+            G.halo_g = sc.halo_y;
             MAD_HIP_TRY(launch_gather(G, s));
         }
         if (fallback_pass) {
@@ -172,12 +193,12 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
             F.hess = hess;
             F.rowptr = p->d_rowptr;
             F.colidx = p->d_colidx;
-            F.fb_list = p->d_fb_list;
-            F.fb_count = p->d_fb_count;
-            F.fb_cap = p->fb_cap;
+            F.fb_list = sc.fb_list;
+            F.fb_count = sc.fb_count;
+            F.fb_cap = sc.fb_cap;
             F.flags = p->d_flags;
             F.eps = p->opt.spd_eps;
-            F.normals = p->d_normals;
+            F.normals = sc.normals;
             F.hvp = hvp ? 1 : 0;
             F.v = v;
             F.y = y;
@@ -187,7 +208,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
                 F.terms[ti].n = t.n;
                 F.terms[ti].stencil = t.d_stencil;
                 F.terms[ti].rest = t.d_rest;
-                F.terms[ti].psi = t.d_psi;
+                F.terms[ti].psi = sc.psi[ti];
                 F.terms[ti].vdata = t.vdata;
                 std::memcpy(F.terms[ti].prm, t.prm, sizeof(t.prm));
             }
@@ -213,14 +234,14 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.slots = t.d_slots;
         L.grad = grad;
         L.hess = hess;
-        L.partial = p->d_partial + ti * (size_t)np;
+        L.partial = sc.partial + ti * (size_t)np;
         L.flags = p->d_flags;
         L.fallbacks = p->d_fallbacks;
         std::memcpy(L.prm, t.prm, sizeof(L.prm));
         L.eps = p->opt.spd_eps;
         L.qmin = p->opt.degenerate_q;
-        L.normals = p->d_normals;
-        L.psi = t.d_psi;
+        L.normals = sc.normals;
+        L.psi = sc.psi[ti];
         L.vdata = t.vdata;
         L.hvp = hvp ? 1 : 0;
         L.v = v;
@@ -230,8 +251,8 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
     }
     if (mode & MAD_ENERGY) {
         const int ncomp = (int)m.comp_off.size() - 1;
-        MAD_HIP_TRY(launch_energy_reduce(p->d_partial, n_partial_terms, np, p->d_comp_patch_ptr,
-                                         std::max(ncomp, 1), m.batched, energy, p->d_comp_energy, s));
+        MAD_HIP_TRY(launch_energy_reduce(sc.partial, n_partial_terms, np, p->d_comp_patch_ptr,
+                                         std::max(ncomp, 1), m.batched, energy, sc.comp_energy, s));
     }
     if (ev) MAD_HIP_TRY(hipEventRecord(ev->back(), s));
     return MAD_OK;

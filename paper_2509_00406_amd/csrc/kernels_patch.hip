@@ -622,7 +622,10 @@ __device__ __forceinline__ void fallback_elem(const FallbackLaunch& F, const Fal
 
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_fallback(FallbackLaunch F) {
-    const int cnt = min(*F.fb_count, F.fb_cap);
+    const int queued = *F.fb_count;
+    const int cnt = min(queued, F.fb_cap);
+    // a queue smaller than the number of queued elements dropped some: the evaluation is not valid
+    if (queued > F.fb_cap && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(F.flags + 1, kFlagQueueOverflow);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
         const uint32_t w = F.fb_list[i];
         const int t = (int)(w >> kFbTermShift), e = (int)(w & kFbElemMask);

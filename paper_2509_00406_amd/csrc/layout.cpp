@@ -161,6 +161,7 @@ static void free_layout(mad_problem* p) {
     p->d_gb_ptr = p->d_gb_src = p->d_gb_gidx = p->d_gb_gidxT = nullptr;
     p->d_orphan_vert = p->d_orphan_block = nullptr;
     p->d_halo_g = p->d_halo_h = p->d_halo_y = nullptr;
+    p->n_halo_v = p->n_halo_b = 0;
     p->d_fb_list = nullptr;
     p->d_fb_count = nullptr;
     p->d_work_order = p->d_work_counter = nullptr;
@@ -336,6 +337,8 @@ int build_scatter(mad_problem* p, hipStream_t s) {
     p->n_orphan_vert = (int32_t)L.orphan_vert.size();
     p->n_orphan_block = (int32_t)L.orphan_block.size();
     const size_t eb = p->prec == MAD_F32 ? 4 : 8;
+    p->n_halo_v = (int64_t)L.gv_src.size();
+    p->n_halo_b = (int64_t)L.gb_src.size();
     if ((rc = alloc_layout(p, &p->d_halo_g, L.gv_src.size() * p->d * eb)) != MAD_OK) return rc;
     if ((rc = alloc_layout(p, &p->d_halo_h, L.gb_src.size() * p->d * p->d * eb)) != MAD_OK) return rc;
     if ((rc = alloc_layout(p, &p->d_halo_y, L.gv_src.size() * p->d * eb)) != MAD_OK) return rc;

@@ -154,6 +154,7 @@ struct mad_problem {
     void* d_halo_g = nullptr;             // [halo vertex slots][D] partial gradients of shared vertices
     void* d_halo_h = nullptr;             // [halo block slots][D*D] partial blocks of shared blocks
     void* d_halo_y = nullptr;             // [halo vertex slots][D] partial Hessian-vector products
+    int64_t n_halo_v = 0, n_halo_b = 0;   // halo slots of shared vertices / shared upper blocks
     uint32_t* d_fb_list = nullptr;
     int32_t* d_fb_count = nullptr;
     int32_t fb_cap = 0;
@@ -172,6 +173,7 @@ namespace mad {
 constexpr int32_t kFlagSlotMissing = 4;        // atomic scatter: an element block is not in the pattern
 constexpr int32_t kFlagRedoBlockMissing = 8;   // FP64 redo: an element block is not in the pattern
 constexpr int32_t kFlagLockTimeout = 16;       // patch kernel: a wait for the LDS lock reached its bound
+constexpr int32_t kFlagQueueOverflow = 32;     // more FP32 elements queued for the FP64 redo than the queue holds
 constexpr int32_t kDefaultLockSpins = 1 << 22;
 
 void set_error(const std::string& msg);
@@ -198,9 +200,31 @@ void build_patches(const mad_mesh& m, int target_faces, Patches& p);
 // layout.cpp: (re)build the element order and the scatter structures of a problem
 int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s);
 int build_scatter(mad_problem* p, hipStream_t s);
-// one evaluation; with v != NULL the matrix-free product y = H v replaces the Hessian (hess NULL)
+// Device buffers an evaluation writes and reads back within itself; nothing in them outlives the
+// evaluation. By default the problem's own (allocated with its layout); mad_problem_eval_static takes
+// them from the library's static scratch array instead.
+struct EvalScratch {
+    double* partial = nullptr;        // [n_terms][n_patch] per-patch energies
+    double* comp_energy = nullptr;    // [n_comp] per-component energies (reduction scratch)
+    int32_t* work_counter = nullptr;  // head of the persistent launch's patch queue
+    int32_t* fb_count = nullptr;      // length of the FP64 redo queue
+    uint32_t* fb_list = nullptr;      // [fb_cap] FP32 elements queued for the FP64 redo
+    int32_t fb_cap = 0;
+    void* halo_g = nullptr;           // [n_halo_v][D]
+    void* halo_h = nullptr;           // [n_halo_b][D*D]
+    void* halo_y = nullptr;           // [n_halo_v][D] (matrix-free products only)
+    double* normals = nullptr;        // [nv][3] unit vertex normals (shell-feature terms)
+    float* psi[8] = {};               // per term: network outputs SoA [28][n] (learned density)
+    float* xh[8] = {};                // per term: scaled features SoA [6][n] (learned density)
+};
+EvalScratch own_scratch(const mad_problem* p);
+// argument checks shared by mad_problem_eval and mad_problem_eval_static
+int check_eval_args(const mad_problem* p, const double* x, uint32_t mode, const double* energy, const void* grad,
+                    const void* hess);
+// one evaluation; with v != NULL the matrix-free product y = H v replaces the Hessian (hess NULL);
+// sc NULL: the problem's own scratch
 int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
-                 hipStream_t s, const double* v = nullptr, void* y = nullptr);
+                 hipStream_t s, const double* v = nullptr, void* y = nullptr, const EvalScratch* sc = nullptr);
 constexpr size_t kLdsBudget = 76 * 1024;  // dynamic LDS per workgroup: two workgroups in a CU's 160 KB
 // work units (64 elements of one term) per patch: the patch kernel keeps one energy slot per unit
 constexpr int kMaxPatchUnits = 256;

@@ -64,6 +64,8 @@ _SIGS = {
     "mad_problem_copy_pattern": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int32),
     "mad_problem_eval": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
                          C.c_int32),
+    "mad_problem_eval_static": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p], C.c_int32),
     "mad_problem_status": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_void_p], C.c_int32),
     "mad_problem_hvp": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
                          C.c_void_p], C.c_int32),
@@ -251,6 +253,11 @@ def mad_problem_copy_pattern(prob, rowptr, colidx, stream=None):
 def mad_problem_eval(prob, x, mode: int, energy=None, grad=None, hess=None, stream=None):
     _check(lib().mad_problem_eval(prob, _ptr(x), mode, _ptr(energy), _ptr(grad), _ptr(hess), _stream(stream)),
            "mad_problem_eval")
+
+
+def mad_problem_eval_static(prob, x, mode: int, energy=None, grad=None, hess=None, stream=None):
+    _check(lib().mad_problem_eval_static(prob, _ptr(x), mode, _ptr(energy), _ptr(grad), _ptr(hess),
+                                         _stream(stream)), "mad_problem_eval_static")
 
 
 def mad_problem_hvp(prob, x, v, mode: int, energy=None, grad=None, y=None, stream=None):
@@ -490,6 +497,14 @@ class Problem:
         energy, grad, hess = out if out is not None else self.outputs(x.device)
         mad_problem_eval(self.handle, x, mode, energy if mode & ENERGY else None,
                          grad if mode & GRAD else None, hess if mode & HESS else None, stream)
+        return energy, grad, hess
+
+    def eval_static(self, x, mode: int = ENERGY | GRAD | HESS, out=None, stream=None):
+        """mad_problem_eval_static: the same evaluation with the library's static scratch (no allocation
+        inside the call; `out` must then be given by callers that cannot allocate)."""
+        energy, grad, hess = out if out is not None else self.outputs(x.device)
+        mad_problem_eval_static(self.handle, x, mode, energy if mode & ENERGY else None,
+                                grad if mode & GRAD else None, hess if mode & HESS else None, stream)
         return energy, grad, hess
 
     def status(self, stream=None):
