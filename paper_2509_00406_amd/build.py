@@ -16,7 +16,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libmad.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels_patch.hip", "kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "host_patch.cpp",
+SOURCES = ["kernels_patch.hip", "kernels_eval.hip", "kernels_pattern.hip", "host_mesh.cpp", "host_patch.cpp", "host_layout.cpp",
            "kernels_mlp.hip", "kernels_jac.hip", "layout.cpp", "eval.cpp", "autotune.cpp", "mlp.cpp", "api.cpp",
            "eval_static.hip"]
 

@@ -27,118 +27,6 @@ static int alloc_layout(mad_problem* p, void** dst, size_t bytes) {
     return MAD_OK;
 }
 
-// Inside each patch, greedy-colour the term's elements so that no two elements of a colour share a
-// vertex, and store them colour by colour (stable), so that the elements a wave evaluates together
-// rarely add into the same LDS accumulators.
-static void color_within_patches(Term& t, int64_t nv) {
-    const int32_t np = (int32_t)t.elem_ptr.size() - 1;
-    // patches are independent: split them over threads, each with its own vertex bit array
-    auto work = [&](int32_t q0, int32_t q1) {
-        std::vector<uint64_t> busy_at((size_t)nv, 0);
-        std::vector<int32_t> color, order, seg;
-        for (int32_t q = q0; q < q1; ++q) {
-            const int32_t b = t.elem_ptr[q], e = t.elem_ptr[q + 1];
-            if (e - b < 2) continue;
-            color.assign((size_t)(e - b), 0);
-            for (int32_t i = b; i < e; ++i) {
-                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                uint64_t busy = 0;
-                for (int a = 0; a < t.ns; ++a) busy |= busy_at[st[a]];
-                int c = 0;
-                while (c < 63 && ((busy >> c) & 1ull)) ++c;
-                color[i - b] = c;
-                for (int a = 0; a < t.ns; ++a) busy_at[st[a]] |= 1ull << c;
-            }
-            for (int32_t i = b; i < e; ++i) {
-                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                for (int a = 0; a < t.ns; ++a) busy_at[st[a]] = 0;
-            }
-            order.resize((size_t)(e - b));
-            std::iota(order.begin(), order.end(), 0);
-            std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return color[x] < color[y]; });
-            seg.assign(t.perm.begin() + b, t.perm.begin() + e);
-            for (int32_t i = 0; i < e - b; ++i) t.perm[b + i] = seg[order[i]];
-        }
-    };
-    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::vector<std::thread> pool;
-    for (int w = 1; w < nth; ++w)
-        pool.emplace_back(work, (int32_t)((int64_t)np * w / nth), (int32_t)((int64_t)np * (w + 1) / nth));
-    work(0, (int32_t)((int64_t)np / nth));
-    for (auto& th : pool) th.join();
-}
-
-// Patch order of every term's elements: faces by their patch, diamonds by their lower face, edges
-// by their first face, vertices by their lowest face; inside a patch by that face's index. Two
-// stable counting sorts (by face, then by patch): linear in the element count. The colour order
-// inside each patch (color_within_patches) is applied once the patches are final.
-static void order_terms(mad_problem* p) {
-    const mad_mesh& m = *p->mesh;
-    const int32_t np = p->patches.n;
-    for (auto& t : p->terms) {
-        std::vector<int32_t> key((size_t)t.n);
-        for (int64_t e = 0; e < t.n; ++e) {
-            if (t.kind == MAD_BENDING) key[e] = m.diamond_faces[2 * e];
-            else if (t.kind == MAD_EDGE_SQLEN || t.kind == MAD_SPRING || t.kind == MAD_RES_EDGE) key[e] = m.edge_face0[e];
-            else if (t.kind == MAD_INERTIA || t.kind == MAD_RES_POSITION) key[e] = m.vert_face0[t.stencil[e]];
-            else key[e] = (int32_t)e;
-        }
-        // by face
-        std::vector<int32_t> cnt((size_t)m.nt + 1, 0), byface((size_t)t.n);
-        for (int64_t e = 0; e < t.n; ++e) cnt[key[e] + 1]++;
-        for (int64_t f = 0; f < m.nt; ++f) cnt[f + 1] += cnt[f];
-        for (int64_t e = 0; e < t.n; ++e) byface[cnt[key[e]]++] = (int32_t)e;
-        // then by patch (stable)
-        t.elem_ptr.assign((size_t)np + 1, 0);
-        for (int64_t e = 0; e < t.n; ++e) t.elem_ptr[p->patches.face_patch[key[e]] + 1]++;
-        for (int32_t q = 0; q < np; ++q) t.elem_ptr[q + 1] += t.elem_ptr[q];
-        std::vector<int32_t> fill(t.elem_ptr.begin(), t.elem_ptr.end() - 1);
-        t.perm.resize((size_t)t.n);
-        for (int32_t e : byface) t.perm[fill[p->patches.face_patch[key[e]]]++] = e;
-    }
-}
-
-// largest per-patch vertex and upper-block counts of the current patching (patches split over
-// threads; each counts its distinct vertices with a stamp array and its distinct pairs by sorting)
-static void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb) {
-    const int64_t nv = p->mesh->nv;
-    const int32_t np = p->patches.n;
-    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    std::vector<int32_t> mv_t((size_t)nth, 0), mb_t((size_t)nth, 0);
-    auto work = [&](int th) {
-        std::vector<int32_t> stamp((size_t)nv, -1);
-        std::vector<int64_t> keys;
-        int32_t mv = 0, mb = 0;
-        for (int32_t q = th; q < np; q += nth) {
-            keys.clear();
-            int32_t nverts = 0;
-            for (const auto& t : p->terms)
-                for (int32_t i = t.elem_ptr[q]; i < t.elem_ptr[q + 1]; ++i) {
-                    const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                    for (int a = 0; a < t.ns; ++a) {
-                        if (stamp[st[a]] != q) {
-                            stamp[st[a]] = q;
-                            ++nverts;
-                        }
-                        for (int b = a; b < t.ns; ++b)
-                            keys.push_back((int64_t)std::min(st[a], st[b]) * nv + std::max(st[a], st[b]));
-                    }
-                }
-            std::sort(keys.begin(), keys.end());
-            mv = std::max(mv, nverts);
-            mb = std::max(mb, (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin()));
-        }
-        mv_t[th] = mv;
-        mb_t[th] = mb;
-    };
-    std::vector<std::thread> pool;
-    for (int th = 1; th < nth; ++th) pool.emplace_back(work, th);
-    work(0);
-    for (auto& th : pool) th.join();
-    *max_lv = *std::max_element(mv_t.begin(), mv_t.end());
-    *max_lb = *std::max_element(mb_t.begin(), mb_t.end());
-}
-
 static void free_layout(mad_problem* p) {
     for (void* q : p->layout_owned) (void)hipFree(q);
     p->layout_owned.clear();
@@ -258,34 +146,6 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
     MAD_HIP_TRY(hipStreamSynchronize(s));
     if (p->h_rowptr.empty()) return MAD_OK;   // pattern not built yet (first layout, inside finalize)
     return build_scatter(p, s);
-}
-
-// Segments of the patch kernel's work units (the 64 consecutive elements of one term in one patch
-// that one wave evaluates together): inside a unit, greedily, each element takes the lowest segment
-// in which no earlier element of the unit shares a vertex with it. Elements of one segment touch
-// disjoint gradient entries and Hessian blocks, so a wave can add a segment's contributions with
-// plain LDS read-add-writes. The colour order inside each patch keeps most units at one or two
-// segments.
-static void unit_segments(const Term& t, int32_t np, int64_t nv, std::vector<uint8_t>& seg) {
-    seg.assign((size_t)std::max<int64_t>(t.n, 1), 0);
-    std::vector<uint64_t> used((size_t)nv, 0);   // segments of the current unit using the vertex
-    for (int32_t q = 0; q < np; ++q)
-        for (int32_t u0 = t.elem_ptr[q]; u0 < t.elem_ptr[q + 1]; u0 += 64) {
-            const int32_t u1 = std::min(u0 + 64, t.elem_ptr[q + 1]);
-            for (int32_t i = u0; i < u1; ++i) {
-                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                uint64_t busy = 0;
-                for (int a = 0; a < t.ns; ++a) busy |= used[st[a]];
-                int sg = 0;
-                while ((busy >> sg) & 1ull) ++sg;   // at most 63: a unit has 64 elements
-                seg[i] = (uint8_t)sg;
-                for (int a = 0; a < t.ns; ++a) used[st[a]] |= 1ull << sg;
-            }
-            for (int32_t i = u0; i < u1; ++i) {
-                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                for (int a = 0; a < t.ns; ++a) used[st[a]] = 0;
-            }
-        }
 }
 
 // Structures of the scatter strategy for the current element order; needs the pattern.

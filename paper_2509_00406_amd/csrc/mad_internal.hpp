@@ -197,6 +197,12 @@ int rest_shell(const mad_mesh& m, const double* rest_pos, std::vector<double>& o
 int rest_spring(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);     // [ne][2]
 int rest_edge_length(const mad_mesh& m, const double* rest_pos, std::vector<double>& out);  // [ne]
 void build_patches(const mad_mesh& m, int target_faces, Patches& p);
+// host_layout.cpp: element order by patch, colour order inside patches, the largest patch's vertex and
+// upper-block counts, segments of the 64-element work units
+void order_terms(mad_problem* p);
+void color_within_patches(Term& t, int64_t nv);
+void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb);
+void unit_segments(const Term& t, int32_t np, int64_t nv, std::vector<uint8_t>& seg);
 // layout.cpp: (re)build the element order and the scatter structures of a problem
 int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s);
 int build_scatter(mad_problem* p, hipStream_t s);
