@@ -2,10 +2,10 @@
 // element-element couplings in parallel, prefix-sum the per-row counts into
 // row offsets, then fill the columns.
 //
-// Every block row is owned by one lane, which gathers the stencils of the
-// elements incident to its vertex (from a vertex -> element incidence built
-// by a count / scan / fill pass) into a sorted, de-duplicated list. The
-// result is unique (sorted unique columns per row, diagonal always present),
+// Every block row is owned by one 64-lane workgroup, which gathers the stencils
+// of the elements incident to its vertex (from a vertex -> element incidence
+// built by a count / scan / fill pass), sorts them and drops repeats; rows of
+// any length (any vertex valence) are handled. The result is unique (sorted unique columns per row, diagonal always present),
 // so the pattern is bit-exact regardless of the order in which atomics
 // filled the incidence lists. Scans are exclusive three-phase scans
 // (block sums, scan of block sums, block-local rescan) with int64 totals so
@@ -21,7 +21,6 @@ namespace mad {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanChunk = kScanThreads * kScanItems;
-constexpr int kMaxRow = 256;   // max distinct block columns per row gathered by one lane
 
 // ---- exclusive scan: out[i] = sum_{j<i} in[j], out[n] = total (int64) ---------------------------
 template <typename TI>
@@ -125,41 +124,100 @@ __global__ void k_incidence(const int32_t* stencil, int64_t n, int ns, int64_t e
     }
 }
 
-// per vertex: sorted unique neighbour list; pass 0 writes counts, pass 1 writes columns
-__global__ void k_rows(TermTable tt, int64_t nv, const int32_t* vptr, const int32_t* inc, int32_t* cnt,
-                       const int32_t* rowptr, int32_t* colidx, int32_t* flags, int pass) {
+// Rows of any length. Row v's candidates are v itself and, for each element incident to v, its stencil
+// vertices in a slot of kMaxStencil entries (shorter stencils padded with INT32_MAX): 1 + kMaxStencil * deg(v)
+// values, padded to the next power of two. One 64-lane workgroup per row sorts them with a bitonic network
+// (in LDS when they fit kRowLds entries, else in the row's own range of a global scratch buffer), then
+// keeps the first of each run of equal values. Pass 0 writes the row's distinct count, pass 1 its columns.
+constexpr int kMaxStencil = 4;
+constexpr int kRowLds = 2048;
+constexpr int kRowThreads = 64;
+
+__host__ __device__ inline int32_t pow2_at_least(int32_t x) {
+    int32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// candidates of row v, padded to a power of two; entries of rows longer than kRowLds go to global scratch
+__global__ void k_row_size(const int32_t* vptr, int64_t nv, int32_t* long_size, int32_t* flags) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nv) return;
-    int32_t list[kMaxRow];
-    int len = 1;
-    list[0] = (int32_t)v;
-    for (int32_t k = vptr[v]; k < vptr[v + 1]; ++k) {
-        const int64_t g = inc[k];
-        int t = 0;
-        while (t + 1 < tt.n_terms && g >= tt.off[t + 1]) ++t;
-        const int ns = tt.ns[t];
-        const int32_t* st = tt.stencil[t] + (g - tt.off[t]) * ns;
-        for (int a = 0; a < ns; ++a) {
-            const int32_t c = st[a];
-            // insertion into the sorted list, skipping duplicates
-            int pos = len;
-            while (pos > 0 && list[pos - 1] > c) --pos;
-            if (pos > 0 && list[pos - 1] == c) continue;
-            if (len >= kMaxRow) {
-                atomicOr(flags + 1, 2);
-                continue;
-            }
-            for (int q = len; q > pos; --q) list[q] = list[q - 1];
-            list[pos] = c;
-            ++len;
+    const int32_t deg = vptr[v + 1] - vptr[v];
+    if (deg > (1 << 27)) {   // the padded candidate count would pass 2^30
+        atomicOr(flags, 1);
+        long_size[v] = 0;
+        return;
+    }
+    const int32_t p = pow2_at_least(1 + kMaxStencil * deg);
+    long_size[v] = p > kRowLds ? p : 0;
+}
+
+// One row's candidates, sorted and de-duplicated by the 64 lanes of the workgroup. `buf` (P entries) is
+// either the workgroup's LDS buffer or the row's range of global scratch: the caller passes one or the
+// other from separate branches, so each inlined copy addresses a single memory space (LDS or global) and
+// no generic (flat) pointer is formed.
+__device__ __forceinline__ void row_sort_body(int32_t* buf, const TermTable& tt, int32_t v, const int32_t* vptr,
+                                              const int32_t* inc, int32_t* cnt, const int32_t* rowptr,
+                                              int32_t* colidx, int pass) {
+    const int lane = (int)threadIdx.x;
+    const int32_t k0 = vptr[v], n = 1 + kMaxStencil * (vptr[v + 1] - k0);
+    const int32_t P = pow2_at_least(n);
+    for (int32_t i = lane; i < P; i += kRowThreads) {
+        int32_t c = INT32_MAX;
+        if (i == 0) {
+            c = v;
+        } else if (i < n) {
+            const int32_t a = (i - 1) % kMaxStencil;
+            const int64_t g = inc[k0 + (i - 1) / kMaxStencil];
+            int t = 0;
+            while (t + 1 < tt.n_terms && g >= tt.off[t + 1]) ++t;
+            const int ns = tt.ns[t];
+            if (a < ns) c = tt.stencil[t][(g - tt.off[t]) * ns + a];
         }
+        buf[i] = c;
     }
-    if (pass == 0) {
-        cnt[v] = len;
-    } else {
-        const int32_t b = rowptr[v];
-        for (int q = 0; q < len; ++q) colidx[b + q] = list[q];
+    __syncthreads();
+    // bitonic sort, ascending
+    for (int32_t size = 2; size <= P; size <<= 1)
+        for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int32_t i = lane; i < P / 2; i += kRowThreads) {
+                const int32_t lo = 2 * stride * (i / stride) + (i & (stride - 1)), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const int32_t a = buf[lo], b = buf[hi];
+                if ((a > b) == up) {
+                    buf[lo] = b;
+                    buf[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    // first of each run of equal values, padding excluded; lane order keeps the columns sorted
+    int32_t done = 0;
+    for (int32_t base = 0; base < P; base += kRowThreads) {
+        const int32_t i = base + lane;
+        int32_t c = INT32_MAX;
+        bool keep = false;
+        if (i < P) {
+            c = buf[i];
+            const int32_t prev = buf[i > 0 ? i - 1 : 0];
+            keep = c != INT32_MAX && (i == 0 || prev != c);
+        }
+        const uint64_t m = __ballot(keep);
+        if (pass == 1 && keep) colidx[rowptr[v] + done + __popcll(m & ((1ull << lane) - 1ull))] = c;
+        done += __popcll(m);
     }
+    if (pass == 0 && lane == 0) cnt[v] = done;
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_row_sort(TermTable tt, const int32_t* vptr, const int32_t* inc,
+                                                          const int64_t* long_off, int32_t* long_buf, int32_t* cnt,
+                                                          const int32_t* rowptr, int32_t* colidx, int pass) {
+    __shared__ int32_t sbuf[kRowLds];
+    const int32_t v = (int32_t)blockIdx.x;
+    const int32_t P = pow2_at_least(1 + kMaxStencil * (vptr[v + 1] - vptr[v]));
+    if (P <= kRowLds) row_sort_body(sbuf, tt, v, vptr, inc, cnt, rowptr, colidx, pass);
+    else row_sort_body(long_buf + long_off[v], tt, v, vptr, inc, cnt, rowptr, colidx, pass);
 }
 
 __global__ void k_i64_to_i32(const int64_t* in, int32_t* out, int64_t n) {
@@ -244,19 +302,36 @@ int build_pattern_device(int64_t nv, const std::vector<PatternTerm>& terms, int3
                            terms[t].stencil, terms[t].n, terms[t].ns, tt.off[t], vptr, cursor, inc);
     }
     PT_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_rows, dim3(blocks_for(nv, 128)), dim3(128), 0, s, tt, nv, vptr, inc, cnt,
-                       (const int32_t*)nullptr, (int32_t*)nullptr, flags, 0);
+    // global scratch for rows whose candidates exceed the LDS buffer (high-valence vertices)
+    hipLaunchKernelGGL(k_row_size, dim3(blocks_for(nv, 256)), dim3(256), 0, s, vptr, nv, cnt, flags);
+    PT_TRY(hipGetLastError());
+    PT_TRY((scan_exclusive<int32_t, int64_t>(cnt, nv, rowptr64, scan_tmp, s)));
+    int64_t long_total = 0;
+    int32_t hflag = 0;
+    PT_TRY(hipMemcpyAsync(&long_total, rowptr64 + nv, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PT_TRY(hipMemcpyAsync(&hflag, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PT_TRY(hipStreamSynchronize(s));
+    if (hflag != 0) {
+        cleanup();
+        return fail(MAD_E_OVERFLOW, "a vertex lies in more than 2^27 element stencils");
+    }
+    int64_t* long_off = nullptr;
+    int32_t* long_buf = nullptr;
+    if (long_total > 0) {
+        if ((e = alloc((void**)&long_off, sizeof(int64_t) * (nv + 1))) != hipSuccess ||
+            (e = alloc((void**)&long_buf, sizeof(int32_t) * (size_t)long_total)) != hipSuccess) {
+            cleanup();
+            return fail(MAD_E_OOM, std::string("pattern scratch: ") + hipGetErrorString(e));
+        }
+        PT_TRY(hipMemcpyAsync(long_off, rowptr64, sizeof(int64_t) * (nv + 1), hipMemcpyDeviceToDevice, s));
+    }
+    hipLaunchKernelGGL(k_row_sort, dim3((unsigned)nv), dim3(kRowThreads), 0, s, tt, vptr, inc,
+                       (const int64_t*)long_off, long_buf, cnt, (const int32_t*)nullptr, (int32_t*)nullptr, 0);
     PT_TRY(hipGetLastError());
     PT_TRY((scan_exclusive<int32_t, int64_t>(cnt, nv, rowptr64, scan_tmp, s)));
     int64_t total = 0;
-    int32_t hflags[4] = {0, 0, 0, 0};
     PT_TRY(hipMemcpyAsync(&total, rowptr64 + nv, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    PT_TRY(hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
     PT_TRY(hipStreamSynchronize(s));
-    if (hflags[1] != 0) {
-        cleanup();
-        return fail(MAD_E_UNSUPPORTED, "a vertex couples to more than 255 other vertices");
-    }
     if (total > INT32_MAX) {
         cleanup();
         return fail(MAD_E_OVERFLOW, "block count exceeds int32");
@@ -273,8 +348,8 @@ int build_pattern_device(int64_t nv, const std::vector<PatternTerm>& terms, int3
         return fail(MAD_E_OOM, "pattern arrays");
     }
     hipLaunchKernelGGL(k_i64_to_i32, dim3(blocks_for(nv + 1, 256)), dim3(256), 0, s, rowptr64, rowptr, nv + 1);
-    hipLaunchKernelGGL(k_rows, dim3(blocks_for(nv, 128)), dim3(128), 0, s, tt, nv, vptr, inc, cnt,
-                       (const int32_t*)rowptr, colidx, flags, 1);
+    hipLaunchKernelGGL(k_row_sort, dim3((unsigned)nv), dim3(kRowThreads), 0, s, tt, vptr, inc,
+                       (const int64_t*)long_off, long_buf, cnt, (const int32_t*)rowptr, colidx, 1);
     PT_TRY(hipGetLastError());
     PT_TRY(hipStreamSynchronize(s));
 #undef PT_TRY
