@@ -408,15 +408,17 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
 
     // flush: entries only this patch touches go straight to the output; shared entries go to their
     // halo slot and are summed by the gather kernel
+    // one vertex's D gradient entries, or one row of a D x D block, per thread: the patch's index lists
+    // are read once per vertex / block row, and each thread writes D consecutive values
     if constexpr (MODE >= 1) {
         if (L.want_grad) {
             T* G = static_cast<T*>(L.grad);
             T* HG = static_cast<T*>(L.halo_g);
-            for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
-                const int k = lv0 + i / D, c = i % D;
-                const int32_t h = L.lv_halo[k];
-                if (h < 0) G[(int64_t)L.lv_global[k] * D + c] = sg[i];
-                else HG[(int64_t)h * D + c] = sg[i];
+            for (int i = threadIdx.x; i < nlv; i += kBlock) {
+                const int32_t h = L.lv_halo[lv0 + i];
+                T* dst = h < 0 ? G + (int64_t)L.lv_global[lv0 + i] * D : HG + (int64_t)h * D;
+#pragma unroll
+                for (int c = 0; c < D; ++c) dst[c] = sg[i * D + c];
             }
         }
     }
@@ -439,18 +441,23 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         }
         T* H = static_cast<T*>(L.hess);
         T* HH = static_cast<T*>(L.halo_h);
-        for (int i = threadIdx.x; i < nlb * DD; i += kBlock) {
-            const int b = lb0 + i / DD, k = i % DD;
-            const int32_t h = L.lb_halo[b];
-            const int32_t g = L.lb_gidx[b], gt = L.lb_gidxT[b];
-            const int r = k / D, c = k % D;
-            // a diagonal block keeps only its upper half in LDS
-            const T v = (g == gt && c < r) ? sh[(i / DD) * DD + c * D + r] : sh[i];
-            if (h >= 0) {
-                HH[(int64_t)h * DD + k] = v;
-            } else {
-                H[(int64_t)g * DD + k] = v;
-                if (gt != g) H[(int64_t)gt * DD + c * D + r] = v;
+        for (int i = threadIdx.x; i < nlb * D; i += kBlock) {
+            const int bl = i / D, r = i % D;
+            const int32_t h = L.lb_halo[lb0 + bl];
+            const int32_t g = L.lb_gidx[lb0 + bl], gt = L.lb_gidxT[lb0 + bl];
+            const T* blk = sh + bl * DD;
+            // row r of the block; a diagonal block keeps only its upper half in LDS
+            T row[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) row[c] = (g == gt && c < r) ? blk[c * D + r] : blk[r * D + c];
+            T* dst = h >= 0 ? HH + (int64_t)h * DD + r * D : H + (int64_t)g * DD + r * D;
+#pragma unroll
+            for (int c = 0; c < D; ++c) dst[c] = row[c];
+            if (h < 0 && gt != g) {
+                // row r of the transposed block (c, r) is column r of this one
+                T* dt = H + (int64_t)gt * DD + r * D;
+#pragma unroll
+                for (int c = 0; c < D; ++c) dt[c] = blk[c * D + r];
             }
         }
     }
