@@ -311,23 +311,34 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
     }
     red[threadIdx.x] = 0.0;   // per-unit energies
     bool bad_x = false;
-    for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
-        const int v = L.lv_global[lv0 + i / D];
-        const double xv = L.x[(int64_t)v * D + (i % D)];
-        sx[i] = xv;
-        bad_x = bad_x || !finite(xv);
-        if constexpr (MODE >= 1) sg[i] = T(0);
-        if constexpr (MODE >= 2) {
-            if (L.hvp) {
-                sh[i] = T(L.v[(int64_t)v * D + (i % D)]);
-                sy[i] = T(0);
+    // one vertex per thread: its index read once, its D coordinates loaded together
+    for (int i = threadIdx.x; i < nlv; i += kBlock) {
+        const int64_t v = L.lv_global[lv0 + i];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const double xv = L.x[v * D + c];
+            sx[i * D + c] = xv;
+            bad_x = bad_x || !finite(xv);
+            if constexpr (MODE >= 1) sg[i * D + c] = T(0);
+            if constexpr (MODE >= 2) {
+                if (L.hvp) {
+                    sh[i * D + c] = T(L.v[v * D + c]);
+                    sy[i * D + c] = T(0);
+                }
             }
         }
     }
     if (bad_x) atomicOr(L.flags, 1);
-    if constexpr (MODE >= 2)
-        if (!L.hvp)
-            for (int i = threadIdx.x; i < nlb * DD; i += kBlock) sh[i] = T(0);
+    if constexpr (MODE >= 2) {
+        if (!L.hvp) {
+            // 16-byte LDS writes (the block area starts 16-byte aligned), then the tail
+            const int nw = nlb * DD;
+            float4* sh4 = reinterpret_cast<float4*>(sh);
+            const int n4 = (nw * (int)sizeof(T)) / 16;
+            for (int i = threadIdx.x; i < n4; i += kBlock) sh4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int i = n4 * (16 / (int)sizeof(T)) + threadIdx.x; i < nw; i += kBlock) sh[i] = T(0);
+        }
+    }
     __syncthreads();
 
     bool bad = false;
