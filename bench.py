@@ -41,15 +41,17 @@ sys.path.insert(0, ROOT)
 # workload (FP32 + FP64 VALU wave instructions x 64 lanes, FMA = 2), and its HBM traffic per launch
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy), from the rocprofv3 counter
 # passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
-FLOPS_PER_ELEM = {"f32": 14924.3, "f64": None}
+FLOPS_PER_ELEM = {"f32": 14925.0, "f64": None}
 # traffic by launch (persistent queue / one workgroup per patch) at the default 384-face layout
-TRAFFIC_BYTES = {"f32": {1: 1.3109e9, 0: 1.0353e9}, "f64": None}
+TRAFFIC_BYTES = {"f32": {1: 1.2522e9, 0: 1.0360e9}, "f64": None}
 # the same for the 1000^2 cloth step at its default layout (profiles/k_eval_patch_f32_cloth1000_counters.md)
 CLOTH_TRAFFIC_BYTES = {"f32": 0.5675e9, "f64": None}
 
 # MI355X published peaks used as roofline denominators
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# the FP32 vector rate without packed FP32 instructions (this build disables them): half the published figure
+VALU_UNPACKED_TFLOPS = {"f32": 78.6, "f64": 78.6}
 
 SHELL_TERMS = ((4, (1.0, 1.0)), (5, (1.0, 1.0)))   # StVK (mu, lambda), bending (k_b, h)
 
@@ -440,7 +442,9 @@ def main():
                     "traffic": ((TRAFFIC_BYTES.get(args.precision) or {}).get(layout["persistent"])
                                 if layout["patch_faces"] == 384 else None),
                     "kernel_ms": dom_ms,
-                    "flops_per_element": fpe}
+                    "flops_per_element": fpe,
+                    "frac_of_unpacked_fp32": achieved / VALU_UNPACKED_TFLOPS[args.precision],
+                    "hbm_frac_alg": step_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     else:
         roofline = {"bound": "alu", "kernel": dom_name, "achieved": None, "peak": peak, "unit": "TFLOP/s",
                     "frac": None, "traffic": None, "kernel_ms": dom_ms, "flops_per_element": None}
