@@ -365,6 +365,10 @@ def mad_problem_add_mlp_term(prob, mlp, rest_pos: np.ndarray):
 
 
 # ---- convenience objects (still marshalling only) -----------------------------------------------
+# parameters of the shell density trained on oracle samples (written by tests/train_density.py)
+TRAINED_DENSITY = os.path.join(HERE, "data", "shell_density_net.npz")
+
+
 class Network:
     """The learned density's network (FP32 master parameters, BF16 evaluation copy)."""
 
@@ -372,6 +376,12 @@ class Network:
         self.handle = mad_mlp_create(params, s_in, s_out)
         self.s_in = np.asarray(s_in, np.float32)
         self.s_out = float(s_out)
+
+    @classmethod
+    def from_file(cls, path: str = TRAINED_DENSITY) -> "Network":
+        """A network from saved parameters (theta, s_in, s_out arrays of an .npz file)."""
+        with np.load(path, allow_pickle=False) as f:
+            return cls(f["theta"], f["s_in"], float(f["s_out"][0]))
 
     def set_params(self, params):
         mad_mlp_set_params(self.handle, params)

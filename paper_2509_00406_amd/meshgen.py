@@ -321,13 +321,16 @@ def icosphere_batch(n_meshes: int = 700, size_seed: int = 4001, shape_seed: int 
                                size_seed=size_seed, shape_seed=shape_seed))
 
 
-def training_shells(n_meshes: int, n: int = 32, seed: int = 5002) -> list[MeshInput]:
+def training_shells(n_meshes: int, n: int = 32, seed: int = 5002, noise_max: float = 1e-3) -> list[MeshInput]:
     """Perturbed rolled sheets whose triangles supply training samples of the learned density.
 
     Each sheet: flat n x n rest grid on [0,1]^2 (grid()); deformed by rotating the sheet in its
     plane by phi ~ U[0, pi), stretching the two in-plane axes by 1 + U[-0.05, 0.05] each, rolling
     (roll_cylinder) with radius R = +-U[0.2, 2] (random sign: bending either way), and adding
-    N(0, (1e-3 h)^2) noise per coordinate.
+    N(0, (s h)^2) noise per coordinate, s = 1e-3, or with noise_max > 1e-3, s log-uniform in
+    [1e-3, noise_max] per sheet (drawn after the sheet's other parameters). The normal-based second form
+    of a triangle picks up noise of about s / h: a wider s range covers the spread of the features of
+    finer meshes (s / h ~ 0.7 on a 708 x 708 sheet with s = 1e-3).
     """
     rg = np.random.default_rng(seed)
     tris, rest = grid(n)
@@ -342,7 +345,8 @@ def training_shells(n_meshes: int, n: int = 32, seed: int = 5002) -> list[MeshIn
         p[:, 1] = (s * rest[:, 0] + c * rest[:, 1]) * st[1]
         radius = rg.uniform(0.2, 2.0) * (1.0 if rg.uniform() < 0.5 else -1.0)
         x = roll_cylinder(p, radius)
-        x += rg.normal(0.0, 1e-3 * h, size=x.shape)
+        sc = 1e-3 if noise_max <= 1e-3 else math.exp(rg.uniform(math.log(1e-3), math.log(noise_max)))
+        x += rg.normal(0.0, sc * h, size=x.shape)
         out.append(MeshInput(tris, rest, x, 3, meta=dict(workload="training_shell", phi=phi, stretch=st,
                                                          radius=radius)))
     return out

@@ -197,7 +197,8 @@ def test_loss_gradient_vs_oracle(torch_cuda):
         g = grad.cpu().numpy().astype(np.float64)
         err = np.max(np.abs(g - gref)) / np.max(np.abs(gref))
         say("batch", count, "grad rel err", err, "loss", float(loss.cpu()), lref)
-        assert err < 2e-4
+        # FP32 sums over up to ~1e4 samples per wave partial against FP64: measured ~5e-7
+        assert err < 5e-6
         assert abs(float(loss.cpu()) - lref) < 1e-4 * lref
 
 
@@ -221,68 +222,58 @@ def test_adam_steps_vs_oracle(torch_cuda):
 
 
 def test_train_and_gain(torch_cuda):
-    """Train on oracle samples, then compare the trained network's term with the analytic
-    density it learned and with the plain StVK + dihedral form on a cylinder."""
-    say("train end to end")
+    """A short training run by the library's kernels on oracle samples (the recipe of tests/train_density.py at
+    a thirteenth of the samples and a third of the epochs): deterministic, the loss falls, and the network it
+    leaves already follows the analytic density on a cylinder to within 10%."""
+    say("train end to end (short)")
     torch = torch_cuda
-    from paper_2509_00406_amd import mad
-    z, W, dW = training_batch(n_meshes=60, n=32, seed=43)      # 115,320 samples
-    s_in = (1.0 / z.std(axis=0)).astype(np.float32)
-    s_out = np.float32(W.std())
-    # one gradient normaliser for all features (per-feature normalisers put the membrane features'
-    # tiny gradients first and lose the energy fit: measured 74% energy error against 1% here)
-    c_e, c_g, lam = float(W.var()), float((dW ** 2).sum(axis=1).mean()), 1.0
-    theta, _, _ = seeded_network(23, scale=0.5)
+    from tests import train_density as TD
+    z, W, dW = TD.oracle_samples(100, 64)                      # 793,800 samples
     nets = []
-    for rep in range(2):                                    # twice: training is deterministic
-        net = mad.Network(theta, s_in, s_out)
-        zt = torch.from_numpy(z.astype(np.float32)).cuda()
-        Wt = torch.from_numpy(W.astype(np.float32)).cuda()
-        dWt = torch.from_numpy(dW.astype(np.float32)).cuda()
-        rng = np.random.default_rng(77)
-        n_batches = (z.shape[0] + 511) // 512
-        hist = torch.zeros(n_batches, dtype=torch.float32, device="cuda")
-        first = None
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        epochs = 40
-        for ep in range(epochs):
-            perm = torch.from_numpy(rng.permutation(z.shape[0]).astype(np.int32)).cuda()
-            lr = 3e-3 if ep < 20 else (1e-3 if ep < 32 else 3e-4)
-            net.train_epoch(zt, Wt, dWt, perm, 512, c_e, c_g, lam, lr, loss_hist=hist)
-            if first is None:
-                torch.cuda.synchronize()
-                first = float(hist[:8].mean())
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        last = float(hist.mean())
-        say(f"rep {rep}: loss {first:.4g} -> {last:.4g}, {epochs} epochs in {dt:.2f} s "
-            f"({epochs * z.shape[0] / dt:.3g} samples/s)")
-        assert last < 0.01 * first
+    for rep in range(2):                                      # twice: training is deterministic
+        net, s_in, s_out, (first, last), dt = TD.train(z, W, dW, epochs=10, log=say)
+        say(f"rep {rep}: loss {first:.4g} -> {last:.4g}, 10 epochs in {dt:.2f} s "
+            f"({10 * z.shape[0] / dt:.3g} samples/s)")
+        assert last < 1e-2 * first
         nets.append(net)
     assert np.array_equal(nets[0].params(0), nets[1].params(0))
-    net = nets[0]
-    # the trained network on a cylinder: energy, gradient and Hessian against the analytic density
-    inp = meshgen.shell_cylinder(n=64, seed=5001)
+    e = TD.errors_vs_analytic(nets[0], 64)
+    say(f"short-trained network vs the analytic density on a 64 x 64 cylinder: {e}")
+    for mode in ("raw", "clamped"):
+        assert e[mode]["energy"] < 0.05 and e[mode]["grad"] < 0.1 and e[mode]["hess"] < 0.1, e
+
+
+# Error bounds of the stored trained network (tests/train_density.py: 10,319,400 oracle samples, 30 epochs)
+# against the analytic density it was trained on, norm-wise over the assembled outputs on the 708 x 708 half
+# cylinder. Measured when it was trained: energy 5.1e-3, gradient 1.7e-3, Hessian 2.2e-3 (raw and clamped).
+TRAINED_BOUNDS = {"energy": 1e-2, "grad": 1e-2, "hess": 1e-2}
+
+
+def test_trained_density_708(torch_cuda):
+    """The stored network on the 708 x 708 cylinder (999,698 triangles): errors against the analytic density
+    within TRAINED_BOUNDS, and what the learned per-triangle form gains over StVK + dihedral bending (blocks,
+    time per evaluation), reported."""
+    torch = torch_cuda
+    from paper_2509_00406_amd import mad
+    from tests import train_density as TD
+    say("trained density 708")
+    net = mad.Network.from_file()
+    e = TD.errors_vs_analytic(net, 708)
+    say(f"trained network vs the analytic density on the 708 x 708 cylinder: {e}")
+    for mode in ("raw", "clamped"):
+        for k, bound in TRAINED_BOUNDS.items():
+            assert e[mode][k] < bound, (mode, k, e[mode][k])
+    inp = meshgen.shell_cylinder(n=708, seed=5001)
     x = torch.from_numpy(inp.x.ravel().copy()).cuda()
     mesh = mad.Mesh(inp.tris, inp.n_verts)
     pm = mad.Problem(mesh, 3, mad.F32)
     pm.add_mlp_term(net, inp.rest)
     pm.finalize()
-    pa = mad.Problem(mesh, 3, mad.F32)
-    pa.add_term(mad.SHELL_TRI, (1.0, 1.0, 1.0), inp.rest)
-    pa.finalize()
     pp = mad.Problem(mesh, 3, mad.F32)
     pp.add_term(mad.STVK, (1.0, 1.0), inp.rest)
     pp.add_term(mad.BENDING, (1.0, 1.0), inp.rest)
     pp.finalize()
     mode = ALL | 8
-    em, gm, hm = pm.eval(x, mode)
-    ea, ga, ha = pa.eval(x, mode)
-    torch.cuda.synchronize()
-    e_err = abs(float(em[0] - ea[0])) / abs(float(ea[0]))
-    g_err = float((gm - ga).norm() / ga.norm())
-    h_err = float((hm - ha).norm() / ha.norm())
 
     def timed(p):
         o = p.outputs()
@@ -290,19 +281,14 @@ def test_train_and_gain(torch_cuda):
             p.eval(x, mode, out=o)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(20):
+        for _ in range(10):
             p.eval(x, mode, out=o)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t) / 20 * 1e3
+        return (time.perf_counter() - t) / 10 * 1e3, o
 
-    t_m, t_a, t_p = timed(pm), timed(pa), timed(pp)
-    say(f"trained network vs analytic density on a 64x64 cylinder: energy rel err {e_err:.3g}, "
-        f"grad {g_err:.3g}, hess {h_err:.3g}")
-    say(f"blocks: learned/analytic triangle form {pm.nnzb}, StVK + dihedral {pp.nnzb}; "
-        f"ms per eval: learned {t_m:.3f}, analytic {t_a:.3f}, StVK + dihedral {t_p:.3f}")
-    assert pm.nnzb == pa.nnzb < pp.nnzb
-    # The network is fitted to values and first derivatives of W over the training sheets, where the
-    # membrane part of W is ~1e-3 of its variation; on the cylinder the Hessian is dominated by the
-    # membrane stiffness, which the fit resolves poorly. Energy is asserted; gradient and Hessian
-    # errors are reported (they are the cost of the learned form, not hidden).
-    assert e_err < 0.05 and np.isfinite(g_err) and np.isfinite(h_err)
+    (t_m, _), (t_p, _) = timed(pm), timed(pp)
+    # (the dihedral and the second-form bending energies are different models with unrelated constants:
+    # their values are not compared)
+    say(f"blocks: learned {pm.nnzb}, StVK + dihedral {pp.nnzb}; ms per evaluation: learned {t_m:.3f}, "
+        f"StVK + dihedral {t_p:.3f}")
+    assert pm.nnzb == 3503186 and pp.nnzb == 6499452
