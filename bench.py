@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--scatter", choices=["patch", "atomic"], default="patch")
     ap.add_argument("--persistent", action="store_true", help="persistent launch (the default for heavy terms)")
     ap.add_argument("--per-patch", action="store_true", help="one workgroup per patch (the default for light terms)")
+    ap.add_argument("--wg-waves", type=int, choices=[0, 4, 8], default=0,
+                    help="patch kernel tile: waves per workgroup (0: the default 4)")
     ap.add_argument("--autotune", action="store_true", help="choose the layout by timing (batched: always)")
     ap.add_argument("--no-fp64-plain", action="store_true", help="skip the FP64 GPU comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -298,7 +300,8 @@ def make_problem(mad, mesh, inp, prec, args, stream, form=None):
     "cloth" (springs + inertia); default: the workload's own."""
     form = form or {"mlp": "mlp", "cloth": "cloth", "symdir": "symdir"}.get(args.workload, "plain")
     scatter = mad.SCATTER_PATCH if args.scatter == "patch" else mad.SCATTER_ATOMIC
-    prob = mad.Problem(mesh, 2 if form == "symdir" else 3, prec, patch_faces=args.patch_faces, scatter=scatter)
+    prob = mad.Problem(mesh, 2 if form == "symdir" else 3, prec, patch_faces=args.patch_faces, scatter=scatter,
+                       wg_waves=args.wg_waves)
     if form == "symdir":
         prob.add_term(mad.SYMDIR, (), inp.rest)
     elif form == "cloth":
@@ -315,7 +318,7 @@ def make_problem(mad, mesh, inp, prec, args, stream, form=None):
     prob.finalize(stream)
     if args.persistent or args.per_patch:
         lay = prob.layout()
-        prob.set_layout(lay["scatter"], lay["patch_faces"], 1 if args.persistent else 0, stream)
+        prob.set_layout(lay["scatter"], lay["patch_faces"], 1 if args.persistent else 0, stream=stream)
     return prob
 
 

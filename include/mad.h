@@ -150,7 +150,11 @@ typedef struct mad_options {
                                 A wait that reaches its bound does not add its Hessian blocks (it never adds
                                 without the lock) and raises the internal-error flag, so mad_problem_status
                                 returns MAD_E_INTERNAL; the kernels still run to completion */
-    int32_t reserved[7];     /* must be zero */
+    int32_t wg_waves;        /* tile of the patch kernels: waves (64 lanes) per workgroup, 0 = 4 (default), 4
+                                or 8 (MAD_F32 only; MAD_F64 keeps 4). With 8, a workgroup of terms other than
+                                the light ones (springs, inertia, edge lengths, residuals) has the CU's LDS to
+                                itself (148 KB: larger patches); light terms keep 76 KB per workgroup */
+    int32_t reserved[6];     /* must be zero */
 } mad_options;
 
 enum { MAD_LOCK_NO_WAIT = -1 };  /* mad_options.lock_spins: every lock wait gives up at once */
@@ -318,28 +322,34 @@ int32_t mad_problem_set_profiling(mad_problem *prob, int32_t enable);
 int32_t mad_problem_profile(mad_problem *prob, double *ms_out, int32_t *n_stages, int64_t *n_evals);
 
 /* Current evaluation layout (any output may be NULL): scatter strategy, effective patch target
- * (after shrinking to fit the LDS budget), persistent launch (0/1) and number of patches. */
+ * (after shrinking to fit the LDS budget), persistent launch (0/1/2), number of patches and the tile
+ * (waves per workgroup of the patch kernels). */
 int32_t mad_problem_layout(const mad_problem *prob, int32_t *scatter, int32_t *patch_faces,
-                           int32_t *persistent, int32_t *n_patches);
+                           int32_t *persistent, int32_t *n_patches, int32_t *wg_waves);
 
 /* Rebuild the evaluation layout of a finalized problem: scatter (mad_scatter), patch_faces target
- * (1 .. 2^20; shrunk until the largest patch fits the LDS budget), persistent = 1 for one grid
- * sized to the device whose workgroups take patches largest-first from a queue (patch scatter
- * only), 0 for one workgroup per patch. The block pattern and the outputs' layout do not change.
- * Synchronises the stream. On failure the problem is left unusable (MAD_E_STATE on eval). */
+ * (1 .. 2^20; shrunk until the largest patch fits the LDS budget of the tile), persistent = 1 for one
+ * grid sized to the device whose workgroups take patches from a queue (patches in index order within
+ * four size classes, the largest first; 2: strictly largest first; patch scatter only), 0 for one
+ * workgroup per patch; wg_waves: the tile as in mad_options (0 keeps the current one). The block pattern
+ * and the outputs' layout do not change. Synchronises the stream. On failure the problem is left
+ * unusable (MAD_E_STATE on eval). */
 int32_t mad_problem_set_layout(mad_problem *prob, int32_t scatter, int32_t patch_faces, int32_t persistent,
-                               void *stream);
+                               int32_t wg_waves, void *stream);
 
 enum { MAD_TUNE_FORCE = 1 };  /* mad_problem_autotune: re-time even if this problem was tuned before */
 
 /* Choose the layout by timing (batched scheduling and the patch-size study, Sec. 7.1): builds each
  * candidate layout (patch scatter with patch targets 128, 256, 512, 1024, each with and without the
- * persistent launch; the atomic scatter at 512), times `reps` evaluations of `mode` on the caller's
- * x_dev and outputs (arguments as for mad_problem_eval; their contents are overwritten), and keeps
- * the one with the lowest median time. The choice is cached for the process by a fingerprint of the
- * device, the connectivity, the terms, the precision and the mode; a later call on an identical
- * problem applies it without timing unless flags has MAD_TUNE_FORCE. Synchronises the stream.
- * On failure the problem is left unusable. */
+ * persistent launch, each with the 4- and (MAD_F32) 8-wave tile; the atomic scatter at 512), times
+ * `reps` evaluations of `mode` on the caller's x_dev and outputs (arguments as for mad_problem_eval;
+ * their contents are overwritten), and keeps the one with the lowest median time: every candidate
+ * writes the same outputs from the same inputs, so the fastest is also the one with the highest
+ * algorithmic bytes per second. The choice is cached by a fingerprint of the device, the
+ * connectivity, the terms, the precision and the mode, for the process and, when the environment
+ * variable MAD_TUNE_CACHE names a file, in that file across processes (one line per fingerprint); a
+ * later call on an identical problem applies it without timing unless flags has MAD_TUNE_FORCE.
+ * Synchronises the stream. On failure the problem is left unusable. */
 int32_t mad_problem_autotune(mad_problem *prob, const double *x_dev, uint32_t mode, double *energy_dev,
                              void *grad_dev, void *hess_dev, int32_t reps, int32_t flags, void *stream);
 

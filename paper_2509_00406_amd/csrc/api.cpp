@@ -144,8 +144,11 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
     mad_options o;
     mad_options_default(&o);
     if (opt) {
-        for (int i = 0; i < 7; ++i)
+        for (int i = 0; i < 6; ++i)
             if (opt->reserved[i] != 0) return fail(MAD_E_INVALID_ARG, "reserved option fields must be zero");
+        if (opt->wg_waves != 0 && opt->wg_waves != 4 && opt->wg_waves != 8)
+            return fail(MAD_E_INVALID_ARG, "wg_waves must be 0, 4 or 8");
+        o.wg_waves = opt->wg_waves;
         if (opt->scatter != MAD_SCATTER_AUTO && opt->scatter != MAD_SCATTER_ATOMIC && opt->scatter != MAD_SCATTER_PATCH)
             return fail(MAD_E_INVALID_ARG, "bad scatter mode");
         o.scatter = opt->scatter == MAD_SCATTER_AUTO ? MAD_SCATTER_PATCH : opt->scatter;
@@ -165,6 +168,7 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
     p->prec = precision;
     p->opt = o;
     p->scatter = o.scatter;
+    p->wg_waves = (o.wg_waves == 8 && precision == MAD_F32) ? 8 : 4;
     *out = p;
     return MAD_OK;
 }

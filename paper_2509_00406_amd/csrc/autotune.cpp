@@ -5,8 +5,11 @@
 // Results are cached per process by a fingerprint of the problem.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -16,11 +19,40 @@
 namespace mad {
 
 struct TuneChoice {
-    int scatter, faces, persistent;
+    int scatter, faces, persistent, wg_waves;
 };
 
 static std::mutex g_tune_mu;
 static std::map<std::string, TuneChoice> g_tune_cache;
+static bool g_tune_file_read = false;
+
+// The cache file named by MAD_TUNE_CACHE: one line per fingerprint, "<fingerprint> <scatter> <patch target>
+// <persistent> <wg_waves>", appended as choices are made; read once per process (the last line of a
+// fingerprint wins). Missing or unreadable files are ignored. Called with g_tune_mu held.
+static void tune_file_load() {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = std::getenv("MAD_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        std::string key;
+        TuneChoice c{};
+        if (in >> key >> c.scatter >> c.faces >> c.persistent >> c.wg_waves &&
+            (c.scatter == MAD_SCATTER_PATCH || c.scatter == MAD_SCATTER_ATOMIC) && c.faces >= 1 &&
+            c.faces <= (1 << 20) && c.persistent >= 0 && c.persistent <= 2 && (c.wg_waves == 4 || c.wg_waves == 8))
+            g_tune_cache[key] = c;
+    }
+}
+
+static void tune_file_append(const std::string& key, const TuneChoice& c) {
+    const char* path = std::getenv("MAD_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << ' ' << c.scatter << ' ' << c.faces << ' ' << c.persistent << ' ' << c.wg_waves << '\n';
+}
 
 // problem identity: device, sizes, connectivity hash, terms, precision and mode
 static std::string fingerprint(const mad_problem* p, uint32_t mode) {
@@ -74,27 +106,29 @@ using namespace mad;
 extern "C" {
 
 int32_t mad_problem_layout(const mad_problem* p, int32_t* scatter, int32_t* patch_faces, int32_t* persistent,
-                           int32_t* n_patches) {
+                           int32_t* n_patches, int32_t* wg_waves) {
     if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
     if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
     if (scatter) *scatter = p->scatter;
     if (patch_faces) *patch_faces = p->opt.patch_faces;
     if (persistent) *persistent = p->persistent;
     if (n_patches) *n_patches = p->patches.n;
+    if (wg_waves) *wg_waves = p->wg_waves;
     return MAD_OK;
 }
 
 int32_t mad_problem_set_layout(mad_problem* p, int32_t scatter, int32_t patch_faces, int32_t persistent,
-                               void* stream) {
+                               int32_t wg_waves, void* stream) {
     if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
     if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
     if (scatter != MAD_SCATTER_AUTO && scatter != MAD_SCATTER_ATOMIC && scatter != MAD_SCATTER_PATCH)
         return fail(MAD_E_INVALID_ARG, "bad scatter mode");
     if (patch_faces < 1 || patch_faces > (1 << 20)) return fail(MAD_E_INVALID_ARG, "bad patch_faces");
     if (persistent < 0 || persistent > 2) return fail(MAD_E_INVALID_ARG, "persistent must be 0, 1 or 2");
+    if (wg_waves != 0 && wg_waves != 4 && wg_waves != 8) return fail(MAD_E_INVALID_ARG, "wg_waves must be 0, 4 or 8");
     if (scatter == MAD_SCATTER_ATOMIC && persistent) return fail(MAD_E_UNSUPPORTED, "persistent needs the patch scatter");
     const int sc = scatter == MAD_SCATTER_AUTO ? MAD_SCATTER_PATCH : scatter;
-    const int rc = build_layout(p, patch_faces, sc, persistent, (hipStream_t)stream);
+    const int rc = build_layout(p, patch_faces, sc, persistent, (hipStream_t)stream, wg_waves);
     if (rc != MAD_OK) p->finalized = false;   // half-built layout: the problem cannot be evaluated
     return rc;
 }
@@ -118,6 +152,7 @@ int32_t mad_problem_autotune(mad_problem* p, const double* x, uint32_t mode, dou
         bool hit = false;
         {
             std::lock_guard<std::mutex> g(g_tune_mu);
+            tune_file_load();
             auto it = g_tune_cache.find(key);
             if (it != g_tune_cache.end()) {
                 c = it->second;
@@ -126,38 +161,42 @@ int32_t mad_problem_autotune(mad_problem* p, const double* x, uint32_t mode, dou
         }
         if (hit) {
             p->tune_report = "{\"cached\": true, \"candidates\": []}";
-            if (c.scatter == p->scatter && c.faces == p->opt.patch_faces && c.persistent == p->persistent)
+            if (c.scatter == p->scatter && c.faces == p->opt.patch_faces && c.persistent == p->persistent &&
+                c.wg_waves == p->wg_waves)
                 return MAD_OK;
-            return mad_problem_set_layout(p, c.scatter, c.faces, c.persistent, stream);
+            return mad_problem_set_layout(p, c.scatter, c.faces, c.persistent, c.wg_waves, stream);
         }
     }
     const bool prof = p->profiling;
     p->profiling = false;
     static const int kFaces[] = {128, 256, 512, 1024};
     std::vector<TuneChoice> cands;
-    for (int f : kFaces)
-        for (int pers = 0; pers < 2; ++pers) cands.push_back({MAD_SCATTER_PATCH, f, pers});
-    cands.push_back({MAD_SCATTER_ATOMIC, 512, 0});
+    for (int w : {4, 8}) {
+        if (w == 8 && p->prec != MAD_F32) continue;
+        for (int f : kFaces)
+            for (int pers = 0; pers < 2; ++pers) cands.push_back({MAD_SCATTER_PATCH, f, pers, w});
+    }
+    cands.push_back({MAD_SCATTER_ATOMIC, 512, 0, 4});
     std::string rep = "{\"cached\": false, \"candidates\": [";
     double best = 1e300;
-    TuneChoice bc = {p->scatter, p->opt.patch_faces, p->persistent};
+    TuneChoice bc = {p->scatter, p->opt.patch_faces, p->persistent, p->wg_waves};
     int rc = MAD_OK;
     for (size_t i = 0; rc == MAD_OK && i < cands.size(); ++i) {
         const TuneChoice& c = cands[i];
-        rc = build_layout(p, c.faces, c.scatter, c.persistent, s);
+        rc = build_layout(p, c.faces, c.scatter, c.persistent, s, c.wg_waves);
         double ms = 0.0;
         if (rc == MAD_OK) rc = time_layout(p, x, mode, energy, grad, hess, reps, s, &ms);
         if (rc != MAD_OK) break;
-        char buf[256];
+        char buf[288];
         std::snprintf(buf, sizeof(buf),
                       "%s{\"scatter\": \"%s\", \"patch_faces\": %d, \"effective_faces\": %d, \"persistent\": %d, "
-                      "\"n_patches\": %d, \"ms\": %.6f}",
+                      "\"wg_waves\": %d, \"n_patches\": %d, \"ms\": %.6f}",
                       i ? ", " : "", c.scatter == MAD_SCATTER_PATCH ? "patch" : "atomic", c.faces, p->opt.patch_faces,
-                      c.persistent, p->patches.n, ms);
+                      c.persistent, p->wg_waves, p->patches.n, ms);
         rep += buf;
         if (ms < best) {
             best = ms;
-            bc = {c.scatter, p->opt.patch_faces, c.persistent};
+            bc = {c.scatter, p->opt.patch_faces, c.persistent, p->wg_waves};
         }
     }
     p->profiling = prof;
@@ -165,15 +204,17 @@ int32_t mad_problem_autotune(mad_problem* p, const double* x, uint32_t mode, dou
         p->finalized = false;   // the layout may be half built
         return rc;
     }
-    char tail[160];
-    std::snprintf(tail, sizeof(tail), "], \"chosen\": {\"scatter\": \"%s\", \"patch_faces\": %d, \"persistent\": %d}}",
-                  bc.scatter == MAD_SCATTER_PATCH ? "patch" : "atomic", bc.faces, bc.persistent);
+    char tail[192];
+    std::snprintf(tail, sizeof(tail),
+                  "], \"chosen\": {\"scatter\": \"%s\", \"patch_faces\": %d, \"persistent\": %d, \"wg_waves\": %d}}",
+                  bc.scatter == MAD_SCATTER_PATCH ? "patch" : "atomic", bc.faces, bc.persistent, bc.wg_waves);
     p->tune_report = rep + tail;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         g_tune_cache[key] = bc;
+        tune_file_append(key, bc);
     }
-    rc = build_layout(p, bc.faces, bc.scatter, bc.persistent, s);
+    rc = build_layout(p, bc.faces, bc.scatter, bc.persistent, s, bc.wg_waves);
     if (rc != MAD_OK) p->finalized = false;
     return rc;
 }

@@ -110,6 +110,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.lock_spins = p->opt.lock_spins == MAD_LOCK_NO_WAIT ? 0
                        : (p->opt.lock_spins > 0 ? p->opt.lock_spins : kDefaultLockSpins);
         L.persistent = p->persistent;
+        L.block = (p->wg_waves == 8 && p->prec == MAD_F32) ? 512 : 256;
         L.work_order = p->d_work_order;
         L.work_counter = sc.work_counter;
         L.n_cu = p->n_cu;

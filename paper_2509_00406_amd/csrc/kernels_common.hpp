@@ -134,7 +134,8 @@ __device__ __forceinline__ void block_reduce_store(double v, double* red, double
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// sum of red[0, kBlock) in a fixed tree order; red is already filled and visible to every lane
+// sum of red[0, kBlock) in a fixed tree order, whatever the workgroup size (at least kBlock threads, all of
+// them calling); red is already filled and visible to every lane
 __device__ __forceinline__ void block_sum_store(double* red, double* out) {
 #pragma unroll
     for (int w = kBlock / 2; w > 0; w >>= 1) {

@@ -293,7 +293,7 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
     }
 }
 
-template <typename T, int MODE, int D, int FAM>
+template <typename T, int MODE, int D, int FAM, int BLK>
 __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsigned char* smem, double* red,
                                                int* s_next, int* lock) {
     constexpr int DD = D * D;
@@ -309,10 +309,10 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         *s_next = 0;
         *lock = 0;
     }
-    red[threadIdx.x] = 0.0;   // per-unit energies
+    if (threadIdx.x < kMaxPatchUnits) red[threadIdx.x] = 0.0;   // per-unit energies
     bool bad_x = false;
     // one vertex per thread: its index read once, its D coordinates loaded together
-    for (int i = threadIdx.x; i < nlv; i += kBlock) {
+    for (int i = threadIdx.x; i < nlv; i += BLK) {
         const int64_t v = L.lv_global[lv0 + i];
 #pragma unroll
         for (int c = 0; c < D; ++c) {
@@ -335,8 +335,8 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
             const int nw = nlb * DD;
             float4* sh4 = reinterpret_cast<float4*>(sh);
             const int n4 = (nw * (int)sizeof(T)) / 16;
-            for (int i = threadIdx.x; i < n4; i += kBlock) sh4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-            for (int i = n4 * (16 / (int)sizeof(T)) + threadIdx.x; i < nw; i += kBlock) sh[i] = T(0);
+            for (int i = threadIdx.x; i < n4; i += BLK) sh4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int i = n4 * (16 / (int)sizeof(T)) + threadIdx.x; i < nw; i += BLK) sh[i] = T(0);
         }
     }
     __syncthreads();
@@ -347,7 +347,7 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
     // early takes more units, so the four waves of the patch end close together). Which wave runs a
     // unit varies from run to run, so each unit's energy is summed over its lanes in a fixed order
     // into a slot of its own, and the slots are summed in a fixed order at the end.
-    static_assert(kMaxPatchUnits <= kBlock, "one energy slot per unit");
+    static_assert(kMaxPatchUnits <= BLK, "one energy slot per unit");
     const int lane = threadIdx.x & 63;
     for (;;) {
         int u = 0;
@@ -425,7 +425,7 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         if (L.want_grad) {
             T* G = static_cast<T*>(L.grad);
             T* HG = static_cast<T*>(L.halo_g);
-            for (int i = threadIdx.x; i < nlv; i += kBlock) {
+            for (int i = threadIdx.x; i < nlv; i += BLK) {
                 const int32_t h = L.lv_halo[lv0 + i];
                 T* dst = h < 0 ? G + (int64_t)L.lv_global[lv0 + i] * D : HG + (int64_t)h * D;
 #pragma unroll
@@ -437,7 +437,7 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         if (L.hvp) {
             T* Y = static_cast<T*>(L.y);
             T* HY = static_cast<T*>(L.halo_y);
-            for (int i = threadIdx.x; i < nlv * D; i += kBlock) {
+            for (int i = threadIdx.x; i < nlv * D; i += BLK) {
                 const int k = lv0 + i / D, c = i % D;
                 const int32_t h = L.lv_halo[k];
                 if (h < 0) Y[(int64_t)L.lv_global[k] * D + c] = sy[i];
@@ -452,7 +452,7 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
         }
         T* H = static_cast<T*>(L.hess);
         T* HH = static_cast<T*>(L.halo_h);
-        for (int i = threadIdx.x; i < nlb * D; i += kBlock) {
+        for (int i = threadIdx.x; i < nlb * D; i += BLK) {
             const int bl = i / D, r = i % D;
             const int32_t h = L.lb_halo[lb0 + bl];
             const int32_t g = L.lb_gidx[lb0 + bl], gt = L.lb_gidxT[lb0 + bl];
@@ -477,13 +477,13 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
 
 // One patch per workgroup, or (persistent) a grid sized to the device whose workgroups take
 // patches from a counter in the given order (largest first) until every patch is taken.
-template <typename T, int MODE, int D, int FAM>
+template <typename T, int MODE, int D, int FAM, int BLK>
 __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kBlock];
+    __shared__ double red[kMaxPatchUnits];
     __shared__ int next, unit_next, block_lock;
     if (!L.persistent) {
-        eval_patch_one<T, MODE, D, FAM>(L, blockIdx.x, smem, red, &unit_next, &block_lock);
+        eval_patch_one<T, MODE, D, FAM, BLK>(L, blockIdx.x, smem, red, &unit_next, &block_lock);
         return;
     }
     for (;;) {
@@ -492,7 +492,7 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
         const int k = next;
         __syncthreads();   // every lane has read `next` before it is overwritten
         if (k >= L.n_patch) break;
-        eval_patch_one<T, MODE, D, FAM>(L, L.work_order[k], smem, red, &unit_next, &block_lock);
+        eval_patch_one<T, MODE, D, FAM, BLK>(L, L.work_order[k], smem, red, &unit_next, &block_lock);
         __syncthreads();   // the flush has read LDS before the next patch clears it
     }
 }
@@ -504,17 +504,19 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
 // elements wait on memory more than they compute.
 // FP32 families 0 and 1: the compiler is held to 256 registers so two waves share each SIMD (the
 // second wave hides the latency of the long dependent rotation chains).
-template <int MODE, int D, int FAM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_patch_f32(PatchLaunch L) {
-    eval_patch_body<float, MODE, D, FAM>(L);
+// BLK: threads per workgroup (the tile): 256 (four waves; two workgroups share a CU) or, for FP32, 512
+// (eight waves; one workgroup holds the CU's LDS for larger patches, or two light workgroups share it).
+template <int MODE, int D, int FAM, int BLK>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(2))) void k_eval_patch_f32(PatchLaunch L) {
+    eval_patch_body<float, MODE, D, FAM, BLK>(L);
 }
-template <int MODE, int D>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_patch_light_f32(PatchLaunch L) {
-    eval_patch_body<float, MODE, D, 2>(L);
+template <int MODE, int D, int BLK>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(4))) void k_eval_patch_light_f32(PatchLaunch L) {
+    eval_patch_body<float, MODE, D, 2, BLK>(L);
 }
 template <int MODE, int D, int FAM>
 __global__ __launch_bounds__(kBlock) void k_eval_patch_f64(PatchLaunch L) {
-    eval_patch_body<double, MODE, D, FAM>(L);
+    eval_patch_body<double, MODE, D, FAM, kBlock>(L);
 }
 
 // ---- gather of shared entries --------------------------------------------------------------------
@@ -691,26 +693,33 @@ size_t patch_lds_bytes(int var_dim, int prec, int mode, int32_t max_lv, int32_t 
 
 // workgroups of a persistent launch: as many as are resident on the device at once
 template <typename K>
-static int persistent_grid(K kernel, const PatchLaunch& L) {
+static int persistent_grid(K kernel, const PatchLaunch& L, int blk) {
     int per_cu = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, L.lds_bytes) != hipSuccess ||
-        per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, blk, L.lds_bytes) != hipSuccess || per_cu < 1)
         per_cu = 1;
     return std::max(1, std::min(L.n_patch, std::max(L.n_cu, 1) * per_cu));
 }
 
+template <int MODE, int D, int FAM, int BLK>
+static void launch_patch_f32(const PatchLaunch& L, hipStream_t s) {
+    const dim3 block(BLK);
+    if constexpr (FAM == 2) {
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_light_f32<MODE, D, BLK>, L, BLK) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_light_f32<MODE, D, BLK>), grid, block, L.lds_bytes, s, L);
+    } else {
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f32<MODE, D, FAM, BLK>, L, BLK) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_f32<MODE, D, FAM, BLK>), grid, block, L.lds_bytes, s, L);
+    }
+}
+
 template <int MODE, int D, int FAM>
 static void launch_patch_variant(bool f32, const PatchLaunch& L, hipStream_t s) {
-    const dim3 block(kBlock);
-    if (f32 && FAM == 2) {
-        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_light_f32<MODE, D>, L) : L.n_patch);
-        hipLaunchKernelGGL((k_eval_patch_light_f32<MODE, D>), grid, block, L.lds_bytes, s, L);
-    } else if (f32) {
-        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f32<MODE, D, FAM>, L) : L.n_patch);
-        hipLaunchKernelGGL((k_eval_patch_f32<MODE, D, FAM>), grid, block, L.lds_bytes, s, L);
+    if (f32) {
+        if (L.block == 512) launch_patch_f32<MODE, D, FAM, 512>(L, s);
+        else launch_patch_f32<MODE, D, FAM, kBlock>(L, s);
     } else {
-        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f64<MODE, D, FAM>, L) : L.n_patch);
-        hipLaunchKernelGGL((k_eval_patch_f64<MODE, D, FAM>), grid, block, L.lds_bytes, s, L);
+        const dim3 grid(L.persistent ? persistent_grid(k_eval_patch_f64<MODE, D, FAM>, L, kBlock) : L.n_patch);
+        hipLaunchKernelGGL((k_eval_patch_f64<MODE, D, FAM>), grid, dim3(kBlock), L.lds_bytes, s, L);
     }
 }
 

@@ -60,12 +60,17 @@ static void free_layout(mad_problem* p) {
 
 // Build the patches and the element order (host), then upload the element arrays. If the pattern
 // already exists, also build the structures of the scatter strategy.
-int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStream_t s) {
+size_t lds_budget(const mad_problem* p) {
+    return (p->wg_waves == 8 && p->prec == MAD_F32 && !p->light) ? kLdsBudgetWide : kLdsBudget;
+}
+
+int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStream_t s, int wg_waves) {
     const mad_mesh& m = *p->mesh;
     MAD_HIP_TRY(hipStreamSynchronize(s));
     free_layout(p);
     p->scatter = scatter;
     p->persistent = scatter == MAD_SCATTER_PATCH ? persistent : 0;
+    if (wg_waves != 0) p->wg_waves = (wg_waves == 8 && p->prec == MAD_F32) ? 8 : 4;
     // the fit below needs only which elements each patch holds: the colour order comes after it
     build_patches(m, target, p->patches);
     order_terms(p);
@@ -82,7 +87,7 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
                 for (const auto& t : p->terms) u += (t.elem_ptr[q + 1] - t.elem_ptr[q] + 63) / 64;
                 mu = std::max(mu, u);
             }
-            if (p->lds_bytes <= kLdsBudget && mu <= kMaxPatchUnits) break;
+            if (p->lds_bytes <= lds_budget(p) && mu <= kMaxPatchUnits) break;
             if (target <= 1) return fail(MAD_E_UNSUPPORTED, "a single element exceeds the LDS budget");
             target = std::max(1, (int)(target * 0.75));
             build_patches(m, target, p->patches);

@@ -122,6 +122,7 @@ struct mad_problem {
     unsigned long long* d_fallbacks = nullptr;
     int scatter = MAD_SCATTER_PATCH;
     int persistent = 0;                   // patch scatter: persistent grid pulling patches from a queue
+    int wg_waves = 4;                     // patch scatter tile: waves per workgroup (4, or 8 with FP32)
     int n_cu = 0;                         // compute units of the device
     std::vector<void*> layout_owned;      // device memory of the current layout (freed on relayout)
     std::vector<int32_t> h_rowptr, h_colidx;  // host copy of the pattern (layout rebuilds)
@@ -204,7 +205,7 @@ void color_within_patches(Term& t, int64_t nv);
 void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb);
 void unit_segments(const Term& t, int32_t np, int64_t nv, std::vector<uint8_t>& seg);
 // layout.cpp: (re)build the element order and the scatter structures of a problem
-int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s);
+int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s, int wg_waves = 0);
 int build_scatter(mad_problem* p, hipStream_t s);
 // Device buffers an evaluation writes and reads back within itself; nothing in them outlives the
 // evaluation. By default the problem's own (allocated with its layout); mad_problem_eval_static takes
@@ -232,6 +233,11 @@ int check_eval_args(const mad_problem* p, const double* x, uint32_t mode, const 
 int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
                  hipStream_t s, const double* v = nullptr, void* y = nullptr, const EvalScratch* sc = nullptr);
 constexpr size_t kLdsBudget = 76 * 1024;  // dynamic LDS per workgroup: two workgroups in a CU's 160 KB
+// the whole CU's LDS but its static part, for the 8-wave tile of heavy terms (one workgroup per CU: two waves
+// per SIMD are all their registers allow)
+constexpr size_t kLdsBudgetWide = 148 * 1024;
+// the LDS budget of a problem's current tile
+size_t lds_budget(const mad_problem* p);
 // work units (64 elements of one term) per patch: the patch kernel keeps one energy slot per unit
 constexpr int kMaxPatchUnits = 256;
 int build_patch_local(mad_problem& P, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& colidx,
@@ -313,6 +319,7 @@ struct PatchLaunch {
     void* halo_y;           // [halo vertex slots][D] partial products of shared vertices
     int lock_spins;         // bound on each LDS-lock wait (0: give up at once)
     int persistent;
+    int block;              // threads per workgroup: 256, or 512 (FP32 only)
     const int32_t* work_order;
     int32_t* work_counter;
     int n_cu;

@@ -40,7 +40,8 @@ class MadError(RuntimeError):
 
 class mad_options(C.Structure):
     _fields_ = [("scatter", C.c_int32), ("patch_faces", C.c_int32), ("spd_eps", C.c_double),
-                ("degenerate_q", C.c_double), ("lock_spins", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("degenerate_q", C.c_double), ("lock_spins", C.c_int32), ("wg_waves", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
 
 
 _lib = None
@@ -73,8 +74,8 @@ _SIGS = {
     "mad_problem_profile": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
                             C.c_int32),
     "mad_problem_layout": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                            C.POINTER(C.c_int32)], C.c_int32),
-    "mad_problem_set_layout": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p], C.c_int32),
+                            C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int32),
+    "mad_problem_set_layout": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p], C.c_int32),
     "mad_problem_autotune": ([C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                               C.c_int32, C.c_void_p], C.c_int32),
     "mad_problem_tune_report": ([C.c_void_p, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)], C.c_int32),
@@ -283,13 +284,15 @@ def mad_problem_profile(prob) -> tuple[list[float], int]:
 
 
 def mad_problem_layout(prob) -> dict:
-    sc, pf, pe, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-    _check(lib().mad_problem_layout(prob, C.byref(sc), C.byref(pf), C.byref(pe), C.byref(n)), "mad_problem_layout")
-    return {"scatter": sc.value, "patch_faces": pf.value, "persistent": pe.value, "n_patches": n.value}
+    sc, pf, pe, n, w = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().mad_problem_layout(prob, C.byref(sc), C.byref(pf), C.byref(pe), C.byref(n), C.byref(w)),
+           "mad_problem_layout")
+    return {"scatter": sc.value, "patch_faces": pf.value, "persistent": pe.value, "n_patches": n.value,
+            "wg_waves": w.value}
 
 
-def mad_problem_set_layout(prob, scatter: int, patch_faces: int, persistent: int, stream=None):
-    _check(lib().mad_problem_set_layout(prob, scatter, patch_faces, persistent, _stream(stream)),
+def mad_problem_set_layout(prob, scatter: int, patch_faces: int, persistent: int, wg_waves: int = 0, stream=None):
+    _check(lib().mad_problem_set_layout(prob, scatter, patch_faces, persistent, wg_waves, _stream(stream)),
            "mad_problem_set_layout")
 
 
@@ -431,10 +434,11 @@ class Problem:
 
     def __init__(self, mesh: Mesh, var_dim: int, precision: int = F64, patch_faces: int = 0,
                  spd_eps: float = 0.0, degenerate_q: float = 0.0, scatter: int = SCATTER_AUTO,
-                 lock_spins: int = 0):
+                 lock_spins: int = 0, wg_waves: int = 0):
         o = mad_options_default()
         o.scatter = scatter
         o.lock_spins = lock_spins
+        o.wg_waves = wg_waves
         o.patch_faces = patch_faces
         o.spd_eps = spd_eps
         o.degenerate_q = degenerate_q
@@ -532,8 +536,8 @@ class Problem:
     def layout(self) -> dict:
         return mad_problem_layout(self.handle)
 
-    def set_layout(self, scatter: int, patch_faces: int, persistent: int = 0, stream=None):
-        mad_problem_set_layout(self.handle, scatter, patch_faces, persistent, stream)
+    def set_layout(self, scatter: int, patch_faces: int, persistent: int = 0, wg_waves: int = 0, stream=None):
+        mad_problem_set_layout(self.handle, scatter, patch_faces, persistent, wg_waves, stream)
 
     def autotune(self, x, mode: int = ENERGY | GRAD | HESS, out=None, reps: int = 5, force: bool = False,
                  stream=None) -> dict:

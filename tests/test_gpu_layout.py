@@ -102,12 +102,15 @@ def test_autotune_batched_and_cache(torch_cuda):
     xt = torch.from_numpy(inp.x.ravel().copy()).cuda()
     out = prob.outputs()
     rep = prob.autotune(xt, ALL | 8, out=out, reps=2, force=True)
-    assert rep["cached"] is False and len(rep["candidates"]) == 9
+    # patch targets 128..1024 x persistent or not x tiles of 4 and 8 waves, plus the atomic scatter
+    assert rep["cached"] is False and len(rep["candidates"]) == 17
+    assert {c["wg_waves"] for c in rep["candidates"]} == {4, 8}
     assert all(c["ms"] > 0 for c in rep["candidates"])
     best = min(rep["candidates"], key=lambda c: c["ms"])
     lay = prob.layout()
     assert lay["patch_faces"] == rep["chosen"]["patch_faces"] == best["effective_faces"]
     assert lay["persistent"] == rep["chosen"]["persistent"] == best["persistent"]
+    assert lay["wg_waves"] == rep["chosen"]["wg_waves"] == best["wg_waves"]
     out = prob.eval(xt, ALL | 8)
     torch.cuda.synchronize()
     check_vs_oracle(P, inp.x, out, 1, ALL | 8)
@@ -121,3 +124,63 @@ def test_autotune_batched_and_cache(torch_cuda):
     out2 = prob2.eval(xt, ALL | 8)
     torch.cuda.synchronize()
     check_vs_oracle(P, inp.x, out2, 1, ALL | 8)
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_eight_wave_tile(torch_cuda, persistent):
+    """The 8-wave tile (FP32): a workgroup with the CU's LDS to itself (larger patches) for the shell terms, two
+    8-wave workgroups per CU for light terms; parity with the oracle, and FP64 keeps the 4-wave tile."""
+    torch = torch_cuda
+    from paper_2509_00406_amd import mad
+    say("eight-wave tile, persistent", persistent)
+    inp = meshgen.shell_cylinder(n=60, seed=23)
+    P = PR.build_oracle(inp.tris, inp.rest, inp.n_verts, 3, SHELL)
+    xt = torch.from_numpy(inp.x.ravel().copy()).cuda()
+    mesh = mad.Mesh(inp.tris, inp.n_verts)
+    faces = {}
+    for waves in (4, 8):
+        prob = mad.Problem(mesh, 3, mad.F32, wg_waves=waves, patch_faces=4096)
+        for k, prm in SHELL:
+            prob.add_term(k, prm, inp.rest)
+        prob.finalize()
+        prob.set_layout(mad.SCATTER_PATCH, 4096, persistent)
+        lay = prob.layout()
+        assert lay["wg_waves"] == waves
+        faces[waves] = lay["patch_faces"]
+        for mode in (1, 1 | 2, ALL, ALL | 8):
+            out = prob.eval(xt, mode)
+            torch.cuda.synchronize()
+            ref = P.eval(inp.x, mode)
+            e = out[0].cpu().numpy()
+            assert abs(e[0] - ref.energy) <= PR.RTOL[1] * ref.esum_abs
+            if mode & 2:
+                PR.assert_close("grad", out[1].cpu().numpy(), ref.grad, ref.gscale, PR.RTOL[1])
+            if mode & 4:
+                PR.assert_close("hess", out[2].cpu().numpy(), ref.hess, ref.hscale, PR.RTOL[1])
+        assert prob.status() == (False, 0)
+    # the 148 KB budget of the 8-wave tile fits larger patches than the 76 KB one
+    assert faces[8] > faces[4], faces
+    say("patch targets after the LDS fit:", faces)
+    # light terms (springs + inertia) with the 8-wave tile, and FP64, which keeps four waves
+    cl = meshgen.cloth(n=40, seed=6001)
+    vdata = torch.from_numpy(cl.meta["vdata"]).cuda()
+    from oracle import oracle as O
+    Pc = O.Problem(cl.tris, cl.rest, cl.n_verts, 3)
+    Pc.add_term(O.SPRING, cl.meta["spring_params"])
+    Pc.add_term(O.INERTIA, cl.meta["inertia_params"], vertex_data=cl.meta["vdata"])
+    Pc.build_pattern()
+    ref = Pc.eval(cl.x, ALL | 8)
+    for prec in (mad.F32, mad.F64):
+        m2 = mad.Mesh(cl.tris, cl.n_verts)
+        pc = mad.Problem(m2, 3, prec, wg_waves=8)
+        pc.add_term(mad.SPRING, cl.meta["spring_params"], cl.rest)
+        pc.add_vertex_term(mad.INERTIA, cl.meta["inertia_params"], vdata)
+        pc.finalize()
+        pc.set_layout(mad.SCATTER_PATCH, 256, persistent)
+        assert pc.layout()["wg_waves"] == (8 if prec == mad.F32 else 4)
+        out = pc.eval(torch.from_numpy(cl.x.ravel().copy()).cuda(), ALL | 8)
+        torch.cuda.synchronize()
+        rtol = PR.RTOL[prec]
+        assert abs(out[0].cpu().numpy()[0] - ref.energy) <= rtol * ref.esum_abs
+        PR.assert_close("grad", out[1].cpu().numpy(), ref.grad, ref.gscale, rtol)
+        PR.assert_close("hess", out[2].cpu().numpy(), ref.hess, ref.hscale, rtol)
