@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--meshes", type=int, default=700, help="meshes of the batched workload")
     ap.add_argument("--mlp-n", type=int, default=708, help="grid side of the learned-density workload")
     ap.add_argument("--patch-faces", type=int, default=0)
-    ap.add_argument("--scatter", choices=["patch", "atomic"], default="patch")
+    ap.add_argument("--scatter", choices=["patch", "atomic", "color"], default="patch")
     ap.add_argument("--persistent", action="store_true", help="persistent launch (the default for heavy terms)")
     ap.add_argument("--per-patch", action="store_true", help="one workgroup per patch (the default for light terms)")
     ap.add_argument("--wg-waves", type=int, choices=[0, 4, 8], default=0,
@@ -299,7 +299,7 @@ def make_problem(mad, mesh, inp, prec, args, stream, form=None):
     """form: "plain" (StVK + bending), "mlp" (learned density), "analytic" (shell-triangle density),
     "cloth" (springs + inertia); default: the workload's own."""
     form = form or {"mlp": "mlp", "cloth": "cloth", "symdir": "symdir"}.get(args.workload, "plain")
-    scatter = mad.SCATTER_PATCH if args.scatter == "patch" else mad.SCATTER_ATOMIC
+    scatter = {"patch": mad.SCATTER_PATCH, "atomic": mad.SCATTER_ATOMIC, "color": mad.SCATTER_COLOR}[args.scatter]
     prob = mad.Problem(mesh, 2 if form == "symdir" else 3, prec, patch_faces=args.patch_faces, scatter=scatter,
                        wg_waves=args.wg_waves)
     if form == "symdir":

@@ -131,15 +131,20 @@ typedef enum mad_scatter {
     MAD_SCATTER_AUTO = 0,    /* library default (MAD_SCATTER_PATCH) */
     MAD_SCATTER_ATOMIC = 1,  /* one kernel per term; every element adds its gradient and Hessian
                                 entries with device-wide atomics into pre-zeroed outputs (Sec. 5.5) */
-    MAD_SCATTER_PATCH = 2    /* one fused kernel over all terms, one workgroup per patch: x staged
+    MAD_SCATTER_PATCH = 2,   /* one fused kernel over all terms, one workgroup per patch: x staged
                                 in LDS, element contributions summed in LDS, then every entry written
                                 once: by its patch if no other patch touches it, else by a gather
                                 kernel summing the patches' partials in a fixed order. No global
                                 atomics and no zero fill of the outputs. */
+    MAD_SCATTER_COLOR = 3    /* the coloring alternative of Sec. 5.5: each term's elements greedily
+                                colored so that no two elements of a color share a vertex, one launch
+                                per color and term, each element adding its entries into pre-zeroed
+                                outputs with plain read-add-writes (race-free within a color, colors in
+                                sequence); no atomics, bitwise reproducible */
 } mad_scatter;
 
 typedef struct mad_options {
-    int32_t scatter;         /* mad_scatter; 0 = default */
+    int32_t scatter;         /* mad_scatter; 0 = default (MAD_SCATTER_PATCH) */
     int32_t patch_faces;     /* target faces per patch (Sec. 7.1 patch study); 0 = by term mix: 256 when
                                 every term is a spring, inertia, edge-length or residual term, else 512 */
     double spd_eps;          /* eigenvalue floor of MAD_SPD; default 0 (PSD) */
@@ -341,7 +346,7 @@ enum { MAD_TUNE_FORCE = 1 };  /* mad_problem_autotune: re-time even if this prob
 
 /* Choose the layout by timing (batched scheduling and the patch-size study, Sec. 7.1): builds each
  * candidate layout (patch scatter with patch targets 128, 256, 512, 1024, each with and without the
- * persistent launch, each with the 4- and (MAD_F32) 8-wave tile; the atomic scatter at 512), times
+ * persistent launch, each with the 4- and (MAD_F32) 8-wave tile; the atomic and the colored scatter), times
  * `reps` evaluations of `mode` on the caller's x_dev and outputs (arguments as for mad_problem_eval;
  * their contents are overwritten), and keeps the one with the lowest median time: every candidate
  * writes the same outputs from the same inputs, so the fastest is also the one with the highest

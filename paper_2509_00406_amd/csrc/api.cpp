@@ -149,7 +149,8 @@ int32_t mad_problem_create(const mad_mesh* mesh, int32_t var_dim, int32_t precis
         if (opt->wg_waves != 0 && opt->wg_waves != 4 && opt->wg_waves != 8)
             return fail(MAD_E_INVALID_ARG, "wg_waves must be 0, 4 or 8");
         o.wg_waves = opt->wg_waves;
-        if (opt->scatter != MAD_SCATTER_AUTO && opt->scatter != MAD_SCATTER_ATOMIC && opt->scatter != MAD_SCATTER_PATCH)
+        if (opt->scatter != MAD_SCATTER_AUTO && opt->scatter != MAD_SCATTER_ATOMIC && opt->scatter != MAD_SCATTER_PATCH &&
+            opt->scatter != MAD_SCATTER_COLOR)
             return fail(MAD_E_INVALID_ARG, "bad scatter mode");
         o.scatter = opt->scatter == MAD_SCATTER_AUTO ? MAD_SCATTER_PATCH : opt->scatter;
         if (opt->patch_faces < 0 || opt->patch_faces > (1 << 20)) return fail(MAD_E_INVALID_ARG, "bad patch_faces");

@@ -41,7 +41,8 @@ static void tune_file_load() {
         std::string key;
         TuneChoice c{};
         if (in >> key >> c.scatter >> c.faces >> c.persistent >> c.wg_waves &&
-            (c.scatter == MAD_SCATTER_PATCH || c.scatter == MAD_SCATTER_ATOMIC) && c.faces >= 1 &&
+            (c.scatter == MAD_SCATTER_PATCH || c.scatter == MAD_SCATTER_ATOMIC || c.scatter == MAD_SCATTER_COLOR) &&
+            c.faces >= 1 &&
             c.faces <= (1 << 20) && c.persistent >= 0 && c.persistent <= 2 && (c.wg_waves == 4 || c.wg_waves == 8))
             g_tune_cache[key] = c;
     }
@@ -73,6 +74,10 @@ static std::string fingerprint(const mad_problem* p, uint32_t mode) {
                     std::to_string(p->prec) + "/" + std::to_string(mode);
     for (const auto& t : p->terms) k += "/" + std::to_string(t.kind);
     return k;
+}
+
+static const char* scatter_name(int sc) {
+    return sc == MAD_SCATTER_PATCH ? "patch" : sc == MAD_SCATTER_ATOMIC ? "atomic" : "color";
 }
 
 static int time_layout(mad_problem* p, const double* x, uint32_t mode, double* energy, void* grad, void* hess,
@@ -121,12 +126,14 @@ int32_t mad_problem_set_layout(mad_problem* p, int32_t scatter, int32_t patch_fa
                                int32_t wg_waves, void* stream) {
     if (!p) return fail(MAD_E_INVALID_ARG, "problem is NULL");
     if (!p->finalized) return fail(MAD_E_STATE, "not finalized");
-    if (scatter != MAD_SCATTER_AUTO && scatter != MAD_SCATTER_ATOMIC && scatter != MAD_SCATTER_PATCH)
+    if (scatter != MAD_SCATTER_AUTO && scatter != MAD_SCATTER_ATOMIC && scatter != MAD_SCATTER_PATCH &&
+        scatter != MAD_SCATTER_COLOR)
         return fail(MAD_E_INVALID_ARG, "bad scatter mode");
     if (patch_faces < 1 || patch_faces > (1 << 20)) return fail(MAD_E_INVALID_ARG, "bad patch_faces");
     if (persistent < 0 || persistent > 2) return fail(MAD_E_INVALID_ARG, "persistent must be 0, 1 or 2");
     if (wg_waves != 0 && wg_waves != 4 && wg_waves != 8) return fail(MAD_E_INVALID_ARG, "wg_waves must be 0, 4 or 8");
-    if (scatter == MAD_SCATTER_ATOMIC && persistent) return fail(MAD_E_UNSUPPORTED, "persistent needs the patch scatter");
+    if (scatter != MAD_SCATTER_PATCH && scatter != MAD_SCATTER_AUTO && persistent)
+        return fail(MAD_E_UNSUPPORTED, "persistent needs the patch scatter");
     const int sc = scatter == MAD_SCATTER_AUTO ? MAD_SCATTER_PATCH : scatter;
     const int rc = build_layout(p, patch_faces, sc, persistent, (hipStream_t)stream, wg_waves);
     if (rc != MAD_OK) p->finalized = false;   // half-built layout: the problem cannot be evaluated
@@ -177,6 +184,7 @@ int32_t mad_problem_autotune(mad_problem* p, const double* x, uint32_t mode, dou
             for (int pers = 0; pers < 2; ++pers) cands.push_back({MAD_SCATTER_PATCH, f, pers, w});
     }
     cands.push_back({MAD_SCATTER_ATOMIC, 512, 0, 4});
+    cands.push_back({MAD_SCATTER_COLOR, 512, 0, 4});
     std::string rep = "{\"cached\": false, \"candidates\": [";
     double best = 1e300;
     TuneChoice bc = {p->scatter, p->opt.patch_faces, p->persistent, p->wg_waves};
@@ -191,7 +199,7 @@ int32_t mad_problem_autotune(mad_problem* p, const double* x, uint32_t mode, dou
         std::snprintf(buf, sizeof(buf),
                       "%s{\"scatter\": \"%s\", \"patch_faces\": %d, \"effective_faces\": %d, \"persistent\": %d, "
                       "\"wg_waves\": %d, \"n_patches\": %d, \"ms\": %.6f}",
-                      i ? ", " : "", c.scatter == MAD_SCATTER_PATCH ? "patch" : "atomic", c.faces, p->opt.patch_faces,
+                      i ? ", " : "", scatter_name(c.scatter), c.faces, p->opt.patch_faces,
                       c.persistent, p->wg_waves, p->patches.n, ms);
         rep += buf;
         if (ms < best) {
@@ -207,7 +215,7 @@ int32_t mad_problem_autotune(mad_problem* p, const double* x, uint32_t mode, dou
     char tail[192];
     std::snprintf(tail, sizeof(tail),
                   "], \"chosen\": {\"scatter\": \"%s\", \"patch_faces\": %d, \"persistent\": %d, \"wg_waves\": %d}}",
-                  bc.scatter == MAD_SCATTER_PATCH ? "patch" : "atomic", bc.faces, bc.persistent, bc.wg_waves);
+                  scatter_name(bc.scatter), bc.faces, bc.persistent, bc.wg_waves);
     p->tune_report = rep + tail;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);

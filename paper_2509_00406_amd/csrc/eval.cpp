@@ -47,8 +47,8 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         MAD_HIP_TRY(hipEventRecord((*ev)[0], s));
     }
     const bool fallback_pass = p->scatter == MAD_SCATTER_PATCH && p->prec == MAD_F32 && (mode & MAD_SPD);
-    // the atomic scatter adds into zeroed outputs; the patch scatter writes every entry exactly once
-    if (p->scatter == MAD_SCATTER_ATOMIC) {
+    // the atomic and colored scatters add into zeroed outputs; the patch scatter writes every entry exactly once
+    if (p->scatter != MAD_SCATTER_PATCH) {
         if (mode & MAD_GRAD) MAD_HIP_TRY(launch_fill(grad, m.nv * d, eb, s));
         if (mode & MAD_HESS) MAD_HIP_TRY(launch_fill(hess, p->nnzb * d * d, eb, s));
         if (hvp) MAD_HIP_TRY(launch_fill(y, m.nv * d, eb, s));
@@ -219,7 +219,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
             for (size_t k = 4; k < ev->size() - 1; ++k) MAD_HIP_TRY(hipEventRecord((*ev)[k], s));
         n_partial_terms = 1;
     }
-    for (size_t ti = 0; p->scatter == MAD_SCATTER_ATOMIC && ti < p->terms.size(); ++ti) {
+    for (size_t ti = 0; p->scatter != MAD_SCATTER_PATCH && ti < p->terms.size(); ++ti) {
         const Term& t = p->terms[ti];
         EvalLaunch L{};
         L.kind = t.kind;
@@ -247,13 +247,29 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         L.hvp = hvp ? 1 : 0;
         L.v = v;
         L.y = y;
-        MAD_HIP_TRY(launch_eval(L, s));
+        if (p->scatter == MAD_SCATTER_COLOR) {
+            // one launch per color: no two elements of a launch share a vertex, so plain adds cannot race
+            L.plain = 1;
+            L.partial = sc.partial;
+            L.slot_map = t.d_slot_map;
+            for (size_t c = 0; c + 1 < t.color_chunk_ptr.size(); ++c) {
+                L.chunk0 = t.color_chunk_ptr[c];
+                L.n_patch = t.color_chunk_ptr[c + 1] - t.color_chunk_ptr[c];
+                MAD_HIP_TRY(launch_eval(L, s));
+            }
+        } else {
+            MAD_HIP_TRY(launch_eval(L, s));
+        }
         if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[3 + ti], s));
     }
     if (mode & MAD_ENERGY) {
         const int ncomp = (int)m.comp_off.size() - 1;
-        MAD_HIP_TRY(launch_energy_reduce(sc.partial, n_partial_terms, np, p->d_comp_patch_ptr,
-                                         std::max(ncomp, 1), m.batched, energy, sc.comp_energy, s));
+        if (p->scatter == MAD_SCATTER_COLOR)
+            MAD_HIP_TRY(launch_energy_reduce(sc.partial, 1, (int)p->n_color_slots, p->d_color_comp_ptr,
+                                             std::max(ncomp, 1), m.batched, energy, sc.comp_energy, s));
+        else
+            MAD_HIP_TRY(launch_energy_reduce(sc.partial, n_partial_terms, np, p->d_comp_patch_ptr,
+                                             std::max(ncomp, 1), m.batched, energy, sc.comp_energy, s));
     }
     if (ev) MAD_HIP_TRY(hipEventRecord(ev->back(), s));
     return MAD_OK;

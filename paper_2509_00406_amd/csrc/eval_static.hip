@@ -58,7 +58,8 @@ size_t carve(const mad_problem* p, unsigned char* base, mad::EvalScratch& sc) {
     const size_t eb = p->prec == MAD_F32 ? 4 : 8;
     const size_t d = (size_t)p->d;
     const size_t np = (size_t)std::max(p->patches.n, 1);
-    sc.partial = reinterpret_cast<double*>(take(sizeof(double) * np * std::max<size_t>(p->terms.size(), 1)));
+    sc.partial = reinterpret_cast<double*>(
+        take(sizeof(double) * std::max(np * std::max<size_t>(p->terms.size(), 1), (size_t)p->n_color_slots)));
     sc.comp_energy =
         reinterpret_cast<double*>(take(sizeof(double) * std::max<size_t>(p->patches.comp_patch_ptr.size(), 1)));
     sc.work_counter = reinterpret_cast<int32_t*>(take(16));

@@ -149,4 +149,95 @@ void unit_segments(const Term& t, int32_t np, int64_t nv, std::vector<uint8_t>& 
         }
 }
 
+// Colored scatter (the coloring alternative of Sec. 5.5). Each term's elements are colored greedily in
+// their current (patch) order: an element takes the lowest color that no earlier element sharing one of its
+// vertices holds (per-vertex bit sets of used colors, widened when a color beyond them is needed), so no two
+// elements of a color share a vertex and so no gradient entry or Hessian block. The elements are then
+// sorted by (color, component), keeping the patch order inside, and cut into chunks of at most kColorChunk
+// elements of one color and one component: a launch per color covers that color's chunks. Each chunk's
+// energy goes to a slot; slots are numbered by component, then term, color and chunk, so the energy
+// reduction sums each component's slots as one contiguous range, always in the same order.
+void color_order(mad_problem* p, std::vector<int32_t>& comp_slot_ptr) {
+    const mad_mesh& m = *p->mesh;
+    const int64_t nv = m.nv;
+    const int ncomp = (int)std::max<size_t>(m.comp_off.size(), 2) - 1;
+    auto comp_of = [&](int32_t v) -> int32_t {
+        if (ncomp == 1) return 0;
+        return (int32_t)(std::upper_bound(m.comp_off.begin(), m.comp_off.end(), (int64_t)v) - m.comp_off.begin() - 1);
+    };
+    const int nt = (int)p->terms.size();
+    std::vector<std::vector<int32_t>> chunk_comp((size_t)nt);
+    for (int ti = 0; ti < nt; ++ti) {
+        Term& t = p->terms[ti];
+        const int64_t n = t.n;
+        std::vector<int32_t> color((size_t)std::max<int64_t>(n, 1), 0);
+        int words = 1;
+        std::vector<uint64_t> used((size_t)nv * words, 0);
+        int32_t n_colors = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+            int c = -1;
+            for (int w = 0; w < words && c < 0; ++w) {
+                uint64_t busy = 0;
+                for (int a = 0; a < t.ns; ++a) busy |= used[(size_t)st[a] * words + w];
+                if (~busy != 0ull) c = 64 * w + __builtin_ctzll(~busy);
+            }
+            if (c < 0) {
+                // every color in the sets is taken around this element: widen the sets by one word
+                std::vector<uint64_t> wider((size_t)nv * (words + 1), 0);
+                for (int64_t v = 0; v < nv; ++v)
+                    for (int w = 0; w < words; ++w) wider[(size_t)v * (words + 1) + w] = used[(size_t)v * words + w];
+                used.swap(wider);
+                c = 64 * words;
+                ++words;
+            }
+            color[(size_t)i] = c;
+            n_colors = std::max(n_colors, c + 1);
+            for (int a = 0; a < t.ns; ++a) used[(size_t)st[a] * words + c / 64] |= 1ull << (c % 64);
+        }
+        // stable counting sort by (color, component)
+        const int64_t nkeys = (int64_t)n_colors * ncomp;
+        std::vector<int64_t> cnt((size_t)nkeys + 1, 0);
+        std::vector<int32_t> key((size_t)std::max<int64_t>(n, 1));
+        for (int64_t i = 0; i < n; ++i) {
+            key[(size_t)i] = color[(size_t)i] * ncomp + comp_of(t.stencil[(int64_t)t.perm[i] * t.ns]);
+            cnt[(size_t)key[(size_t)i] + 1]++;
+        }
+        for (int64_t k = 0; k < nkeys; ++k) cnt[(size_t)k + 1] += cnt[(size_t)k];
+        std::vector<int32_t> perm((size_t)n);
+        {
+            std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+            for (int64_t i = 0; i < n; ++i) perm[(size_t)fill[(size_t)key[(size_t)i]]++] = t.perm[i];
+        }
+        t.perm.swap(perm);
+        // chunks: runs of at most kColorChunk elements inside one (color, component) group
+        t.elem_ptr.assign(1, 0);
+        t.color_chunk_ptr.assign((size_t)n_colors + 1, 0);
+        chunk_comp[ti].clear();
+        for (int32_t c = 0; c < n_colors; ++c) {
+            t.color_chunk_ptr[c] = (int32_t)chunk_comp[ti].size();
+            for (int q = 0; q < ncomp; ++q) {
+                const int64_t b = cnt[(size_t)c * ncomp + q], e = cnt[(size_t)c * ncomp + q + 1];
+                for (int64_t s0 = b; s0 < e; s0 += kColorChunk) {
+                    t.elem_ptr.push_back((int32_t)std::min<int64_t>(e, s0 + kColorChunk));
+                    chunk_comp[ti].push_back(q);
+                }
+            }
+        }
+        t.color_chunk_ptr[n_colors] = (int32_t)chunk_comp[ti].size();
+    }
+    // energy slots: by component, then term, then chunk (chunks are in color order within a term)
+    comp_slot_ptr.assign((size_t)ncomp + 1, 0);
+    for (int ti = 0; ti < nt; ++ti)
+        for (int32_t q : chunk_comp[ti]) comp_slot_ptr[(size_t)q + 1]++;
+    for (int q = 0; q < ncomp; ++q) comp_slot_ptr[(size_t)q + 1] += comp_slot_ptr[(size_t)q];
+    std::vector<int32_t> next(comp_slot_ptr.begin(), comp_slot_ptr.end() - 1);
+    for (int ti = 0; ti < nt; ++ti) {
+        Term& t = p->terms[ti];
+        t.slot_map.resize(chunk_comp[ti].size());
+        for (size_t k = 0; k < chunk_comp[ti].size(); ++k) t.slot_map[k] = next[(size_t)chunk_comp[ti][k]]++;
+    }
+    p->n_color_slots = comp_slot_ptr[(size_t)ncomp];
+}
+
 }  // namespace mad

@@ -1,16 +1,26 @@
-// Device-wide atomic assembly (Sec. 5.5, Sec. 6.2), the deterministic FP64
-// energy reduction, and a fill kernel for zeroing outputs.
+// Device-wide atomic and colored assembly (Sec. 5.5, Sec. 6.2), the
+// deterministic FP64 energy reduction, and a fill kernel for zeroing outputs.
 //
 // One kernel per term and one workgroup per patch: the patch's elements of
 // that term are contiguous in the device arrays. Each lane evaluates whole
 // elements with the local gradient and Hessian in registers, then adds every
 // stencil entry to the global gradient / block-CSR values with hardware
 // floating-point atomics (global_atomic_add_f32/_f64), as the paper does.
+// The colored variant (PLAIN) runs one launch per color over chunks of
+// elements of that color, which share no vertex, and adds with plain
+// read-add-writes.
 #include "kernels_common.hpp"
 
 namespace mad {
 
-template <class Term, typename T, int MODE>
+// add into a global entry: a hardware atomic, or (colored scatter, PLAIN) a plain read-add-write
+template <bool PLAIN, typename T>
+__device__ __forceinline__ void global_add(T* p, T v) {
+    if constexpr (PLAIN) *p += v;
+    else atomic_add(p, v);
+}
+
+template <class Term, typename T, int MODE, bool PLAIN>
 __device__ __forceinline__ void scatter_global(const ElemOut<Term, T>& o, const int* vs, int e, const EvalLaunch& L,
                                                bool want_grad) {
     constexpr int NS = Term::NS, D = Term::D;
@@ -19,7 +29,7 @@ __device__ __forceinline__ void scatter_global(const ElemOut<Term, T>& o, const 
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int c = 0; c < D; ++c) atomic_add(g + (int64_t)vs[s] * D + c, o.g[s * D + c]);
+            for (int c = 0; c < D; ++c) global_add<PLAIN>(g + (int64_t)vs[s] * D + c, o.g[s * D + c]);
     }
     if constexpr (MODE >= 2) {
         const T te = T(L.eps > 0.0 ? L.eps : 0.0);
@@ -35,7 +45,7 @@ __device__ __forceinline__ void scatter_global(const ElemOut<Term, T>& o, const 
 #pragma unroll
             for (int s = 0; s < NS; ++s)
 #pragma unroll
-                for (int c = 0; c < D; ++c) atomic_add(y + (int64_t)vs[s] * D + c, yl[s * D + c]);
+                for (int c = 0; c < D; ++c) global_add<PLAIN>(y + (int64_t)vs[s] * D + c, yl[s * D + c]);
             return;
         }
         T* h = static_cast<T*>(L.hess);
@@ -49,16 +59,16 @@ __device__ __forceinline__ void scatter_global(const ElemOut<Term, T>& o, const 
                 for (int c = 0; c < D; ++c)
 #pragma unroll
                     for (int c2 = 0; c2 < D; ++c2)
-                        atomic_add(blk + c * D + c2, hfull<Term, MODE>(o, s * D + c, t * D + c2, te));
+                        global_add<PLAIN>(blk + c * D + c2, hfull<Term, MODE>(o, s * D + c, t * D + c2, te));
             }
     }
 }
 
-template <class Term, typename T, int MODE>
+template <class Term, typename T, int MODE, bool PLAIN>
 __global__ __launch_bounds__(kBlock) void k_eval(EvalLaunch L) {
     constexpr int NS = Term::NS, D = Term::D, NF = NS * D;
     __shared__ double red[kBlock];
-    const int p = blockIdx.x;
+    const int p = (int)blockIdx.x + L.chunk0;
     const int beg = L.elem_ptr[p], end = L.elem_ptr[p + 1];
     double esum = 0.0;
     bool bad = false;
@@ -93,23 +103,28 @@ __global__ __launch_bounds__(kBlock) void k_eval(EvalLaunch L) {
         }
         esum += o.f;
         bad = bad || !out_finite<Term, T>(o, MODE);
-        if constexpr (MODE >= 1) scatter_global<Term, T, MODE>(o, vs, e, L, L.want_grad != 0);
+        if constexpr (MODE >= 1) scatter_global<Term, T, MODE, PLAIN>(o, vs, e, L, L.want_grad != 0);
     }
     if (bad) atomicOr(L.flags, 1);
-    block_reduce_store(esum, red, L.partial + p);
+    block_reduce_store(esum, red, L.partial + (L.slot_map ? L.slot_map[p] : p));
+}
+
+template <class Term, typename T, bool PLAIN>
+static hipError_t launch_mode_t(const EvalLaunch& L, hipStream_t s) {
+    dim3 grid(L.n_patch), block(kBlock);
+    switch (L.mode) {
+    case 0: hipLaunchKernelGGL((k_eval<Term, T, 0, PLAIN>), grid, block, 0, s, L); break;
+    case 1: hipLaunchKernelGGL((k_eval<Term, T, 1, PLAIN>), grid, block, 0, s, L); break;
+    case 2: hipLaunchKernelGGL((k_eval<Term, T, 2, PLAIN>), grid, block, 0, s, L); break;
+    case 3: hipLaunchKernelGGL((k_eval<Term, T, 3, PLAIN>), grid, block, 0, s, L); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <class Term, typename T>
 static hipError_t launch_mode(const EvalLaunch& L, hipStream_t s) {
-    dim3 grid(L.n_patch), block(kBlock);
-    switch (L.mode) {
-    case 0: hipLaunchKernelGGL((k_eval<Term, T, 0>), grid, block, 0, s, L); break;
-    case 1: hipLaunchKernelGGL((k_eval<Term, T, 1>), grid, block, 0, s, L); break;
-    case 2: hipLaunchKernelGGL((k_eval<Term, T, 2>), grid, block, 0, s, L); break;
-    case 3: hipLaunchKernelGGL((k_eval<Term, T, 3>), grid, block, 0, s, L); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return L.plain ? launch_mode_t<Term, T, true>(L, s) : launch_mode_t<Term, T, false>(L, s);
 }
 
 template <class Term>

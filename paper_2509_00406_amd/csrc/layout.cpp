@@ -41,7 +41,9 @@ static void free_layout(mad_problem* p) {
         t.d_psi = nullptr;
         t.d_xh = nullptr;
         t.d_perm = nullptr;
+        t.d_slot_map = nullptr;
     }
+    p->d_color_comp_ptr = nullptr;
     p->d_lv_ptr = p->d_lv_global = p->d_lv_halo = nullptr;
     p->d_lb_ptr = p->d_lb_gidx = p->d_lb_gidxT = p->d_lb_halo = nullptr;
     p->n_lb = 0;
@@ -95,6 +97,9 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
         }
     }
     for (auto& t : p->terms) color_within_patches(t, m.nv);
+    std::vector<int32_t> comp_slot_ptr;
+    p->n_color_slots = 0;
+    if (scatter == MAD_SCATTER_COLOR) color_order(p, comp_slot_ptr);
     p->opt.patch_faces = target;
     const int32_t np = p->patches.n;
     int rc;
@@ -113,6 +118,9 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
         if (kind_nres(t.kind) > 0 &&
             (rc = upload_layout(p, (void**)&t.d_perm, t.perm.data(), t.perm.size() * 4, s)) != MAD_OK)
             return rc;
+        if (scatter == MAD_SCATTER_COLOR &&
+            (rc = upload_layout(p, (void**)&t.d_slot_map, t.slot_map.data(), t.slot_map.size() * 4, s)) != MAD_OK)
+            return rc;
         if (t.kind == MAD_MLP) {
             const size_t n = (size_t)std::max<int64_t>(t.n, 1);
             if ((rc = alloc_layout(p, (void**)&t.d_psi, sizeof(float) * (size_t)kPsi * n)) != MAD_OK) return rc;
@@ -122,9 +130,12 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
     if ((rc = upload_layout(p, (void**)&p->d_comp_patch_ptr, p->patches.comp_patch_ptr.data(),
                             p->patches.comp_patch_ptr.size() * 4, s)) != MAD_OK)
         return rc;
-    if ((rc = alloc_layout(p, (void**)&p->d_partial, sizeof(double) * std::max<size_t>(1, (size_t)np * p->terms.size()))) !=
-        MAD_OK)
+    if (scatter == MAD_SCATTER_COLOR &&
+        (rc = upload_layout(p, (void**)&p->d_color_comp_ptr, comp_slot_ptr.data(), comp_slot_ptr.size() * 4, s)) !=
+            MAD_OK)
         return rc;
+    const size_t n_partial = std::max<size_t>({(size_t)1, (size_t)np * p->terms.size(), (size_t)p->n_color_slots});
+    if ((rc = alloc_layout(p, (void**)&p->d_partial, sizeof(double) * n_partial)) != MAD_OK) return rc;
     if ((rc = alloc_layout(p, (void**)&p->d_comp_energy,
                            sizeof(double) * std::max<size_t>(1, p->patches.comp_patch_ptr.size()))) != MAD_OK)
         return rc;
@@ -168,7 +179,7 @@ int build_scatter(mad_problem* p, hipStream_t s) {
         p->host_pattern_stale = false;
     }
     p->n_extra = 0;
-    if (p->scatter == MAD_SCATTER_ATOMIC) {
+    if (p->scatter != MAD_SCATTER_PATCH) {   // atomic and colored: the global block of every element pair
         for (auto& t : p->terms) {
             if ((rc = alloc_layout(p, (void**)&t.d_slots, sizeof(int32_t) * std::max<int64_t>(1, t.n * t.ns * t.ns))) !=
                 MAD_OK)

@@ -52,6 +52,12 @@ struct Term {
     float* d_xh = nullptr;               // learned density: SoA [6][n] scaled features, patch order
     const double* vdata = nullptr;       // vertex terms: the caller's [nv][NVD] device array (not owned)
     int32_t* d_perm = nullptr;           // residual terms: [n] patch slot -> element (row ownership)
+    // colored scatter: elements sorted by color; elem_ptr then delimits chunks of at most kColorChunk elements
+    // of one color and one component, color_chunk_ptr[c] is the first chunk of color c, and d_slot_map gives
+    // each chunk's energy slot (slots ordered by component, then term, color and chunk)
+    std::vector<int32_t> color_chunk_ptr;
+    std::vector<int32_t> slot_map;       // host copy of d_slot_map
+    int32_t* d_slot_map = nullptr;
 };
 
 // patch-local index structures of the LDS-accumulating assembly (host_patch.cpp)
@@ -126,6 +132,8 @@ struct mad_problem {
     int n_cu = 0;                         // compute units of the device
     std::vector<void*> layout_owned;      // device memory of the current layout (freed on relayout)
     std::vector<int32_t> h_rowptr, h_colidx;  // host copy of the pattern (layout rebuilds)
+    int32_t* d_color_comp_ptr = nullptr;  // colored scatter: [n_comp + 1] energy slots of each component
+    int64_t n_color_slots = 0;            // colored scatter: energy slots (chunks of all terms)
     int32_t* d_work_order = nullptr;      // patches, largest first (persistent launch)
     int32_t* d_work_counter = nullptr;
     std::string tune_report;              // last autotune table (JSON)
@@ -204,6 +212,10 @@ void order_terms(mad_problem* p);
 void color_within_patches(Term& t, int64_t nv);
 void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb);
 void unit_segments(const Term& t, int32_t np, int64_t nv, std::vector<uint8_t>& seg);
+// colored scatter: greedy coloring of each term's elements (no shared vertex within a color), elements
+// sorted by color then component, chunks, energy slots; comp_slot_ptr [n_comp + 1] (host)
+constexpr int kColorChunk = 256;
+void color_order(mad_problem* p, std::vector<int32_t>& comp_slot_ptr);
 // layout.cpp: (re)build the element order and the scatter structures of a problem
 int build_layout(mad_problem* p, int target_faces, int scatter, int persistent, hipStream_t s, int wg_waves = 0);
 int build_scatter(mad_problem* p, hipStream_t s);
@@ -271,6 +283,9 @@ struct EvalLaunch {
     int hvp;                // matrix-free mode: atomically add H_j v_j to y
     const double* v;
     void* y;
+    int plain;              // colored scatter: plain read-add-writes (no two elements of the launch share a vertex)
+    int chunk0;             // colored scatter: first chunk (workgroup p handles chunk chunk0 + p)
+    const int32_t* slot_map;  // colored scatter: energy slot of each chunk (NULL: slot = chunk)
 };
 hipError_t launch_eval(const EvalLaunch& L, hipStream_t s);
 

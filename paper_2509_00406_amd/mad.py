@@ -20,7 +20,7 @@ SPRING, INERTIA = 9, 10
 RES_POSITION, RES_EDGE = 11, 12
 ENERGY, GRAD, HESS, SPD = 1, 2, 4, 8
 F64, F32 = 0, 1
-SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_PATCH = 0, 1, 2
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_PATCH, SCATTER_COLOR = 0, 1, 2, 3
 TUNE_FORCE = 1
 
 STATUS = {0: "MAD_OK", -1: "MAD_E_INVALID_ARG", -2: "MAD_E_BAD_MESH", -3: "MAD_E_DEGENERATE_REST",

@@ -188,6 +188,49 @@ static void check_problem(const MeshIn& in, int target) {
             }
         }
     }
+    // colored scatter: each color's elements share no vertex, chunks hold one color and one component, and the
+    // energy slots number every chunk once, each component's slots contiguous
+    {
+        std::vector<int32_t> comp_slot_ptr;
+        color_order(&P, comp_slot_ptr);
+        const int ncomp = (int)mesh.comp_off.size() - 1;
+        auto comp_of = [&](int32_t v) {
+            return (int)(std::upper_bound(mesh.comp_off.begin(), mesh.comp_off.end(), (int64_t)v) -
+                         mesh.comp_off.begin() - 1);
+        };
+        CHECK((int)comp_slot_ptr.size() == ncomp + 1 && comp_slot_ptr[ncomp] == P.n_color_slots);
+        std::vector<int32_t> slot_uses((size_t)P.n_color_slots, 0);
+        for (const Term& t : P.terms) {
+            std::vector<int32_t> seen(t.perm.begin(), t.perm.end());
+            std::sort(seen.begin(), seen.end());
+            for (int64_t i = 0; i < t.n; ++i) CHECK(seen[i] == i);
+            const int ncol = (int)t.color_chunk_ptr.size() - 1;
+            std::vector<int32_t> stamp((size_t)mesh.nv, -1);
+            for (int c = 0; c < ncol; ++c) {
+                for (int32_t k = t.color_chunk_ptr[c]; k < t.color_chunk_ptr[c + 1]; ++k) {
+                    const int q = comp_of(t.stencil[(int64_t)t.perm[t.elem_ptr[k]] * t.ns]);
+                    const int32_t slot = t.slot_map[k];
+                    CHECK(slot >= comp_slot_ptr[q] && slot < comp_slot_ptr[q + 1]);
+                    slot_uses[slot]++;
+                    CHECK(t.elem_ptr[k + 1] - t.elem_ptr[k] <= kColorChunk && t.elem_ptr[k + 1] > t.elem_ptr[k]);
+                    for (int32_t i = t.elem_ptr[k]; i < t.elem_ptr[k + 1]; ++i) {
+                        const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                        CHECK(comp_of(st[0]) == q);
+                        for (int a = 0; a < t.ns; ++a) {
+                            // a vertex appears at most once per color (an element may not repeat a vertex either)
+                            CHECK(stamp[st[a]] != c);
+                            stamp[st[a]] = c;
+                        }
+                    }
+                }
+            }
+            CHECK(t.elem_ptr.back() == t.n);
+        }
+        for (int32_t u : slot_uses) CHECK(u == 1);
+        std::printf("  colored: %lld energy slots; colors per term:", (long long)P.n_color_slots);
+        for (const Term& t : P.terms) std::printf(" %zu", t.color_chunk_ptr.size() - 1);
+        std::printf("\n");
+    }
     // every shared vertex is gathered from at least two halo slots, every slot exactly once
     std::vector<int32_t> slot_uses(L.gv_src.size(), 0);
     for (size_t v = 0; v + 1 < L.gv_ptr.size(); ++v) {

@@ -102,8 +102,9 @@ def test_autotune_batched_and_cache(torch_cuda):
     xt = torch.from_numpy(inp.x.ravel().copy()).cuda()
     out = prob.outputs()
     rep = prob.autotune(xt, ALL | 8, out=out, reps=2, force=True)
-    # patch targets 128..1024 x persistent or not x tiles of 4 and 8 waves, plus the atomic scatter
-    assert rep["cached"] is False and len(rep["candidates"]) == 17
+    # patch targets 128..1024 x persistent or not x tiles of 4 and 8 waves, plus the atomic and colored scatters
+    assert rep["cached"] is False and len(rep["candidates"]) == 18
+    assert {c["scatter"] for c in rep["candidates"]} == {"patch", "atomic", "color"}
     assert {c["wg_waves"] for c in rep["candidates"]} == {4, 8}
     assert all(c["ms"] > 0 for c in rep["candidates"])
     best = min(rep["candidates"], key=lambda c: c["ms"])
