@@ -49,6 +49,7 @@ def sampled_compare(P, mask, x, grad, hess, rtol):
     g = PR.assert_close("grad(sampled)", grad[gi], ref.grad[gi], ref.gscale[gi], rtol)
     bi = np.concatenate([np.arange(P.rowptr[r], P.rowptr[r + 1]) for r in rows])
     h = PR.assert_close("hess(sampled)", hess[bi], ref.hess[bi], ref.hscale[bi], rtol)
+    assert PR.normwise(hess[bi], ref.hess[bi]) <= rtol   # the headline norm-wise error over the sampled rows
     return g, h, bi.size
 
 

@@ -51,11 +51,16 @@ def run_case(torch, tris, rest, x, var_dim, terms, precision, mode, patch_faces=
     if check_energy:
         e = energy.cpu().numpy()
         assert abs(e[0] - ref.energy) <= rtol * ref.esum_abs + 1e-300, (e[0], ref.energy, ref.esum_abs)
+    # per entry against the contributing elements' scale; for the Hessian also the headline norm-wise error
+    # max |H - H_ref| / max |H_ref| under the same bar (the gradient's is reported only: near a stationary
+    # point max |g_ref| is itself a sum that cancels, and no bar relative to it is meaningful)
     if mode & 2:
         out["grad"] = PR.assert_close("grad", grad.cpu().numpy(), ref.grad, ref.gscale, rtol)
+        out["grad_norm"] = PR.normwise(grad.cpu().numpy(), ref.grad)
     if mode & 4:
         out["hess"] = PR.assert_close("hess", hess.cpu().numpy(), ref.hess, ref.hscale, rtol)
         out["hess_norm"] = PR.normwise(hess.cpu().numpy(), ref.hess)
+        assert out["hess_norm"] <= rtol, out
     return out, prob, (energy, grad, hess)
 
 
