@@ -45,7 +45,10 @@ FLOPS_PER_ELEM = {"f32": 14925.0, "f64": None}
 # traffic by launch (persistent queue / one workgroup per patch) at the default 384-face layout
 TRAFFIC_BYTES = {"f32": {1: 1.2522e9, 0: 1.0360e9}, "f64": None}
 # the same for the 1000^2 cloth step at its default layout (profiles/k_eval_patch_f32_cloth1000_counters.md)
-CLOTH_TRAFFIC_BYTES = {"f32": 0.5675e9, "f64": None}
+CLOTH_TRAFFIC_BYTES = {"f32": 0.5687e9, "f64": None}
+# and for the 1001^2 symmetric Dirichlet parameterisation at its default layout (512-face patches, persistent
+# launch; profiles/k_eval_patch_f32_symdir1001_trace_counters.md)
+SYMDIR_TRAFFIC_BYTES = {"f32": 0.3656e9, "f64": None}
 
 # MI355X published peaks used as roofline denominators
 HBM_PEAK_GBS = 8000.0
@@ -434,14 +437,17 @@ def main():
     if args.workload == "symdir":
         # a 4x4 reduced Hessian per triangle: few operations per byte, so the HBM stream is the roofline
         achieved = step_bytes / (dom_ms * 1e-3) / 1e9
+        at_1001 = (args.symdir_n == 1001 and layout["scatter"] == mad.SCATTER_PATCH and layout["patch_faces"] == 512
+                   and layout["persistent"] and layout["wg_waves"] == 4)
         roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel_ms": dom_ms,
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": SYMDIR_TRAFFIC_BYTES.get(args.precision) if at_1001 else None, "kernel_ms": dom_ms,
                     "alg_bytes_per_launch": step_bytes}
     elif args.workload == "cloth":
         # springs are cheap (one 3x3 reduced Hessian each): the fused kernel is held to its HBM stream
         achieved = step_bytes / (dom_ms * 1e-3) / 1e9
         at_1000 = (args.cloth_n == 1000 and layout["scatter"] == mad.SCATTER_PATCH and layout["patch_faces"] == 256
-                   and not layout["persistent"])
+                   and not layout["persistent"] and layout["wg_waves"] == 4)
         roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS,
                     "traffic": CLOTH_TRAFFIC_BYTES.get(args.precision) if at_1000 else None, "kernel_ms": dom_ms,
