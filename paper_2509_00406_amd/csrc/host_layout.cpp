@@ -80,35 +80,69 @@ void order_terms(mad_problem* p) {
     }
 }
 
-// largest per-patch vertex and upper-block counts of the current patching (patches split over
-// threads; each counts its distinct vertices with a stamp array and its distinct pairs by sorting)
+// largest per-patch vertex and upper-block counts of the current patching (patches split over threads)
 void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb) {
     const int64_t nv = p->mesh->nv;
     const int32_t np = p->patches.n;
     const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
     std::vector<int32_t> mv_t((size_t)nth, 0), mb_t((size_t)nth, 0);
+    // Per patch: distinct vertices through a per-thread vertex map (first-seen local numbers), distinct upper
+    // blocks through a dense table of local (row, column) pairs for patches of at most kDenseLocal vertices
+    // (sorted keys beyond); both are reset after each patch, so a patch costs time in proportion to its elements.
+    constexpr int32_t kDenseLocal = 1024;
     auto work = [&](int th) {
-        std::vector<int32_t> stamp((size_t)nv, -1);
+        std::vector<int32_t> loc((size_t)nv, -1), verts, marked;
+        std::vector<uint8_t> tab;
         std::vector<int64_t> keys;
         int32_t mv = 0, mb = 0;
         for (int32_t q = th; q < np; q += nth) {
-            keys.clear();
-            int32_t nverts = 0;
+            verts.clear();
             for (const auto& t : p->terms)
                 for (int32_t i = t.elem_ptr[q]; i < t.elem_ptr[q + 1]; ++i) {
                     const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                    for (int a = 0; a < t.ns; ++a) {
-                        if (stamp[st[a]] != q) {
-                            stamp[st[a]] = q;
-                            ++nverts;
+                    for (int a = 0; a < t.ns; ++a)
+                        if (loc[st[a]] < 0) {
+                            loc[st[a]] = (int32_t)verts.size();
+                            verts.push_back(st[a]);
                         }
-                        for (int b = a; b < t.ns; ++b)
-                            keys.push_back((int64_t)std::min(st[a], st[b]) * nv + std::max(st[a], st[b]));
-                    }
                 }
-            std::sort(keys.begin(), keys.end());
-            mv = std::max(mv, nverts);
-            mb = std::max(mb, (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin()));
+            const int32_t nloc = (int32_t)verts.size();
+            int32_t nblocks = 0;
+            if (nloc <= kDenseLocal) {
+                if (tab.size() < (size_t)nloc * nloc) tab.assign((size_t)nloc * nloc, 0);
+                marked.clear();
+                for (const auto& t : p->terms)
+                    for (int32_t i = t.elem_ptr[q]; i < t.elem_ptr[q + 1]; ++i) {
+                        const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                        for (int a = 0; a < t.ns; ++a)
+                            for (int b = a; b < t.ns; ++b) {
+                                // a block is (min, max) of its global vertices; first-seen local numbers do
+                                // not follow global order, so the pair is ordered by the global indices
+                                const int32_t r = std::min(st[a], st[b]), c = std::max(st[a], st[b]);
+                                const int32_t key = loc[r] * nloc + loc[c];
+                                if (!tab[key]) {
+                                    tab[key] = 1;
+                                    marked.push_back(key);
+                                }
+                            }
+                    }
+                nblocks = (int32_t)marked.size();
+                for (int32_t key : marked) tab[key] = 0;
+            } else {
+                keys.clear();
+                for (const auto& t : p->terms)
+                    for (int32_t i = t.elem_ptr[q]; i < t.elem_ptr[q + 1]; ++i) {
+                        const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                        for (int a = 0; a < t.ns; ++a)
+                            for (int b = a; b < t.ns; ++b)
+                                keys.push_back((int64_t)std::min(st[a], st[b]) * nv + std::max(st[a], st[b]));
+                    }
+                std::sort(keys.begin(), keys.end());
+                nblocks = (int32_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
+            }
+            for (int32_t v : verts) loc[v] = -1;
+            mv = std::max(mv, nloc);
+            mb = std::max(mb, nblocks);
         }
         mv_t[th] = mv;
         mb_t[th] = mb;

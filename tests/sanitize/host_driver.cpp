@@ -245,7 +245,7 @@ static void check_problem(const MeshIn& in, int target) {
 
 int main() {
     for (const MeshIn& m : meshes())
-        for (int target : {1, 7, 64, 384}) check_problem(m, target);
+        for (int target : {1, 7, 64, 384, 3000}) check_problem(m, target);
     std::printf("host runtime checks passed\n");
     return 0;
 }
