@@ -72,6 +72,7 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         H.s_out = t.mlp->s_out;
         H.xh = sc.xh[ti];
         H.psi = sc.psi[ti];
+        H.n_cu = p->n_cu;
         MAD_HIP_TRY(launch_mlp_head(H, s));
     }
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[2], s));

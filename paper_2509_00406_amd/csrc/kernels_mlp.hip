@@ -5,13 +5,14 @@
 //
 // Network pass. Forward mode is seeded on the six (scaled) features: layer 1's
 // unit k carries, in closed form, sp(a1) and its first derivatives
-// sigma(a1) W1[k,i] (second derivatives sigma'(a1) W1[k,i] W1[k,j]). Layer 2
-// is a dense contraction over 64 units for every (triangle, channel) column and
-// runs on the matrix cores (v_mfma_f32_16x16x32_bf16), as does the transposed
-// contraction u = W2^T v that folds layer 2's second-order channels into one
-// (see k_mlp_head). W2 is BF16 exactly; every activation is split into three
-// BF16 terms (hi + mid + lo carries all 24 bits of an FP32 significand), so
-// the three MFMAs per tile reproduce FP32 products with FP32 accumulation.
+// sigma(a1) W1[k,i] (second derivatives sigma'(a1) W1[k,i] W1[k,j]). Layer 2's
+// value and first-order channels, the transposed contraction u = W2^T v that
+// folds layer 2's second-order channels into one, and the layer-1 part of the
+// second derivatives are contractions over the 64 units and run on the matrix
+// cores (v_mfma_f32_16x16x32_bf16; see k_mlp_head). Weights and products of
+// two weights are exact in one or two BF16 terms; every activation is split
+// into three BF16 terms (hi + mid + lo carries all 24 bits of an FP32
+// significand), so the MFMAs reproduce FP32 products with FP32 accumulation.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -149,36 +150,84 @@ __device__ __forceinline__ void split3(float v, bf16x8& h, bf16x8& m, bf16x8& l,
 // u = W2^T v, the network's derivatives with respect to the scaled features xh are
 //   dpsi/dxh_i        = sum_k u_k sigma(a1_k) W1[k,i]
 //   d2psi/dxh_i dxh_j = sum_k u_k sigma'(a1_k) W1[k,i] W1[k,j] + sum_m w3_m sigma'(a2_m) g_mi g_mj,
-// g_mi = sum_k W2[m,k] sigma(a1_k) W1[k,i] (layer 2's first-order channels). So the matrix cores
-// run seven forward channels (value and g_i: a2 = W2 [sp(a1) | sigma(a1) W1]) and one transposed
-// contraction (u = W2^T v); the rest is per-triangle VALU work.
-// Layouts (16x16x32 MFMA): B operand lane l holds column l % 16 (a triangle) and hidden units
-// k = 32 ks + 8 (l / 16) + j; accumulators hold rows 4 (l / 16) + jj of each 16-row tile.
+// g_mi = sum_k W2[m,k] sigma(a1_k) W1[k,i] (layer 2's first-order channels). Three groups of contractions run
+// on the matrix cores (v_mfma_f32_16x16x32_bf16):
+//   a2 - b2 = W2 sp(a1), g_i = W2 (sigma(a1) W1[:,i])   W2 exact in BF16 (held in registers as the A operand),
+//                                                      the seven activation channels in three BF16 terms;
+//   u = W2^T v                                         v in three BF16 terms, W2^T read from LDS;
+//   S1[t,q] = sum_k (u sigma') C[k,q]                  C[k,q] = W1[k,i_q] W1[k,j_q] over the 21 packed pairs, a
+//                                                      product of two BF16 values (16 significant bits: exactly
+//                                                      two BF16 terms), built once per workgroup in LDS; u sigma'
+//                                                      in three terms: the layer-1 part of the second derivatives.
+// A product of three-term by two-term operands drops only the lo x lo part (2^-24 relative), so every
+// contraction reproduces FP32 products with FP32 accumulation. The layer-2 part of the second derivatives (a
+// rank-6 sum per triangle) and the first derivatives are per-triangle VALU work. (Moving the six first-order
+// channels to constant operands G_i = W2 diag(W1[:,i]) in LDS, split once, cut the VALU instructions by a
+// quarter but ran slower: at one wave per SIMD the extra MFMA chains and LDS reads were not hidden.)
+// Layouts (16x16x32 MFMA): B operand lane l holds column l % 16 and k = 32 ks + 8 (l / 16) + j; A operand lane
+// l holds row l % 16 and the same k; accumulators hold rows 4 (l / 16) + jj of column l % 16.
 constexpr int kHeadWaves = 4;
+constexpr int kLdsRow = kHid + 8;   // BF16 row stride of the LDS operand tables (144 B: 16-byte reads spread over banks)
+
+struct HeadSmem {   // byte offsets into the network pass's dynamic LDS
+    static constexpr int w1 = 0;                                   // float [64][6]
+    static constexpr int b1 = w1 + kHid * 6 * 4;                   // float [64]
+    static constexpr int b2 = b1 + kHid * 4;
+    static constexpr int w3 = b2 + kHid * 4;
+    static constexpr int w2t = w3 + kHid * 4;                      // bf16 [k][kLdsRow]: W2 transposed
+    static constexpr int c = w2t + kHid * kLdsRow * 2;             // bf16 [2][32][kLdsRow]: C hi, lo (q >= 21: 0)
+    static constexpr int t = c + 2 * 32 * kLdsRow * 2;             // float [waves][16][kHid + 1]
+    static constexpr int bytes = t + kHeadWaves * 16 * (kHid + 1) * 4;
+};
+static_assert(HeadSmem::w2t % 16 == 0 && HeadSmem::c % 16 == 0 && HeadSmem::t % 16 == 0,
+              "16-byte LDS operand reads");
+static_assert(HeadSmem::bytes <= 160 * 1024, "network pass LDS fits a CU");
+
+// a product of two BF16 values (exact in FP32) as hi + lo BF16 terms, both exact
+__device__ __forceinline__ void split2_exact(float p, uint16_t& hi, uint16_t& lo) {
+    hi = f2bf(p);
+    lo = f2bf(p - bf2f(hi));
+}
+
+__device__ __forceinline__ bf16x8 lds_bf16x8(const uint16_t* p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const short8*>(p));
+}
 
 __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
-    __shared__ float sW1[kHid * 6], sB1[kHid], sB2[kHid], sW3[kHid];
-    __shared__ uint16_t sW2[kHid * kHid];
-    __shared__ float sT[kHeadWaves][16][kHid + 1];   // per wave: v, then u, as [triangle][unit]
+    extern __shared__ __align__(16) unsigned char head_smem[];
+    float* sW1 = reinterpret_cast<float*>(head_smem + HeadSmem::w1);
+    float* sB1 = reinterpret_cast<float*>(head_smem + HeadSmem::b1);
+    float* sB2 = reinterpret_cast<float*>(head_smem + HeadSmem::b2);
+    float* sW3 = reinterpret_cast<float*>(head_smem + HeadSmem::w3);
+    uint16_t* sW2T = reinterpret_cast<uint16_t*>(head_smem + HeadSmem::w2t);
+    uint16_t* sC = reinterpret_cast<uint16_t*>(head_smem + HeadSmem::c);
     for (int i = threadIdx.x; i < kHid * 6; i += blockDim.x) sW1[i] = bf2f(L.wbf[kOffW1 + i]);
-    for (int i = threadIdx.x; i < kHid * kHid; i += blockDim.x) sW2[i] = L.wbf[kOffW2 + i];
     for (int i = threadIdx.x; i < kHid; i += blockDim.x) {
         sB1[i] = bf2f(L.wbf[kOffB1 + i]);
         sB2[i] = bf2f(L.wbf[kOffB2 + i]);
         sW3[i] = bf2f(L.wbf[kOffW3 + i]);
     }
+    for (int idx = threadIdx.x; idx < kHid * kHid; idx += blockDim.x)
+        sW2T[(idx % kHid) * kLdsRow + idx / kHid] = L.wbf[kOffW2 + idx];
+    for (int idx = threadIdx.x; idx < 32 * kHid; idx += blockDim.x) {
+        const int q = idx / kHid, k = idx % kHid;
+        const float p = q < 21 ? bf2f(L.wbf[kOffW1 + k * 6 + pair_i(q)]) * bf2f(L.wbf[kOffW1 + k * 6 + pair_j(q)]) : 0.0f;
+        uint16_t hi, lo;
+        split2_exact(p, hi, lo);
+        sC[(0 * 32 + q) * kLdsRow + k] = hi;
+        sC[(1 * 32 + q) * kLdsRow + k] = lo;
+    }
     __syncthreads();
     const float b3 = bf2f(L.wbf[kOffB3]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
-    float (*T)[kHid + 1] = sT[wave];
-    // A operand: W2 rows m = 16 mt + col, k = 32 ks + 8 g + j
+    float (*T)[kHid + 1] = reinterpret_cast<float (*)[kHid + 1]>(head_smem + HeadSmem::t) + wave * 16;
+    // A operand of channel 0: W2 rows m = 16 mt + col, k = 32 ks + 8 g + j (16-byte global reads)
     short8 A[4][2];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) A[mt][ks][j] = (short)sW2[(16 * mt + col) * kHid + 32 * ks + 8 * g + j];
+            A[mt][ks] = *reinterpret_cast<const short8*>(L.wbf + kOffW2 + (16 * mt + col) * kHid + 32 * ks + 8 * g);
     const int64_t tiles = (L.n + 15) / 16;
     for (int64_t tile = (int64_t)blockIdx.x * kHeadWaves + wave; tile < tiles;
          tile += (int64_t)gridDim.x * kHeadWaves) {
@@ -187,7 +236,7 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
         float xh[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) xh[i] = valid ? L.xh[(int64_t)i * L.n + e] : 0.0f;
-        // layer 1 at this lane's 16 units (B layout); sp(a1) goes straight into channel 0's operands
+        // layer 1 at this lane's 16 units (B layout): sp(a1) and sigma(a1), each split into three BF16 terms
         float s1[2][8];
         bf16x8 b0h[2], b0m[2], b0l[2];
 #pragma unroll
@@ -203,30 +252,40 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
                 s1[ks][j] = sg;
                 split3(sp, b0h[ks], b0m[ks], b0l[ks], j);
             }
-        // layer 2, seven forward channels: c = 0 value, c = 1 + i first derivative along xh_i
+        // channel 0: the value through layer 2
         float P0 = 0.0f, PH[21];
 #pragma unroll
         for (int q = 0; q < 21; ++q) PH[q] = 0.0f;
         float v[4][4], ws2p[4][4], a2g[6][4][4];
 #pragma unroll
-        for (int c = 0; c < 7; ++c) {
-            bf16x8 bh[2], bm[2], bl[2];
-            if (c == 0) {
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-                for (int ks = 0; ks < 2; ++ks) {
-                    bh[ks] = b0h[ks];
-                    bm[ks] = b0m[ks];
-                    bl[ks] = b0l[ks];
-                }
-            } else {
-#pragma unroll
-                for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int k = 32 * ks + 8 * g + j;
-                        split3(s1[ks][j] * sW1[k * 6 + c - 1], bh[ks], bm[ks], bl[ks], j);
-                    }
+            for (int ks = 0; ks < 2; ++ks) {
+                const bf16x8 a = __builtin_bit_cast(bf16x8, A[mt][ks]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0h[ks], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0m[ks], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0l[ks], acc, 0, 0, 0);
             }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int m = 16 * mt + 4 * g + jj;
+                const float a2 = acc[jj] + sB2[m];
+                float sp, sg;
+                softplus_logistic(a2, sp, sg);
+                v[mt][jj] = sW3[m] * sg;
+                ws2p[mt][jj] = sW3[m] * sg * (1.0f - sg);
+                P0 = fmaf(sW3[m], sp, P0);
+            }
+        }
+        // channels 1..6: g_i = W2 (sigma(a1) W1[:,i]), the B operand split per channel
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            bf16x8 bh[2], bm[2], bl[2];
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) split3(s1[ks][j] * sW1[(32 * ks + 8 * g + j) * 6 + i], bh[ks], bm[ks], bl[ks], j);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -238,19 +297,7 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
                     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[ks], acc, 0, 0, 0);
                 }
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int m = 16 * mt + 4 * g + jj;
-                    if (c == 0) {
-                        const float a2 = acc[jj] + sB2[m];
-                        float sp, sg;
-                        softplus_logistic(a2, sp, sg);
-                        v[mt][jj] = sW3[m] * sg;
-                        ws2p[mt][jj] = sW3[m] * sg * (1.0f - sg);
-                        P0 = fmaf(sW3[m], sp, P0);
-                    } else {
-                        a2g[c - 1][mt][jj] = acc[jj];
-                    }
-                }
+                for (int jj = 0; jj < 4; ++jj) a2g[i][mt][jj] = acc[jj];
             }
         }
         // second-order part through layer 2's nonlinearity: sum_m w3 sigma'(a2) g_mi g_mj
@@ -282,10 +329,8 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
             U[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
-                short8 wb;   // B operand: W2[m][k], m = 32 ks + 8 g + j, k = 16 nt + col
-#pragma unroll
-                for (int j = 0; j < 8; ++j) wb[j] = (short)sW2[(32 * ks + 8 * g + j) * kHid + 16 * nt + col];
-                const bf16x8 b = __builtin_bit_cast(bf16x8, wb);
+                // B operand: W2[m][k], m = 32 ks + 8 g + j, k = 16 nt + col (a row of W2^T)
+                const bf16x8 b = lds_bf16x8(sW2T + (16 * nt + col) * kLdsRow + 32 * ks + 8 * g);
                 U[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vh[ks], b, U[nt], 0, 0, 0);
                 U[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vm[ks], b, U[nt], 0, 0, 0);
                 U[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vl[ks], b, U[nt], 0, 0, 0);
@@ -297,29 +342,37 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) T[4 * g + jj][16 * nt + col] = U[nt][jj];
         wave_sync();
-        // first derivatives and the layer-1 part of the second, over this lane's 16 units
+        // first derivatives over this lane's 16 units; u sigma' split as the A operand of the layer-1
+        // second-order contraction (rows = triangles, the same lane distribution as the B layout)
         float Pg[6] = {0, 0, 0, 0, 0, 0};
+        bf16x8 uh[2], um[2], ul[2];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = 32 * ks + 8 * g + j;
                 const float u = T[col][k];
-                const float us = u * s1[ks][j], usp = us * (1.0f - s1[ks][j]);
-                float w[6];
+                const float us = u * s1[ks][j];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) {
-                    w[i] = sW1[k * 6 + i];
-                    Pg[i] = fmaf(us, w[i], Pg[i]);
-                }
-#pragma unroll
-                for (int i = 0; i < 6; ++i) {
-                    const float t = usp * w[i];
-#pragma unroll
-                    for (int j2 = i; j2 < 6; ++j2) PH[Packed<6>::at(i, j2)] = fmaf(t, w[j2], PH[Packed<6>::at(i, j2)]);
-                }
+                for (int i = 0; i < 6; ++i) Pg[i] = fmaf(us, sW1[k * 6 + i], Pg[i]);
+                split3(us * (1.0f - s1[ks][j]), uh[ks], um[ks], ul[ks], j);
             }
-        wave_sync();   // u is read before the next tile writes v
+        f32x4 S1[2];
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            S1[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const uint16_t* crow = sC + (16 * nt + col) * kLdsRow + 32 * ks + 8 * g;
+                const bf16x8 ch = lds_bf16x8(crow), cl = lds_bf16x8(crow + 32 * kLdsRow);
+                S1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ks], ch, S1[nt], 0, 0, 0);
+                S1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(um[ks], ch, S1[nt], 0, 0, 0);
+                S1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ul[ks], ch, S1[nt], 0, 0, 0);
+                S1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(uh[ks], cl, S1[nt], 0, 0, 0);
+                S1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(um[ks], cl, S1[nt], 0, 0, 0);
+            }
+        }
+        wave_sync();   // u is read before the layer-2 second derivatives overwrite it
         // sum over the four lanes holding the same triangle
         P0 += __shfl_xor(P0, 16);
         P0 += __shfl_xor(P0, 32);
@@ -333,15 +386,33 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
             PH[q] += __shfl_xor(PH[q], 16);
             PH[q] += __shfl_xor(PH[q], 32);
         }
+        if (g == 0) {
+#pragma unroll
+            for (int q = 0; q < 21; ++q) T[col][q] = PH[q];
+        }
         if (valid && g == 0) {
             // back to z: dpsi/dz_i = s_out s_in[i] dpsi/dxh_i, likewise for the second derivatives
             L.psi[e] = L.s_out * (P0 + b3);
 #pragma unroll
             for (int i = 0; i < 6; ++i) L.psi[(int64_t)(1 + i) * L.n + e] = L.s_out * L.s_in[i] * Pg[i];
-#pragma unroll
-            for (int q = 0; q < 21; ++q)
-                L.psi[(int64_t)(7 + q) * L.n + e] = L.s_out * L.s_in[pair_i(q)] * L.s_in[pair_j(q)] * PH[q];
         }
+        wave_sync();
+        // second derivatives: the layer-1 part (S1 rows = triangles 4 g + jj, column q = 16 nt + col) plus
+        // the layer-2 part from LDS
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            const int q = 16 * nt + col;
+            if (q < 21) {
+                const float sc = L.s_out * L.s_in[pair_i(q)] * L.s_in[pair_j(q)];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int t = 4 * g + jj;
+                    const int64_t et = tile * 16 + t;
+                    if (et < L.n) L.psi[(int64_t)(7 + q) * L.n + et] = sc * (S1[nt][jj] + T[t][q]);
+                }
+            }
+        }
+        wave_sync();   // the layer-2 part is read before the next tile writes v
     }
 }
 
@@ -361,8 +432,8 @@ hipError_t launch_mlp_head(const MlpHeadLaunch& L, hipStream_t s) {
         hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)blocks), dim3(256), 0, s, L);
     }
     const int64_t tiles = (L.n + 15) / 16;
-    const int64_t blocks = std::min<int64_t>((tiles + kHeadWaves - 1) / kHeadWaves, 2048);
-    hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)blocks), dim3(kHeadWaves * 64), 0, s, L);
+    const int64_t blocks = std::min<int64_t>((tiles + kHeadWaves - 1) / kHeadWaves, std::max(L.n_cu, 1));
+    hipLaunchKernelGGL(k_mlp_head, dim3((unsigned)blocks), dim3(kHeadWaves * 64), HeadSmem::bytes, s, L);
     return hipGetLastError();
 }
 

@@ -31,6 +31,8 @@ struct MlpHeadLaunch {
     float s_out;
     float* xh;                // SoA [6][n] scaled features s_in * z (written by the feature pass)
     float* psi;               // SoA [28][n]
+    int32_t n_cu;             // compute units: the network pass runs at most one workgroup per CU (its registers
+                              // allow one wave per SIMD; its LDS operand tables are built once per workgroup)
 };
 // feature pass (one lane per triangle, FP64 features rounded to FP32 and scaled), then the
 // network pass reading them
