@@ -43,7 +43,7 @@ sys.path.insert(0, ROOT)
 # passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
 FLOPS_PER_ELEM = {"f32": 14925.0, "f64": None}
 # traffic by launch (persistent queue / one workgroup per patch) at the default 384-face layout
-TRAFFIC_BYTES = {"f32": {1: 1.2522e9, 0: 1.0360e9}, "f64": None}
+TRAFFIC_BYTES = {"f32": {1: 1.2745e9, 0: 1.0360e9}, "f64": None}
 # the same for the 1000^2 cloth step at its default layout (profiles/k_eval_patch_f32_cloth1000_counters.md)
 CLOTH_TRAFFIC_BYTES = {"f32": 0.5687e9, "f64": None}
 # and for the 1001^2 symmetric Dirichlet parameterisation at its default layout (512-face patches, persistent
