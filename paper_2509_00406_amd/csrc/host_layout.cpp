@@ -2,6 +2,7 @@
 // the colour order inside patches, the largest patch's LDS working set and the segments of the patch
 // kernel's work units. Threaded over patches; layout.cpp uploads the results.
 #include <algorithm>
+#include <functional>
 #include <numeric>
 #include <thread>
 
@@ -57,7 +58,7 @@ void color_within_patches(Term& t, int64_t nv) {
 void order_terms(mad_problem* p) {
     const mad_mesh& m = *p->mesh;
     const int32_t np = p->patches.n;
-    for (auto& t : p->terms) {
+    auto one = [&](Term& t) {
         std::vector<int32_t> key((size_t)t.n);
         for (int64_t e = 0; e < t.n; ++e) {
             if (t.kind == MAD_BENDING) key[e] = m.diamond_faces[2 * e];
@@ -77,7 +78,12 @@ void order_terms(mad_problem* p) {
         std::vector<int32_t> fill(t.elem_ptr.begin(), t.elem_ptr.end() - 1);
         t.perm.resize((size_t)t.n);
         for (int32_t e : byface) t.perm[fill[p->patches.face_patch[key[e]]]++] = e;
-    }
+    };
+    // terms are independent: one thread each
+    std::vector<std::thread> pool;
+    for (size_t i = 1; i < p->terms.size(); ++i) pool.emplace_back(one, std::ref(p->terms[i]));
+    if (!p->terms.empty()) one(p->terms[0]);
+    for (auto& th : pool) th.join();
 }
 
 // largest per-patch vertex and upper-block counts of the current patching (patches split over threads)
@@ -163,24 +169,33 @@ void patch_extent(const mad_problem* p, int32_t* max_lv, int32_t* max_lb) {
 // segments.
 void unit_segments(const Term& t, int32_t np, int64_t nv, std::vector<uint8_t>& seg) {
     seg.assign((size_t)std::max<int64_t>(t.n, 1), 0);
-    std::vector<uint64_t> used((size_t)nv, 0);   // segments of the current unit using the vertex
-    for (int32_t q = 0; q < np; ++q)
-        for (int32_t u0 = t.elem_ptr[q]; u0 < t.elem_ptr[q + 1]; u0 += 64) {
-            const int32_t u1 = std::min(u0 + 64, t.elem_ptr[q + 1]);
-            for (int32_t i = u0; i < u1; ++i) {
-                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                uint64_t busy = 0;
-                for (int a = 0; a < t.ns; ++a) busy |= used[st[a]];
-                int sg = 0;
-                while ((busy >> sg) & 1ull) ++sg;   // at most 63: a unit has 64 elements
-                seg[i] = (uint8_t)sg;
-                for (int a = 0; a < t.ns; ++a) used[st[a]] |= 1ull << sg;
+    // units are independent: patches split over threads, each with its own vertex bit array
+    auto work = [&](int32_t q0, int32_t q1) {
+        std::vector<uint64_t> used((size_t)nv, 0);   // segments of the current unit using the vertex
+        for (int32_t q = q0; q < q1; ++q)
+            for (int32_t u0 = t.elem_ptr[q]; u0 < t.elem_ptr[q + 1]; u0 += 64) {
+                const int32_t u1 = std::min(u0 + 64, t.elem_ptr[q + 1]);
+                for (int32_t i = u0; i < u1; ++i) {
+                    const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                    uint64_t busy = 0;
+                    for (int a = 0; a < t.ns; ++a) busy |= used[st[a]];
+                    int sg = 0;
+                    while ((busy >> sg) & 1ull) ++sg;   // at most 63: a unit has 64 elements
+                    seg[i] = (uint8_t)sg;
+                    for (int a = 0; a < t.ns; ++a) used[st[a]] |= 1ull << sg;
+                }
+                for (int32_t i = u0; i < u1; ++i) {
+                    const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
+                    for (int a = 0; a < t.ns; ++a) used[st[a]] = 0;
+                }
             }
-            for (int32_t i = u0; i < u1; ++i) {
-                const int32_t* st = &t.stencil[(int64_t)t.perm[i] * t.ns];
-                for (int a = 0; a < t.ns; ++a) used[st[a]] = 0;
-            }
-        }
+    };
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int w = 1; w < nth; ++w)
+        pool.emplace_back(work, (int32_t)((int64_t)np * w / nth), (int32_t)((int64_t)np * (w + 1) / nth));
+    work(0, (int32_t)((int64_t)np / nth));
+    for (auto& th : pool) th.join();
 }
 
 // Colored scatter (the coloring alternative of Sec. 5.5). Each term's elements are colored greedily in

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <deque>
 #include <numeric>
+#include <thread>
 
 #include "mad_internal.hpp"
 
@@ -51,82 +52,139 @@ int kind_nrest(int kind) {
 // edge is directed in the lower-indexed face f1, v2 opposite in f1, v3 opposite in f2.
 int build_topology(mad_mesh& m) {
     // edge-sides as corner ids c = 3 f + k: the side from tris[c] to the next corner of face f,
-    // opposite the remaining corner
-    const int64_t nr = 3 * m.nt;
+    // opposite the remaining corner. Every step is split over threads; the results do not depend on
+    // their number.
+    const int64_t nr = 3 * m.nt, nv = m.nv;
     const int32_t* T = m.tris.data();
-    auto from = [&](int64_t c) { return T[c]; };
     auto to = [&](int64_t c) { return T[c - c % 3 + (c % 3 + 1) % 3]; };
     auto opp = [&](int64_t c) { return T[c - c % 3 + (c % 3 + 2) % 3]; };
-    auto lo = [&](int64_t c) { return std::min(from(c), to(c)); };
-    auto hi = [&](int64_t c) { return std::max(from(c), to(c)); };
-    // order by (lo, hi, face): a counting sort by lo (ids are generated in face order, so each
-    // bucket keeps ascending faces), then an insertion sort by hi inside each bucket (a vertex's
-    // bucket holds a handful of sides)
-    std::vector<int32_t> rec((size_t)nr);
-    {
-        std::vector<int64_t> start((size_t)m.nv + 1, 0);
-        for (int64_t c = 0; c < nr; ++c) ++start[(size_t)lo(c) + 1];
-        for (int64_t v = 0; v < m.nv; ++v) start[v + 1] += start[v];
-        std::vector<int64_t> fill(start.begin(), start.end() - 1);
-        for (int64_t c = 0; c < nr; ++c) rec[(size_t)fill[lo(c)]++] = (int32_t)c;
-        for (int64_t v = 0; v < m.nv; ++v)
-            for (int64_t a = start[v] + 1; a < start[v + 1]; ++a) {
-                const int32_t x = rec[(size_t)a];
-                const int32_t hx = hi(x);
-                int64_t b = a;
-                while (b > start[v] && hi(rec[(size_t)b - 1]) > hx) {
-                    rec[(size_t)b] = rec[(size_t)b - 1];
-                    --b;
-                }
-                rec[(size_t)b] = x;
-            }
-    }
-    m.edges.clear();
-    m.edge_nf.clear();
-    m.edge_face0.clear();
-    m.diamonds.clear();
-    m.diamond_faces.clear();
-    std::vector<int32_t> deg((size_t)m.nt, 0);
-    std::vector<std::pair<int32_t, int32_t>> links;
-    // a closed manifold has 3T/2 edges, each interior one a diamond and a face link
-    m.edges.reserve((size_t)nr + 2);
-    m.edge_nf.reserve((size_t)nr / 2 + 1);
-    m.edge_face0.reserve((size_t)nr / 2 + 1);
-    m.diamonds.reserve((size_t)nr * 2);
-    m.diamond_faces.reserve((size_t)nr);
-    links.reserve((size_t)nr / 2 + 1);
-    for (int64_t i = 0; i < nr;) {
-        const int32_t li = lo(rec[i]), hi_i = hi(rec[i]);
-        int64_t j = i;
-        while (j < nr && lo(rec[j]) == li && hi(rec[j]) == hi_i) ++j;
-        const int32_t f0 = rec[i] / 3;
-        m.edges.push_back(li);
-        m.edges.push_back(hi_i);
-        m.edge_nf.push_back((int32_t)(j - i));
-        m.edge_face0.push_back(f0);
-        if (j - i == 2) {
-            m.diamonds.insert(m.diamonds.end(), {from(rec[i]), to(rec[i]), opp(rec[i]), opp(rec[i + 1])});
-            m.diamond_faces.insert(m.diamond_faces.end(), {f0, rec[i + 1] / 3});
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto parallel = [&](int64_t n, auto&& fn) {   // fn(i0, i1) over nth contiguous ranges of [0, n)
+        std::vector<std::thread> pool;
+        for (int w = 1; w < nth; ++w) pool.emplace_back(fn, n * w / nth, n * (w + 1) / nth);
+        fn((int64_t)0, n / nth);
+        for (auto& th : pool) th.join();
+    };
+    // each side's (lo, hi) vertex pair, and the sides bucketed by lo
+    std::vector<int32_t> side_lo((size_t)nr), side_hi((size_t)nr), cnt((size_t)nv + 1, 0);
+    parallel(nr, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            const int32_t a = T[c], b = to(c);
+            side_lo[c] = std::min(a, b);
+            side_hi[c] = std::max(a, b);
+            __atomic_fetch_add(&cnt[(size_t)side_lo[c] + 1], 1, __ATOMIC_RELAXED);
         }
-        for (int64_t a = i; a < j; ++a)
-            for (int64_t b = a + 1; b < j; ++b)
-                if (rec[a] / 3 != rec[b] / 3) links.push_back({rec[a] / 3, rec[b] / 3});
-        i = j;
+    });
+    std::vector<int64_t> start((size_t)nv + 1, 0);
+    for (int64_t v = 0; v < nv; ++v) start[v + 1] = start[v] + cnt[v + 1];
+    std::vector<int64_t> cursor(start.begin(), start.end() - 1);
+    std::vector<int32_t> rec((size_t)nr);
+    parallel(nr, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c)
+            rec[(size_t)__atomic_fetch_add(&cursor[side_lo[c]], 1, __ATOMIC_RELAXED)] = (int32_t)c;
+    });
+    // inside each bucket by (hi, side): an insertion sort (a vertex's bucket holds a handful of sides);
+    // then per vertex the count of its edges (runs of equal hi), diamonds (runs of two) and face links
+    std::vector<int64_t> ne_v((size_t)nv + 1, 0), nd_v((size_t)nv + 1, 0), nl_v((size_t)nv + 1, 0);
+    parallel(nv, [&](int64_t v0, int64_t v1) {
+        for (int64_t v = v0; v < v1; ++v) {
+            const int64_t b = start[v], e = start[v + 1];
+            for (int64_t a = b + 1; a < e; ++a) {
+                const int32_t x = rec[(size_t)a];
+                const int32_t hx = side_hi[x];
+                int64_t k = a;
+                while (k > b && (side_hi[rec[(size_t)k - 1]] > hx || (side_hi[rec[(size_t)k - 1]] == hx && rec[(size_t)k - 1] > x))) {
+                    rec[(size_t)k] = rec[(size_t)k - 1];
+                    --k;
+                }
+                rec[(size_t)k] = x;
+            }
+            int64_t ne = 0, nd = 0, nl = 0;
+            for (int64_t i = b; i < e;) {
+                int64_t j = i;
+                while (j < e && side_hi[rec[(size_t)j]] == side_hi[rec[(size_t)i]]) ++j;
+                ++ne;
+                if (j - i == 2) ++nd;
+                for (int64_t a = i; a < j; ++a)
+                    for (int64_t c = a + 1; c < j; ++c)
+                        if (rec[(size_t)a] / 3 != rec[(size_t)c] / 3) ++nl;
+                i = j;
+            }
+            ne_v[v + 1] = ne;
+            nd_v[v + 1] = nd;
+            nl_v[v + 1] = nl;
+        }
+    });
+    for (int64_t v = 0; v < nv; ++v) {
+        ne_v[v + 1] += ne_v[v];
+        nd_v[v + 1] += nd_v[v];
+        nl_v[v + 1] += nl_v[v];
     }
-    // face adjacency CSR
-    for (auto& l : links) {
-        ++deg[l.first];
-        ++deg[l.second];
-    }
+    const int64_t ne = ne_v[nv], nd = nd_v[nv], nl = nl_v[nv];
+    m.edges.assign((size_t)ne * 2, 0);
+    m.edge_nf.assign((size_t)ne, 0);
+    m.edge_face0.assign((size_t)ne, 0);
+    m.diamonds.assign((size_t)nd * 4, 0);
+    m.diamond_faces.assign((size_t)nd * 2, 0);
+    std::vector<int32_t> links((size_t)nl * 2);
+    // edges sorted by (lo, hi); per edge its sides in ascending face order: the first face is the lowest. An
+    // edge with exactly two sides is a diamond, directed as in its lower face
+    parallel(nv, [&](int64_t v0, int64_t v1) {
+        for (int64_t v = v0; v < v1; ++v) {
+            int64_t oe = ne_v[v], od = nd_v[v], ol = nl_v[v];
+            const int64_t b = start[v], e = start[v + 1];
+            for (int64_t i = b; i < e;) {
+                const int32_t ci = rec[(size_t)i];
+                int64_t j = i;
+                while (j < e && side_hi[rec[(size_t)j]] == side_hi[ci]) ++j;
+                m.edges[2 * oe] = (int32_t)v;
+                m.edges[2 * oe + 1] = side_hi[ci];
+                m.edge_nf[oe] = (int32_t)(j - i);
+                m.edge_face0[oe] = ci / 3;
+                ++oe;
+                if (j - i == 2) {
+                    const int32_t cj = rec[(size_t)i + 1];
+                    m.diamonds[4 * od] = T[ci];
+                    m.diamonds[4 * od + 1] = to(ci);
+                    m.diamonds[4 * od + 2] = opp(ci);
+                    m.diamonds[4 * od + 3] = opp(cj);
+                    m.diamond_faces[2 * od] = ci / 3;
+                    m.diamond_faces[2 * od + 1] = cj / 3;
+                    ++od;
+                }
+                for (int64_t a = i; a < j; ++a)
+                    for (int64_t c = a + 1; c < j; ++c)
+                        if (rec[(size_t)a] / 3 != rec[(size_t)c] / 3) {
+                            links[2 * ol] = rec[(size_t)a] / 3;
+                            links[2 * ol + 1] = rec[(size_t)c] / 3;
+                            ++ol;
+                        }
+                i = j;
+            }
+        }
+    });
+    // face adjacency CSR (rows sorted)
+    std::vector<int32_t> deg((size_t)m.nt, 0);
+    parallel(nl, [&](int64_t l0, int64_t l1) {
+        for (int64_t l = l0; l < l1; ++l) {
+            __atomic_fetch_add(&deg[links[2 * l]], 1, __ATOMIC_RELAXED);
+            __atomic_fetch_add(&deg[links[2 * l + 1]], 1, __ATOMIC_RELAXED);
+        }
+    });
     m.fadj_ptr.assign((size_t)m.nt + 1, 0);
     for (int64_t f = 0; f < m.nt; ++f) m.fadj_ptr[f + 1] = m.fadj_ptr[f] + deg[f];
     m.fadj.assign((size_t)m.fadj_ptr[m.nt], 0);
     std::vector<int32_t> cur(m.fadj_ptr.begin(), m.fadj_ptr.end() - 1);
-    for (auto& l : links) {
-        m.fadj[cur[l.first]++] = l.second;
-        m.fadj[cur[l.second]++] = l.first;
-    }
-    for (int64_t f = 0; f < m.nt; ++f) std::sort(m.fadj.begin() + m.fadj_ptr[f], m.fadj.begin() + m.fadj_ptr[f + 1]);
+    parallel(nl, [&](int64_t l0, int64_t l1) {
+        for (int64_t l = l0; l < l1; ++l) {
+            const int32_t f = links[2 * l], g = links[2 * l + 1];
+            m.fadj[__atomic_fetch_add(&cur[f], 1, __ATOMIC_RELAXED)] = g;
+            m.fadj[__atomic_fetch_add(&cur[g], 1, __ATOMIC_RELAXED)] = f;
+        }
+    });
+    parallel(m.nt, [&](int64_t f0, int64_t f1) {
+        for (int64_t f = f0; f < f1; ++f) std::sort(m.fadj.begin() + m.fadj_ptr[f], m.fadj.begin() + m.fadj_ptr[f + 1]);
+    });
     // lowest face of every vertex (places a vertex term's element in that face's patch)
     m.vert_face0.assign((size_t)m.nv, -1);
     for (int64_t f = m.nt - 1; f >= 0; --f)
