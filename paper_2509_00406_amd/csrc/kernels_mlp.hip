@@ -221,7 +221,8 @@ __global__ __launch_bounds__(kHeadWaves * 64) void k_mlp_head(MlpHeadLaunch L) {
     const float b3 = bf2f(L.wbf[kOffB3]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, col = lane & 15;
     float (*T)[kHid + 1] = reinterpret_cast<float (*)[kHid + 1]>(head_smem + HeadSmem::t) + wave * 16;
-    // A operand of channel 0: W2 rows m = 16 mt + col, k = 32 ks + 8 g + j (16-byte global reads)
+    // A operand (all seven forward channels): W2 rows m = 16 mt + col, k = 32 ks + 8 g + j, as 16-byte global
+    // reads (the BF16 parameters are their own allocation, and kOffW2 and every row start are multiples of 8)
     short8 A[4][2];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
