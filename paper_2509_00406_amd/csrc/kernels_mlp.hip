@@ -182,6 +182,7 @@ struct HeadSmem {   // byte offsets into the network pass's dynamic LDS
 static_assert(HeadSmem::w2t % 16 == 0 && HeadSmem::c % 16 == 0 && HeadSmem::t % 16 == 0,
               "16-byte LDS operand reads");
 static_assert(HeadSmem::bytes <= 160 * 1024, "network pass LDS fits a CU");
+static_assert(kOffW2 % 8 == 0 && kHid % 8 == 0, "16-byte reads of W2 rows from the BF16 parameters");
 
 // a product of two BF16 values (exact in FP32) as hi + lo BF16 terms, both exact
 __device__ __forceinline__ void split2_exact(float p, uint16_t& hi, uint16_t& lo) {
