@@ -94,3 +94,27 @@ def test_full_shell_stress_noise_fp32(full):
                                       STVK_PRM, BEND_PRM)
     assert abs(float(energy.cpu()[0]) - e_ref) <= 1e-5 * e_abs
     say(f"stress: worst grad {g:.2e} hess {h:.2e}; fp64 fallbacks {fallbacks}; nonfinite {nonfinite}")
+
+
+@pytest.mark.parametrize("scatter", ["atomic", "color"])
+def test_full_shell_other_scatters_fp32(full, scatter):
+    """The paper's device-wide atomic scatter and its coloring alternative at the benchmark size: sampled rows
+    against the oracle and the energy against the independent FP64 evaluation, FP32."""
+    import torch
+    from paper_2509_00406_amd import mad
+    inp, P, mask = full
+    say("full shell 1024 fp32, scatter", scatter)
+    sc = {"atomic": mad.SCATTER_ATOMIC, "color": mad.SCATTER_COLOR}[scatter]
+    mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, TERMS, 1, scatter=sc)
+    assert prob.layout()["scatter"] == sc
+    x = torch.from_numpy(inp.x.ravel().copy()).cuda()
+    energy, grad, hess = prob.eval(x, mad.ENERGY | mad.GRAD | mad.HESS | mad.SPD)
+    torch.cuda.synchronize()
+    nonfinite, fallbacks = prob.status()
+    assert not nonfinite
+    g, h, nb = sampled_compare(P, mask, inp.x, grad.cpu().numpy(), hess.cpu().numpy(), PR.RTOL[1])
+    e_ref, e_abs = npref.shell_energy(inp.tris, inp.rest, inp.x, P.topo.diamonds, P.topo.diamond_faces,
+                                      STVK_PRM, BEND_PRM)
+    e = float(energy.cpu()[0])
+    assert abs(e - e_ref) <= PR.RTOL[1] * e_abs, (e, e_ref, e_abs)
+    say(f"{scatter}: worst grad {g:.2e} hess {h:.2e} over {nb} blocks; fp64 fallbacks {fallbacks}")
