@@ -141,36 +141,36 @@ __device__ __forceinline__ void add_blocks(const PatchLaunch& L, const PatchTerm
     } else {
         for (int g = 0; g < nseg; ++g) {
             if (seg != g) continue;
-            // row by row of the stencil's pairs (s, t >= s): read the row's entries, then write them
-            // back summed
+            // row by row of the stencil's pairs (s, t >= s): read the row's blocks, then write them back
+            // summed. Each block is read and written at fixed offsets from its base, so the compiler pairs
+            // entries into two-address LDS instructions; a block stored as (c, r) (the transpose of the
+            // element's (s, t) block) receives the transpose of the element's values instead.
             int k0 = 0;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 T cur[NS][DD];
 #pragma unroll
                 for (int t = s; t < NS; ++t) {
-                    const int k = k0 + (t - s);
-                    const T* blk = sh + (int)(wv[k] & 0x3fffu) * DD;
-                    const bool tr = (wv[k] >> 14) == 1u;   // block stored as (c, r): the transpose
+                    const T* blk = sh + (int)(wv[k0 + (t - s)] & 0x3fffu) * DD;
 #pragma unroll
                     for (int c = 0; c < D; ++c)
 #pragma unroll
                         for (int c2 = 0; c2 < D; ++c2) {
                             if (s == t && c2 < c) continue;
-                            cur[t][c * D + c2] = blk[(s != t && tr) ? (c2 * D + c) : (c * D + c2)];
+                            cur[t][c * D + c2] = blk[c * D + c2];
                         }
                 }
 #pragma unroll
                 for (int t = s; t < NS; ++t) {
                     const int k = k0 + (t - s);
                     T* blk = sh + (int)(wv[k] & 0x3fffu) * DD;
-                    const bool tr = (wv[k] >> 14) == 1u;
+                    const bool tr = s != t && (wv[k] >> 14) == 1u;
 #pragma unroll
                     for (int c = 0; c < D; ++c)
 #pragma unroll
                         for (int c2 = 0; c2 < D; ++c2) {
                             if (s == t && c2 < c) continue;
-                            blk[(s != t && tr) ? (c2 * D + c) : (c * D + c2)] = cur[t][c * D + c2] + hv[k][c * D + c2];
+                            blk[c * D + c2] = cur[t][c * D + c2] + (tr ? hv[k][c2 * D + c] : hv[k][c * D + c2]);
                         }
                 }
                 k0 += NS - s;
