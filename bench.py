@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-sizes", action="store_true", help="cloth: skip the Table 1 size sweep")
     ap.add_argument("--no-hvp", action="store_true", help="shell: skip the matrix-free product timing")
     ap.add_argument("--no-dynamic", action="store_true", help="shell: skip the pair-insertion timing")
+    ap.add_argument("--no-jacobian", action="store_true", help="cloth: skip the residual Jacobian timing")
     ap.add_argument("--pairs", type=int, default=100000, help="interaction pairs inserted by the dynamic timing")
     ap.add_argument("--cpu-elements", type=int, default=300000, help="elements in the oracle timing sample")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
@@ -533,6 +534,8 @@ def main():
         res["one_launch_per_mesh"] = per_mesh_baseline(torch, mad, inp, prec, stream, ms_per_step, args)
     if args.workload == "cloth" and not args.no_sizes:
         res["table1_sizes"] = cloth_sizes(torch, mad, args, stream)
+    if args.workload == "cloth" and not args.no_jacobian:
+        res["residual_jacobian"] = residual_jacobian(torch, mad, args, prec, stream)
     if prec == mad.F32 and not args.no_fp64_plain:
         res["vs_fp64_plain"] = fp64_plain(torch, mad, mesh, inp, args, stream, x, out, ms_per_step)
     if not args.no_cpu_baseline:
@@ -582,6 +585,50 @@ def cpu_baseline_symdir(inp, budget):
 
 # Table 1 of the paper (RTX 4090, precision not stated): grad + Hessian ms per step by vertex count
 PAPER_TABLE1_MS = {10: 0.18, 50: 0.22, 100: 0.25, 500: 3.09, 1000: 11.7}
+
+
+def residual_jacobian(torch, mad, args, prec, stream):
+    """Residual terms and their sparse Jacobian (Eq. 3) on the cloth's grid: an edge-length residual on every
+    edge and a positional residual on every vertex (a quarter of them pulled toward targets, weight 0
+    elsewhere). Timed: the Jacobian (residuals r in FP64 and the row-owned CSR values J) and the Gauss-Newton
+    evaluation through the patch assembly (energy 1/2 |r|^2, gradient J^T r, Hessian J^T J)."""
+    import numpy as np
+    from paper_2509_00406_amd import meshgen
+    n = args.cloth_n
+    tris, rest = meshgen.grid(n)
+    rng = np.random.default_rng(7001)
+    x = rest + 0.05 * rng.normal(size=rest.shape)
+    vd = np.zeros((n * n, 4))
+    vd[:, 0] = rng.uniform(0.5, 2.0, n * n) * (rng.random(n * n) < 0.25)
+    vd[:, 1:] = rest + np.array([0.0, 0.0, 0.2]) + 0.05 * rng.normal(size=rest.shape)
+    mesh = mad.Mesh(tris, n * n)
+    prob = mad.Problem(mesh, 3, prec)
+    prob.add_term(mad.RES_EDGE, (3.0,), rest)
+    vdt = torch.from_numpy(np.ascontiguousarray(vd)).cuda()
+    prob.add_vertex_term(mad.RES_POSITION, (), vdt)
+    prob.finalize(stream)
+    xt = torch.from_numpy(x.ravel().copy()).cuda()
+    m, nnz = mad.mad_problem_jacobian_info(prob.handle)
+    pb = 4 if prec == mad.F32 else 8
+    r = torch.empty(m, dtype=torch.float64, device="cuda")
+    vals = torch.empty(max(nnz, 1), dtype=torch.float32 if prec == mad.F32 else torch.float64, device="cuda")
+    jac = lambda: mad.mad_problem_jacobian(prob.handle, xt, r, vals, stream)   # noqa: E731
+    jac_ms, _ = time_steps(torch, jac, 20, 3, stream)
+    out = prob.outputs()
+    gn = lambda: prob.eval(xt, mad.ENERGY | mad.GRAD | mad.HESS, out=out, stream=stream)   # noqa: E731
+    gn_ms, _ = time_steps(torch, gn, 20, 3, stream)
+    jms = float(np.median(jac_ms))
+    # algorithmic bytes of the Jacobian: x, edges, edge rest lengths and per-vertex (w, x_t) read once; r and the
+    # values written once (the row pointers and columns are fixed at setup)
+    ne, nv = mesh.n_edges, mesh.n_verts
+    jbytes = nv * 3 * 8 + ne * 2 * 4 + ne * 8 + nv * 4 * 8 + m * 8 + nnz * pb
+    return {"rows": m, "nnz": nnz, "edges": ne, "vertices": nv,
+            "ms_jacobian": jms, "alg_bytes": jbytes, "jacobian_GBs": jbytes / (jms * 1e-3) / 1e9,
+            "jacobian_hbm_frac": jbytes / (jms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "ms_gauss_newton_eval": float(np.median(gn_ms)),
+            "gauss_newton_elements_per_s": (ne + nv) / (float(np.median(gn_ms)) * 1e-3),
+            "note": "edge-length residuals on every edge + positional residuals on every vertex; the Gauss-Newton "
+                    "evaluation assembles J^T r and J^T J through the patch kernel"}
 
 
 def cloth_sizes(torch, mad, args, stream):

@@ -415,9 +415,8 @@ static int jac_launch(const mad_problem* p, JacLaunch& L, int64_t* m_out, int64_
         JacTerm& J = L.terms[L.n_terms++];
         J.kind = t.kind;
         J.n = t.n;
-        J.stencil = t.d_stencil;
-        J.perm = t.d_perm;
-        J.rest = t.d_rest;
+        J.stencil = t.d_jstencil;
+        J.rest = t.d_jrest;
         J.vdata = t.vdata;
         std::memcpy(J.prm, t.prm, sizeof(t.prm));
         J.row_off = m;

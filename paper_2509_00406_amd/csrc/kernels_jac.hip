@@ -12,12 +12,12 @@ template <class Term, typename T>
 __global__ __launch_bounds__(256) void k_jacobian(JacLaunch L, int t) {
     constexpr int NS = Term::NS, D = Term::D, KR = Term::KR, NF = NS * D, M = Term::NRES;
     const JacTerm& A = L.terms[t];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    const int64_t e = A.perm[i];
+    // one element per lane, in element order: consecutive lanes write consecutive rows
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.n) return;
     int vs[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) vs[s] = A.stencil[i * NS + s];
+    for (int s = 0; s < NS; ++s) vs[s] = A.stencil[e * NS + s];
     // stencil vertices in ascending order: the row's column order
     int ord[NS];
 #pragma unroll
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_jacobian(JacLaunch L, int t) {
             bad = bad || !finite(xs[s * D + c]);
         }
     double rest[n_inputs<Term>()];
-    gather_inputs<Term>(rest, A.rest, A.n, i, nullptr, vs, nullptr, A.vdata);
+    gather_inputs<Term>(rest, A.rest, A.n, e, nullptr, vs, nullptr, A.vdata);
     double r[KR];
     if constexpr (Term::TI) {
 #pragma unroll

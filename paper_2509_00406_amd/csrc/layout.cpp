@@ -40,7 +40,8 @@ static void free_layout(mad_problem* p) {
         t.d_lseg = nullptr;
         t.d_psi = nullptr;
         t.d_xh = nullptr;
-        t.d_perm = nullptr;
+        t.d_jstencil = nullptr;
+        t.d_jrest = nullptr;
         t.d_slot_map = nullptr;
     }
     p->d_color_comp_ptr = nullptr;
@@ -115,9 +116,16 @@ int build_layout(mad_problem* p, int target, int scatter, int persistent, hipStr
         if ((rc = upload_layout(p, (void**)&t.d_rest, rs.data(), rs.size() * 8, s)) != MAD_OK) return rc;
         if ((rc = upload_layout(p, (void**)&t.d_elem_ptr, t.elem_ptr.data(), t.elem_ptr.size() * 4, s)) != MAD_OK)
             return rc;
-        if (kind_nres(t.kind) > 0 &&
-            (rc = upload_layout(p, (void**)&t.d_perm, t.perm.data(), t.perm.size() * 4, s)) != MAD_OK)
-            return rc;
+        if (kind_nres(t.kind) > 0) {
+            // the Jacobian kernel runs in element order, so that each element's rows are written next to its
+            // neighbours' (the evaluation kernels run in patch order)
+            std::vector<double> rj((size_t)t.n * t.nrest);
+            for (int64_t e = 0; e < t.n; ++e)
+                for (int k = 0; k < t.nrest; ++k) rj[(int64_t)k * t.n + e] = t.rest[(int64_t)e * t.nrest + k];
+            if ((rc = upload_layout(p, (void**)&t.d_jstencil, t.stencil.data(), t.stencil.size() * 4, s)) != MAD_OK)
+                return rc;
+            if ((rc = upload_layout(p, (void**)&t.d_jrest, rj.data(), rj.size() * 8, s)) != MAD_OK) return rc;
+        }
         if (scatter == MAD_SCATTER_COLOR &&
             (rc = upload_layout(p, (void**)&t.d_slot_map, t.slot_map.data(), t.slot_map.size() * 4, s)) != MAD_OK)
             return rc;

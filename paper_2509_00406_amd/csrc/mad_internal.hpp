@@ -51,7 +51,8 @@ struct Term {
     float* d_psi = nullptr;              // learned density: SoA [28][n] network outputs, patch order
     float* d_xh = nullptr;               // learned density: SoA [6][n] scaled features, patch order
     const double* vdata = nullptr;       // vertex terms: the caller's [nv][NVD] device array (not owned)
-    int32_t* d_perm = nullptr;           // residual terms: [n] patch slot -> element (row ownership)
+    int32_t* d_jstencil = nullptr;       // residual terms: [n][ns] in element order (the rows' owners)
+    double* d_jrest = nullptr;           // residual terms: SoA [nrest][n] in element order
     // colored scatter: elements sorted by color; elem_ptr then delimits chunks of at most kColorChunk elements
     // of one color and one component, color_chunk_ptr[c] is the first chunk of color c, and d_slot_map gives
     // each chunk's energy slot (slots ordered by component, then term, color and chunk)
@@ -404,9 +405,8 @@ hipError_t launch_slots(const int32_t* stencil, int64_t n, int ns, const int32_t
 struct JacTerm {
     int kind;
     int64_t n;
-    const int32_t* stencil;  // [n][ns] global vertices, patch order
-    const int32_t* perm;     // [n] patch slot -> element (the element owns its rows)
-    const double* rest;      // SoA [nrest][n], patch order
+    const int32_t* stencil;  // [n][ns] global vertices, element order (element e owns its rows)
+    const double* rest;      // SoA [nrest][n], element order
     const double* vdata;     // [nv][NVD] caller's per-vertex data
     double prm[4];
     int64_t row_off, nz_off; // the term's first row and first entry

@@ -198,3 +198,37 @@ def test_gauss_newton_iterations_reduce_the_residual(torch_cuda):
     _, g, _ = prob.eval(torch.from_numpy(xk.ravel().copy()).cuda(), 1 | 2)
     assert f < 0.05 * f0
     assert np.linalg.norm(g.cpu().numpy()) < 1e-2 * g0
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_jacobian_full_size_1000(torch_cuda, precision):
+    """The benchmark's residual workload at its size (1000 x 1000 grid: 2,996,001 edge-length residuals and
+    3,000,000 positional residual rows): the whole CSR pattern of J bit-exact, every value and residual against
+    the oracle, and the Gauss-Newton form (J^T r, J^T J) on sampled block rows."""
+    torch = torch_cuda
+    from paper_2509_00406_amd import mad
+    say("jacobian full size 1000", precision)
+    n = 1000
+    tris, rest = meshgen.grid(n)
+    rng = np.random.default_rng(7001)
+    x = rest + 0.05 * rng.normal(size=rest.shape)
+    vd = np.zeros((n * n, 4))
+    vd[:, 0] = rng.uniform(0.5, 2.0, n * n) * (rng.random(n * n) < 0.25)
+    vd[:, 1:] = rest + np.array([0.0, 0.0, 0.2]) + 0.05 * rng.normal(size=rest.shape)
+    _, prob, P, _ = build(torch, tris, rest, vd, precision)
+    rr, rpr, _, _ = check_jacobian(torch, prob, P, x, precision)
+    e, g, h = prob.eval(torch.from_numpy(x.ravel().copy()).cuda(), mad.ENERGY | mad.GRAD | mad.HESS)
+    torch.cuda.synchronize()
+    mask = np.zeros(n * n, bool)
+    mask[np.random.default_rng(8).choice(n * n, 200, replace=False)] = True
+    mask[[0, n - 1, n * n - 1, n * (n // 2) + n // 2]] = True
+    ref = P.eval(x, O.GRAD | O.HESS, row_mask=mask)
+    rows = np.nonzero(mask)[0]
+    gi = np.concatenate([np.arange(3 * r, 3 * r + 3) for r in rows])
+    rtol = PR.RTOL[precision]
+    PR.assert_close("J^T r(sampled)", g.cpu().numpy()[gi], ref.grad[gi], ref.gscale[gi], rtol)
+    bi = np.concatenate([np.arange(P.rowptr[r], P.rowptr[r + 1]) for r in rows])
+    PR.assert_close("J^T J(sampled)", h.cpu().numpy()[bi], ref.hess[bi], ref.hscale[bi], rtol)
+    # the energy is half the squared residual norm, summed in FP64
+    e_ref = 0.5 * float(np.sum(rr * rr))
+    assert abs(float(e.cpu()[0]) - e_ref) <= 1e-12 * e_ref
