@@ -458,27 +458,62 @@ __global__ void k_row_unique(int64_t nv, const int32_t* rp, const int32_t* coff,
     rowcnt[r] = rp[r + 1] - rp[r] + k;
 }
 
-// one lane per row: merge the old and the new columns into the new row; old block j -> map[j]; the new
-// blocks' indices are listed at extra[noff[r] ...]
-__global__ void k_row_merge(int64_t nv, const int32_t* rp, const int32_t* ci, const int32_t* coff,
-                            const int32_t* stage, const int32_t* nnew, const int64_t* rp_new, const int32_t* noff,
-                            int32_t* ci_new, int32_t* map, int32_t* extra) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nv) return;
-    int32_t i = rp[r];
-    const int32_t ie = rp[r + 1];
-    const int32_t* nv_ = stage + coff[r];
-    const int32_t ne = nnew[r];
-    int32_t j = 0;
-    int32_t o = (int32_t)rp_new[r];
-    int32_t x = noff[r];
-    while (i < ie || j < ne) {
-        if (j >= ne || (i < ie && ci[i] < nv_[j])) {
-            map[i] = o;
-            ci_new[o++] = ci[i++];
-        } else {
-            extra[x++] = o;
-            ci_new[o++] = nv_[j++];
+// Merge the old and the new columns into the new rows; old block j -> map[j]; the new blocks' indices are
+// listed at extra[noff[r] ...]. One wave per kMergeRows consecutive rows. A row without new blocks (almost
+// every row) only shifts, by noff[r] (the new blocks of the rows before it): the wave's lanes copy all such
+// entries of its rows together, each lane finding its entry's row by a binary search over the wave's row
+// starts in LDS, so reads and writes are coalesced. A row with new blocks is merged by its own lane.
+constexpr int kMergeRows = 64, kMergeWaves = 4;
+__global__ __launch_bounds__(64 * kMergeWaves) void k_row_merge(int64_t nv, const int32_t* rp, const int32_t* ci,
+                                                                 const int32_t* coff, const int32_t* stage,
+                                                                 const int32_t* nnew, const int64_t* rp_new,
+                                                                 const int32_t* noff, int32_t* ci_new, int32_t* map,
+                                                                 int32_t* extra) {
+    __shared__ int32_t s_rp[kMergeWaves][kMergeRows + 1];
+    __shared__ int32_t s_shift[kMergeWaves][kMergeRows];   // noff[r], or -1 for a row with new blocks
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = ((int64_t)blockIdx.x * kMergeWaves + w) * kMergeRows;
+    if (r0 >= nv) return;   // wave-uniform
+    const int nrows = (int)(nv - r0 < kMergeRows ? nv - r0 : kMergeRows);
+    const int64_t r = r0 + lane;
+    if (lane < nrows) {
+        s_rp[w][lane] = rp[r];
+        s_shift[w][lane] = nnew[r] == 0 ? noff[r] : -1;
+    }
+    if (lane == 0) s_rp[w][nrows] = rp[r0 + nrows];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int32_t lo = s_rp[w][0], hi = s_rp[w][nrows];
+    for (int32_t i = lo + lane; i < hi; i += 64) {
+        int a = 0, b = nrows;   // the last row start <= i: s_rp[a] <= i < s_rp[a + 1]
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if (s_rp[w][m] <= i) a = m;
+            else b = m;
+        }
+        const int32_t sh = s_shift[w][a];
+        if (sh >= 0) {
+            map[i] = i + sh;
+            ci_new[i + sh] = ci[i];
+        }
+    }
+    if (lane < nrows && s_shift[w][lane] < 0) {
+        int32_t i = s_rp[w][lane];
+        const int32_t ie = s_rp[w][lane + 1];
+        const int32_t* nv_ = stage + coff[r];
+        const int32_t ne = nnew[r];
+        int32_t j = 0;
+        int32_t o = (int32_t)rp_new[r];
+        int32_t x = noff[r];
+        while (i < ie || j < ne) {
+            if (j >= ne || (i < ie && ci[i] < nv_[j])) {
+                map[i] = o;
+                ci_new[o++] = ci[i++];
+            } else {
+                extra[x++] = o;
+                ci_new[o++] = nv_[j++];
+            }
         }
     }
 }
@@ -518,7 +553,8 @@ int insert_pairs_device(mad_problem* p, const int32_t* pairs, int64_t n, int64_t
     if (total > p->nnzb_cap) return fail(MAD_E_CAPACITY, "the new blocks exceed the reserve");
     // write the inactive buffer, then make it the active one
     hipLaunchKernelGGL(k_i64_to_i32, dim3(blocks_for(nv + 1, 256)), dim3(256), 0, s, B.rp64, p->d_rowptr_b, nv + 1);
-    hipLaunchKernelGGL(k_row_merge, dim3(blocks_for(nv, 256)), dim3(256), 0, s, nv, p->d_rowptr, p->d_colidx,
+    hipLaunchKernelGGL(k_row_merge, dim3(blocks_for(nv, kMergeRows * kMergeWaves)), dim3(64 * kMergeWaves), 0, s, nv,
+                       p->d_rowptr, p->d_colidx,
                        (const int32_t*)B.coff, (const int32_t*)B.stage, (const int32_t*)B.nnew,
                        (const int64_t*)B.rp64, (const int32_t*)B.noff, p->d_colidx_b, B.map,
                        p->d_extra_blocks + p->n_extra);
