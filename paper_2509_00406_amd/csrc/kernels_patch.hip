@@ -525,15 +525,30 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherLaunch G) {
     constexpr int DD = D * D;
     const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x, stride = (int64_t)gridDim.x * kBlock;
     if (G.want_hess) {
+        // one shared block per lane: its index lists read once, each halo partial read whole, the sum and its
+        // transpose written row by row (the partials are summed in slot order, as for every entry before)
         T* H = static_cast<T*>(G.hess);
         const T* HH = static_cast<const T*>(G.halo_h);
-        for (int64_t i = tid; i < (int64_t)G.n_gb * DD; i += stride) {
-            const int b = (int)(i / DD), k = (int)(i % DD);
-            T v = T(0);
-            for (int j = G.gb_ptr[b]; j < G.gb_ptr[b + 1]; ++j) v += HH[(int64_t)G.gb_src[j] * DD + k];
+        for (int64_t b = tid; b < (int64_t)G.n_gb; b += stride) {
+            T v[DD];
+#pragma unroll
+            for (int k = 0; k < DD; ++k) v[k] = T(0);
+            for (int j = G.gb_ptr[b]; j < G.gb_ptr[b + 1]; ++j) {
+                const T* src = HH + (int64_t)G.gb_src[j] * DD;
+#pragma unroll
+                for (int k = 0; k < DD; ++k) v[k] += src[k];
+            }
             const int32_t g = G.gb_gidx[b], gt = G.gb_gidxT[b];
-            H[(int64_t)g * DD + k] = v;
-            if (gt != g) H[(int64_t)gt * DD + (k % D) * D + k / D] = v;
+            T* dst = H + (int64_t)g * DD;
+#pragma unroll
+            for (int k = 0; k < DD; ++k) dst[k] = v[k];
+            if (gt != g) {
+                T* dt = H + (int64_t)gt * DD;
+#pragma unroll
+                for (int r = 0; r < D; ++r)
+#pragma unroll
+                    for (int c = 0; c < D; ++c) dt[r * D + c] = v[c * D + r];
+            }
         }
         for (int64_t i = tid; i < (int64_t)G.n_orphan_block * DD; i += stride)
             H[(int64_t)G.orphan_block[i / DD] * DD + i % DD] = T(0);
@@ -541,11 +556,18 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherLaunch G) {
     if (G.want_grad) {
         T* GR = static_cast<T*>(G.grad);
         const T* HG = static_cast<const T*>(G.halo_g);
-        for (int64_t i = tid; i < (int64_t)G.n_gv * D; i += stride) {
-            const int b = (int)(i / D), c = (int)(i % D);
-            T v = T(0);
-            for (int j = G.gv_ptr[b]; j < G.gv_ptr[b + 1]; ++j) v += HG[(int64_t)G.gv_src[j] * D + c];
-            GR[(int64_t)G.gv_vert[b] * D + c] = v;
+        for (int64_t b = tid; b < (int64_t)G.n_gv; b += stride) {
+            T v[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) v[c] = T(0);
+            for (int j = G.gv_ptr[b]; j < G.gv_ptr[b + 1]; ++j) {
+                const T* src = HG + (int64_t)G.gv_src[j] * D;
+#pragma unroll
+                for (int c = 0; c < D; ++c) v[c] += src[c];
+            }
+            T* dst = GR + (int64_t)G.gv_vert[b] * D;
+#pragma unroll
+            for (int c = 0; c < D; ++c) dst[c] = v[c];
         }
         for (int64_t i = tid; i < (int64_t)G.n_orphan_vert * D; i += stride)
             GR[(int64_t)G.orphan_vert[i / D] * D + i % D] = T(0);
@@ -554,7 +576,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherLaunch G) {
 
 template <typename T>
 static hipError_t launch_gather_t(const GatherLaunch& G, hipStream_t s) {
-    const int64_t work = std::max<int64_t>((int64_t)G.n_gb * G.var_dim * G.var_dim, (int64_t)G.n_gv * G.var_dim);
+    const int64_t work = std::max<int64_t>({(int64_t)G.n_gb, (int64_t)G.n_gv, (int64_t)G.n_orphan_block * G.var_dim *
+                                                                              G.var_dim});
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + kBlock - 1) / kBlock, 8192));
     switch (G.var_dim) {
     case 1: hipLaunchKernelGGL((k_gather<T, 1>), dim3(blocks), dim3(kBlock), 0, s, G); break;
