@@ -205,8 +205,19 @@ __global__ __launch_bounds__(kBlock) void k_energy_comp(const double* partial, i
     const int c = blockIdx.x;
     const int pb = comp_patch_ptr[c], pe = comp_patch_ptr[c + 1];
     double acc = 0.0;
-    for (int t = 0; t < n_terms; ++t)
-        for (int i = pb + (int)threadIdx.x; i < pe; i += kBlock) acc += partial[(int64_t)t * n_patch + i];
+    for (int t = 0; t < n_terms; ++t) {
+        const double* pt = partial + (int64_t)t * n_patch;
+        int i = pb + (int)threadIdx.x;
+        // eight loads in flight, then the additions in the same order as one at a time
+        for (; i + 7 * kBlock < pe; i += 8 * kBlock) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = pt[i + k * kBlock];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc += v[k];
+        }
+        for (; i < pe; i += kBlock) acc += pt[i];
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
