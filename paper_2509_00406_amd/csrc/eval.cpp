@@ -53,8 +53,9 @@ int eval_problem(mad_problem* p, const double* x, uint32_t mode, double* energy,
         if (mode & MAD_HESS) MAD_HIP_TRY(launch_fill(hess, p->nnzb * d * d, eb, s));
         if (hvp) MAD_HIP_TRY(launch_fill(y, m.nv * d, eb, s));
     }
-    if (fallback_pass) MAD_HIP_TRY(launch_fill(sc.fb_count, 1, 4, s));
-    if (p->scatter == MAD_SCATTER_PATCH && p->persistent) MAD_HIP_TRY(launch_fill(sc.work_counter, 1, 4, s));
+    // the FP64 redo queue's count and the persistent queue's head, cleared by one small kernel
+    MAD_HIP_TRY(launch_zero_counters(fallback_pass ? sc.fb_count : nullptr,
+                                     (p->scatter == MAD_SCATTER_PATCH && p->persistent) ? sc.work_counter : nullptr, s));
     if (ev) MAD_HIP_TRY(hipEventRecord((*ev)[1], s));
     // learned and analytic shell densities: vertex normals of x, then the network pass per MLP term
     if (p->shell) MAD_HIP_TRY(launch_vertex_normals(x, m.nv, p->d_vf_ptr, p->d_vf, p->d_tris, sc.normals, s));

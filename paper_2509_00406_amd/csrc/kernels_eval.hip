@@ -178,6 +178,17 @@ hipError_t launch_zero_blocks(void* hess, const int32_t* list, int64_t n, int dd
     return hipGetLastError();
 }
 
+__global__ void k_zero_counters(int32_t* a, int32_t* b) {
+    if (threadIdx.x == 0 && a) *a = 0;
+    if (threadIdx.x == 1 && b) *b = 0;
+}
+
+hipError_t launch_zero_counters(int32_t* a, int32_t* b, hipStream_t s) {
+    if (!a && !b) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, a, b);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(void* ptr, int64_t n_elems, int elem_bytes, hipStream_t s) {
     const int64_t bytes = n_elems * elem_bytes;
     if (bytes <= 0) return hipSuccess;

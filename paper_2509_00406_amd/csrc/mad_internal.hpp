@@ -387,6 +387,8 @@ struct FallbackLaunch {
 };
 hipError_t launch_fallback(const FallbackLaunch& F, hipStream_t s);
 hipError_t launch_fill(void* ptr, int64_t n_elems, int elem_bytes, hipStream_t s);
+// one small kernel that zeroes up to two int32 counters (either may be null)
+hipError_t launch_zero_counters(int32_t* a, int32_t* b, hipStream_t s);
 hipError_t launch_energy_reduce(const double* partial, int n_terms, int n_patch, const int32_t* comp_patch_ptr,
                                 int n_comp, bool batched, double* energy, double* comp_scratch, hipStream_t s);
 
