@@ -80,8 +80,9 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="choose the layout by timing (batched: always)")
     ap.add_argument("--no-fp64-plain", action="store_true", help="skip the FP64 GPU comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-sizes", action="store_true", help="cloth: skip the Table 1 size sweep")
-    ap.add_argument("--no-hvp", action="store_true", help="shell: skip the matrix-free product timing")
+    ap.add_argument("--no-sizes", action="store_true",
+                    help="cloth: skip the Table 1 size sweep; symdir: skip the Table 2 product sweep")
+    ap.add_argument("--no-hvp", action="store_true", help="shell, symdir: skip the matrix-free product timing")
     ap.add_argument("--no-dynamic", action="store_true", help="shell: skip the pair-insertion timing")
     ap.add_argument("--no-jacobian", action="store_true", help="cloth: skip the residual Jacobian timing")
     ap.add_argument("--pairs", type=int, default=100000, help="interaction pairs inserted by the dynamic timing")
@@ -518,7 +519,7 @@ def main():
         res["network"] = density_network(mad)[1]
         res["vs_other_forms"] = other_forms(torch, mad, mesh, inp, args, stream, x, ms_per_step)
         res["learned_vs_analytic"] = learned_vs_analytic(torch, mad, mesh, inp, args, stream, x, out)
-    if args.workload == "shell" and not args.no_hvp:
+    if args.workload in ("shell", "symdir") and not args.no_hvp:
         # the matrix-free mode: y = H v with each element's clamped Hessian applied in LDS, no assembly
         v = torch.randn_like(x)
         y = torch.empty_like(out[1])
@@ -536,6 +537,8 @@ def main():
         res["one_launch_per_mesh"] = per_mesh_baseline(torch, mad, inp, prec, stream, ms_per_step, args)
     if args.workload == "cloth" and not args.no_sizes:
         res["table1_sizes"] = cloth_sizes(torch, mad, args, stream)
+    if args.workload == "symdir" and not args.no_sizes and not args.no_hvp:
+        res["table2_sizes"] = symdir_hvp_sizes(torch, mad, args, stream)
     if args.workload == "cloth" and not args.no_jacobian:
         res["residual_jacobian"] = residual_jacobian(torch, mad, args, prec, stream)
     if prec == mad.F32 and not args.no_fp64_plain:
@@ -649,6 +652,37 @@ def cloth_sizes(torch, mad, args, stream):
             step_ms, wall = time_steps(torch, lambda: p.eval(x, mode, out=o, stream=stream), 20, 3, stream)
             row[f"ms_{name}"] = max(wall * 1e3, sum(step_ms)) / len(step_ms)
             del p, o
+        rows.append(row)
+    return rows
+
+
+# Sec. 7.2, Table 2: time per conjugate-gradient iteration of the paper's matrix-free Newton solver
+# (one Hessian-vector product plus the iteration's vector operations) for the symmetric Dirichlet
+# energy, by vertex count, on an RTX 4090 (context, not a target)
+PAPER_TABLE2_MS = {1550: 0.026, 160000: 0.108, 560000: 0.383, 1520000: 0.817, 1830000: 1.102}
+
+
+def symdir_hvp_sizes(torch, mad, args, stream):
+    """Matrix-free Hessian-vector products of the symmetric Dirichlet energy (FP32 and FP64, clamped and
+    plain) on warped grids whose vertex counts are closest to the Table 2 rows."""
+    from paper_2509_00406_amd import meshgen
+    rows = []
+    for nv in sorted(PAPER_TABLE2_MS):
+        n = int(round(nv ** 0.5))
+        inp = meshgen.warped_grid(n=n, seed=3001)
+        mesh = mad.Mesh(inp.tris, inp.n_verts)
+        x = torch.from_numpy(inp.x.ravel().copy()).cuda()
+        v = torch.randn_like(x)
+        row = {"vertices": n * n, "triangles": mesh.n_tris, "paper_rtx4090_ms_per_cg_iteration": PAPER_TABLE2_MS[nv]}
+        for prec, name in ((mad.F32, "f32"), (mad.F64, "f64")):
+            p = make_problem(mad, mesh, inp, prec, args, stream, form="symdir")
+            y = torch.empty(x.numel(), dtype=torch.float32 if prec == mad.F32 else torch.float64, device=x.device)
+            for hmode, tag in ((mad.SPD, "spd"), (0, "plain")):
+                def prod():
+                    mad.mad_problem_hvp(p.handle, x, v, hmode, None, None, y, stream)
+                ms, wall = time_steps(torch, prod, 20, 3, stream)
+                row[f"ms_{name}_{tag}"] = max(wall * 1e3, sum(ms)) / len(ms)
+            del p, y
         rows.append(row)
     return rows
 
