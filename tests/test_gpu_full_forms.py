@@ -3,7 +3,8 @@ configuration the benchmark times (whole pattern bit-exact, sampled block rows a
 oracle element by element, energies against an independent vectorised FP64 evaluation):
 
 * symmetric Dirichlet on the 1001 x 1001 warped grid (2,000,000 triangles, 2x2 blocks, clamped), FP32 and
-  FP64: the two-DOF persistent multi-patch path at size;
+  FP64: the two-DOF persistent multi-patch path at size, and its matrix-free Hessian-vector product (clamped
+  and plain) on the same sampled rows;
 * 700 geodesic icospheres of lognormal size in one autotuned launch: sampled rows over all meshes and every
   per-component energy;
 * the learned density on the 708 x 708 cylinder (999,698 triangles), FP32 and FP64: the network pass loops
@@ -91,6 +92,40 @@ def test_symdir_1001_sampled(torch_cuda, symdir_full, precision):
     assert abs(e - e_ref) <= rtol * e_abs, (e, e_ref, e_abs)
     say(f"layout {lay}; worst grad {g:.2e} hess {h:.2e} over {nb} blocks; energy {e:.12e} vs {e_ref:.12e}; "
         f"fp64 fallbacks {fallbacks}")
+
+
+@pytest.mark.parametrize("precision,spd", [(1, True), (1, False), (0, True), (0, False)])
+def test_symdir_1001_hvp(torch_cuda, symdir_full, precision, spd):
+    """The matrix-free product (Sec. 5.5 matrix-free mode) at the benchmark size: y = H v on the sampled rows
+    against the oracle's sampled block rows applied to the same v (per entry within rtol of
+    sum_b scale_b |v|), clamped and plain, with the same pass's energy."""
+    from paper_2509_00406_amd import mad
+    torch = torch_cuda
+    inp, P, mask, e_ref, e_abs = symdir_full
+    say("symdir 1001 hvp", "fp32" if precision else "fp64", "clamped" if spd else "plain")
+    mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 2, [(6, ())], precision)
+    x = np.ascontiguousarray(inp.x, dtype=np.float64).ravel()
+    v = np.random.default_rng(78).normal(size=x.size)
+    y, energy, _ = prob.hvp(torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda(),
+                            mad.ENERGY | (mad.SPD if spd else 0))
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    ref = P.eval(inp.x, O.HESS | (O.SPD if spd else 0), row_mask=mask)
+    rows = np.nonzero(mask)[0]
+    yref = np.zeros((rows.size, 2))
+    yscale = np.zeros((rows.size, 2))
+    V = v.reshape(-1, 2)
+    for n, r in enumerate(rows):
+        for b in range(P.rowptr[r], P.rowptr[r + 1]):
+            c = P.colidx[b]
+            yref[n] += ref.hess[b].reshape(2, 2) @ V[c]
+            yscale[n] += ref.hscale[b].reshape(2, 2) @ np.abs(V[c])
+    gi = np.concatenate([np.arange(2 * r, 2 * r + 2) for r in rows])
+    rtol = PR.RTOL[precision]
+    w = PR.assert_close("hvp(sampled)", y[gi], yref.ravel(), yscale.ravel(), rtol)
+    e = float(energy.cpu()[0])
+    assert abs(e - e_ref) <= rtol * e_abs, (e, e_ref, e_abs)
+    say(f"hvp: worst {w:.2e} over {rows.size} rows")
 
 
 # ------------------------------------------------------------------ 700 icospheres, autotuned
