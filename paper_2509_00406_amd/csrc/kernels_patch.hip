@@ -295,7 +295,7 @@ __device__ __forceinline__ void patch_term(const PatchLaunch& L, const PatchTerm
 
 template <typename T, int MODE, int D, int FAM, int BLK>
 __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsigned char* smem, double* red,
-                                               int* s_next, int* lock) {
+                                               int* s_next, int* lock, int* s_terms) {
     constexpr int DD = D * D;
     const int lv0 = L.lv_ptr[p], nlv = L.lv_ptr[p + 1] - lv0;
     const int lb0 = L.lb_ptr[p], nlb = L.lb_ptr[p + 1] - lb0;
@@ -308,6 +308,13 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
     if (threadIdx.x == 0) {
         *s_next = 0;
         *lock = 0;
+    }
+    // the patch's element range of each term, in unit order (read by every unit below)
+    if (threadIdx.x < L.n_terms) {
+        const int tt = L.term_order[threadIdx.x];
+        const int b = L.terms[tt].elem_ptr[p];
+        s_terms[2 * threadIdx.x] = b;
+        s_terms[2 * threadIdx.x + 1] = L.terms[tt].elem_ptr[p + 1] - b;
     }
     if (threadIdx.x < kMaxPatchUnits) red[threadIdx.x] = 0.0;   // per-unit energies
     bool bad_x = false;
@@ -352,22 +359,26 @@ __device__ __forceinline__ void eval_patch_one(const PatchLaunch& L, int p, unsi
     for (;;) {
         int u = 0;
         if (lane == 0) u = atomicAdd(s_next, 1);
-        u = __shfl(u, 0);
+        u = __builtin_amdgcn_readfirstlane(__shfl(u, 0));
         const int unit = u;
         double esum = 0.0;
         int t = -1, first = 0, last = 0;
         for (int k = 0; k < L.n_terms; ++k) {
-            const int tt = L.term_order[k];
-            const int b = L.terms[tt].elem_ptr[p], n = L.terms[tt].elem_ptr[p + 1] - b;
+            const int b = s_terms[2 * k], n = s_terms[2 * k + 1];
             const int nc = (n + 63) >> 6;
             if (u < nc) {
-                t = tt;
+                t = L.term_order[k];
                 first = b + (u << 6);
                 last = min(b + n, first + 64);
                 break;
             }
             u -= nc;
         }
+        // the same for every lane of the wave: kept in scalar registers, so the term's arguments are
+        // scalar loads and the dispatch below a scalar branch
+        t = __builtin_amdgcn_readfirstlane(t);
+        first = __builtin_amdgcn_readfirstlane(first);
+        last = __builtin_amdgcn_readfirstlane(last);
         if (t < 0) break;
         const PatchTermArgs& A = L.terms[t];
         const int e0 = first + lane;
@@ -482,8 +493,9 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kMaxPatchUnits];
     __shared__ int next, unit_next, block_lock;
+    __shared__ int term_range[16];
     if (!L.persistent) {
-        eval_patch_one<T, MODE, D, FAM, BLK>(L, blockIdx.x, smem, red, &unit_next, &block_lock);
+        eval_patch_one<T, MODE, D, FAM, BLK>(L, blockIdx.x, smem, red, &unit_next, &block_lock, term_range);
         return;
     }
     for (;;) {
@@ -492,7 +504,7 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
         const int k = next;
         __syncthreads();   // every lane has read `next` before it is overwritten
         if (k >= L.n_patch) break;
-        eval_patch_one<T, MODE, D, FAM, BLK>(L, L.work_order[k], smem, red, &unit_next, &block_lock);
+        eval_patch_one<T, MODE, D, FAM, BLK>(L, L.work_order[k], smem, red, &unit_next, &block_lock, term_range);
         __syncthreads();   // the flush has read LDS before the next patch clears it
     }
 }
