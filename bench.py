@@ -43,12 +43,12 @@ sys.path.insert(0, ROOT)
 # passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
 FLOPS_PER_ELEM = {"f32": 14925.0, "f64": None}
 # traffic by launch (persistent queue / one workgroup per patch) at the default 384-face layout
-TRAFFIC_BYTES = {"f32": {1: 1.2796e9, 0: 1.0360e9}, "f64": None}
+TRAFFIC_BYTES = {"f32": {1: 1.1655e9, 0: 1.0359e9}, "f64": None}
 # the same for the 1000^2 cloth step at its default layout (profiles/k_eval_patch_f32_cloth1000_counters.md)
 CLOTH_TRAFFIC_BYTES = {"f32": 0.5685e9, "f64": None}
 # and for the 1001^2 symmetric Dirichlet parameterisation at its default layout (512-face patches, persistent
 # launch; profiles/k_eval_patch_f32_symdir1001_trace_counters.md)
-SYMDIR_TRAFFIC_BYTES = {"f32": 0.3652e9, "f64": None}
+SYMDIR_TRAFFIC_BYTES = {"f32": 0.3657e9, "f64": None}
 
 # MI355X published peaks used as roofline denominators
 HBM_PEAK_GBS = 8000.0
