@@ -41,9 +41,9 @@ sys.path.insert(0, ROOT)
 # workload (FP32 + FP64 VALU wave instructions x 64 lanes, FMA = 2), and its HBM traffic per launch
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, factors from a 1 GiB copy), from the rocprofv3 counter
 # passes in profiles/k_eval_patch_f32_shell1024_counters.md. Valid for the kernel as profiled there.
-FLOPS_PER_ELEM = {"f32": 14925.0, "f64": None}
+FLOPS_PER_ELEM = {"f32": 14697.7, "f64": None}
 # traffic by launch (persistent queue / one workgroup per patch) at the default 384-face layout
-TRAFFIC_BYTES = {"f32": {1: 1.1655e9, 0: 1.0359e9}, "f64": None}
+TRAFFIC_BYTES = {"f32": {1: 1.1680e9, 0: 1.0358e9}, "f64": None}
 # the same for the 1000^2 cloth step at its default layout (profiles/k_eval_patch_f32_cloth1000_counters.md)
 CLOTH_TRAFFIC_BYTES = {"f32": 0.5685e9, "f64": None}
 # and for the 1001^2 symmetric Dirichlet parameterisation at its default layout (512-face patches, persistent
