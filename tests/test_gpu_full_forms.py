@@ -6,7 +6,7 @@ oracle element by element, energies against an independent vectorised FP64 evalu
   FP64: the two-DOF persistent multi-patch path at size, and its matrix-free Hessian-vector product (clamped
   and plain) on the same sampled rows;
 * 700 geodesic icospheres of lognormal size in one autotuned launch: sampled rows over all meshes and every
-  per-component energy;
+  per-component energy, also in FP64 and through the clamped matrix-free product;
 * the learned density on the 708 x 708 cylinder (999,698 triangles), FP32 and FP64: the network pass loops
   over many tiles per wave at this size.
 """
@@ -129,21 +129,36 @@ def test_symdir_1001_hvp(torch_cuda, symdir_full, precision, spd):
 
 
 # ------------------------------------------------------------------ 700 icospheres, autotuned
-def test_icospheres_700_autotuned(torch_cuda):
-    from paper_2509_00406_amd import mad
-    torch = torch_cuda
+ICO_TERMS = [(4, (1.0, 1.0)), (5, (1.0, 1.0))]
+
+
+@pytest.fixture(scope="module")
+def ico_full():
     say("700 icospheres oracle setup")
     inp = meshgen.icosphere_batch(n_meshes=700)
-    terms = [(4, (1.0, 1.0)), (5, (1.0, 1.0))]
-    P = PR.build_oracle(inp.tris, inp.rest, inp.n_verts, 3, terms)
+    P = PR.build_oracle(inp.tris, inp.rest, inp.n_verts, 3, ICO_TERMS)
     co = inp.comp_offsets
     # rows of the first, last and a spread of meshes, plus random ones
     extra = [int(co[c]) for c in (0, 1, 350, 698, 699)] + [int(co[c + 1]) - 1 for c in (0, 350, 699)]
     mask = sample_rows(inp.n_verts, 240, 654, extra=extra)
     e_ref, e_abs = npref.shell_energy_by_component(inp.tris, inp.rest, inp.x, P.topo.diamonds,
                                                    P.topo.diamond_faces, (1.0, 1.0), (1.0, 1.0), co)
+    return inp, P, mask, e_ref, e_abs
+
+
+def check_component_energies(e, e_ref, e_abs, rtol):
+    assert e.shape[0] == 701
+    bad = np.nonzero(np.abs(e[1:] - e_ref) > rtol * e_abs)[0]
+    assert bad.size == 0, (bad[:5], e[1 + bad[:5]], e_ref[bad[:5]])
+    assert abs(e[0] - e_ref.sum()) <= rtol * e_abs.sum()
+
+
+def test_icospheres_700_autotuned(torch_cuda, ico_full):
+    torch = torch_cuda
+    inp, P, mask, e_ref, e_abs = ico_full
+    co = inp.comp_offsets
     say("700 icospheres GPU, autotune")
-    mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, terms, 1, comp_offsets=co)
+    mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, ICO_TERMS, 1, comp_offsets=co)
     x = torch.from_numpy(inp.x.ravel().copy()).cuda()
     out = prob.outputs()
     tune = prob.autotune(x, SPD_ALL, out=out, reps=3, force=True)
@@ -156,13 +171,58 @@ def test_icospheres_700_autotuned(torch_cuda):
     assert not nonfinite
     rtol = PR.RTOL[1]
     g, h, nb = sampled_compare(P, mask, inp.x, grad.cpu().numpy(), hess.cpu().numpy(), 3, rtol)
-    e = energy.cpu().numpy()
-    assert e.shape[0] == 701
-    bad = np.nonzero(np.abs(e[1:] - e_ref) > rtol * e_abs)[0]
-    assert bad.size == 0, (bad[:5], e[1 + bad[:5]], e_ref[bad[:5]])
-    assert abs(e[0] - e_ref.sum()) <= rtol * e_abs.sum()
+    check_component_energies(energy.cpu().numpy(), e_ref, e_abs, rtol)
     say(f"chosen {tune.get('chosen')} layout {lay}; worst grad {g:.2e} hess {h:.2e} over {nb} blocks; "
         f"700 component energies in bounds; fp64 fallbacks {fallbacks}")
+
+
+def test_icospheres_700_fp64(torch_cuda, ico_full):
+    """The batched persistent launch in FP64 at the default layout: sampled rows and every component energy
+    at the FP64 tolerance."""
+    torch = torch_cuda
+    inp, P, mask, e_ref, e_abs = ico_full
+    say("700 icospheres GPU, fp64")
+    mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, ICO_TERMS, 0, comp_offsets=inp.comp_offsets)
+    lay = prob.layout()
+    assert lay["persistent"] == 1
+    x = torch.from_numpy(inp.x.ravel().copy()).cuda()
+    energy, grad, hess = prob.eval(x, SPD_ALL)
+    torch.cuda.synchronize()
+    assert not prob.status()[0]
+    rtol = PR.RTOL[0]
+    g, h, nb = sampled_compare(P, mask, inp.x, grad.cpu().numpy(), hess.cpu().numpy(), 3, rtol)
+    check_component_energies(energy.cpu().numpy(), e_ref, e_abs, rtol)
+    say(f"layout {lay}; worst grad {g:.2e} hess {h:.2e} over {nb} blocks; 700 component energies in bounds")
+
+
+def test_icospheres_700_hvp_fp32(torch_cuda, ico_full):
+    """The clamped matrix-free product over the 700 meshes in one launch: y = H v on the sampled rows against the
+    oracle's sampled block rows applied to the same v, and the per-component energies of the same pass."""
+    from paper_2509_00406_amd import mad
+    torch = torch_cuda
+    inp, P, mask, e_ref, e_abs = ico_full
+    say("700 icospheres GPU, clamped hvp fp32")
+    mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, ICO_TERMS, 1, comp_offsets=inp.comp_offsets)
+    x = np.ascontiguousarray(inp.x, dtype=np.float64).ravel()
+    v = np.random.default_rng(79).normal(size=x.size)
+    y, energy, _ = prob.hvp(torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda(), mad.ENERGY | mad.SPD)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    ref = P.eval(inp.x, O.HESS | O.SPD, row_mask=mask)
+    rows = np.nonzero(mask)[0]
+    yref = np.zeros((rows.size, 3))
+    yscale = np.zeros((rows.size, 3))
+    V = v.reshape(-1, 3)
+    for n, r in enumerate(rows):
+        for b in range(P.rowptr[r], P.rowptr[r + 1]):
+            c = P.colidx[b]
+            yref[n] += ref.hess[b].reshape(3, 3) @ V[c]
+            yscale[n] += ref.hscale[b].reshape(3, 3) @ np.abs(V[c])
+    gi = np.concatenate([np.arange(3 * r, 3 * r + 3) for r in rows])
+    rtol = PR.RTOL[1]
+    w = PR.assert_close("hvp(sampled)", y[gi], yref.ravel(), yscale.ravel(), rtol)
+    check_component_energies(energy.cpu().numpy(), e_ref, e_abs, rtol)
+    say(f"hvp: worst {w:.2e} over {rows.size} rows; 700 component energies in bounds")
 
 
 # ------------------------------------------------------------------ learned density, 708^2
