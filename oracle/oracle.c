@@ -937,8 +937,14 @@ int oracle_eval(int64_t nv, int var_dim, int n_terms, const int *kind, const int
                     for (int j = 0; j < k; ++j) Hl[i * k + j] = r.h[i][j];
                 if (mode & OR_SPD) oracle_spd_project(k, Hl, spd_eps, Hp);
                 else memcpy(Hp, Hl, sizeof(double) * k * k);
+                /* the entry scale: the element's largest Hessian entry, before or after the clamp (the
+                   clamp's eigen-decomposition errs relative to the matrix it decomposes; an element whose
+                   Hessian clamps to zero would otherwise be measured against its own rounding noise) */
                 double hmax = 0.0;
-                for (int i = 0; i < k * k; ++i) hmax = fabs(Hp[i]) > hmax ? fabs(Hp[i]) : hmax;
+                for (int i = 0; i < k * k; ++i) {
+                    hmax = fabs(Hp[i]) > hmax ? fabs(Hp[i]) : hmax;
+                    hmax = fabs(Hl[i]) > hmax ? fabs(Hl[i]) : hmax;
+                }
                 for (int a = 0; a < ss; ++a) {
                     if (row_mask && !row_mask[s[a]]) continue;
                     for (int b = 0; b < ss; ++b) {

@@ -84,8 +84,9 @@ def oracle_params(theta32, s_in, s_out):
     return O.mlp_pack(float(s_out), np.asarray(s_in, np.float64), W1, b1, W2, b2, w3, b3)
 
 
-def run_term(torch, inp, precision, mode, term, spd_eps=0.0, patch_faces=0, scatter=0):
-    """Build the GPU problem with one shell-feature term and the oracle twin; compare."""
+def run_term(torch, inp, precision, mode, term, spd_eps=0.0, patch_faces=0, scatter=0, hvp=False):
+    """Build the GPU problem with one shell-feature term and the oracle twin; compare. With hvp, also the
+    matrix-free product y = H v (clamped when mode has SPD) against the oracle's assembled Hessian times v."""
     from paper_2509_00406_amd import mad
     nv = inp.n_verts
     mesh = mad.Mesh(inp.tris, nv, inp.comp_offsets)
@@ -118,6 +119,14 @@ def run_term(torch, inp, precision, mode, term, spd_eps=0.0, patch_faces=0, scat
         out["grad"] = PR.assert_close("grad", grad.cpu().numpy(), ref.grad, ref.gscale, rtol)
     if mode & 4:
         out["hess"] = PR.assert_close("hess", hess.cpu().numpy(), ref.hess, ref.hscale, rtol)
+    if hvp:
+        spd = bool(mode & 8)
+        v = np.random.default_rng(81).normal(size=xt.numel())
+        y, ey, _ = prob.hvp(xt, torch.from_numpy(v).cuda(), mad.ENERGY | (mad.SPD if spd else 0))
+        torch.cuda.synchronize()
+        yref, yscale = P.hvp(inp.x, v, spd=spd, spd_eps=spd_eps)
+        out["hvp"] = PR.assert_close("hvp", y.cpu().numpy(), yref, yscale, rtol)
+        assert abs(ey.cpu().numpy()[0] - ref.energy) <= rtol * ref.esum_abs
     say("worst |err|/scale", out)
     return out, prob, (energy, grad, hess)
 
@@ -152,6 +161,19 @@ def test_mlp_term_ragged_and_curved_rest(torch_cuda):
     inp = meshgen.icosphere_batch(n_meshes=2, mean_verts=700, vmin=600, vmax=900)
     run_term(torch_cuda, inp, 1, ALL | 8, ("mlp", seeded_network(12)))
     run_term(torch_cuda, inp, 0, ALL, ("mlp", seeded_network(12)), scatter=1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("spd", [False, True])
+def test_shell_feature_terms_hvp(torch_cuda, precision, spd):
+    """The matrix-free product through the network pass and the shell-feature element chain (learned and
+    analytic densities), plain and clamped."""
+    say("shell-feature hvp", precision, spd)
+    inp = meshgen.shell_cylinder(n=33, seed=33)
+    run_term(torch_cuda, inp, precision, ALL | (8 if spd else 0), ("mlp", seeded_network(14)), patch_faces=128,
+             hvp=True)
+    run_term(torch_cuda, inp, precision, ALL | (8 if spd else 0), ("shell", (1.0, 0.8, 0.5)), patch_faces=128,
+             hvp=True)
 
 
 def test_mlp_tiny_mesh(torch_cuda):
