@@ -493,7 +493,7 @@ __device__ __forceinline__ void eval_patch_body(const PatchLaunch& L) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kMaxPatchUnits];
     __shared__ int next, unit_next, block_lock;
-    __shared__ int term_range[16];
+    __shared__ int term_range[2 * sizeof(PatchLaunch::term_order) / sizeof(int)];   // (first, count) per term
     if (!L.persistent) {
         eval_patch_one<T, MODE, D, FAM, BLK>(L, blockIdx.x, smem, red, &unit_next, &block_lock, term_range);
         return;
