@@ -71,6 +71,19 @@ def test_static_eval_two_calls_second_smaller(torch_cuda, precision, persistent)
         say(f"  {prob.layout()}; worst vs eval: grad {w['grad']:.2e} hess {w['hess']:.2e}")
 
 
+def test_static_eval_batched_components(torch_cuda):
+    """Disjoint meshes in one problem: the per-component energies come from the static array's reduction
+    slots; two calls in a row, the second on fewer, smaller meshes."""
+    torch = torch_cuda
+    for nm, mean_v in ((6, 900), (3, 700)):
+        say(f"static eval {nm} icospheres")
+        inp = meshgen.icosphere_batch(n_meshes=nm, mean_verts=mean_v, vmin=mean_v - 300, vmax=mean_v + 400)
+        mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, SHELL, 1, comp_offsets=inp.comp_offsets)
+        P = PR.build_oracle(inp.tris, inp.rest, inp.n_verts, 3, SHELL)
+        w = compare(torch, prob, P, inp.x, 1)
+        say(f"  {prob.layout()}; worst vs eval: grad {w['grad']:.2e} hess {w['hess']:.2e}")
+
+
 def test_static_eval_fp64_redo_queue(torch_cuda):
     """FP32 with the quality threshold at 1 (the equilateral triangle's quality; these faces are near
     right isosceles, quality about 0.87): every element goes through the FP64 redo queue, which lives in
