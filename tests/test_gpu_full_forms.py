@@ -7,8 +7,8 @@ oracle element by element, energies against an independent vectorised FP64 evalu
   and plain) on the same sampled rows;
 * 700 geodesic icospheres of lognormal size in one autotuned launch: sampled rows over all meshes and every
   per-component energy, also in FP64 and through the clamped matrix-free product;
-* the learned density on the 708 x 708 cylinder (999,698 triangles), FP32 and FP64: the network pass loops
-  over many tiles per wave at this size.
+* the learned density on the 708 x 708 cylinder (999,698 triangles), FP32 and FP64, and its clamped
+  matrix-free product: the network pass loops over many tiles per wave at this size.
 """
 import sys
 
@@ -267,3 +267,38 @@ def test_mlp_708_sampled(torch_cuda, mlp_full, precision):
     e = float(energy.cpu()[0])
     assert abs(e - e_ref) <= rtol * e_abs, (e, e_ref, e_abs)
     say(f"worst grad {g:.2e} hess {h:.2e} over {nb} blocks; energy {e:.12e} vs {e_ref:.12e}")
+
+
+def test_mlp_708_hvp_fp32(torch_cuda, mlp_full):
+    """The clamped matrix-free product through the network pass at 708^2 (many network tiles per wave): y = H v
+    on the sampled rows against the oracle's sampled block rows applied to the same v, and the pass's energy."""
+    from paper_2509_00406_amd import mad
+    from tests.test_gpu_mlp import RTOL_MLP
+    torch = torch_cuda
+    inp, P, mask, (theta, s_in, s_out), e_ref, e_abs = mlp_full
+    say("mlp 708 clamped hvp fp32")
+    mesh = mad.Mesh(inp.tris, inp.n_verts)
+    prob = mad.Problem(mesh, 3, 1)
+    prob.add_mlp_term(mad.Network(theta, s_in, s_out), inp.rest)
+    prob.finalize()
+    x = np.ascontiguousarray(inp.x, dtype=np.float64).ravel()
+    v = np.random.default_rng(80).normal(size=x.size)
+    y, energy, _ = prob.hvp(torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda(), mad.ENERGY | mad.SPD)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    ref = P.eval(inp.x, O.HESS | O.SPD, row_mask=mask)
+    rows = np.nonzero(mask)[0]
+    yref = np.zeros((rows.size, 3))
+    yscale = np.zeros((rows.size, 3))
+    V = v.reshape(-1, 3)
+    for n, r in enumerate(rows):
+        for b in range(P.rowptr[r], P.rowptr[r + 1]):
+            c = P.colidx[b]
+            yref[n] += ref.hess[b].reshape(3, 3) @ V[c]
+            yscale[n] += ref.hscale[b].reshape(3, 3) @ np.abs(V[c])
+    gi = np.concatenate([np.arange(3 * r, 3 * r + 3) for r in rows])
+    rtol = max(PR.RTOL[1], RTOL_MLP)
+    w = PR.assert_close("hvp(sampled)", y[gi], yref.ravel(), yscale.ravel(), rtol)
+    e = float(energy.cpu()[0])
+    assert abs(e - e_ref) <= rtol * e_abs, (e, e_ref, e_abs)
+    say(f"hvp: worst {w:.2e} over {rows.size} rows")
