@@ -153,7 +153,7 @@ def test_cloth_vertex_term_errors(torch_cuda):
 def test_cloth_full_size_sampled(torch_cuda, precision):
     # the benchmark's configuration: 1000 x 1000 vertices, 2,996,001 springs + 1,000,000 vertices,
     # filtered Hessian; the pattern bit-exact, sampled rows element by element, total energy against
-    # an independent vectorised evaluation
+    # an independent vectorised evaluation; then the filtered matrix-free product on the same rows
     torch = torch_cuda
     from paper_2509_00406_amd import mad
     n = 1000
@@ -185,3 +185,18 @@ def test_cloth_full_size_sampled(torch_cuda, precision):
     e_ref, e_abs = npref.cloth_energy(inp.tris, inp.rest, inp.x, inp.meta["vdata"], inp.meta["spring_params"],
                                       inp.meta["inertia_params"])
     assert abs(float(energy.cpu()[0]) - e_ref) <= rtol * e_abs
+    # the filtered matrix-free product of the same step on the same rows
+    v = np.random.default_rng(82).normal(size=x.numel())
+    y, ey, _ = prob.hvp(x, torch.from_numpy(v).cuda(), mad.ENERGY | mad.SPD)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    V = v.reshape(-1, 3)
+    yref = np.zeros((r.size, 3))
+    yscale = np.zeros((r.size, 3))
+    for k, i in enumerate(r):
+        for b in range(P.rowptr[i], P.rowptr[i + 1]):
+            c = P.colidx[b]
+            yref[k] += ref.hess[b].reshape(3, 3) @ V[c]
+            yscale[k] += ref.hscale[b].reshape(3, 3) @ np.abs(V[c])
+    PR.assert_close("hvp(sampled)", y[gi], yref.ravel(), yscale.ravel(), rtol)
+    assert abs(float(ey.cpu()[0]) - e_ref) <= rtol * e_abs
