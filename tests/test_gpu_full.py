@@ -120,15 +120,16 @@ def test_full_shell_other_scatters_fp32(full, scatter):
     say(f"{scatter}: worst grad {g:.2e} hess {h:.2e} over {nb} blocks; fp64 fallbacks {fallbacks}")
 
 
-def test_full_shell_hvp_fp32(full):
+@pytest.mark.parametrize("precision", [1, 0])
+def test_full_shell_hvp(full, precision):
     """The matrix-free clamped Hessian-vector product at the benchmark size: y = H v on the sampled rows against
     the oracle's sampled Hessian rows applied to the same v (per entry within rtol of sum_b scale_b |v|), and the
     same pass's gradient on those rows."""
     import torch
     from paper_2509_00406_amd import mad
     inp, P, mask = full
-    say("full shell 1024 fp32, clamped Hessian-vector product")
-    mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, TERMS, 1)
+    say("full shell 1024", "fp32" if precision else "fp64", "clamped Hessian-vector product")
+    mesh, prob = PR.build_gpu(inp.tris, inp.rest, inp.n_verts, 3, TERMS, precision)
     x = np.ascontiguousarray(inp.x, dtype=np.float64).ravel()
     v = np.random.default_rng(77).normal(size=x.size)
     y, energy, grad = prob.hvp(torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda(),
@@ -146,9 +147,9 @@ def test_full_shell_hvp_fp32(full):
             yref[n] += ref.hess[b].reshape(3, 3) @ V[c]
             yscale[n] += ref.hscale[b].reshape(3, 3) @ np.abs(V[c])
     gi = np.concatenate([np.arange(3 * r, 3 * r + 3) for r in rows])
-    w = PR.assert_close("hvp(sampled)", y[gi], yref.ravel(), yscale.ravel(), PR.RTOL[1])
-    g = PR.assert_close("grad(sampled)", grad.cpu().numpy()[gi], ref.grad[gi], ref.gscale[gi], PR.RTOL[1])
+    w = PR.assert_close("hvp(sampled)", y[gi], yref.ravel(), yscale.ravel(), PR.RTOL[precision])
+    g = PR.assert_close("grad(sampled)", grad.cpu().numpy()[gi], ref.grad[gi], ref.gscale[gi], PR.RTOL[precision])
     e_ref, e_abs = npref.shell_energy(inp.tris, inp.rest, inp.x, P.topo.diamonds, P.topo.diamond_faces,
                                       STVK_PRM, BEND_PRM)
-    assert abs(float(energy.cpu()[0]) - e_ref) <= PR.RTOL[1] * e_abs
+    assert abs(float(energy.cpu()[0]) - e_ref) <= PR.RTOL[precision] * e_abs
     say(f"hvp: worst {w:.2e} over {rows.size} rows, grad {g:.2e}")
